@@ -1,0 +1,197 @@
+"""CPU oracle (plain FP64 C, OpenMP over rows) for the Cholesky path.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the benchmark's CPU-baseline leg, never by the GPU library.  It shares no
+code with the GPU library.  ``build()`` compiles ``cd_oracle.c`` with gcc.
+
+Every function follows the paper's Sec. 2 (decomposition), Sec. 4.1 (J/K
+from the vectors, AO->MO transform); see ``cd_oracle.c`` for the formulas.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import NamedTuple, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.or_boys0.restype = ctypes.c_double
+        L.or_boys0.argtypes = [ctypes.c_double]
+        L.or_eri.restype = ctypes.c_double
+        L.or_eri.argtypes = [_d, _d, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_unpack_pair.restype = None
+        L.or_unpack_pair.argtypes = [ctypes.c_int64, _i32, _i32]
+        L.or_diagonal_all.restype = None
+        L.or_diagonal_all.argtypes = [ctypes.c_int, _d, _d, _d]
+        L.or_rows.restype = ctypes.c_int64
+        L.or_rows.argtypes = [ctypes.c_int, _d, _d, ctypes.c_double, _i64, _d]
+        L.or_eri_matrix.restype = None
+        L.or_eri_matrix.argtypes = [_d, _d, ctypes.c_int64, _i64, _d]
+        L.or_decompose.restype = ctypes.c_int
+        L.or_decompose.argtypes = [_d, _d, ctypes.c_int64, _i64, ctypes.c_double, ctypes.c_int64,
+                                   _d, _i64, _d, _d, _i64, _i64, ctypes.c_int64,
+                                   ctypes.c_double, _i64]
+        L.or_jk_cd.restype = None
+        L.or_jk_cd.argtypes = [ctypes.c_int, ctypes.c_int64, _i64, _d, ctypes.c_int64, _d,
+                               ctypes.c_int, _d, _d]
+        L.or_jk_exact.restype = None
+        L.or_jk_exact.argtypes = [ctypes.c_int, _d, _d, _d, ctypes.c_int, _d, _d]
+        L.or_e2.restype = ctypes.c_double
+        L.or_e2.argtypes = [ctypes.c_int, _d, ctypes.c_int, _d, _d]
+        L.or_transform.restype = None
+        L.or_transform.argtypes = [ctypes.c_int, ctypes.c_int64, _i64, _d, ctypes.c_int64, _d,
+                                   ctypes.c_int, _d, ctypes.c_int, _d]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def boys0(T: float) -> float:
+    return lib().or_boys0(float(T))
+
+
+def eri(xyz, alpha, mu, nu, sg, rh) -> float:
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    return lib().or_eri(_p(xyz, _d), _p(alpha, _d), mu, nu, sg, rh)
+
+
+def unpack_pair(pq: int):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    lib().or_unpack_pair(int(pq), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def diagonal_all(xyz, alpha) -> np.ndarray:
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    N = alpha.shape[0]
+    out = np.empty(N * (N + 1) // 2)
+    lib().or_diagonal_all(N, _p(xyz, _d), _p(alpha, _d), _p(out, _d))
+    return out
+
+
+def rows(xyz, alpha, schwarz: float):
+    """Screened row list (packed pair indices, ascending) and max D^1."""
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    N = alpha.shape[0]
+    rp = np.empty(max(1, N * (N + 1) // 2), dtype=np.int64)
+    mx = ctypes.c_double()
+    n = lib().or_rows(N, _p(xyz, _d), _p(alpha, _d), float(schwarz), _p(rp, _i64),
+                      ctypes.byref(mx))
+    return rp[:n].copy(), mx.value
+
+
+def eri_matrix(xyz, alpha, row_pair) -> np.ndarray:
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    rp = np.ascontiguousarray(row_pair, dtype=np.int64)
+    n = rp.shape[0]
+    A = np.empty((n, n))
+    lib().or_eri_matrix(_p(xyz, _d), _p(alpha, _d), n, _p(rp, _i64), _p(A, _d))
+    return A
+
+
+class CD(NamedTuple):
+    rc: int
+    M: int
+    L: np.ndarray        # [M][n]
+    pivots: np.ndarray   # [M] row indices
+    dpiv: np.ndarray     # [M] pivot values d_K
+    D: np.ndarray        # [n] final residual diagonal
+    bad: int             # replay: first pivot that was not a valid argmax (or -1)
+
+
+def decompose(xyz, alpha, row_pair, tau: float, max_vectors: Optional[int] = None,
+              given: Optional[np.ndarray] = None, tie_tol: float = 0.0) -> CD:
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    rp = np.ascontiguousarray(row_pair, dtype=np.int64)
+    n = rp.shape[0]
+    if max_vectors is None:
+        max_vectors = n
+    L = np.zeros((max(1, max_vectors), max(1, n)))
+    piv = np.zeros(max(1, max_vectors), dtype=np.int64)
+    dp = np.zeros(max(1, max_vectors))
+    D = np.zeros(max(1, n))
+    M = ctypes.c_int64()
+    bad = ctypes.c_int64()
+    if given is not None:
+        g = np.ascontiguousarray(given, dtype=np.int64)
+        gp, ng = _p(g, _i64), g.shape[0]
+    else:
+        g, gp, ng = None, None, 0
+    rc = lib().or_decompose(_p(xyz, _d), _p(alpha, _d), n, _p(rp, _i64), float(tau),
+                            int(max_vectors), _p(L, _d), _p(piv, _i64), _p(dp, _d), _p(D, _d),
+                            ctypes.byref(M), gp, ng, float(tie_tol), ctypes.byref(bad))
+    m = M.value
+    return CD(rc, m, L[:m, :n].copy(), piv[:m].copy(), dp[:m].copy(), D[:n].copy(), bad.value)
+
+
+def jk_cd(N: int, row_pair, L, C):
+    rp = np.ascontiguousarray(row_pair, dtype=np.int64)
+    L = _f64(L)
+    C = _f64(C)
+    M = L.shape[0] if L.ndim == 2 else 0
+    O = C.shape[1]
+    J = np.empty((N, N))
+    K = np.empty((N, N))
+    lib().or_jk_cd(N, rp.shape[0], _p(rp, _i64), _p(L, _d), M, _p(C, _d), O, _p(J, _d),
+                   _p(K, _d))
+    return J, K
+
+
+def jk_exact(xyz, alpha, C):
+    xyz, alpha, C = _f64(xyz), _f64(alpha), _f64(C)
+    N = alpha.shape[0]
+    J = np.empty((N, N))
+    K = np.empty((N, N))
+    lib().or_jk_exact(N, _p(xyz, _d), _p(alpha, _d), _p(C, _d), C.shape[1], _p(J, _d),
+                      _p(K, _d))
+    return J, K
+
+
+def e2(C, J, K) -> float:
+    C, J, K = _f64(C), _f64(J), _f64(K)
+    return lib().or_e2(C.shape[0], _p(C, _d), C.shape[1], _p(J, _d), _p(K, _d))
+
+
+def transform(N: int, row_pair, L, C1, C2) -> np.ndarray:
+    rp = np.ascontiguousarray(row_pair, dtype=np.int64)
+    L, C1, C2 = _f64(L), _f64(C1), _f64(C2)
+    M = L.shape[0]
+    p, q = C1.shape[1], C2.shape[1]
+    out = np.empty((M, p, q))
+    lib().or_transform(N, rp.shape[0], _p(rp, _i64), _p(L, _d), M, _p(C1, _d), p, _p(C2, _d),
+                       q, _p(out, _d))
+    return out

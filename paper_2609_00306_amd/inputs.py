@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs: molecules made of normalised s-type Gaussians.
+
+This module only draws random numbers and lays them out; it holds none of the
+decomposition's arithmetic (no pair data, no integrals, no screening), so both
+the CPU oracle and the GPU library can be fed from it.
+
+Recipe (the paper's workloads are real molecules in real basis sets; these
+synthetic stand-ins keep their basis sizes, occupied-orbital counts and
+thresholds):
+
+* Centres are drawn one at a time, uniform in the cube [0, L)^3 (L given in
+  angstrom, converted with 1 bohr = 0.529177210903 angstrom, CODATA 2018); a
+  draw closer than ``min_sep`` bohr to an earlier centre is rejected and drawn
+  again.
+* Every centre carries one primitive per exponent; functions are ordered
+  centre-major, exponent-minor.
+* The occupied coefficients C [N][O] are the Q factor of the QR decomposition
+  of an N x O matrix of standard normal deviates, drawn after the centres from
+  the same generator.
+* The generator is ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+BOHR_ANGSTROM = 0.529177210903
+ANGSTROM_TO_BOHR = 1.0 / BOHR_ANGSTROM
+
+#: four exponents in geometric progression from 0.1 to 10 bohr^-2
+GEOMETRIC4 = tuple(float(x) for x in 10.0 ** np.linspace(-1.0, 1.0, 4))
+
+
+@dataclasses.dataclass
+class Molecule:
+    """One synthetic molecule; all arrays are C-contiguous float64."""
+
+    name: str
+    seed: int
+    xyz: np.ndarray      # [N][3] bohr, one row per basis function
+    alpha: np.ndarray    # [N] bohr^-2
+    C: np.ndarray        # [N][O] occupied coefficients (orthonormal columns)
+
+    @property
+    def n_basis(self) -> int:
+        return int(self.alpha.shape[0])
+
+    @property
+    def n_occ(self) -> int:
+        return int(self.C.shape[1])
+
+
+def draw_centres(rng: np.random.Generator, n_centres: int, box_bohr: float,
+                 min_sep: float = 1.0, max_tries: int = 1_000_000) -> np.ndarray:
+    """Uniform centres in [0, box)^3 with rejection of close pairs."""
+    out = np.empty((n_centres, 3))
+    k = 0
+    tries = 0
+    while k < n_centres:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place centres; box too small for min_sep")
+        c = rng.uniform(0.0, box_bohr, size=3)
+        if k and np.min(np.sum((out[:k] - c) ** 2, axis=1)) < min_sep * min_sep:
+            continue
+        out[k] = c
+        k += 1
+    return out
+
+
+def make_molecule(n_centres: int, box_angstrom: float, exponents: Sequence[float],
+                  n_occ: int, seed: int, min_sep: float = 1.0, name: str = "",
+                  rng: np.random.Generator | None = None) -> Molecule:
+    if rng is None:
+        rng = np.random.Generator(np.random.PCG64(seed))
+    centres = draw_centres(rng, n_centres, box_angstrom * ANGSTROM_TO_BOHR, min_sep)
+    ne = len(exponents)
+    xyz = np.ascontiguousarray(np.repeat(centres, ne, axis=0))
+    alpha = np.ascontiguousarray(np.tile(np.asarray(exponents, dtype=np.float64), n_centres))
+    n = n_centres * ne
+    if n_occ > 0:
+        g = rng.standard_normal((n, n_occ))
+        q, _ = np.linalg.qr(g)
+        C = np.ascontiguousarray(q[:, :n_occ])
+    else:
+        C = np.zeros((n, 0))
+    return Molecule(name=name or f"s{n}", seed=seed, xyz=xyz, alpha=alpha, C=C)
+
+
+def random_small(seed: int, n_centres: int = 3, exps: Tuple[float, ...] = (0.3, 1.7),
+                 box_angstrom: float = 3.0, n_occ: int = 2) -> Molecule:
+    """Tiny molecules for brute-force checks."""
+    return make_molecule(n_centres, box_angstrom, exps, n_occ, seed,
+                         min_sep=0.5, name=f"tiny{seed}")
+
+
+# Workloads. The thresholds are the ones each workload is run at; 'schwarz'
+# is the pair-screening threshold.
+CONFIGS: Dict[str, dict] = {
+    # the full 1830 x 1830 unique-pair matrix: no screening
+    "C1": dict(n_centres=20, box=8.0, exponents=(0.2, 1.0, 5.0), n_occ=10, seed=1,
+               taus=(1e-6,), schwarz=0.0),
+    "C2": dict(n_centres=100, box=16.0, exponents=GEOMETRIC4, n_occ=50, seed=2,
+               taus=(1e-4, 1e-5, 1e-6), schwarz=1e-12),
+    "C3": dict(n_centres=250, box=16.0 * (250 / 100) ** (1.0 / 3.0), exponents=GEOMETRIC4,
+               n_occ=120, seed=3, taus=(1e-6,), schwarz=1e-12),
+    "C5": dict(n_centres=300, box=24.0, exponents=GEOMETRIC4, n_occ=150, seed=5,
+               taus=(1e-6,), schwarz=1e-12),
+}
+
+#: batched workload: 64 molecules, seeds 4000+i, c ~ U{13..100} centres,
+#: box 16 (c/100)^(1/3) angstrom, O = N // 8, tau = 1e-5
+BATCH_C4 = dict(count=64, seed0=4000, cmin=13, cmax=100, exponents=GEOMETRIC4,
+                tau=1e-5, schwarz=1e-12)
+
+
+def config_molecule(name: str) -> Molecule:
+    c = CONFIGS[name]
+    return make_molecule(c["n_centres"], c["box"], c["exponents"], c["n_occ"], c["seed"],
+                         name=name)
+
+
+def batch_c4(count: int | None = None) -> List[Molecule]:
+    b = BATCH_C4
+    cnt = b["count"] if count is None else count
+    mols = []
+    for i in range(cnt):
+        seed = b["seed0"] + i
+        rng = np.random.Generator(np.random.PCG64(seed))
+        c = int(rng.integers(b["cmin"], b["cmax"] + 1))
+        nb = c * len(b["exponents"])
+        mols.append(make_molecule(c, 16.0 * (c / 100.0) ** (1.0 / 3.0), b["exponents"],
+                                  nb // 8, seed, name=f"C4_{i}", rng=rng))
+    return mols

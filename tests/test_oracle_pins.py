@@ -1,0 +1,365 @@
+"""Pins for the CPU oracle: checks against what the mathematics and the paper
+fix, independent of the oracle's own formulas.
+
+* Boys F0 against arbitrary-precision quadrature of its defining integral.
+* ERIs against closed special cases (self-repulsion, far-field multipole
+  limit), against a fully numerical route (Laplace transform of 1/r plus
+  grid quadrature, no Gaussian product theorem and no Boys function), and
+  for 8-fold permutational symmetry and positive semi-definiteness.
+* The decomposition against LAPACK's complete-pivoting Cholesky (dpstrf),
+  against the density-fitting identity of Sec. 3 (Eq. CVsLT: L = A[:,B]
+  chol(A[B,B])^-T), and for the invariants of Sec. 2 (stop rule, error
+  bound, non-increasing pivots, prefix property in tau).
+* J/K against brute force from exact integrals and closed cases.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+import scipy.linalg.lapack as lapack
+
+from paper_2609_00306_amd.inputs import config_molecule, make_molecule, random_small
+
+
+# ---------------------------------------------------------------- Boys F0
+@pytest.mark.parametrize("T", [0.0, 1e-12, 1e-3, 0.5, 1.0, 7.5, 30.0, 1e3])
+def test_boys0_matches_mp_quadrature(orc, T):
+    import mpmath
+    mpmath.mp.dps = 40
+    ref = mpmath.quad(lambda t: mpmath.e ** (-mpmath.mpf(T) * t * t), [0, 1])
+    got = orc.boys0(T)
+    assert abs(got - float(ref)) <= 2e-15 * float(ref)
+
+
+def test_boys0_large_T_asymptote(orc):
+    T = 1e4
+    assert orc.boys0(T) == pytest.approx(0.5 * math.sqrt(math.pi / T), rel=1e-15)
+
+
+# ---------------------------------------------------------------- ERIs
+@pytest.mark.parametrize("a", [0.1, 0.2, 1.0, 5.0, 10.0])
+def test_self_repulsion_closed_form(orc, a):
+    xyz = np.zeros((1, 3))
+    alpha = np.array([a])
+    assert orc.eri(xyz, alpha, 0, 0, 0, 0) == pytest.approx(2.0 * math.sqrt(a / math.pi), rel=1e-14)
+
+
+def test_self_repulsion_value_at_unit_exponent(orc):
+    # 2 / sqrt(pi)
+    assert orc.eri(np.zeros((1, 3)), np.array([1.0]), 0, 0, 0, 0) == pytest.approx(
+        1.1283791670955126, rel=1e-15)
+
+
+def _overlap_textbook(a, b, R):
+    # <g_a|g_b> for normalised s Gaussians: (2 sqrt(ab)/(a+b))^{3/2} exp(-ab R^2/(a+b))
+    return (2.0 * math.sqrt(a * b) / (a + b)) ** 1.5 * math.exp(-a * b * R * R / (a + b))
+
+
+def test_far_field_limit(orc):
+    R = 1000.0
+    xyz = np.array([[0, 0, 0], [0.3, 0, 0], [0, 0, R], [0, 0.2, R]], dtype=float)
+    alpha = np.array([0.7, 1.3, 0.4, 2.0])
+    # (aa|cc) R -> 1 for two unit charges
+    assert orc.eri(xyz, alpha, 0, 0, 2, 2) * R == pytest.approx(1.0, rel=1e-12)
+    # (ab|cd) -> S_ab S_cd / R_PQ (monopole term)
+    Sab = _overlap_textbook(0.7, 1.3, 0.3)
+    Scd = _overlap_textbook(0.4, 2.0, 0.2)
+    Pz = 0.0
+    Qz = R
+    Px = 0.3 * 1.3 / 2.0
+    Qy = 0.2 * 2.0 / 2.4
+    RPQ = math.sqrt(Px ** 2 + Qy ** 2 + (Qz - Pz) ** 2)
+    assert orc.eri(xyz, alpha, 0, 1, 2, 3) == pytest.approx(Sab * Scd / RPQ, rel=1e-9)
+
+
+def _eri_numerical(A, a, B, b, Cc, c, Dd, d):
+    """(ab|cd) by 1/r = (2/sqrt(pi)) int_0^inf exp(-u^2 r^2) du, with each
+    Cartesian factor evaluated by quadrature of the plain 1-D Gaussians (no
+    Gaussian product theorem, no Boys function)."""
+    def g1(x, ctr, e):
+        return (2.0 * e / math.pi) ** 0.25 * np.exp(-e * (x - ctr) ** 2)
+
+    h = 0.02
+    sn, sw = np.polynomial.hermite.hermgauss(80)   # weight exp(-s^2)
+    dims = []
+    for k in range(3):
+        x = np.arange(min(A[k], B[k]) - 6.0, max(A[k], B[k]) + 6.0, h)
+        y = np.arange(min(Cc[k], Dd[k]) - 6.0, max(Cc[k], Dd[k]) + 6.0, h)
+        dims.append((k, x, y, g1(x, A[k], a) * g1(x, B[k], b) * h,
+                     g1(y, Cc[k], c) * g1(y, Dd[k], d) * h))
+
+    def factor(u, k, x, y, f1, f2):
+        if u < 1.0:      # wide kernel: plain 2-D grid sum
+            return f1 @ np.exp(-(u * u) * (x[:, None] - y[None, :]) ** 2) @ f2
+        # narrow kernel: y = x - s/u, Gauss-Hermite in s
+        yy = x[:, None] - sn[None, :] / u
+        f2y = g1(yy, Cc[k], c) * g1(yy, Dd[k], d)
+        return (f1 @ (f2y @ sw)) / u
+
+    def integrand(u):
+        val = 1.0
+        for dd in dims:
+            val *= factor(u, *dd)
+        return val
+
+    tot = scipy.integrate.quad(integrand, 0.0, 1.0, epsabs=0, epsrel=1e-12, limit=200)[0]
+    tot += scipy.integrate.quad(integrand, 1.0, 8.0, epsabs=0, epsrel=1e-12, limit=200)[0]
+    tot += scipy.integrate.quad(lambda t: integrand(8.0 / t) * 8.0 / (t * t), 0.0, 1.0,
+                                epsabs=0, epsrel=1e-12, limit=200)[0]
+    return 2.0 / math.sqrt(math.pi) * tot
+
+
+def test_eri_matches_numerical_route(orc):
+    xyz = np.array([[0.0, 0.0, 0.0], [0.6, -0.2, 0.3], [1.1, 0.4, -0.5], [-0.4, 0.9, 0.8]])
+    alpha = np.array([0.8, 1.5, 0.6, 1.1])
+    for (i, j, k, l) in [(0, 1, 2, 3), (0, 0, 2, 2), (1, 3, 3, 2)]:
+        ref = _eri_numerical(xyz[i], alpha[i], xyz[j], alpha[j], xyz[k], alpha[k], xyz[l], alpha[l])
+        got = orc.eri(xyz, alpha, i, j, k, l)
+        assert got == pytest.approx(ref, rel=1e-9), (i, j, k, l, got, ref)
+
+
+def test_eri_eightfold_symmetry(orc):
+    m = random_small(7, n_centres=3, exps=(0.3, 2.0))
+    rng = np.random.default_rng(0)
+    N = m.n_basis
+    for _ in range(20):
+        a, b, c, d = (int(v) for v in rng.integers(0, N, 4))
+        ref = orc.eri(m.xyz, m.alpha, a, b, c, d)
+        for (w, x, y, z) in [(b, a, c, d), (a, b, d, c), (b, a, d, c), (c, d, a, b),
+                             (d, c, a, b), (c, d, b, a), (d, c, b, a)]:
+            assert orc.eri(m.xyz, m.alpha, w, x, y, z) == pytest.approx(ref, rel=1e-14, abs=1e-300)
+
+
+def test_eri_matrix_is_psd_c1(orc):
+    m = config_molecule("C1")
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    assert len(rp) == 1830
+    A = orc.eri_matrix(m.xyz, m.alpha, rp)
+    assert np.array_equal(A, A.T) or np.abs(A - A.T).max() <= 1e-15 * np.abs(A).max()
+    w = np.linalg.eigvalsh(A)
+    assert w.min() >= -1e-13 * w.max()
+
+
+def test_pair_unpack_roundtrip(orc):
+    for pq in [0, 1, 2, 3, 4, 5, 100, 1829, 720599, 10 ** 9]:
+        mu, nu = orc.unpack_pair(pq)
+        assert mu >= nu >= 0
+        assert mu * (mu + 1) // 2 + nu == pq
+
+
+def test_screening_rule(orc):
+    m = config_molecule("C2")
+    D1 = orc.diagonal_all(m.xyz, m.alpha)
+    rp, mx = orc.rows(m.xyz, m.alpha, 1e-12)
+    assert mx == D1.max()
+    assert np.all(np.diff(rp) > 0)
+    kept = np.zeros(D1.shape, bool)
+    kept[rp] = True
+    assert np.all(np.sqrt(D1[kept] * mx) >= 1e-12)
+    assert np.all(np.sqrt(D1[~kept] * mx) < 1e-12)
+    rp2, _ = orc.rows(m.xyz, m.alpha, 1e-8)
+    assert len(rp2) < len(rp) and np.all(np.isin(rp2, rp))
+    # the largest diagonal of s functions is a one-centre pair of the
+    # tightest exponent: 2 sqrt(alpha_max/pi)
+    assert mx == pytest.approx(2.0 * math.sqrt(10.0 / math.pi), rel=1e-14)
+
+
+# ---------------------------------------------------------------- decomposition
+def _cd_with_matrix(orc, m, tau, schwarz=0.0):
+    rp, _ = orc.rows(m.xyz, m.alpha, schwarz)
+    A = orc.eri_matrix(m.xyz, m.alpha, rp)
+    cd = orc.decompose(m.xyz, m.alpha, rp, tau)
+    return rp, A, cd
+
+
+@pytest.fixture(scope="module")
+def c1_cd(orc):
+    return _cd_with_matrix(orc, config_molecule("C1"), 1e-6)
+
+
+def test_cd_matches_lapack_dpstrf_c1(orc, c1_cd):
+    rp, A, cd = c1_cd
+    c, piv, rank, info = lapack.dpstrf(A.copy(), tol=1e-6, lower=1)
+    piv = piv - 1
+    assert rank == cd.M == 235
+    assert np.array_equal(piv[:rank], cd.pivots)
+    Lf = np.tril(c)[:, :rank]
+    assert np.abs(Lf - cd.L.T[piv]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cd_matches_lapack_dpstrf_tiny(orc, seed):
+    m = random_small(100 + seed, n_centres=3 + seed % 2, exps=(0.25, 1.0, 4.0)[: 2 + seed % 2])
+    for tau in (1e-3, 1e-6, 1e-9):
+        rp, A, cd = _cd_with_matrix(orc, m, tau)
+        c, piv, rank, info = lapack.dpstrf(A.copy(), tol=tau, lower=1)
+        piv = piv - 1
+        assert rank == cd.M
+        assert np.array_equal(piv[:rank], cd.pivots)
+        assert np.abs(np.tril(c)[:, :rank] - cd.L.T[piv]).max() <= 1e-12
+
+
+def test_density_fitting_identity(orc, c1_cd):
+    # Sec. 3, Eq. (CVsLT): with the Cholesky basis B, L = A[:, B] M^-T, S = M M^T
+    rp, A, cd = c1_cd
+    B = cd.pivots
+    S = A[np.ix_(B, B)]
+    Mf = np.linalg.cholesky(S)
+    Ldf = scipy.linalg.solve_triangular(Mf, A[:, B].T, lower=True).T
+    assert np.abs(Ldf - cd.L.T).max() <= 1e-10
+
+
+def test_invariants_c1(orc, c1_cd):
+    rp, A, cd = c1_cd
+    tau = 1e-6
+    assert cd.rc == 0
+    assert cd.D.max() < tau                       # stop rule, Sec. 2
+    assert cd.D.min() >= -1e-12                   # no large negative residuals
+    R = A - cd.L.T @ cd.L
+    assert np.abs(R).max() <= tau                 # Cauchy-Schwarz bound, Sec. 2
+    assert np.abs(np.diag(R) - cd.D).max() <= 1e-12
+    assert np.all(np.diff(cd.dpiv) <= 0)          # non-increasing diagonal, Sec. 3
+    for K in range(cd.M):
+        earlier = cd.pivots[:K]
+        assert np.abs(cd.L[K, earlier]).max(initial=0) <= 1e-12
+        assert cd.L[K, cd.pivots[K]] == pytest.approx(math.sqrt(cd.dpiv[K]), rel=1e-8)
+    # a pivot's residual is zeroed when its vector is formed; later vectors
+    # only subtract squares of rounding-level values there
+    assert np.abs(cd.D[cd.pivots]).max() <= 1e-24
+
+
+def test_prefix_and_monotone_count(orc):
+    m = config_molecule("C1")
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    res = [orc.decompose(m.xyz, m.alpha, rp, t) for t in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)]
+    Ms = [r.M for r in res]
+    assert all(a < b for a, b in zip(Ms[:-1], Ms[1:]))
+    for r in res[:-1]:
+        assert np.array_equal(r.pivots, res[-1].pivots[: r.M])
+        assert np.abs(r.L - res[-1].L[: r.M]).max() == 0.0
+
+
+def test_tau_zero_reconstructs(orc):
+    m = make_molecule(6, 4.0, (0.3, 1.0, 3.0), 2, seed=11)
+    rp, A, cd = _cd_with_matrix(orc, m, 0.0)
+    n = len(rp)
+    floor = n * 2.0 ** -53 * np.diag(A).max()
+    assert cd.D.max() <= floor
+    assert np.abs(A - cd.L.T @ cd.L).max() <= 10 * floor
+
+
+def test_replay_own_pivots_identical(orc, c1_cd):
+    rp, A, cd = c1_cd
+    m = config_molecule("C1")
+    rep = orc.decompose(m.xyz, m.alpha, rp, 1e-6, given=cd.pivots, tie_tol=0.0)
+    assert rep.bad == -1 and rep.M == cd.M
+    assert np.array_equal(rep.L, cd.L)
+
+
+def test_replay_flags_invalid_pivot(orc, c1_cd):
+    rp, A, cd = c1_cd
+    m = config_molecule("C1")
+    g = cd.pivots.copy()
+    # at step 5 take the row with the smallest residual that is still >= tau
+    base = orc.decompose(m.xyz, m.alpha, rp, 1e-6, max_vectors=5)
+    cand = np.where(base.D >= 1e-3)[0]
+    g[5] = cand[np.argmin(base.D[cand])]
+    rep = orc.decompose(m.xyz, m.alpha, rp, 1e-6, given=g, tie_tol=1e-12)
+    assert rep.bad == 5
+
+
+def test_capacity_limit(orc):
+    m = config_molecule("C1")
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    cd = orc.decompose(m.xyz, m.alpha, rp, 1e-6, max_vectors=50)
+    assert cd.rc == 1 and cd.M == 50
+
+
+def test_empty_molecule(orc):
+    rp = np.zeros(0, dtype=np.int64)
+    cd = orc.decompose(np.zeros((0, 3)), np.zeros(0), rp, 1e-6)
+    assert cd.M == 0
+
+
+# ---------------------------------------------------------------- J and K
+def test_jk_cd_vs_bruteforce_c1(orc, c1_cd):
+    rp, A, cd = c1_cd
+    m = config_molecule("C1")
+    J, K = orc.jk_cd(m.n_basis, rp, cd.L, m.C)
+    Je, Ke = orc.jk_exact(m.xyz, m.alpha, m.C)
+    Dm = m.C @ m.C.T
+    bound = 1e-6 * np.abs(Dm).sum()
+    assert np.abs(J - Je).max() <= bound
+    assert np.abs(K - Ke).max() <= bound
+    assert np.abs(J - J.T).max() <= 1e-13 and np.abs(K - K.T).max() <= 1e-13
+    assert np.sum(Dm * J) > 0 and np.sum(Dm * K) > 0
+    e_cd = orc.e2(m.C, J, K)
+    e_ex = orc.e2(m.C, Je, Ke)
+    assert abs(e_cd - e_ex) <= 1e-6 * np.abs(Dm).sum() ** 2
+
+
+def test_jk_exact_at_tau_zero(orc):
+    m = make_molecule(4, 3.0, (0.4, 1.7), 3, seed=21)
+    rp, A, cd = _cd_with_matrix(orc, m, 0.0)
+    J, K = orc.jk_cd(m.n_basis, rp, cd.L, m.C)
+    Je, Ke = orc.jk_exact(m.xyz, m.alpha, m.C)
+    assert np.abs(J - Je).max() <= 1e-12
+    assert np.abs(K - Ke).max() <= 1e-12
+
+
+def test_jk_single_function(orc):
+    a = 0.9
+    c = 0.7
+    xyz = np.zeros((1, 3))
+    alpha = np.array([a])
+    C = np.array([[c]])
+    rp, _ = orc.rows(xyz, alpha, 0.0)
+    cd = orc.decompose(xyz, alpha, rp, 0.0)
+    J, K = orc.jk_cd(1, rp, cd.L, C)
+    ref = c * c * 2.0 * math.sqrt(a / math.pi)
+    assert J[0, 0] == pytest.approx(ref, rel=1e-14)
+    assert K[0, 0] == pytest.approx(ref, rel=1e-14)
+
+
+def test_jk_linear_in_density(orc):
+    m = make_molecule(5, 4.0, (0.3, 1.2), 4, seed=31)
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    cd = orc.decompose(m.xyz, m.alpha, rp, 1e-8)
+    C1, C2 = m.C[:, :2], m.C[:, 2:]
+    J, K = orc.jk_cd(m.n_basis, rp, cd.L, m.C)
+    J1, K1 = orc.jk_cd(m.n_basis, rp, cd.L, C1)
+    J2, K2 = orc.jk_cd(m.n_basis, rp, cd.L, C2)
+    assert np.abs(J - J1 - J2).max() <= 1e-13
+    assert np.abs(K - K1 - K2).max() <= 1e-13
+
+
+# ---------------------------------------------------------------- transform
+def _unpack(orc, N, rp, L):
+    S = np.zeros((L.shape[0], N, N))
+    for r, pq in enumerate(rp):
+        mu, nu = orc.unpack_pair(int(pq))
+        S[:, mu, nu] = L[:, r]
+        S[:, nu, mu] = L[:, r]
+    return S
+
+
+def test_transform_identity_and_orthogonal(orc):
+    m = make_molecule(5, 4.0, (0.3, 1.2), 3, seed=41)
+    N = m.n_basis
+    rp, _ = orc.rows(m.xyz, m.alpha, 1e-10)
+    cd = orc.decompose(m.xyz, m.alpha, rp, 1e-7)
+    I = np.eye(N)
+    out = orc.transform(N, rp, cd.L, I, I)
+    S = _unpack(orc, N, rp, cd.L)
+    assert np.abs(out - S).max() == 0.0
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((N, N)))
+    out = orc.transform(N, rp, cd.L, Q, Q)
+    assert np.allclose(np.linalg.norm(out, axis=(1, 2)), np.linalg.norm(S, axis=(1, 2)),
+                       rtol=1e-13, atol=1e-15)
+    # rectangular, two different coefficient sets, against the explicit product
+    C1, C2 = Q[:, :3], Q[:, 4:6]
+    out = orc.transform(N, rp, cd.L, C1, C2)
+    ref = np.matmul(np.matmul(C1.T[None], S), C2[None])
+    assert np.abs(out - ref).max() <= 1e-13
