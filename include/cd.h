@@ -1,0 +1,193 @@
+/*
+ * cd.h -- C ABI of the MI355X (gfx950) Cholesky-decomposition library.
+ *
+ * The library computes, on the GPU, for molecules made of normalised s-type
+ * Gaussians (paper: "Use of Cholesky decomposition in the CFOUR program
+ * package"):
+ *   cd_decompose  the threshold-truncated, fully pivoted Cholesky
+ *                 decomposition of the two-electron-integral matrix over
+ *                 composite pair indices (Sec. 2: initial diagonal, argmax
+ *                 pivots, Eq. (subtr) vectors, Eq. (diag) diagonal update,
+ *                 stop when max D < tau);
+ *   cd_build_jk   the Coulomb and exchange matrices from the Cholesky vectors
+ *                 and the occupied coefficients (Sec. 4.1: O(N^2 M) for J,
+ *                 O(O N^2 M) for K);
+ *   cd_transform  the AO->MO transform of the vectors (Sec. 4.1, CASSCF;
+ *                 two-coefficient form of Sec. 9).
+ *
+ * Conventions
+ *   - Plain C, fixed-width integers; no C++ types or exceptions cross it.
+ *   - Pointers documented as "device" are HIP device pointers; "host" are
+ *     ordinary host memory.  The library never frees or retains caller
+ *     memory.  Device inputs are read only.
+ *   - Every call is stream ordered on the HIP stream passed as 'stream'
+ *     (a hipStream_t, or NULL for the default stream) and asynchronous unless
+ *     CD_SYNC is set or the function says otherwise.  Data-dependent results
+ *     (number of vectors, status) are written to device memory.
+ *   - Functions are ordered centre-major as given by the caller.  A "row" is
+ *     a unique pair (mu >= nu) with packed index pq = mu(mu+1)/2 + nu; rows
+ *     are kept iff sqrt(D1_row * max D1) >= schwarz (D1 = (mu nu|mu nu)) and
+ *     are stored in ascending pq.
+ *   - L is vector-major: L[K * n_rows + r] is vector K at row r.
+ *   - Units: bohr, bohr^-2, hartree.
+ *   - Return value: host-detectable errors (bad arguments, workspace too
+ *     small, launch failure).  Device-detected conditions go to the
+ *     problem's status word: CD_ERR_CAPACITY (max_vectors reached before the
+ *     threshold), CD_ERR_NOT_PSD (a non-finite diagonal), CD_ERR_DEVICE (a
+ *     device-side wait exceeded its bound).  With CD_SYNC the call
+ *     synchronises the stream and folds status words into its return value.
+ *   - cd_last_error() returns a thread-local message for the last error.
+ */
+#ifndef CD_MI355X_H
+#define CD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CD_OK = 0,
+    CD_ERR_INVALID_ARG = 1,
+    CD_ERR_WORKSPACE = 2,
+    CD_ERR_CAPACITY = 3,
+    CD_ERR_NOT_PSD = 4,
+    CD_ERR_DEVICE = 5,
+    CD_ERR_UNSUPPORTED = 6
+} cd_status;
+
+typedef enum {
+    CD_FP64 = 0,   /* all contractions in FP64 */
+    CD_FP32 = 1,   /* J/K contractions in FP32 (MFMA), FP64 across k-slabs */
+    CD_BF16X3 = 2  /* J/K contractions on a 3-way BF16 split, 6 products, FP32
+                      accumulation inside k-slabs, FP64 across slabs */
+} cd_precision;
+
+/* flags for cd_decomp_opts.flags and the J/K / transform calls */
+#define CD_SYNC 1u /* synchronise the stream and fold device status into the return value */
+
+/* One molecule.  xyz and alpha are DEVICE pointers. */
+typedef struct {
+    int32_t n_basis;       /* N >= 0 */
+    const double *xyz;     /* device [N][3], bohr */
+    const double *alpha;   /* device [N], bohr^-2, > 0 */
+} cd_molecule;
+
+typedef struct {
+    double tau;            /* decomposition threshold (Sec. 2): stop when max D < tau; tau >= 0.
+                              tau == 0 stops at max D <= n_rows * 2^-53 * max D1 */
+    double schwarz;        /* row screening threshold, >= 0 (0 keeps all N(N+1)/2 rows) */
+    uint32_t flags;        /* CD_SYNC */
+    void *const *events;   /* optional (may be NULL): host array of 4 hipEvent_t that the call
+                              records on 'stream' at the phase boundaries of the last problem:
+                              [0] before the pair/diagonal setup, [1] before pivot selection,
+                              [2] before the all-row solve, [3] after it */
+} cd_decomp_opts;
+
+/* Sizes of one decomposition problem, filled by cd_query. */
+typedef struct {
+    int64_t n_rows;        /* rows kept after screening */
+    int64_t n_active;      /* rows with D1 >= tau (the only possible pivots) */
+    size_t ws_bytes;       /* device workspace cd_decompose needs for this problem
+                              at the max_vectors passed to cd_query */
+} cd_sizes;
+
+/* Outputs of one decomposition (all DEVICE pointers, caller-allocated). */
+typedef struct {
+    cd_molecule mol;
+    int64_t n_rows;        /* from cd_query */
+    int64_t n_active;      /* from cd_query (same tau and schwarz) */
+    int64_t max_vectors;   /* capacity of L and pivots */
+    int64_t *row_pair;     /* [n_rows]   packed pair index of each row */
+    double *L;             /* [max_vectors][n_rows] Cholesky vectors */
+    int64_t *pivots;       /* [max_vectors] row index of pivot K (the Cholesky basis) */
+    double *diag;          /* [n_rows] final residual diagonal (pivot rows zeroed when chosen) */
+    int64_t *n_vectors;    /* [1] number of vectors M */
+    int32_t *status;       /* [1] device status word (cd_status) */
+} cd_problem;
+
+/*
+ * cd_query: screen the rows of each molecule on the device (blocking: it
+ * synchronises 'stream') and report sizes and workspace.  'sizes' is a host
+ * array of 'count' entries; 'max_vectors' is a host array of capacities.
+ * Returns CD_ERR_INVALID_ARG for N < 0, tau < 0, schwarz < 0, null pointers.
+ */
+cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts *opts,
+                   const int64_t *max_vectors, cd_sizes *sizes, void *stream);
+
+/*
+ * cd_decompose: decompose 'count' molecules (host array 'probs') with the
+ * workspace 'ws' (device, ws_bytes >= the sum of cd_query's ws_bytes).
+ * Asynchronous and free of host synchronisation unless CD_SYNC is set.  The
+ * device recounts the rows; a count that differs from n_rows / n_active
+ * gives status CD_ERR_DEVICE and no vectors.
+ * The pivots follow Sec. 2 exactly: the pivot is the row of largest residual
+ * diagonal (lowest row index among equal values), the vector is
+ * [(r|P) - sum_J L^J_r L^J_P] / sqrt(d_P) with d_P the tracked diagonal, the
+ * pivot's own residual is set to zero, and the loop ends when max D < tau.
+ * Rows whose D1 < tau can never be pivots and are only solved for at the
+ * end (the two-step organisation of Sec. 3, with exact pivoting).
+ */
+cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* One J/K build (all pointers DEVICE unless noted). */
+typedef struct {
+    int32_t n_basis;
+    int64_t n_rows;
+    int64_t max_vectors;
+    const int64_t *row_pair;   /* [n_rows] from cd_decompose */
+    const double *L;           /* [max_vectors][n_rows] */
+    const int64_t *n_vectors;  /* [1] */
+    int32_t n_occ;             /* O >= 0 */
+    const double *C;           /* [N][O] occupied coefficients, D = C C^T */
+    double *J;                 /* [N][N] out */
+    double *K;                 /* [N][N] out */
+    int32_t *status;           /* [1] */
+} cd_jk_problem;
+
+/* Workspace for cd_build_jk at the given precision (host-side, no device work). */
+cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
+                      size_t *ws_bytes);
+
+/*
+ * cd_build_jk: J_{mu nu} = sum_P L^P_{mu nu} V^P, V^P = sum_{rho sigma} L^P_{rho sigma} D_{rho sigma};
+ * K_{mu nu} = sum_P sum_i X^P_{i mu} X^P_{i nu}, X^P_{i mu} = sum_sigma L^P_{mu sigma} C_{sigma i}.
+ * Screened pairs contribute nothing; J and K are symmetric and written in full.
+ */
+cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
+                      uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* One AO->MO transform (all pointers DEVICE). */
+typedef struct {
+    int32_t n_basis;
+    int64_t n_rows;
+    int64_t max_vectors;
+    const int64_t *row_pair;
+    const double *L;
+    const int64_t *n_vectors;
+    int32_t p;                 /* columns of C1 */
+    const double *C1;          /* [N][p] */
+    int32_t q;                 /* columns of C2 */
+    const double *C2;          /* [N][q] */
+    double *Lmo;               /* [max_vectors][p][q] out: sum C1[mu][a] L^P_{mu nu} C2[nu][b] */
+    int32_t *status;           /* [1] */
+} cd_transform_problem;
+
+cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, size_t *ws_bytes);
+
+cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_t flags,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Thread-local message describing the last error returned on this thread. */
+const char *cd_last_error(void);
+
+/* Library version string. */
+const char *cd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

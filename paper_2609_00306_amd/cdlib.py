@@ -1,0 +1,278 @@
+"""Thin ctypes binding of the C ABI in include/cd.h.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory and the stream.  The library must
+have been built (``paper_2609_00306_amd.build.build()``); there is no CPU
+fallback, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcd.so")
+
+CD_OK, CD_ERR_INVALID_ARG, CD_ERR_WORKSPACE, CD_ERR_CAPACITY, CD_ERR_NOT_PSD, \
+    CD_ERR_DEVICE, CD_ERR_UNSUPPORTED = range(7)
+CD_FP64, CD_FP32, CD_BF16X3 = 0, 1, 2
+CD_SYNC = 1
+PRECISIONS = {"fp64": CD_FP64, "fp32": CD_FP32, "bf16x3": CD_BF16X3}
+
+_vp = ctypes.c_void_p
+
+
+class cd_molecule(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int32), ("xyz", _vp), ("alpha", _vp)]
+
+
+class cd_decomp_opts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("schwarz", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("events", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class cd_sizes(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_active", ctypes.c_int64),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
+class cd_problem(ctypes.Structure):
+    _fields_ = [("mol", cd_molecule), ("n_rows", ctypes.c_int64),
+                ("n_active", ctypes.c_int64), ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
+                ("pivots", _vp), ("diag", _vp), ("n_vectors", _vp), ("status", _vp)]
+
+
+class cd_jk_problem(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
+                ("n_vectors", _vp), ("n_occ", ctypes.c_int32), ("C", _vp), ("J", _vp),
+                ("K", _vp), ("status", _vp)]
+
+
+class cd_transform_problem(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
+                ("n_vectors", _vp), ("p", ctypes.c_int32), ("C1", _vp), ("q", ctypes.c_int32),
+                ("C2", _vp), ("Lmo", _vp), ("status", _vp)]
+
+
+#: every function include/cd.h declares
+EXPORTS = ("cd_query", "cd_decompose", "cd_query_jk", "cd_build_jk", "cd_query_transform",
+           "cd_transform", "cd_last_error", "cd_version")
+
+_lib = None
+
+
+class CDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cd status {status}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libcd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing; run "
+                           "paper_2609_00306_amd.build.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.cd_query.argtypes = [P(cd_molecule), ctypes.c_int32, P(cd_decomp_opts),
+                           P(ctypes.c_int64), P(cd_sizes), _vp]
+    L.cd_decompose.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp,
+                               ctypes.c_size_t, _vp]
+    L.cd_query_jk.argtypes = [P(cd_jk_problem), ctypes.c_int32, ctypes.c_int,
+                              P(ctypes.c_size_t)]
+    L.cd_build_jk.argtypes = [P(cd_jk_problem), ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
+                              _vp, ctypes.c_size_t, _vp]
+    L.cd_query_transform.argtypes = [P(cd_transform_problem), ctypes.c_int32,
+                                     P(ctypes.c_size_t)]
+    L.cd_transform.argtypes = [P(cd_transform_problem), ctypes.c_int32, ctypes.c_uint32, _vp,
+                               ctypes.c_size_t, _vp]
+    for f in ("cd_query", "cd_decompose", "cd_query_jk", "cd_build_jk", "cd_query_transform",
+              "cd_transform"):
+        getattr(L, f).restype = ctypes.c_int
+    L.cd_last_error.restype = ctypes.c_char_p
+    L.cd_last_error.argtypes = []
+    L.cd_version.restype = ctypes.c_char_p
+    L.cd_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != CD_OK:
+        raise CDError(st, load().cd_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None or t.numel() == 0 else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev_f64(a, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+
+
+@dataclasses.dataclass
+class Decomposition:
+    """Device-resident result of cd_decompose for one molecule."""
+    n_basis: int
+    n_rows: int
+    n_active: int
+    max_vectors: int
+    xyz: torch.Tensor
+    alpha: torch.Tensor
+    row_pair: torch.Tensor   # [n_rows] int64
+    L: torch.Tensor          # [max_vectors][n_rows] float64
+    pivots: torch.Tensor     # [max_vectors] int64
+    diag: torch.Tensor       # [n_rows] float64
+    n_vectors: torch.Tensor  # [1] int64
+    status: torch.Tensor     # [1] int32
+    workspace: torch.Tensor
+
+    def M(self) -> int:
+        return int(self.n_vectors.item())
+
+
+def molecule(xyz: torch.Tensor, alpha: torch.Tensor) -> cd_molecule:
+    return cd_molecule(int(alpha.shape[0]), _ptr(xyz), _ptr(alpha))
+
+
+def query(mols: Sequence[cd_molecule], tau: float, schwarz: float,
+          max_vectors: Sequence[int], stream=None) -> List[cd_sizes]:
+    L = load()
+    n = len(mols)
+    arr = (cd_molecule * n)(*mols)
+    caps = (ctypes.c_int64 * n)(*[int(c) for c in max_vectors])
+    out = (cd_sizes * n)()
+    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None)
+    _check(L.cd_query(arr, n, ctypes.byref(opts), caps, out, _stream(stream)))
+    return list(out)
+
+
+def allocate(xyz, alpha, tau: float, schwarz: float, max_vectors: Optional[int] = None,
+             device="cuda", stream=None) -> Decomposition:
+    """Allocate outputs and workspace for one molecule (sizes from cd_query).
+
+    Without ``max_vectors`` the capacity is the number of active rows, which
+    bounds the number of vectors (every pivot is an active row)."""
+    xyz = _dev_f64(xyz, device).reshape(-1, 3)
+    alpha = _dev_f64(alpha, device).reshape(-1)
+    if max_vectors is None:
+        sz = query([molecule(xyz, alpha)], tau, schwarz, [0], stream)[0]
+        max_vectors = max(1, int(sz.n_active))
+    sz = query([molecule(xyz, alpha)], tau, schwarz, [max_vectors], stream)[0]
+    n, mv = int(sz.n_rows), int(max_vectors)
+    i64 = dict(dtype=torch.int64, device=device)
+    f64 = dict(dtype=torch.float64, device=device)
+    return Decomposition(
+        n_basis=int(alpha.shape[0]), n_rows=n, n_active=int(sz.n_active), max_vectors=mv,
+        xyz=xyz, alpha=alpha,
+        row_pair=torch.empty(n, **i64), L=torch.empty((mv, n), **f64),
+        pivots=torch.empty(mv, **i64), diag=torch.empty(n, **f64),
+        n_vectors=torch.zeros(1, **i64), status=torch.zeros(1, dtype=torch.int32, device=device),
+        workspace=torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=device))
+
+
+def problem(d: Decomposition) -> cd_problem:
+    return cd_problem(molecule(d.xyz, d.alpha), d.n_rows, d.n_active, d.max_vectors,
+                      _ptr(d.row_pair),
+                      _ptr(d.L), _ptr(d.pivots), _ptr(d.diag), _ptr(d.n_vectors),
+                      _ptr(d.status))
+
+
+def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, sync: bool = False,
+                  stream=None, workspace: Optional[torch.Tensor] = None,
+                  events: Optional[Sequence] = None):
+    """cd_decompose on already allocated problems (one workspace per call).
+
+    ``events``: optional four torch.cuda.Event(enable_timing=True) that the
+    library records at its phase boundaries on the stream."""
+    L = load()
+    n = len(decs)
+    arr = (cd_problem * n)(*[problem(d) for d in decs])
+    ev = None
+    if events is not None:
+        ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
+    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev)
+    if workspace is None:
+        if n != 1:
+            raise ValueError("pass a shared workspace for more than one molecule")
+        workspace = decs[0].workspace
+    _check(L.cd_decompose(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
+                          _stream(stream)))
+
+
+def decompose(xyz, alpha, tau: float, schwarz: float = 1e-12, max_vectors: Optional[int] = None,
+              sync: bool = True, device="cuda", stream=None) -> Decomposition:
+    d = allocate(xyz, alpha, tau, schwarz, max_vectors, device, stream)
+    run_decompose([d], tau, schwarz, sync=sync, stream=stream)
+    return d
+
+
+@dataclasses.dataclass
+class JK:
+    J: torch.Tensor
+    K: torch.Tensor
+    status: torch.Tensor
+    workspace: torch.Tensor
+    problem: cd_jk_problem
+    C: torch.Tensor
+
+
+def prepare_jk(d: Decomposition, C, prec: str = "fp64") -> JK:
+    dev = d.L.device
+    C = _dev_f64(C, dev)
+    N = d.n_basis
+    J = torch.empty((N, N), dtype=torch.float64, device=dev)
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    p = cd_jk_problem(N, d.n_rows, d.max_vectors, _ptr(d.row_pair), _ptr(d.L), _ptr(d.n_vectors),
+                      int(C.shape[1]) if C.ndim == 2 else 0, _ptr(C), _ptr(J), _ptr(K), _ptr(st))
+    ws = ctypes.c_size_t()
+    _check(load().cd_query_jk(ctypes.byref(p), 1, PRECISIONS[prec], ctypes.byref(ws)))
+    w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    return JK(J, K, st, w, p, C)
+
+
+def run_jk(jk: JK, prec: str = "fp64", sync: bool = False, stream=None):
+    _check(load().cd_build_jk(ctypes.byref(jk.problem), 1, PRECISIONS[prec],
+                              CD_SYNC if sync else 0, _ptr(jk.workspace), jk.workspace.numel(),
+                              _stream(stream)))
+
+
+def build_jk(d: Decomposition, C, prec: str = "fp64", sync: bool = True, stream=None):
+    jk = prepare_jk(d, C, prec)
+    run_jk(jk, prec, sync, stream)
+    return jk.J, jk.K
+
+
+def transform(d: Decomposition, C1, C2, sync: bool = True, stream=None) -> torch.Tensor:
+    dev = d.L.device
+    C1 = _dev_f64(C1, dev)
+    C2 = _dev_f64(C2, dev)
+    p, q = int(C1.shape[1]), int(C2.shape[1])
+    out = torch.empty((d.max_vectors, p, q), dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    prob = cd_transform_problem(d.n_basis, d.n_rows, d.max_vectors, _ptr(d.row_pair), _ptr(d.L),
+                                _ptr(d.n_vectors), p, _ptr(C1), q, _ptr(C2), _ptr(out), _ptr(st))
+    ws = ctypes.c_size_t()
+    L = load()
+    _check(L.cd_query_transform(ctypes.byref(prob), 1, ctypes.byref(ws)))
+    w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    _check(L.cd_transform(ctypes.byref(prob), 1, CD_SYNC if sync else 0, _ptr(w), w.numel(),
+                          _stream(stream)))
+    return out

@@ -1,0 +1,183 @@
+// Device-side building blocks shared by the library's kernels (gfx950).
+//
+// Integrals over normalised s-type Gaussians g(r) = (2a/pi)^{3/4} exp(-a|r-A|^2).
+// For a pair (mu nu): p = a_mu + a_nu, P = (a_mu A_mu + a_nu A_nu)/p,
+// E = N_mu N_nu exp(-a_mu a_nu/p |A_mu - A_nu|^2).  The paper evaluates ERIs
+// with the McMurchie-Davidson scheme (Sec. 7); for s functions it reduces to
+//   (ab|cd) = 2 pi^{5/2} / (p q sqrt(p+q)) E_ab E_cd F0(T),  T = pq/(p+q)|P-Q|^2,
+// with F0(T) = (1/2) sqrt(pi/T) erf(sqrt T), F0(0) = 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdk {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kPi52x2 = 34.986836655249725;     // 2 pi^{5/2}
+constexpr double kSqrtPiHalf = 0.88622692545275801; // sqrt(pi)/2
+
+// One screened row: pair centre, exponent sum and c = E/p.
+struct __align__(64) RowRec {
+    double x, y, z, p;   // product centre P and exponent p
+    double c;            // E / p
+    double d1;           // (mu nu|mu nu)
+    double pad0, pad1;
+};
+
+__device__ __forceinline__ void unpack_pair(int64_t pq, int &mu, int &nu)
+{
+    double s = sqrt(8.0 * (double)pq + 1.0);
+    int64_t m = (int64_t)((s - 1.0) * 0.5);
+    while (m * (m + 1) / 2 > pq) --m;
+    while ((m + 1) * (m + 2) / 2 <= pq) ++m;
+    mu = (int)m;
+    nu = (int)(pq - m * (m + 1) / 2);
+}
+
+__device__ __forceinline__ RowRec make_row(const double *__restrict__ xyz,
+                                           const double *__restrict__ alpha, int mu, int nu)
+{
+    double a = alpha[mu], b = alpha[nu];
+    double ax = xyz[3 * mu], ay = xyz[3 * mu + 1], az = xyz[3 * mu + 2];
+    double bx = xyz[3 * nu], by = xyz[3 * nu + 1], bz = xyz[3 * nu + 2];
+    double p = a + b;
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double na = pow(2.0 * a / kPi, 0.75);
+    double nb = pow(2.0 * b / kPi, 0.75);
+    double e = na * nb * exp(-a * b / p * r2);
+    RowRec R;
+    R.x = (a * ax + b * bx) / p;
+    R.y = (a * ay + b * by) / p;
+    R.z = (a * az + b * bz) / p;
+    R.p = p;
+    R.c = e / p;
+    // T = 0: 2 pi^{5/2} E^2 / (p^2 sqrt(2p))
+    R.d1 = kPi52x2 * R.c * R.c / sqrt(2.0 * p);
+    R.pad0 = 0.0;
+    R.pad1 = 0.0;
+    return R;
+}
+
+// F0(T) = int_0^1 exp(-T t^2) dt
+__device__ __forceinline__ double boys0(double T)
+{
+    if (T < 1e-8) return 1.0 - T * (1.0 / 3.0);
+    double x = sqrt(T);
+    return kSqrtPiHalf * erf(x) / x;
+}
+
+__device__ __forceinline__ double eri(const RowRec &a, double bx, double by, double bz,
+                                      double bp, double bc)
+{
+    double s = a.p + bp;
+    double dx = a.x - bx, dy = a.y - by, dz = a.z - bz;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double T = a.p * bp / s * r2;
+    return kPi52x2 * a.c * bc / sqrt(s) * boys0(T);
+}
+
+__device__ __forceinline__ double eri(const RowRec &a, const RowRec &b)
+{
+    return eri(a, b.x, b.y, b.z, b.p, b.c);
+}
+
+// ---------------------------------------------------------------- grid barrier
+// Sense-free generation barrier for a cooperative launch (all workgroups
+// co-resident).  Every wait is bounded: after 'spin_limit' polls the
+// workgroup gives up and reports false; the caller then records a device
+// error and leaves.
+struct GridSync {
+    unsigned int count;
+    unsigned int gen;
+    unsigned int abort;
+    unsigned int pad[13];
+};
+
+__device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned int nblocks,
+                                             unsigned int &gen_local, unsigned int spin_limit)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned int g = gen_local;
+        unsigned int prev = __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nblocks - 1) {
+            __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gs->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned int spins = 0;
+            while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > spin_limit ||
+                    __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    __hip_atomic_store(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        gen_local = g + 1u;
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------- ordering
+// Pivot order: larger residual first, lower row index on ties.
+struct Nom {
+    double d;
+    int32_t idx;
+    int32_t pad;
+};
+
+__device__ __forceinline__ bool nom_before(double da, int ia, double db, int ib)
+{
+    return (da > db) || (da == db && ia < ib);
+}
+
+// In-place bitonic sort of n (power of two) entries in LDS into pivot order.
+// Must be called by all threads of the block.
+__device__ __forceinline__ void block_sort_noms(Nom *s, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    Nom a = s[i], b = s[ixj];
+                    bool asc = ((i & k) == 0);   // this half goes in pivot order
+                    bool a_first = nom_before(a.d, a.idx, b.d, b.idx);
+                    if (asc ? !a_first : a_first) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Wave-wide (64 lanes) selection of the lane holding the first entry in pivot order.
+__device__ __forceinline__ void wave_best(double &d, int &idx, int &lane_of)
+{
+    int lane = threadIdx.x & 63;
+    lane_of = lane;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double od = __shfl_xor(d, off, 64);
+        int oi = __shfl_xor(idx, off, 64);
+        int ol = __shfl_xor(lane_of, off, 64);
+        if (nom_before(od, oi, d, idx)) {
+            d = od;
+            idx = oi;
+            lane_of = ol;
+        }
+    }
+}
+
+}  // namespace cdk

@@ -1,0 +1,33 @@
+// Parameter blocks shared between the host entry points and the kernels.
+#pragma once
+#include <stdint.h>
+#include "cd_device.hpp"
+
+namespace cdk {
+
+struct Step1Params {
+    const RowRec *rows;        // [n_rows]
+    const int32_t *act_row;    // [n_act] row of each active slot
+    const int64_t *n_act_dev;  // device count of active rows (must equal n_act)
+    int64_t n_act;
+    double *D_act;             // [n_act] residual diagonal of the active rows
+    double *L_act;             // [max_vectors][n_act] vectors on the active rows
+    double *Cbuf;              // [QMAX][n_act] candidate columns
+    Nom *noms;                 // [G][CNOM + 1]
+    GridSync *gs;
+    int64_t *pivots;           // [max_vectors] row index of each pivot
+    int32_t *piv_slot;         // [max_vectors] active slot of each pivot
+    double *dpiv;              // [max_vectors] pivot values d_K
+    int32_t *pivot_of_row;     // [n_rows] vector index whose pivot is this row, or -1
+    int64_t *n_vectors;        // [1]
+    int32_t *status;           // [1]
+    double tau;
+    const unsigned long long *d1max_bits;  // max D1 (bit pattern)
+    int64_t n_rows;            // tau == 0: stop at max D <= n_rows 2^-53 max D1
+    int64_t max_vectors;
+    int32_t q;                 // candidate batch size (<= QMAX)
+    int32_t slice;             // active rows per workgroup
+    uint32_t spin_limit;
+};
+
+}  // namespace cdk

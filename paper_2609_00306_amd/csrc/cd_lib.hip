@@ -1,0 +1,482 @@
+// Host side of the C ABI declared in include/cd.h: argument checks, workspace
+// layout and stream-ordered launches.  All kernels live in this one
+// translation unit (unity build) so that plain hipcc -shared suffices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cd.h"
+#include "cd_decompose.hip"
+#include "cd_jk.hip"
+
+using namespace cdk;
+
+namespace {
+
+thread_local std::string g_err;
+
+cd_status fail(cd_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+cd_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return CD_OK;
+}
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+int64_t n_pairs(int64_t N) { return N * (N + 1) / 2; }
+int64_t blocks_of(int64_t n, int64_t b) { return (n + b - 1) / b; }
+
+// Workspace layout of one decomposition.
+struct DecompWs {
+    double *D1all;
+    unsigned long long *d1max;
+    int32_t *cnt_rows, *cnt_act;
+    int64_t *off_rows, *off_act, *totals;
+    RowRec *rows;
+    int32_t *act_row;
+    double *D_act;
+    double *L_act;
+    double *Cbuf;
+    Nom *noms;
+    GridSync *gs;
+    int32_t *piv_slot;
+    double *dpiv;
+    int32_t *pivot_of_row;
+    double *Lp;
+    RowRec *prow;
+    size_t bytes;
+};
+
+DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
+{
+    DecompWs w{};
+    Carver c(ws);
+    const int64_t np = n_pairs(N);
+    const int64_t nblk = std::max<int64_t>(1, blocks_of(np, 256));
+    w.D1all = c.take<double>(std::max<int64_t>(1, np));
+    w.d1max = c.take<unsigned long long>(1);
+    w.cnt_rows = c.take<int32_t>(nblk);
+    w.cnt_act = c.take<int32_t>(nblk);
+    w.off_rows = c.take<int64_t>(nblk);
+    w.off_act = c.take<int64_t>(nblk);
+    w.totals = c.take<int64_t>(4);
+    w.rows = c.take<RowRec>(std::max<int64_t>(1, n));
+    w.act_row = c.take<int32_t>(std::max<int64_t>(1, na));
+    w.D_act = c.take<double>(std::max<int64_t>(1, na));
+    w.L_act = c.take<double>(std::max<int64_t>(1, mv * na));
+    w.Cbuf = c.take<double>(std::max<int64_t>(1, (int64_t)QMAX * na));
+    w.noms = c.take<Nom>((size_t)S1_MAXG * (CNOM + 1));
+    w.gs = c.take<GridSync>(1);
+    w.piv_slot = c.take<int32_t>(std::max<int64_t>(1, mv));
+    w.dpiv = c.take<double>(std::max<int64_t>(1, mv));
+    w.pivot_of_row = c.take<int32_t>(std::max<int64_t>(1, n));
+    w.Lp = c.take<double>(std::max<int64_t>(1, mv * mv));
+    w.prow = c.take<RowRec>(std::max<int64_t>(1, mv));
+    w.bytes = c.off;
+    return w;
+}
+
+struct DevInfo {
+    int dev = -1;
+    int n_cu = 0;
+    int coop_blocks_per_cu = 0;
+};
+
+cd_status dev_info(DevInfo &di)
+{
+    if (hipGetDevice(&di.dev) != hipSuccess) return fail(CD_ERR_DEVICE, "no HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, di.dev) != hipSuccess)
+        return fail(CD_ERR_DEVICE, "hipGetDeviceProperties failed");
+    di.n_cu = prop.multiProcessorCount;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step1, 256, 0) != hipSuccess)
+        return fail(CD_ERR_DEVICE, "occupancy query failed");
+    di.coop_blocks_per_cu = nb;
+    return CD_OK;
+}
+
+cd_status check_mol(const cd_molecule &m)
+{
+    if (m.n_basis < 0) return fail(CD_ERR_INVALID_ARG, "n_basis < 0");
+    if (m.n_basis > 0 && (!m.xyz || !m.alpha)) return fail(CD_ERR_INVALID_ARG, "null xyz/alpha");
+    if ((int64_t)m.n_basis * (m.n_basis + 1) / 2 > (int64_t)INT32_MAX)
+        return fail(CD_ERR_UNSUPPORTED, "too many basis functions");
+    return CD_OK;
+}
+
+cd_status check_opts(const cd_decomp_opts *o)
+{
+    if (!o) return fail(CD_ERR_INVALID_ARG, "null opts");
+    if (!(o->tau >= 0.0) || !(o->schwarz >= 0.0))
+        return fail(CD_ERR_INVALID_ARG, "tau and schwarz must be finite and >= 0");
+    return CD_OK;
+}
+
+// Setup kernels: D1 of all pairs, max, counts, prefix sums (+ scatter when
+// outputs are given).
+cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const DecompWs &w,
+                       int64_t *row_pair, int64_t n_cap, int64_t na_cap, hipStream_t st,
+                       bool scatter)
+{
+    const int64_t np = n_pairs(m.n_basis);
+    const int64_t nblk = blocks_of(np, 256);
+    if (np == 0) return CD_OK;
+    k_diag_all<<<(unsigned)nblk, 256, 0, st>>>(m.n_basis, m.xyz, m.alpha, np, w.D1all, w.d1max);
+    k_count<<<(unsigned)nblk, 256, 0, st>>>(np, w.D1all, w.d1max, o->schwarz, o->tau, w.cnt_rows,
+                                            w.cnt_act);
+    k_scan<<<1, 256, 0, st>>>((int32_t)nblk, w.cnt_rows, w.cnt_act, w.off_rows, w.off_act,
+                              w.totals);
+    if (scatter)
+        k_scatter<<<(unsigned)nblk, 256, 0, st>>>(m.n_basis, m.xyz, m.alpha, np, w.D1all,
+                                                  w.d1max, o->schwarz, o->tau, w.off_rows,
+                                                  w.off_act, n_cap, na_cap, row_pair, w.rows,
+                                                  w.act_row, w.D_act, w.pivot_of_row);
+    return check_launch("setup kernels");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cd_last_error(void) { return g_err.c_str(); }
+
+const char *cd_version(void) { return "cd-mi355x 0.1 (gfx950)"; }
+
+cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts *opts,
+                   const int64_t *max_vectors, cd_sizes *sizes, void *stream)
+{
+    if (count < 0 || (count > 0 && (!mols || !max_vectors || !sizes)))
+        return fail(CD_ERR_INVALID_ARG, "null argument");
+    cd_status s = check_opts(opts);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int32_t i = 0; i < count; ++i) {
+        if ((s = check_mol(mols[i]))) return s;
+        if (max_vectors[i] < 0) return fail(CD_ERR_INVALID_ARG, "max_vectors < 0");
+        const int64_t N = mols[i].n_basis;
+        int64_t tot[2] = {0, 0};
+        if (N > 0) {
+            DecompWs probe = carve_decomp(nullptr, N, 0, 0, 0);
+            void *tmp = nullptr;
+            if (hipMalloc(&tmp, probe.bytes) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "hipMalloc of %zu bytes failed", probe.bytes);
+            DecompWs w = carve_decomp(tmp, N, 0, 0, 0);
+            k_init_decompose<<<1, 64, 0, st>>>(w.gs, w.cnt_rows, w.totals, w.d1max);
+            s = launch_setup(mols[i], opts, w, nullptr, 0, 0, st, false);
+            if (!s && hipMemcpyAsync(tot, w.totals, sizeof tot, hipMemcpyDeviceToHost, st) !=
+                          hipSuccess)
+                s = fail(CD_ERR_DEVICE, "copy of row counts failed");
+            if (!s && hipStreamSynchronize(st) != hipSuccess)
+                s = fail(CD_ERR_DEVICE, "stream synchronise failed");
+            hipFree(tmp);
+            if (s) return s;
+        }
+        sizes[i].n_rows = tot[0];
+        sizes[i].n_active = tot[1];
+        sizes[i].ws_bytes = carve_decomp(nullptr, N, tot[0], tot[1], max_vectors[i]).bytes;
+    }
+    return CD_OK;
+}
+
+cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return fail(CD_ERR_INVALID_ARG, "null problems");
+    cd_status s = check_opts(opts);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    size_t need = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_problem &p = probs[i];
+        if ((s = check_mol(p.mol))) return s;
+        if (p.max_vectors < 0 || p.n_rows < 0 || p.n_active < 0 || p.n_active > p.n_rows)
+            return fail(CD_ERR_INVALID_ARG, "problem %d: bad sizes", i);
+        if (p.n_rows > n_pairs(p.mol.n_basis))
+            return fail(CD_ERR_INVALID_ARG, "problem %d: n_rows exceeds N(N+1)/2", i);
+        if (!p.n_vectors || !p.status) return fail(CD_ERR_INVALID_ARG, "null n_vectors/status");
+        if (p.n_rows > 0 && (!p.row_pair || !p.diag))
+            return fail(CD_ERR_INVALID_ARG, "null row_pair/diag");
+        if (p.n_rows > 0 && p.max_vectors > 0 && (!p.L || !p.pivots))
+            return fail(CD_ERR_INVALID_ARG, "null L/pivots");
+        if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
+        need += carve_decomp(nullptr, p.mol.n_basis, p.n_rows, p.n_active, p.max_vectors).bytes;
+    }
+    if (need > ws_bytes || (need > 0 && !ws))
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    DevInfo di;
+    if ((s = dev_info(di))) return s;
+
+    char *wbase = static_cast<char *>(ws);
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_problem &p = probs[i];
+        const int64_t N = p.mol.n_basis, n = p.n_rows, na = p.n_active, mv = p.max_vectors;
+        DecompWs w = carve_decomp(wbase, N, n, na, mv);
+        wbase += w.bytes;
+        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[0]), st);
+        k_init_decompose<<<1, 64, 0, st>>>(w.gs, p.status, p.n_vectors, w.d1max);
+        if ((s = launch_setup(p.mol, opts, w, p.row_pair, n, na, st, true))) return s;
+        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[1]), st);
+        if (na > 0 && mv > 0) {
+            int G = (int)std::min<int64_t>(di.n_cu, std::max<int64_t>(1, blocks_of(na, 16)));
+            G = std::max<int>(G, (int)blocks_of(na, SMAX));
+            G = std::min(G, S1_MAXG);
+            const int slice = (int)blocks_of(na, G);
+            if (slice > SMAX || G > di.n_cu * std::max(1, di.coop_blocks_per_cu))
+                return fail(CD_ERR_UNSUPPORTED, "%lld active rows exceed the step-1 capacity",
+                            (long long)na);
+            Step1Params P1;
+            P1.rows = w.rows;
+            P1.act_row = w.act_row;
+            P1.n_act_dev = w.totals + 1;
+            P1.n_act = na;
+            P1.D_act = w.D_act;
+            P1.L_act = w.L_act;
+            P1.Cbuf = w.Cbuf;
+            P1.noms = w.noms;
+            P1.gs = w.gs;
+            P1.pivots = p.pivots;
+            P1.piv_slot = w.piv_slot;
+            P1.dpiv = w.dpiv;
+            P1.pivot_of_row = w.pivot_of_row;
+            P1.n_vectors = p.n_vectors;
+            P1.status = p.status;
+            P1.tau = opts->tau;
+            P1.d1max_bits = w.d1max;
+            P1.n_rows = n;
+            P1.max_vectors = mv;
+            P1.q = QMAX;
+            P1.slice = slice;
+            P1.spin_limit = 1u << 22;
+            void *args[] = {&P1};
+            hipError_t e = hipLaunchCooperativeKernel((const void *)k_step1, dim3(G), dim3(256),
+                                                      args, 0, st);
+            if (e != hipSuccess)
+                return fail(CD_ERR_DEVICE, "step-1 launch (%d workgroups): %s", G,
+                            hipGetErrorString(e));
+            const int gx = (int)std::min<int64_t>(16, std::max<int64_t>(1, blocks_of(mv, 256)));
+            k_gather_pivots<<<dim3(gx, (unsigned)mv), 256, 0, st>>>(
+                w.L_act, na, w.piv_slot, p.pivots, w.rows, p.n_vectors, w.Lp, mv, w.prow);
+            if ((s = check_launch("pivot gather"))) return s;
+        }
+        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[2]), st);
+        if (n > 0) {
+            k_step2<<<(unsigned)blocks_of(n, TM), 256, 0, st>>>(w.rows, n, w.prow, w.dpiv, w.Lp,
+                                                               mv, w.pivot_of_row, p.n_vectors,
+                                                               p.L, p.diag);
+            if ((s = check_launch("step 2"))) return s;
+        }
+        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[3]), st);
+    }
+    if (opts->flags & CD_SYNC) {
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "stream synchronise failed");
+        for (int32_t i = 0; i < count; ++i) {
+            int32_t v = 0;
+            hipMemcpy(&v, probs[i].status, sizeof v, hipMemcpyDeviceToHost);
+            if (v != 0) return fail((cd_status)v, "problem %d: device status %d", i, v);
+        }
+    }
+    return CD_OK;
+}
+
+// ------------------------------------------------------------------ J / K
+namespace {
+
+int jk_nsplit(int N, int n_cu)
+{
+    const int T = (N + TM - 1) / TM;
+    const int pairs = T * (T + 1) / 2;
+    int ns = (2 * n_cu + pairs - 1) / std::max(1, pairs);
+    return std::max(1, std::min(ns, 64));
+}
+
+struct JkWs {
+    double *Dm, *w, *V, *X, *Kp;
+    int32_t *rowof;
+    size_t bytes;
+};
+
+JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
+{
+    JkWs w{};
+    Carver c(ws);
+    const int64_t N = p.n_basis;
+    w.Dm = c.take<double>(std::max<int64_t>(1, N * N));
+    w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
+    w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
+    w.rowof = c.take<int32_t>(std::max<int64_t>(1, N * N));
+    w.X = c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_occ * N));
+    w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
+    w.bytes = c.off;
+    return w;
+}
+
+cd_status check_jk(const cd_jk_problem &p)
+{
+    if (p.n_basis < 0 || p.n_rows < 0 || p.max_vectors < 0 || p.n_occ < 0)
+        return fail(CD_ERR_INVALID_ARG, "negative size");
+    if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
+    if (p.n_basis > 0 && (!p.J || !p.K)) return fail(CD_ERR_INVALID_ARG, "null J/K");
+    if (!p.n_vectors || !p.status) return fail(CD_ERR_INVALID_ARG, "null n_vectors/status");
+    if (p.n_rows > 0 && (!p.row_pair || (p.max_vectors > 0 && !p.L)))
+        return fail(CD_ERR_INVALID_ARG, "null row_pair/L");
+    if (p.n_occ > 0 && p.n_basis > 0 && !p.C) return fail(CD_ERR_INVALID_ARG, "null C");
+    return CD_OK;
+}
+
+}  // namespace
+
+cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
+                      size_t *ws_bytes)
+{
+    if (count < 0 || (count > 0 && !probs) || !ws_bytes)
+        return fail(CD_ERR_INVALID_ARG, "null argument");
+    if (prec != CD_FP64) return fail(CD_ERR_UNSUPPORTED, "precision %d not built yet", (int)prec);
+    DevInfo di;
+    cd_status s = dev_info(di);
+    if (s) return s;
+    size_t tot = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if ((s = check_jk(probs[i]))) return s;
+        tot += carve_jk(nullptr, probs[i], jk_nsplit(probs[i].n_basis, di.n_cu)).bytes;
+    }
+    *ws_bytes = tot;
+    return CD_OK;
+}
+
+cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
+                      uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    cd_status s = cd_query_jk(probs, count, prec, &need);
+    if (s) return s;
+    if (need > ws_bytes || (need > 0 && !ws))
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    DevInfo di;
+    if ((s = dev_info(di))) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *wbase = static_cast<char *>(ws);
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_jk_problem &p = probs[i];
+        const int nsplit = jk_nsplit(p.n_basis, di.n_cu);
+        JkWs w = carve_jk(wbase, p, nsplit);
+        wbase += w.bytes;
+        const int64_t N = p.n_basis, NN = N * N, n = p.n_rows, mv = p.max_vectors;
+        const int O = p.n_occ;
+        if (N == 0) continue;
+        const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
+        k_fill_f64<<<fb, 256, 0, st>>>(p.J, NN, 0.0);
+        k_fill_f64<<<fb, 256, 0, st>>>(p.K, NN, 0.0);
+        if (O == 0 || n == 0 || mv == 0) continue;
+        k_fill_i32<<<fb, 256, 0, st>>>(w.rowof, NN, -1);
+        k_rowmap<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, w.rowof);
+        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>((int)N, O, p.C, w.Dm);
+        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, w.Dm, w.w);
+        k_jV<<<(unsigned)mv, 256, 0, st>>>(p.L, n, w.w, p.n_vectors, w.V);
+        k_jJ<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
+                                                          (int)N, p.J);
+        k_half<true><<<dim3((unsigned)blocks_of(N, TM), (unsigned)blocks_of(O, TN), (unsigned)mv),
+                       256, 0, st>>>(p.L, n, w.rowof, (int)N, p.C, O, p.n_vectors, 0, w.X);
+        const int T = (int)blocks_of(N, TM);
+        k_syrk<<<dim3(T * (T + 1) / 2, nsplit), 256, 0, st>>>(w.X, (int)N, p.n_vectors, O, 0, mv,
+                                                             nsplit, w.Kp);
+        k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>(w.Kp, (int)N, nsplit, 0, p.K);
+        if ((s = check_launch("J/K kernels"))) return s;
+    }
+    if (flags & CD_SYNC) {
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "stream synchronise failed");
+    }
+    return CD_OK;
+}
+
+// ------------------------------------------------------------------ transform
+cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, size_t *ws_bytes)
+{
+    if (count < 0 || (count > 0 && !probs) || !ws_bytes)
+        return fail(CD_ERR_INVALID_ARG, "null argument");
+    size_t tot = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_transform_problem &p = probs[i];
+        if (p.n_basis < 0 || p.n_rows < 0 || p.max_vectors < 0 || p.p < 0 || p.q < 0)
+            return fail(CD_ERR_INVALID_ARG, "negative size");
+        if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
+        Carver c(nullptr);
+        c.take<int32_t>(std::max<int64_t>(1, (int64_t)p.n_basis * p.n_basis));
+        c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_basis * p.q));
+        tot += c.off;
+    }
+    *ws_bytes = tot;
+    return CD_OK;
+}
+
+cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_t flags,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    cd_status s = cd_query_transform(probs, count, &need);
+    if (s) return s;
+    if (need > ws_bytes || (need > 0 && !ws))
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *wbase = static_cast<char *>(ws);
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_transform_problem &p = probs[i];
+        const int64_t N = p.n_basis, NN = N * N, n = p.n_rows, mv = p.max_vectors;
+        Carver c(wbase);
+        int32_t *rowof = c.take<int32_t>(std::max<int64_t>(1, NN));
+        double *Y = c.take<double>(std::max<int64_t>(1, mv * N * p.q));
+        wbase += c.off;
+        if (N == 0 || mv == 0 || p.p == 0 || p.q == 0) continue;
+        if (!p.Lmo || !p.C1 || !p.C2 || !p.n_vectors || (n > 0 && (!p.L || !p.row_pair)))
+            return fail(CD_ERR_INVALID_ARG, "null pointer in transform problem %d", i);
+        const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
+        k_fill_i32<<<fb, 256, 0, st>>>(rowof, NN, -1);
+        if (n > 0)
+            k_rowmap<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, rowof);
+        k_half<false><<<dim3((unsigned)blocks_of(N, TM), (unsigned)blocks_of(p.q, TN),
+                             (unsigned)mv),
+                        256, 0, st>>>(p.L, n, rowof, (int)N, p.C2, p.q, p.n_vectors, 0, Y);
+        k_tr2<<<dim3((unsigned)blocks_of(p.p, TM), (unsigned)blocks_of(p.q, TN), (unsigned)mv),
+                256, 0, st>>>(Y, (int)N, p.C1, p.p, p.q, p.n_vectors, 0, p.Lmo);
+        if ((s = check_launch("transform kernels"))) return s;
+    }
+    if (flags & CD_SYNC) {
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "stream synchronise failed");
+    }
+    return CD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/cd.h declares, and the binding mirrors the header's
+structs."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(cd_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_00306_amd import build, cdlib
+    if not os.path.exists(cdlib.LIB_PATH):
+        build.build()
+    return cdlib.load()
+
+
+def test_header_declares_the_three_calls():
+    names = _declared_functions()
+    for f in ("cd_decompose", "cd_build_jk", "cd_transform", "cd_query", "cd_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2609_00306_amd import cdlib
+    names = _declared_functions()
+    assert sorted(cdlib.EXPORTS) == names
+    for f in names:
+        assert hasattr(lib, f), f
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.cd_version()
+
+
+def _struct_sizes_from_c():
+    """Compile a tiny host program that prints sizeof/offsetof of the ABI structs."""
+    import subprocess
+    import tempfile
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "cd.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(cd_molecule), sizeof(cd_decomp_opts),
+         sizeof(cd_sizes), sizeof(cd_problem), sizeof(cd_jk_problem),
+         sizeof(cd_transform_problem));
+  printf("%zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
+         offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, c])
+        out = subprocess.check_output([exe]).decode().split()
+    return [int(x) for x in out]
+
+
+def test_binding_structs_match_header():
+    from paper_2609_00306_amd import cdlib
+    got = _struct_sizes_from_c()
+    mine = [ctypes.sizeof(cdlib.cd_molecule), ctypes.sizeof(cdlib.cd_decomp_opts),
+            ctypes.sizeof(cdlib.cd_sizes), ctypes.sizeof(cdlib.cd_problem),
+            ctypes.sizeof(cdlib.cd_jk_problem), ctypes.sizeof(cdlib.cd_transform_problem),
+            cdlib.cd_problem.status.offset, cdlib.cd_jk_problem.status.offset,
+            cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset]
+    assert mine == got
+
+
+def test_argument_validation_without_device(lib):
+    from paper_2609_00306_amd import cdlib
+    # null opts / negative count are rejected before any device work
+    assert lib.cd_query(None, -1, None, None, None, None) == cdlib.CD_ERR_INVALID_ARG
+    mol = cdlib.cd_molecule(-3, None, None)
+    opts = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None)
+    caps = (ctypes.c_int64 * 1)(10)
+    sizes = (cdlib.cd_sizes * 1)()
+    assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(opts), caps, sizes,
+                        None) == cdlib.CD_ERR_INVALID_ARG
+    assert b"n_basis" in lib.cd_last_error()
+    bad = cdlib.cd_decomp_opts(-1.0, 1e-12, 0, None)
+    mol = cdlib.cd_molecule(0, None, None)
+    assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(bad), caps, sizes,
+                        None) == cdlib.CD_ERR_INVALID_ARG
+    nan = cdlib.cd_decomp_opts(float("nan"), 1e-12, 0, None)
+    assert lib.cd_decompose(None, 0, ctypes.byref(nan), None, 0, None) == cdlib.CD_ERR_INVALID_ARG
+    # an N = 0 molecule needs no device work: zero rows
+    assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(opts), caps, sizes, None) == 0
+    assert sizes[0].n_rows == 0 and sizes[0].n_active == 0
+    # a problem whose workspace is too small is rejected on the host
+    p = cdlib.cd_problem(cdlib.cd_molecule(0, None, None), 0, 0, 4, None, None, None, None,
+                         1, 1)
+    assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(opts), None, 0,
+                            None) == cdlib.CD_ERR_WORKSPACE
+    p.n_active = 5
+    assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(opts), None, 0,
+                            None) == cdlib.CD_ERR_INVALID_ARG
+
+
+def test_product_path_refuses_missing_library(tmp_path):
+    from paper_2609_00306_amd import cdlib
+    saved = cdlib._lib
+    cdlib._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            cdlib.load(str(tmp_path / "nope.so"))
+    finally:
+        cdlib._lib = saved

@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bar: row sets and pivot sequences identical (or, where the sequences part at
+a near-tie, every GPU pivot a valid argmax of the oracle's own residuals
+within 1e-12 max D1, with the oracle replaying the GPU's pivots); vectors
+and final residual diagonal within 1e-10 absolute; J and K (FP64) within
+1e-10.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2609_00306_amd import cdlib  # noqa: E402
+from paper_2609_00306_amd.inputs import config_molecule, make_molecule, random_small  # noqa: E402
+
+TOL_L = 1e-10
+TOL_JK = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cdlib.load()
+    return torch.device("cuda:0")
+
+
+def run_gpu(m, tau, schwarz, max_vectors=None):
+    d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, max_vectors=max_vectors)
+    M = d.M()
+    return d, M
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_cd(m, rp, tau, cap):
+    key = (m.name, m.seed, m.n_basis, tau, len(rp), cap)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=cap)
+    return _ORACLE_CACHE[key]
+
+
+def check_against_oracle(m, tau, schwarz, d, M, expect_status=0):
+    """Compare one GPU decomposition with the oracle; returns the oracle result used."""
+    assert int(d.status.item()) == expect_status
+    rp, _ = oracle.rows(m.xyz, m.alpha, schwarz)
+    rp_g = d.row_pair.cpu().numpy()
+    assert np.array_equal(rp, rp_g), "screened row sets differ"
+    piv = d.pivots[:M].cpu().numpy()
+    cap = d.max_vectors
+    ref = oracle_cd(m, rp, tau, cap)
+    if not (ref.M == M and np.array_equal(ref.pivots, piv)):
+        D1max = float(np.max(oracle.diagonal_all(m.xyz, m.alpha))) if m.n_basis else 0.0
+        ref = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=cap, given=piv,
+                               tie_tol=1e-12 * D1max)
+        assert ref.bad == -1, f"GPU pivot {ref.bad} is not a valid argmax"
+        assert ref.M == M
+    L = d.L[:M].cpu().numpy()
+    if M:
+        err = np.abs(L - ref.L).max()
+        assert err <= TOL_L, f"max |dL| = {err:.3e}"
+    diag = d.diag.cpu().numpy()
+    if len(diag):
+        assert np.abs(diag - ref.D).max() <= TOL_L
+    return rp, ref
+
+
+@pytest.mark.parametrize("seed,tau", [(1, 1e-3), (2, 1e-6), (3, 1e-9), (4, 0.0), (5, 1e-6)])
+def test_tiny_molecules(seed, tau):
+    m = random_small(seed, n_centres=3 + seed % 3, exps=(0.25, 1.0, 4.0))
+    d, M = run_gpu(m, tau, 0.0)
+    check_against_oracle(m, tau, 0.0, d, M)
+
+
+def test_c1_full_matrix():
+    m = config_molecule("C1")
+    d, M = run_gpu(m, 1e-6, 0.0)
+    assert d.n_rows == 1830
+    rp, ref = check_against_oracle(m, 1e-6, 0.0, d, M)
+    assert M == 235
+
+
+def test_ragged_sizes_several_tiles():
+    # 37 functions: 703 rows, not a multiple of any tile; small tau -> many batches
+    m = make_molecule(37, 6.0, (0.5,), 3, seed=77)
+    d, M = run_gpu(m, 1e-10, 1e-12)
+    check_against_oracle(m, 1e-10, 1e-12, d, M)
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-6])
+def test_c2_parity(tau):
+    m = config_molecule("C2")
+    d, M = run_gpu(m, tau, 1e-12)
+    check_against_oracle(m, tau, 1e-12, d, M)
+
+
+def test_capacity_limit():
+    m = config_molecule("C1")
+    d, M = run_gpu(m, 1e-6, 0.0, max_vectors=50)
+    assert M == 50
+    check_against_oracle(m, 1e-6, 0.0, d, M, expect_status=cdlib.CD_ERR_CAPACITY)
+
+
+def test_empty_and_single_function():
+    m0 = make_molecule(0, 1.0, (1.0,), 0, seed=1)
+    d, M = run_gpu(m0, 1e-6, 1e-12, max_vectors=1)
+    assert M == 0 and d.n_rows == 0 and int(d.status.item()) == 0
+    xyz = np.zeros((1, 3))
+    alpha = np.array([0.8])
+    d = cdlib.decompose(xyz, alpha, 1e-6, schwarz=0.0)
+    assert d.M() == 1
+    assert d.L[0, 0].item() == pytest.approx(np.sqrt(2.0 * np.sqrt(0.8 / np.pi)), rel=1e-14)
+
+
+def test_deterministic_repeat():
+    m = config_molecule("C2")
+    d1, M1 = run_gpu(m, 1e-5, 1e-12)
+    d2, M2 = run_gpu(m, 1e-5, 1e-12)
+    assert M1 == M2
+    assert torch.equal(d1.pivots[:M1], d2.pivots[:M2])
+    assert torch.equal(d1.L[:M1], d2.L[:M2])
+
+
+@pytest.mark.parametrize("name,schwarz", [("C1", 0.0), ("C2", 1e-12)])
+def test_jk_fp64_parity(name, schwarz):
+    m = config_molecule(name)
+    tau = 1e-6
+    d, M = run_gpu(m, tau, schwarz)
+    rp, ref = check_against_oracle(m, tau, schwarz, d, M)
+    J, K = cdlib.build_jk(d, m.C, "fp64")
+    Jr, Kr = oracle.jk_cd(m.n_basis, rp, ref.L, m.C)
+    J = J.cpu().numpy()
+    K = K.cpu().numpy()
+    assert np.abs(J - Jr).max() <= TOL_JK
+    assert np.abs(K - Kr).max() <= TOL_JK
+    assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
+
+
+def test_transform_parity():
+    m = config_molecule("C1")
+    d, M = run_gpu(m, 1e-6, 0.0)
+    rp, ref = check_against_oracle(m, 1e-6, 0.0, d, M)
+    C1 = m.C[:, :7]
+    C2 = m.C[:, 2:10]
+    out = cdlib.transform(d, C1, C2)[:M].cpu().numpy()
+    exp = oracle.transform(m.n_basis, rp, ref.L, C1, C2)
+    assert np.abs(out - exp).max() <= TOL_L
