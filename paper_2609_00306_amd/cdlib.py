@@ -206,6 +206,9 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
     arr = (cd_problem * n)(*[problem(d) for d in decs])
     ev = None
     if events is not None:
+        for e in events:
+            if not e.cuda_event:        # torch creates the event on its first record
+                e.record(torch.cuda.current_stream() if stream is None else stream)
         ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
     opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev)
     if workspace is None:

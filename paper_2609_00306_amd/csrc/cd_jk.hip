@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_syrk(const double *__restrict__ X, int 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int m = m0 + wm + 16 * i + 4 * (lane >> 4) + v;
+                int m = m0 + wm + 16 * i + mfma_row(lane, v);
                 int n = n0 + wn + 16 * j + (lane & 15);
                 if (m < N && n < N) out[(int64_t)m * N + n] = acc.c[i][j][v];
             }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int N
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int a = m0 + wm + 16 * i + 4 * (lane >> 4) + v;
+                int a = m0 + wm + 16 * i + mfma_row(lane, v);
                 int b = n0 + wn + 16 * j + (lane & 15);
                 if (a < p && b < q) out[(int64_t)a * q + b] = acc.c[i][j][v];
             }

@@ -243,10 +243,12 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         const int64_t N = p.mol.n_basis, n = p.n_rows, na = p.n_active, mv = p.max_vectors;
         DecompWs w = carve_decomp(wbase, N, n, na, mv);
         wbase += w.bytes;
-        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[0]), st);
+        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[0]), st) != hipSuccess)
+            return fail(CD_ERR_INVALID_ARG, "timing event 0 could not be recorded");
         k_init_decompose<<<1, 64, 0, st>>>(w.gs, p.status, p.n_vectors, w.d1max);
         if ((s = launch_setup(p.mol, opts, w, p.row_pair, n, na, st, true))) return s;
-        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[1]), st);
+        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[1]), st) != hipSuccess)
+            return fail(CD_ERR_INVALID_ARG, "timing event 1 could not be recorded");
         if (na > 0 && mv > 0) {
             int G = (int)std::min<int64_t>(di.n_cu, std::max<int64_t>(1, blocks_of(na, 16)));
             G = std::max<int>(G, (int)blocks_of(na, SMAX));
@@ -289,14 +291,16 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
                 w.L_act, na, w.piv_slot, p.pivots, w.rows, p.n_vectors, w.Lp, mv, w.prow);
             if ((s = check_launch("pivot gather"))) return s;
         }
-        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[2]), st);
+        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[2]), st) != hipSuccess)
+            return fail(CD_ERR_INVALID_ARG, "timing event 2 could not be recorded");
         if (n > 0) {
             k_step2<<<(unsigned)blocks_of(n, TM), 256, 0, st>>>(w.rows, n, w.prow, w.dpiv, w.Lp,
                                                                mv, w.pivot_of_row, p.n_vectors,
                                                                p.L, p.diag);
             if ((s = check_launch("step 2"))) return s;
         }
-        if (opts->events) hipEventRecord(static_cast<hipEvent_t>(opts->events[3]), st);
+        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[3]), st) != hipSuccess)
+            return fail(CD_ERR_INVALID_ARG, "timing event 3 could not be recorded");
     }
     if (opts->flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)

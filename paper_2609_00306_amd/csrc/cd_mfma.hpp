@@ -7,7 +7,8 @@
 // Operand/result lane layout of the 16x16x4 FP64 instruction (wave64):
 //   A (16 x 4):  lane l holds A[m = l % 16][k = l / 16]
 //   B (4 x 16):  lane l holds B[k = l / 16][n = l % 16]
-//   D (16 x 16): lane l, element v holds D[m = 4 (l / 16) + v][n = l % 16]
+//   D (16 x 16): lane l, element v holds D[m = 4 v + l / 16][n = l % 16]
+// (the result layout was read back on gfx950 with a one-MFMA probe)
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -68,6 +69,9 @@ __device__ __forceinline__ void mfma_tile_f64(int64_t kbeg, int64_t kend, LoadA 
     }
 }
 
+// Row of the 16 x 16 result held by element v of 'lane'.
+__device__ __forceinline__ int mfma_row(int lane, int v) { return 4 * v + (lane >> 4); }
+
 // Write the accumulator into an LDS tile sT[m * ldt + n].
 __device__ __forceinline__ void tile_to_lds(const TileAcc &acc, double *sT, int ldt)
 {
@@ -82,7 +86,7 @@ __device__ __forceinline__ void tile_to_lds(const TileAcc &acc, double *sT, int 
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int m = wm + 16 * i + 4 * (lane >> 4) + v;
+                int m = wm + 16 * i + mfma_row(lane, v);
                 int n = wn + 16 * j + (lane & 15);
                 sT[m * ldt + n] = acc.c[i][j][v];
             }

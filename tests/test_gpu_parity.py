@@ -30,7 +30,10 @@ def gpu():
 
 
 def run_gpu(m, tau, schwarz, max_vectors=None):
-    d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, max_vectors=max_vectors)
+    # asynchronous call; the device status word is checked by the caller
+    d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, max_vectors=max_vectors,
+                        sync=False)
+    torch.cuda.synchronize()
     M = d.M()
     return d, M
 
