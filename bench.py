@@ -95,6 +95,24 @@ def main():
     torch.cuda.synchronize()
     assert d.M() == M and int(d.status.item()) == 0
 
+    # per-batch device-clock stamps of the pivot selection (one untimed step)
+    cap = 4096
+    timeline = torch.zeros(1 + 16 * cap, dtype=torch.int64, device=dev)
+    cdlib.run_decompose([d], tau, schwarz, timeline=timeline)
+    torch.cuda.synchronize()
+    tl = timeline.cpu().numpy()
+    nbatch = int(tl[0])
+    st = tl[1:1 + 8 * min(nbatch, cap)].reshape(-1, 8)[:, :7].astype(float) / 100.0  # 100 MHz -> us
+    stages = ["nominate+exchange", "union+select", "candidate_columns", "exchange_columns",
+              "block_factor", "row_update"]
+    breakdown = {k: float((st[:, i + 1] - st[:, i]).sum()) for i, k in enumerate(stages)
+                 if st.shape[0]}
+    nblk = (M + 63) // 64
+    s2 = tl[1 + 8 * cap:1 + 8 * cap + 8 * min(nblk, cap)].reshape(-1, 8)[:, :6].astype(float) / 100.0
+    s2_stages = ["off_block_product", "stage", "integrals", "substitution", "store"]
+    s2_breakdown = {k: float((s2[:, i + 1] - s2[:, i]).sum()) for i, k in enumerate(s2_stages)
+                    if s2.shape[0]}
+
     evs = [([mk() for _ in range(4)], [mk() for _ in range(3)]) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,6 +163,9 @@ def main():
         "jk_tflops": (w_j + w_k) / (t_jk * 1e-3) / 1e12,
         "transform_ms": t_tr,
         "phases_ms": {"setup": t_setup, "pivot_selection": t_sel, "all_row_solve": t_solve},
+        "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
+                            "stage_us_total": breakdown},
+        "all_row_solve_wg0_stage_us_total": s2_breakdown,
         "roofline": {"kernel": "k_step2 (all-row blocked forward substitution, FP64 MFMA)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"],
                      "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"], "traffic": None},

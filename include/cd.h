@@ -84,6 +84,16 @@ typedef struct {
                               records on 'stream' at the phase boundaries of the last problem:
                               [0] before the pair/diagonal setup, [1] before pivot selection,
                               [2] before the all-row solve, [3] after it */
+    int64_t *timeline;     /* optional (may be NULL): DEVICE buffer of 1 + 16 * timeline_cap int64
+                              of device-clock (100 MHz) stamps of the last problem, for profiling.
+                              [0]: number of candidate batches of the pivot selection;
+                              [1 + 8 b + i]: batch b, stage i: 0 start, 1 nominations exchanged,
+                              2 candidates chosen, 3 candidate columns formed, 4 columns
+                              exchanged, 5 candidate block factored, 6 rows updated;
+                              [1 + 8 cap + 8 k + i]: workgroup 0 of the all-row solve, 64-vector
+                              block k, stage i: 0 start, 1 off-block product done, 2 staged,
+                              3 integrals subtracted, 4 substitution done, 5 stored */
+    int64_t timeline_cap;  /* batches / blocks the timeline can hold */
 } cd_decomp_opts;
 
 /* Sizes of one decomposition problem, filled by cd_query. */

@@ -32,7 +32,8 @@ class cd_molecule(ctypes.Structure):
 
 class cd_decomp_opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("schwarz", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("events", ctypes.POINTER(ctypes.c_void_p))]
+                ("flags", ctypes.c_uint32), ("events", ctypes.POINTER(ctypes.c_void_p)),
+                ("timeline", _vp), ("timeline_cap", ctypes.c_int64)]
 
 
 class cd_sizes(ctypes.Structure):
@@ -158,7 +159,7 @@ def query(mols: Sequence[cd_molecule], tau: float, schwarz: float,
     arr = (cd_molecule * n)(*mols)
     caps = (ctypes.c_int64 * n)(*[int(c) for c in max_vectors])
     out = (cd_sizes * n)()
-    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None)
+    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None, None, 0)
     _check(L.cd_query(arr, n, ctypes.byref(opts), caps, out, _stream(stream)))
     return list(out)
 
@@ -196,7 +197,7 @@ def problem(d: Decomposition) -> cd_problem:
 
 def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, sync: bool = False,
                   stream=None, workspace: Optional[torch.Tensor] = None,
-                  events: Optional[Sequence] = None):
+                  events: Optional[Sequence] = None, timeline: Optional[torch.Tensor] = None):
     """cd_decompose on already allocated problems (one workspace per call).
 
     ``events``: optional four torch.cuda.Event(enable_timing=True) that the
@@ -210,7 +211,9 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
             if not e.cuda_event:        # torch creates the event on its first record
                 e.record(torch.cuda.current_stream() if stream is None else stream)
         ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
-    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev)
+    tl, cap = (None, 0) if timeline is None else (timeline.data_ptr(),
+                                                   (timeline.numel() - 1) // 16)
+    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev, tl, cap)
     if workspace is None:
         if n != 1:
             raise ValueError("pass a shared workspace for more than one molecule")

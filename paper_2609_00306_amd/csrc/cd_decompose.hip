@@ -173,52 +173,82 @@ __global__ __launch_bounds__(256) void k_scatter(
 
 // ---------------------------------------------------------------- step 1
 constexpr int QMAX = 64;       // candidate batch size
-constexpr int CNOM = 16;       // nominations per workgroup
+constexpr int CNOM = 4;        // nominations per workgroup
 constexpr int SMAX = 256;      // active rows per workgroup
-constexpr int NOMSORT = 4096;  // union capacity (workgroups * CNOM)
+constexpr int NOMSORT = 1024;  // union capacity (workgroups * CNOM)
 constexpr int S1_MAXG = NOMSORT / CNOM;
+using S1K = SplitK<2, 16>;     // candidate-column product: 32 rows per pass, k-chunks of 16
+constexpr int S1_UNION = (4 * S1K::kWaveDoubles > 2 * QMAX * (QMAX + 1))
+                             ? 4 * S1K::kWaveDoubles : 2 * QMAX * (QMAX + 1);
 
 __device__ __forceinline__ bool eligible(double d, double tau, double floor_tol)
 {
     return d >= tau && !(tau <= 0.0 && d <= floor_tol);
 }
 
+__device__ __forceinline__ void stamp(const Step1Params &P, int64_t batch, int what)
+{
+    if (P.timeline && batch < P.timeline_cap && blockIdx.x == 0 && threadIdx.x == 0)
+        P.timeline[batch * 8 + what] = (int64_t)wall_clock64();
+}
+
 __global__ __launch_bounds__(256) void k_step1(Step1Params P)
 {
-    __shared__ double sD[SMAX];
-    __shared__ Nom sNom[NOMSORT];                 // sort buffer; reused as B staging
-    __shared__ double sS[QMAX][QMAX + 1];         // candidate block
-    __shared__ double sLq[QMAX][QMAX + 1];        // in-batch vectors on the candidates
-    __shared__ int sQ[QMAX];                      // candidate slots
-    __shared__ int sPiv[QMAX];                    // candidate index of in-batch pivot t
-    __shared__ double sDp[QMAX];                  // pivot values
-    __shared__ double sRs[QMAX];                  // sqrt of pivot values
-    __shared__ int s_nq, s_kb, s_stop, s_status;
+    __shared__ double sU[S1_UNION];   // phase-dependent: nominations / GEMM staging / candidate block
+    __shared__ double sD[SMAX];       // residual diagonal of this workgroup's active rows
+    __shared__ int sList[SMAX];       // this workgroup's eligible rows (local indices)
+    __shared__ int sQ[QMAX];          // candidate slots
+    __shared__ RowRec sQrow[QMAX];    // candidate pair data
+    __shared__ int sPiv[QMAX];        // candidate index of in-batch pivot t
+    __shared__ double sDp[QMAX];      // pivot values
+    __shared__ double sRs[QMAX];      // 1 / sqrt of pivot values
+    __shared__ int s_nq, s_kb, s_stop, s_status, s_cnt;
     __shared__ double s_U;
     __shared__ int s_iU;
+
+    Nom *sNom = reinterpret_cast<Nom *>(sU);
+    double (*sS)[QMAX + 1] = reinterpret_cast<double (*)[QMAX + 1]>(sU);
+    double (*sLq)[QMAX + 1] = reinterpret_cast<double (*)[QMAX + 1]>(sU + QMAX * (QMAX + 1));
 
     const int tid = threadIdx.x;
     const int G = gridDim.x;
     const int g = blockIdx.x;
     const int64_t n_act = P.n_act;
+    const int64_t ldT = P.max_vectors;
     const int64_t s0 = (int64_t)g * P.slice;
     const int ns = (int)max((int64_t)0, min((int64_t)P.slice, n_act - s0));
     const double tau = P.tau;
     const double ftol = (tau <= 0.0)
         ? (double)P.n_rows * 0x1p-53 * __longlong_as_double((long long)*P.d1max_bits) : 0.0;
     const int q = P.q;
+    double *LT = P.LT_act;
     unsigned int gen = 0;
 
-    if (*P.n_act_dev != n_act) {
+    if (*P.n_act_dev != n_act || P.n_rows_dev[0] != P.n_rows) {
         if (g == 0 && tid == 0) *P.status = 5;  // CD_ERR_DEVICE: device and host counts differ
         return;
     }
     for (int i = tid; i < ns; i += 256) sD[i] = P.D_act[s0 + i];
     int64_t K = 0;
+    int64_t batch = 0;
     int status = 0;
     __syncthreads();
 
-    for (;;) {
+    for (;; ++batch) {
+        stamp(P, batch, 0);
+        // ---- this workgroup's eligible rows (compacted list)
+        if (tid < 64) {
+            int base = 0;
+            for (int c = 0; c < ns; c += 64) {
+                int i = c + tid;
+                bool e = (i < ns) && eligible(sD[i], tau, ftol);
+                unsigned long long mask = __ballot(e);
+                unsigned long long below = (tid == 0) ? 0ull : (~0ull >> (64 - tid));
+                if (e) sList[base + __popcll(mask & below)] = i;
+                base += __popcll(mask);
+            }
+            if (tid == 0) s_cnt = base;
+        }
         // ---- local nominations: first CNOM+1 own rows in pivot order
         int P2 = 32;
         while (P2 < ns) P2 <<= 1;
@@ -246,6 +276,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             status = 5;
             break;
         }
+        stamp(P, batch, 1);
         // ---- union of nominations; bound = first row not nominated anywhere
         const int nu = G * CNOM;
         int U2 = 32;
@@ -300,59 +331,53 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             break;
         }
         const int nq = s_nq;
-        if (tid < nq) sQ[tid] = sNom[tid].idx;
+        // candidates in ascending row order: in the block factorisation the
+        // lowest lane among equal residuals is then the lowest row (rule R1)
+        if (tid < nq) {
+            const int me = sNom[tid].idx;
+            int rank = 0;
+            for (int j = 0; j < nq; ++j) rank += (sNom[j].idx < me);
+            sQ[rank] = me;
+            sQrow[rank] = P.rows[P.act_row[me]];
+        }
         __syncthreads();
+        stamp(P, batch, 2);
 
-        // ---- candidate columns on own eligible rows:
-        //      C[j][s] = (s|Q_j) - sum_{J<K} L_act[J][s] L_act[J][Q_j]
-        {
-            double *sB = reinterpret_cast<double *>(sNom);   // [64][QMAX]
-            const int nout = ns * nq;
-            // outputs in chunks of 8 per thread
-            for (int ob = 0; ob < nout; ob += 8 * 256) {
-                double acc[8];
-                int os[8];
-                int oj[8];
+        // ---- candidate columns on own eligible rows (FP64 MFMA):
+        //      C[j][s] = (s|Q_j) - sum_{J<K} L^J_s L^J_{Q_j}
+        const int cnt = s_cnt;
+        for (int pb = 0; pb < cnt; pb += S1K::kRows) {
+            const int rows_m = min(S1K::kRows, cnt - pb);
+            const int rt = (rows_m + 15) >> 4;
+            f64x4 acc[2][4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int o = ob + tid + 256 * u;
-                    os[u] = (o < nout) ? (o % ns) : -1;
-                    oj[u] = (o < nout) ? (o / ns) : 0;
-                    acc[u] = 0.0;
-                    if (os[u] >= 0 && !eligible(sD[os[u]], tau, ftol)) os[u] = -1;
-                }
-                for (int64_t J0 = 0; J0 < K; J0 += 64) {
-                    int jc = (int)min((int64_t)64, K - J0);
-                    for (int e = tid; e < 64 * QMAX; e += 256) {
-                        int jj = e / QMAX, c = e % QMAX;
-                        sB[e] = (jj < jc && c < nq) ? P.L_act[(J0 + jj) * n_act + sQ[c]] : 0.0;
-                    }
-                    __syncthreads();
-                    const double *Abase = P.L_act + J0 * n_act + s0;
-                    for (int jj = 0; jj < jc; ++jj) {
+            for (int r = 0; r < 2; ++r)
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            if (os[u] >= 0)
-                                acc[u] = fma(Abase[jj * n_act + os[u]], sB[jj * QMAX + oj[u]],
-                                             acc[u]);
-                        }
-                    }
-                    __syncthreads();
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (os[u] >= 0) {
-                        const RowRec ra = P.rows[P.act_row[s0 + os[u]]];
-                        const RowRec rb = P.rows[P.act_row[sQ[oj[u]]]];
-                        P.Cbuf[(int64_t)oj[u] * n_act + s0 + os[u]] = eri(ra, rb) - acc[u];
-                    }
+                for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+            S1K::run(
+                K, rt, rows_m,
+                [&](int64_t k, int m) -> double { return LT[(s0 + sList[pb + m]) * ldT + k]; },
+                [&](int64_t k, int n) -> double {
+                    return (n < nq) ? LT[(int64_t)sQ[n] * ldT + k] : 0.0;
+                },
+                acc, sU);
+            S1K::wave_sum_to_lds(acc, rt, sU);
+            for (int e = tid; e < rows_m * 64; e += 256) {
+                const int m = e >> 6, n = e & 63;
+                if (n < nq) {
+                    const int64_t slot = s0 + sList[pb + m];
+                    const RowRec ra = P.rows[P.act_row[slot]];
+                    P.Cbuf[(int64_t)n * n_act + slot] = eri(ra, sQrow[n]) - sU[m * 65 + n];
                 }
             }
+            __syncthreads();
         }
+        stamp(P, batch, 3);
         if (!grid_barrier(P.gs, G, gen, P.spin_limit)) {
             status = 5;
             break;
         }
+        stamp(P, batch, 4);
 
         // ---- in-batch factorisation of the candidate block (every workgroup)
         for (int e = tid; e < nq * nq; e += 256) {
@@ -364,25 +389,27 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             const int i = tid;
             const bool valid = i < nq;
             double dq = valid ? P.D_act[sQ[i]] : -INFINITY;
-            const int idx = valid ? sQ[i] : 0x7fffffff;
             bool used = !valid;
             const double U = s_U;
             const int iU = s_iU;
             int kb = 0, stop = 0, st = 0;
             // lane i's own in-batch values live in sLq[.][i]
             for (int t = 0; t < QMAX; ++t) {
-                double bd = used ? -INFINITY : dq;
-                int bi = used ? 0x7fffffff : idx;
-                int bl;
-                wave_best(bd, bi, bl);
-                if (bd != bd) { stop = 1; st = 4; break; }
+                const double val = used ? -INFINITY : dq;
+                if (__ballot(val != val)) { stop = 1; st = 4; break; }
+                const double bd = wave_max_f64(val);
+                const unsigned long long tie = __ballot(!used && val == bd);
+                if (tie == 0ull) break;                          // every candidate used
+                const int bl = __ffsll((long long)tie) - 1;      // lowest lane = lowest row
+                const int bi = sQ[bl];
                 if (!nom_before(bd, bi, U, iU)) break;           // may not be the global argmax
                 if (!eligible(bd, tau, ftol)) { stop = 1; break; }   // max D < tau: done
                 if (K + t >= P.max_vectors) { stop = 1; st = 3; break; }
-                const double rs = sqrt(bd);
+                const double inv = 1.0 / sqrt(bd);
                 double a = sS[i][bl];
+#pragma unroll 8
                 for (int tp = 0; tp < t; ++tp) a = fma(-sLq[tp][i], sLq[tp][bl], a);
-                const double lt = a / rs;
+                const double lt = a * inv;
                 dq = fma(-lt, lt, dq);
                 if (i == bl) {
                     dq = 0.0;
@@ -392,7 +419,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
                 if (i == 0) {
                     sPiv[t] = bl;
                     sDp[t] = bd;
-                    sRs[t] = rs;
+                    sRs[t] = inv;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -406,14 +433,15 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             }
         }
         __syncthreads();
+        stamp(P, batch, 5);
         const int kb = s_kb;
 
         // ---- apply the accepted pivots to own eligible rows (same arithmetic
         //      as the candidate block, so candidate rows agree bit for bit)
-        for (int sl = tid; sl < ns; sl += 256) {
-            double d = sD[sl];
-            if (!eligible(d, tau, ftol)) continue;
+        for (int li = tid; li < cnt; li += 256) {
+            const int sl = sList[li];
             const int64_t slot = s0 + sl;
+            double d = sD[sl];
             double l[QMAX];
 #pragma unroll
             for (int t = 0; t < QMAX; ++t) {
@@ -422,10 +450,10 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
                     double a = P.Cbuf[(int64_t)it * n_act + slot];
 #pragma unroll
                     for (int tp = 0; tp < t; ++tp) a = fma(-l[tp], sLq[tp][it], a);
-                    l[t] = a / sRs[t];
+                    l[t] = a * sRs[t];
                     d = fma(-l[t], l[t], d);
                     if (sQ[it] == slot) d = 0.0;
-                    P.L_act[(K + t) * n_act + slot] = l[t];
+                    LT[slot * ldT + K + t] = l[t];
                 }
             }
             sD[sl] = d;
@@ -443,6 +471,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
         }
         K += kb;
         __syncthreads();
+        stamp(P, batch, 6);
         if (s_stop) {
             status = s_status;
             break;
@@ -451,15 +480,16 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
     if (g == 0 && tid == 0) {
         *P.n_vectors = K;
         *P.status = status;
+        if (P.timeline_count) *P.timeline_count = batch + 1;
     }
     if (status == 5 && tid == 0) *P.status = 5;
 }
 
 // ---------------------------------------------------------------- pivot block
-// Lp[J][K] = L^J at pivot row P_K  (J < K), from the active-row vectors;
-// prow[K] = pair data of pivot row K.
-__global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict__ L_act,
-                                                       int64_t n_act,
+// Lp[K][J] = L^J at pivot row P_K (J < K), copied from the active-row
+// vectors; prow[K] = pair data of pivot row K.  One workgroup per K.
+__global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict__ LT,
+                                                       int64_t ldT,
                                                        const int32_t *__restrict__ piv_slot,
                                                        const int64_t *__restrict__ pivots,
                                                        const RowRec *__restrict__ rows,
@@ -468,108 +498,153 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
                                                        RowRec *__restrict__ prow)
 {
     const int64_t M = *n_vectors;
-    const int64_t J = blockIdx.y;
-    if (J >= M) return;
-    for (int64_t Kc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; Kc < M;
-         Kc += (int64_t)gridDim.x * blockDim.x) {
-        if (Kc > J) Lp[J * ldp + Kc] = L_act[J * n_act + piv_slot[Kc]];
-        if (J == 0) prow[Kc] = rows[pivots[Kc]];
-    }
+    const int64_t Kc = blockIdx.x;
+    if (Kc >= M) return;
+    const double *src = LT + (int64_t)piv_slot[Kc] * ldT;
+    for (int64_t J = threadIdx.x; J < Kc; J += 256) Lp[Kc * ldp + J] = src[J];
+    if (threadIdx.x == 0) prow[Kc] = rows[pivots[Kc]];
 }
 
 // ---------------------------------------------------------------- step 2
-// Every row r: L[K][r] = [ (r|P_K) - sum_{J<K} L[J][r] Lp[J][K] ] / sqrt(d_K),
-// blocked over 64 vectors; the off-block sum is an MFMA tile, the in-block
-// part a per-row substitution.  Also the final residual diagonal.
+// Every row r: L[K][r] = [ (r|P_K) - sum_{J<K} L[J][r] Lp[K][J] ] / sqrt(d_K),
+// blocked over 64 vectors.  The off-block sum is an FP64 MFMA product over a
+// (16 RT)-row tile, the in-block part a substitution in 16-column panels
+// with the ERIs (r|P_K) generated in between.  Also the final residual
+// diagonal (R4: a row is zeroed when it is chosen as pivot).
+// k-chunk of the all-row solve: 64 where the prefetch registers still fit
+// without spilling (checked with the compiler's resource report), else 32.
+__host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3 || rt == 5) ? 64 : 32; }
+
+template <int RT>
 __global__ __launch_bounds__(256) void k_step2(const RowRec *__restrict__ rows, int64_t n_rows,
                                                const RowRec *__restrict__ prow,
                                                const double *__restrict__ dpiv,
                                                const double *__restrict__ Lp, int64_t ldp,
                                                const int32_t *__restrict__ pivot_of_row,
                                                const int64_t *__restrict__ n_vectors,
-                                               double *__restrict__ L, double *__restrict__ diag)
+                                               double *__restrict__ L, double *__restrict__ diag,
+                                               int64_t *__restrict__ timeline, int64_t tl_cap)
 {
-    __shared__ double sA[TK * TM];
-    __shared__ double sB[TK * TN];
-    __shared__ double sT[TM][TN + 1];
-    __shared__ double sLb[TN][TN + 1];
-    __shared__ double sRs[TN];
-    __shared__ RowRec sPr[TN];
+    // optional device-clock stamps of workgroup 0, per 64-vector block
+    auto mark = [&](int64_t blk, int what) {
+        if (timeline && blockIdx.x == 0 && threadIdx.x == 0 && blk < tl_cap)
+            timeline[blk * 8 + what] = (int64_t)wall_clock64();
+    };
+    constexpr int R = 16 * RT;
+    constexpr int TKC = s2_tkc(RT);
+    using SA = OperandStage<R, TKC, true>;
+    using SB = OperandStage<64, TKC, false>;
+    constexpr int kUnion = (SA::kSize + SB::kSize > R * 65) ? SA::kSize + SB::kSize : R * 65;
+    __shared__ double sU[kUnion];
+    __shared__ double sLb[64][65];
+    __shared__ double sRs[64];
+    __shared__ RowRec sPr[64];
+    __shared__ RowRec sRow[R];
+    double *sA = sU;
+    double *sB = sU + SA::kSize;
+    double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
 
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * TM;
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int rows_here = (int)min((int64_t)R, n_rows - r0);
+    const int rt = (rows_here + 15) >> 4;
     const int64_t M = *n_vectors;
-    const int myr = tid;   // rows handled in the substitution (tid < 64)
     double Dfin = 0.0;
     int kp = -1;
-    RowRec me;
-    if (tid < TM && r0 + myr < n_rows) {
-        me = rows[r0 + myr];
-        Dfin = me.d1;
-        kp = pivot_of_row[r0 + myr];
+    for (int e = tid; e < rows_here; e += 256) sRow[e] = rows[r0 + e];
+    if (tid < rows_here) {
+        Dfin = rows[r0 + tid].d1;
+        kp = pivot_of_row[r0 + tid];
     }
-    for (int64_t b0 = 0; b0 < M; b0 += TN) {
-        const int nb = (int)min((int64_t)TN, M - b0);
-        TileAcc acc;
-        acc.zero();
-        mfma_tile_f64(
-            0, b0,
+    for (int64_t b0 = 0; b0 < M; b0 += 64) {
+        const int nb = (int)min((int64_t)64, M - b0);
+        const int64_t blk = b0 >> 6;
+        mark(blk, 0);
+        f64x4 acc[RT];
+        zero_acc(acc);
+        gemm_tile<RT, TKC, true, false>(
+            0, b0, rt,
             [&](int64_t k, int m) -> double {
-                int64_t r = r0 + m;
-                return (r < n_rows) ? L[k * n_rows + r] : 0.0;
+                return (m < rows_here) ? L[k * n_rows + r0 + m] : 0.0;
             },
             [&](int64_t k, int n) -> double {
-                return (n < nb) ? Lp[k * ldp + b0 + n] : 0.0;
+                return (n < nb) ? Lp[(b0 + n) * ldp + k] : 0.0;
             },
             acc, sA, sB);
-        tile_to_lds(acc, &sT[0][0], TN + 1);
-        for (int e = tid; e < TN; e += 256) {
+        for (int e = tid; e < 64; e += 256) {
             if (e < nb) {
                 sPr[e] = prow[b0 + e];
-                sRs[e] = sqrt(dpiv[b0 + e]);
+                sRs[e] = 1.0 / sqrt(dpiv[b0 + e]);
             }
         }
-        for (int e = tid; e < TN * TN; e += 256) {
-            int jj = e / TN, j = e % TN;
-            sLb[jj][j] = (jj < j && j < nb) ? Lp[(b0 + jj) * ldp + b0 + j] : 0.0;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int j = e >> 6, jj = e & 63;
+            sLb[jj][j] = (jj < j && j < nb) ? Lp[(b0 + j) * ldp + b0 + jj] : 0.0;
         }
+        mark(blk, 1);
+        for_each_acc(acc, rt, [&](int m, int n, double v) { sT[m][n] = v; });
         __syncthreads();
+        mark(blk, 2);
         // right-hand side: (r|P_K) - off-block sum
-        for (int e = tid; e < TM * TN; e += 256) {
-            int m = e / TN, j = e % TN;
-            if (j < nb && r0 + m < n_rows) {
-                const RowRec a = rows[r0 + m];
-                sT[m][j] = eri(a, sPr[j]) - sT[m][j];
+        for (int e = tid; e < R * 64; e += 256) {
+            const int m = e >> 6, j = e & 63;
+            if (m < rows_here && j < nb) sT[m][j] = eri(sRow[m], sPr[j]) - sT[m][j];
+        }
+        __syncthreads();
+        mark(blk, 3);
+        // in-block substitution, 16-column panels
+        for (int jb = 0; jb < nb; jb += 16) {
+            const int je = min(jb + 16, nb);
+            if (tid < rows_here) {
+                double lv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int j = jb + u;
+                    if (j < je) {
+                        double a = sT[tid][j];
+#pragma unroll
+                        for (int v = 0; v < u; ++v) a = fma(-lv[v], sLb[jb + v][j], a);
+                        lv[u] = a * sRs[j];
+                        sT[tid][j] = lv[u];
+                        Dfin = fma(-lv[u], lv[u], Dfin);
+                        if (b0 + j == kp) Dfin = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            if (je < nb) {
+                // columns beyond the panel: one column per lane, rows strided by 4
+                const int j = je + (tid & 63);
+                if (j < nb) {
+                    for (int m = tid >> 6; m < rows_here; m += 4) {
+                        double a = sT[m][j];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u)
+                            if (jb + u < je) a = fma(-sT[m][jb + u], sLb[jb + u][j], a);
+                        sT[m][j] = a;
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
-        if (tid < TM && r0 + myr < n_rows) {
-            for (int j = 0; j < nb; ++j) {
-                double a = sT[myr][j];
-                for (int jj = 0; jj < j; ++jj) a = fma(-sT[myr][jj], sLb[jj][j], a);
-                double l = a / sRs[j];
-                sT[myr][j] = l;
-                Dfin = fma(-l, l, Dfin);
-                if (b0 + j == kp) Dfin = 0.0;
-            }
+        mark(blk, 4);
+        for (int e = tid; e < nb * R; e += 256) {
+            const int j = e / R, m = e % R;
+            if (m < rows_here) L[(b0 + j) * n_rows + r0 + m] = sT[m][j];
         }
         __syncthreads();
-        for (int e = tid; e < TM * TN; e += 256) {
-            int j = e / TM, m = e % TM;
-            if (j < nb && r0 + m < n_rows) L[(b0 + j) * n_rows + r0 + m] = sT[m][j];
-        }
-        __syncthreads();
+        mark(blk, 5);
     }
-    if (tid < TM && r0 + myr < n_rows) diag[r0 + myr] = Dfin;
+    if (tid < rows_here) diag[r0 + tid] = Dfin;
 }
 
 __global__ void k_init_decompose(GridSync *gs, int32_t *status, int64_t *n_vectors,
                                  unsigned long long *d1max_bits)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        gs->count = 0;
-        gs->gen = 0;
-        gs->abort = 0;
+    for (int i = threadIdx.x; i < kMaxGridBlocks * 16; i += blockDim.x) gs->arrive[i] = 0u;
+    if (threadIdx.x == 0) {
+        gs->release = 0u;
+        gs->abort = 0u;
         *status = 0;
         *n_vectors = 0;
         *d1max_bits = 0ull;

@@ -83,44 +83,60 @@ __device__ __forceinline__ double eri(const RowRec &a, const RowRec &b)
 }
 
 // ---------------------------------------------------------------- grid barrier
-// Sense-free generation barrier for a cooperative launch (all workgroups
-// co-resident).  Every wait is bounded: after 'spin_limit' polls the
-// workgroup gives up and reports false; the caller then records a device
-// error and leaves.
+// Barrier for a cooperative launch (all workgroups co-resident) without a
+// contended counter: every workgroup publishes its arrival in its own
+// 64-byte slot, workgroup 0 polls all slots in parallel (one thread per
+// slot) and then opens the next generation with a single flag that the
+// others poll.  Stores are agent-scope releases and polls agent-scope
+// acquires, so everything written before the barrier is visible after it
+// (across XCDs).  Every wait is bounded: after 'spin_limit' polls the
+// workgroup gives up, raises 'abort' and reports false.
+constexpr int kMaxGridBlocks = 256;
+
 struct GridSync {
-    unsigned int count;
-    unsigned int gen;
+    unsigned int release;
     unsigned int abort;
-    unsigned int pad[13];
+    unsigned int pad[14];
+    unsigned int arrive[kMaxGridBlocks * 16];   // one 64-byte slot per workgroup
 };
+
+// Polls with relaxed agent-scope loads (no cache invalidation per poll) and
+// takes one agent-scope acquire fence once the value is seen.
+__device__ __forceinline__ bool spin_until_eq(unsigned int *addr, unsigned int want,
+                                              unsigned int *abort_flag, unsigned int spin_limit)
+{
+    unsigned int spins = 0;
+    while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit ||
+            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
 
 __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned int nblocks,
                                              unsigned int &gen_local, unsigned int spin_limit)
 {
     __shared__ int s_ok;
+    const unsigned int want = gen_local + 1u;
+    gen_local = want;
+    if (threadIdx.x == 0) s_ok = 1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        unsigned int g = gen_local;
-        unsigned int prev = __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nblocks - 1) {
-            __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&gs->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned int spins = 0;
-            while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > spin_limit ||
-                    __hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    __hip_atomic_store(&gs->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-        gen_local = g + 1u;
-        s_ok = ok;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&gs->arrive[blockIdx.x * 16], want, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (blockIdx.x == 0) {
+        for (unsigned int i = threadIdx.x; i < nblocks; i += blockDim.x)
+            if (!spin_until_eq(&gs->arrive[i * 16], want, &gs->abort, spin_limit)) s_ok = 0;
+        __syncthreads();
+        if (threadIdx.x == 0 && s_ok)
+            __hip_atomic_store(&gs->release, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (threadIdx.x == 0) {
+        if (!spin_until_eq(&gs->release, want, &gs->abort, spin_limit)) s_ok = 0;
     }
     __syncthreads();
     return s_ok != 0;
@@ -160,6 +176,46 @@ __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
             __syncthreads();
         }
     }
+}
+
+// Wave-wide (64 lanes) maximum of a double, broadcast to every lane, with
+// DPP row shifts and row broadcasts (no LDS round trips).  NaN inputs are
+// ignored (fmax), callers test for them separately.
+__device__ __forceinline__ double dpp_f64(double v, double old, int ctrl, int row_mask)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int olo = __double2loint(old), ohi = __double2hiint(old);
+    int rlo, rhi;
+    switch (ctrl) {   // the DPP control must be a compile-time constant
+    case 0x111: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x111, 0xf, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x111, 0xf, 0xf, false); break;
+    case 0x112: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x112, 0xf, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x112, 0xf, 0xf, false); break;
+    case 0x114: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x114, 0xf, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x114, 0xf, 0xf, false); break;
+    case 0x118: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x118, 0xf, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x118, 0xf, 0xf, false); break;
+    case 0x142: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x142, 0xa, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x142, 0xa, 0xf, false); break;
+    default:    rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x143, 0xc, 0xf, false);
+                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x143, 0xc, 0xf, false); break;
+    }
+    (void)row_mask;
+    return __hiloint2double(rhi, rlo);
+}
+
+__device__ __forceinline__ double wave_max_f64(double v)
+{
+    const double ninf = -INFINITY;
+    v = fmax(v, dpp_f64(v, ninf, 0x111, 0xf));   // row_shr:1
+    v = fmax(v, dpp_f64(v, ninf, 0x112, 0xf));   // row_shr:2
+    v = fmax(v, dpp_f64(v, ninf, 0x114, 0xf));   // row_shr:4
+    v = fmax(v, dpp_f64(v, ninf, 0x118, 0xf));   // row_shr:8   -> lane 15 of each row
+    v = fmax(v, dpp_f64(v, ninf, 0x142, 0xa));   // row_bcast:15 -> lanes 31, 63
+    v = fmax(v, dpp_f64(v, ninf, 0x143, 0xc));   // row_bcast:31 -> lane 63
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Wave-wide (64 lanes) selection of the lane holding the first entry in pivot order.

@@ -81,23 +81,203 @@ __global__ __launch_bounds__(256) void k_jV(const double *__restrict__ L, int64_
     if (threadIdx.x == 0) V[Pv] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
 }
 
-// J at row r = sum_P L[P][r] V[P]; written to both (mu,nu) and (nu,mu)
+// J at row r = sum_P L[P][r] V[P]; written to both (mu,nu) and (nu,mu).
+// 64 rows per workgroup, the vectors split over the 4 waves, combined in LDS.
 __global__ __launch_bounds__(256) void k_jJ(const double *__restrict__ L, int64_t n_rows,
                                             const double *__restrict__ V,
                                             const int64_t *__restrict__ n_vectors,
                                             const int64_t *__restrict__ row_pair, int N,
                                             double *__restrict__ J)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rows) return;
+    __shared__ double s_part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * 64 + lane;
     const int64_t M = *n_vectors;
-    double s = 0.0;
-    for (int64_t Pv = 0; Pv < M; ++Pv) s = fma(L[Pv * n_rows + r], V[Pv], s);
-    int mu, nu;
-    unpack_pair(row_pair[r], mu, nu);
-    J[(int64_t)mu * N + nu] = s;
-    J[(int64_t)nu * N + mu] = s;
+    double s0 = 0.0, s1 = 0.0;
+    if (r < n_rows) {
+        int64_t Pv = w;
+        for (; Pv + 4 < M; Pv += 8) {
+            s0 = fma(L[Pv * n_rows + r], V[Pv], s0);
+            s1 = fma(L[(Pv + 4) * n_rows + r], V[Pv + 4], s1);
+        }
+        for (; Pv < M; Pv += 4) s0 = fma(L[Pv * n_rows + r], V[Pv], s0);
+    }
+    s_part[w][lane] = s0 + s1;
+    __syncthreads();
+    if (w == 0 && r < n_rows) {
+        const double s = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
+        int mu, nu;
+        unpack_pair(row_pair[r], mu, nu);
+        J[(int64_t)mu * N + nu] = s;
+        J[(int64_t)nu * N + mu] = s;
+    }
 }
+
+constexpr int JK_TKC = 32;
+using JKS = OperandStage<64, JK_TKC, true>;
+using JKR = OperandStage<64, JK_TKC, false>;
+
+// ---------------------------------------------------------------- sparse unpacking
+// The unpacked vector Lt^P[mu][sigma] is nonzero only on kept pairs, so the
+// half transform runs over each function's neighbour list (sigma with (mu,
+// sigma) kept, ascending sigma) instead of all N sigma.  The vectors are
+// first transposed to row-major LT[row][P] so that one row's M values are
+// contiguous.
+
+// LT[r][P] = L[P][r]  (64 x 64 tiles through LDS)
+__global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ L, int64_t n_rows,
+                                                   const int64_t *__restrict__ n_vectors,
+                                                   double *__restrict__ LT, int64_t ldt)
+{
+    __shared__ double t[64][65];
+    const int64_t r0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * 64;
+    const int64_t M = *n_vectors;
+    if (p0 >= M) return;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int pp = e >> 6, rr = e & 63;
+        t[pp][rr] = (p0 + pp < M && r0 + rr < n_rows) ? L[(p0 + pp) * n_rows + r0 + rr] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int rr = e >> 6, pp = e & 63;
+        if (r0 + rr < n_rows && p0 + pp < M) LT[(r0 + rr) * ldt + p0 + pp] = t[pp][rr];
+    }
+}
+
+// deg[mu] = number of kept pairs (mu, sigma) over all sigma; one wave per mu
+__global__ __launch_bounds__(256) void k_nbr_count(const int32_t *__restrict__ rowof, int N,
+                                                   int32_t *__restrict__ deg)
+{
+    const int mu = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (mu >= N) return;
+    int c = 0;
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        const int sg = s0 + lane;
+        c += __popcll(__ballot(sg < N && rowof[(int64_t)mu * N + sg] >= 0));
+    }
+    if (lane == 0) deg[mu] = c;
+}
+
+// off[0..N]: exclusive prefix sum of deg (one workgroup)
+__global__ __launch_bounds__(256) void k_scan_deg(const int32_t *__restrict__ deg, int N,
+                                                  int64_t *__restrict__ off)
+{
+    __shared__ int64_t s[256];
+    __shared__ int64_t base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < N; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const int64_t v = (i < N) ? deg[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int64_t a = (threadIdx.x >= o) ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < N) off[i] = base + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 255) base += s[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[N] = base;
+}
+
+// neighbour lists in ascending sigma: nb_s = sigma, nb_r = row of (mu, sigma)
+__global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ rowof, int N,
+                                                  const int64_t *__restrict__ off,
+                                                  int32_t *__restrict__ nb_s,
+                                                  int32_t *__restrict__ nb_r)
+{
+    const int mu = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (mu >= N) return;
+    int64_t pos = off[mu];
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int s0 = 0; s0 < N; s0 += 64) {
+        const int sg = s0 + lane;
+        const int32_t r = (sg < N) ? rowof[(int64_t)mu * N + sg] : -1;
+        const unsigned long long b = __ballot(r >= 0);
+        if (r >= 0) {
+            const int64_t q = pos + __popcll(b & below);
+            nb_s[q] = sg;
+            nb_r[q] = r;
+        }
+        pos += __popcll(b);
+    }
+}
+
+// Half transform over neighbour lists (FP64):
+//   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
+// tile: m = P (64), n = i (64), k = neighbour index.
+__global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
+                                                     const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ nb_s,
+                                                     const int32_t *__restrict__ nb_r,
+                                                     const double *__restrict__ C, int ncol,
+                                                     const int64_t *__restrict__ n_vectors,
+                                                     double *__restrict__ Y, int64_t ldy)
+{
+    __shared__ double sU[2 * JKS::kSize];
+    double *sA = sU, *sB = sU + JKS::kSize;
+    const int64_t M = *n_vectors;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    if (p0 >= M) return;
+    const int n0 = blockIdx.y * 64;
+    const int mu = blockIdx.z;
+    const int64_t j0 = off[mu], deg = off[mu + 1] - j0;
+    f64x4 acc[4];
+    zero_acc(acc);
+    gemm_tile<4, JK_TKC, true, true>(
+        0, deg, 4,
+        [&](int64_t k, int m) -> double {
+            return (p0 + m < M) ? LT[(int64_t)nb_r[j0 + k] * ldt + p0 + m] : 0.0;
+        },
+        [&](int64_t k, int n) -> double {
+            return (n0 + n < ncol) ? C[(int64_t)nb_s[j0 + k] * ncol + n0 + n] : 0.0;
+        },
+        acc, sA, sB);
+    double *out = Y + (int64_t)mu * ldy;
+    for_each_acc(acc, 4, [&](int m, int n, double v) {
+        if (p0 + m < M && n0 + n < ncol) out[(p0 + m) * ncol + n0 + n] = v;
+    });
+}
+
+// Partial K from row-major X (row mu holds the M * ncol values X^P_{i mu}):
+//   Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k]   (lower tile pairs)
+__global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X, int64_t ldx,
+                                                   int N, const int64_t *__restrict__ n_vectors,
+                                                   int ncol, int nsplit, double *__restrict__ Kp)
+{
+    __shared__ double sU[2 * JKR::kSize];
+    double *sA = sU, *sB = sU + JKR::kSize;
+    const int t = blockIdx.x;
+    int tm = 0;
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    const int s = blockIdx.y;
+    const int64_t nk = *n_vectors * ncol;
+    int64_t per = (nk + nsplit - 1) / nsplit;
+    per = (per + JK_TKC - 1) / JK_TKC * JK_TKC;
+    const int64_t kb = s * per;
+    const int64_t ke = (kb + per < nk) ? kb + per : nk;
+    const int m0 = tm * 64, n0 = tn * 64;
+    f64x4 acc[4];
+    zero_acc(acc);
+    gemm_tile<4, JK_TKC, false, false>(
+        kb, ke, 4,
+        [&](int64_t k, int m) -> double { return (m0 + m < N) ? X[(m0 + m) * ldx + k] : 0.0; },
+        [&](int64_t k, int n) -> double { return (n0 + n < N) ? X[(n0 + n) * ldx + k] : 0.0; },
+        acc, sA, sB);
+    double *out = Kp + (int64_t)s * N * N;
+    for_each_acc(acc, 4, [&](int m, int n, double v) {
+        if (m0 + m < N && n0 + n < N) out[(int64_t)(m0 + m) * N + n0 + n] = v;
+    });
+}
+
 
 // Half transform Y^P = Lt^P C  (Lt^P the unpacked symmetric N x N vector):
 //   Y^P[mu][i] = sum_sigma Lt^P[sigma][mu] C[sigma][i]
@@ -111,39 +291,39 @@ __global__ __launch_bounds__(256) void k_half(const double *__restrict__ L, int6
                                               const int64_t *__restrict__ n_vectors,
                                               int64_t p_base, double *__restrict__ Y)
 {
-    __shared__ double sA[TK * TM];
-    __shared__ double sB[TK * TN];
-    __shared__ double sT[TM][TN + 1];
+    __shared__ double sU[(2 * JKS::kSize > 64 * 65) ? 2 * JKS::kSize : 64 * 65];
+    double *sA = sU, *sB = sU + JKS::kSize;
+    double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
     const int64_t Pv = p_base + blockIdx.z;
     if (Pv >= *n_vectors) return;
-    const int m0 = blockIdx.x * TM;
-    const int n0 = blockIdx.y * TN;
-    const double *Lp = L + Pv * n_rows;
-    TileAcc acc;
-    acc.zero();
-    mfma_tile_f64(
-        0, N,
+    const int m0 = blockIdx.x * 64;
+    const int n0 = blockIdx.y * 64;
+    const double *Lv = L + Pv * n_rows;
+    f64x4 acc[4];
+    zero_acc(acc);
+    gemm_tile<4, JK_TKC, true, true>(
+        0, N, 4,
         [&](int64_t k, int m) -> double {
             int mu = m0 + m;
             if (mu >= N) return 0.0;
             int32_t r = rowof[k * N + mu];
-            return (r >= 0) ? Lp[r] : 0.0;
+            return (r >= 0) ? Lv[r] : 0.0;
         },
         [&](int64_t k, int n) -> double {
             int i = n0 + n;
             return (i < ncol) ? C[k * ncol + i] : 0.0;
         },
         acc, sA, sB);
-    tile_to_lds(acc, &sT[0][0], TN + 1);
+    for_each_acc(acc, 4, [&](int m, int n, double v) { sT[m][n] = v; });
     __syncthreads();
     const int64_t Yb = (Pv - p_base);
-    for (int e = threadIdx.x; e < TM * TN; e += 256) {
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
         if (TRANSPOSED) {
-            int n = e / TM, m = e % TM;
+            int n = e >> 6, m = e & 63;
             if (m0 + m < N && n0 + n < ncol)
                 Y[(Yb * ncol + n0 + n) * (int64_t)N + m0 + m] = sT[m][n];
         } else {
-            int m = e / TN, n = e % TN;
+            int m = e >> 6, n = e & 63;
             if (m0 + m < N && n0 + n < ncol)
                 Y[(Yb * N + m0 + m) * (int64_t)ncol + n0 + n] = sT[m][n];
         }
@@ -157,9 +337,8 @@ __global__ __launch_bounds__(256) void k_syrk(const double *__restrict__ X, int 
                                               int64_t p_base, int64_t p_count, int nsplit,
                                               double *__restrict__ Kp)
 {
-    __shared__ double sA[TK * TM];
-    __shared__ double sB[TK * TN];
-    // tile pair from blockIdx.x: tm >= tn
+    __shared__ double sU[2 * JKS::kSize];
+    double *sA = sU, *sB = sU + JKS::kSize;
     int t = blockIdx.x;
     int tm = 0;
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
@@ -170,35 +349,21 @@ __global__ __launch_bounds__(256) void k_syrk(const double *__restrict__ X, int 
     if (M < 0) M = 0;
     const int64_t nk = M * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
-    per = (per + TK - 1) / TK * TK;
+    per = (per + JK_TKC - 1) / JK_TKC * JK_TKC;
     const int64_t kb = s * per;
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
-    TileAcc acc;
-    acc.zero();
-    const int m0 = tm * TM, n0 = tn * TN;
-    if (kb < ke)
-        mfma_tile_f64(
-            kb, ke,
-            [&](int64_t k, int m) -> double {
-                return (m0 + m < N) ? X[k * N + m0 + m] : 0.0;
-            },
-            [&](int64_t k, int n) -> double {
-                return (n0 + n < N) ? X[k * N + n0 + n] : 0.0;
-            },
-            acc, sA, sB);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f64x4 acc[4];
+    zero_acc(acc);
+    const int m0 = tm * 64, n0 = tn * 64;
+    gemm_tile<4, JK_TKC, true, true>(
+        kb, ke, 4,
+        [&](int64_t k, int m) -> double { return (m0 + m < N) ? X[k * N + m0 + m] : 0.0; },
+        [&](int64_t k, int n) -> double { return (n0 + n < N) ? X[k * N + n0 + n] : 0.0; },
+        acc, sA, sB);
     double *out = Kp + (int64_t)s * N * N;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m = m0 + wm + 16 * i + mfma_row(lane, v);
-                int n = n0 + wn + 16 * j + (lane & 15);
-                if (m < N && n < N) out[(int64_t)m * N + n] = acc.c[i][j][v];
-            }
+    for_each_acc(acc, 4, [&](int m, int n, double v) {
+        if (m0 + m < N && n0 + n < N) out[(int64_t)(m0 + m) * N + n0 + n] = v;
+    });
 }
 
 // K[mu][nu] (+)= sum_s Kp[s][max][min]  -- exactly symmetric
@@ -214,39 +379,30 @@ __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int 
     K[e] = accumulate ? K[e] + s : s;
 }
 
-// Lmo[P][a][b] = sum_mu C1[mu][a] Y[P][mu][b]   (Y from k_half<false> with C2)
-__global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int N,
+// Lmo[P][a][b] = sum_mu C1[mu][a] Y[mu][P q + b]   (Y from k_half_sparse with C2)
+__global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int64_t ldy, int N,
                                              const double *__restrict__ C1, int p, int q,
                                              const int64_t *__restrict__ n_vectors,
                                              int64_t p_base, double *__restrict__ Lmo)
 {
-    __shared__ double sA[TK * TM];
-    __shared__ double sB[TK * TN];
+    __shared__ double sU[2 * JKS::kSize];
+    double *sA = sU, *sB = sU + JKS::kSize;
     const int64_t Pv = p_base + blockIdx.z;
     if (Pv >= *n_vectors) return;
-    const int m0 = blockIdx.x * TM;   // a
-    const int n0 = blockIdx.y * TN;   // b
-    const double *Yp = Y + (Pv - p_base) * (int64_t)N * q;
-    TileAcc acc;
-    acc.zero();
-    mfma_tile_f64(
-        0, N,
+    const int m0 = blockIdx.x * 64;   // a
+    const int n0 = blockIdx.y * 64;   // b
+    const double *Yp = Y + (Pv - p_base) * (int64_t)q;   // Y[mu][P q + b], row stride ldy
+    f64x4 acc[4];
+    zero_acc(acc);
+    gemm_tile<4, JK_TKC, true, true>(
+        0, N, 4,
         [&](int64_t k, int m) -> double { return (m0 + m < p) ? C1[k * p + m0 + m] : 0.0; },
-        [&](int64_t k, int n) -> double { return (n0 + n < q) ? Yp[k * q + n0 + n] : 0.0; },
+        [&](int64_t k, int n) -> double { return (n0 + n < q) ? Yp[k * ldy + n0 + n] : 0.0; },
         acc, sA, sB);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     double *out = Lmo + Pv * (int64_t)p * q;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int a = m0 + wm + 16 * i + mfma_row(lane, v);
-                int b = n0 + wn + 16 * j + (lane & 15);
-                if (a < p && b < q) out[(int64_t)a * q + b] = acc.c[i][j][v];
-            }
+    for_each_acc(acc, 4, [&](int m, int n, double v) {
+        if (m0 + m < p && n0 + n < q) out[(int64_t)(m0 + m) * q + n0 + n] = v;
+    });
 }
 
 }  // namespace cdk

@@ -11,7 +11,8 @@ struct Step1Params {
     const int64_t *n_act_dev;  // device count of active rows (must equal n_act)
     int64_t n_act;
     double *D_act;             // [n_act] residual diagonal of the active rows
-    double *L_act;             // [max_vectors][n_act] vectors on the active rows
+    double *LT_act;            // [n_act][max_vectors] vectors on the active rows, row-major
+    const int64_t *n_rows_dev; // device count of rows (must equal n_rows)
     double *Cbuf;              // [QMAX][n_act] candidate columns
     Nom *noms;                 // [G][CNOM + 1]
     GridSync *gs;
@@ -28,6 +29,9 @@ struct Step1Params {
     int32_t q;                 // candidate batch size (<= QMAX)
     int32_t slice;             // active rows per workgroup
     uint32_t spin_limit;
+    int64_t *timeline;         // optional: [timeline_cap][8] device clock stamps per batch
+    int64_t *timeline_count;   // optional: number of batches
+    int64_t timeline_cap;
 };
 
 }  // namespace cdk

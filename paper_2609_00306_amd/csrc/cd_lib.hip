@@ -13,6 +13,7 @@
 #include "../../include/cd.h"
 #include "cd_decompose.hip"
 #include "cd_jk.hip"
+#include "cd_jk_lp.hip"
 
 using namespace cdk;
 
@@ -65,7 +66,7 @@ struct DecompWs {
     RowRec *rows;
     int32_t *act_row;
     double *D_act;
-    double *L_act;
+    double *LT_act;
     double *Cbuf;
     Nom *noms;
     GridSync *gs;
@@ -93,7 +94,7 @@ DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
     w.rows = c.take<RowRec>(std::max<int64_t>(1, n));
     w.act_row = c.take<int32_t>(std::max<int64_t>(1, na));
     w.D_act = c.take<double>(std::max<int64_t>(1, na));
-    w.L_act = c.take<double>(std::max<int64_t>(1, mv * na));
+    w.LT_act = c.take<double>(std::max<int64_t>(1, mv * na));
     w.Cbuf = c.take<double>(std::max<int64_t>(1, (int64_t)QMAX * na));
     w.noms = c.take<Nom>((size_t)S1_MAXG * (CNOM + 1));
     w.gs = c.take<GridSync>(1);
@@ -165,6 +166,32 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
     return check_launch("setup kernels");
 }
 
+// Row tile of the all-row solve: the smallest 16-row multiple (2..8) that
+// gives at most one tile per compute unit, else 8 (128 rows).
+cd_status launch_step2(const DecompWs &w, const cd_problem &p, int64_t n, int64_t mv, int n_cu,
+                       hipStream_t st, int64_t *timeline, int64_t tl_cap)
+{
+    int rt = (int)std::min<int64_t>(8, std::max<int64_t>(2, blocks_of(n, 16 * (int64_t)n_cu)));
+    const unsigned grid = (unsigned)blocks_of(n, 16 * rt);
+#define CD_STEP2(RT)                                                                        \
+    case RT:                                                                                \
+        k_step2<RT><<<grid, 256, 0, st>>>(w.rows, n, w.prow, w.dpiv, w.Lp, mv,               \
+                                          w.pivot_of_row, p.n_vectors, p.L, p.diag,         \
+                                          timeline, tl_cap);                                \
+        break;
+    switch (rt) {
+        CD_STEP2(2)
+        CD_STEP2(3)
+        CD_STEP2(4)
+        CD_STEP2(5)
+        CD_STEP2(6)
+        CD_STEP2(7)
+        CD_STEP2(8)
+    }
+#undef CD_STEP2
+    return check_launch("all-row solve");
+}
+
 }  // namespace
 
 extern "C" {
@@ -192,14 +219,14 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
             if (hipMalloc(&tmp, probe.bytes) != hipSuccess)
                 return fail(CD_ERR_DEVICE, "hipMalloc of %zu bytes failed", probe.bytes);
             DecompWs w = carve_decomp(tmp, N, 0, 0, 0);
-            k_init_decompose<<<1, 64, 0, st>>>(w.gs, w.cnt_rows, w.totals, w.d1max);
+            k_init_decompose<<<1, 256, 0, st>>>(w.gs, w.cnt_rows, w.totals, w.d1max);
             s = launch_setup(mols[i], opts, w, nullptr, 0, 0, st, false);
             if (!s && hipMemcpyAsync(tot, w.totals, sizeof tot, hipMemcpyDeviceToHost, st) !=
                           hipSuccess)
                 s = fail(CD_ERR_DEVICE, "copy of row counts failed");
             if (!s && hipStreamSynchronize(st) != hipSuccess)
                 s = fail(CD_ERR_DEVICE, "stream synchronise failed");
-            hipFree(tmp);
+            (void)hipFree(tmp);
             if (s) return s;
         }
         sizes[i].n_rows = tot[0];
@@ -245,12 +272,12 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         wbase += w.bytes;
         if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[0]), st) != hipSuccess)
             return fail(CD_ERR_INVALID_ARG, "timing event 0 could not be recorded");
-        k_init_decompose<<<1, 64, 0, st>>>(w.gs, p.status, p.n_vectors, w.d1max);
+        k_init_decompose<<<1, 256, 0, st>>>(w.gs, p.status, p.n_vectors, w.d1max);
         if ((s = launch_setup(p.mol, opts, w, p.row_pair, n, na, st, true))) return s;
         if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[1]), st) != hipSuccess)
             return fail(CD_ERR_INVALID_ARG, "timing event 1 could not be recorded");
         if (na > 0 && mv > 0) {
-            int G = (int)std::min<int64_t>(di.n_cu, std::max<int64_t>(1, blocks_of(na, 16)));
+            int G = (int)std::min<int64_t>(di.n_cu, std::max<int64_t>(1, blocks_of(na, 32)));
             G = std::max<int>(G, (int)blocks_of(na, SMAX));
             G = std::min(G, S1_MAXG);
             const int slice = (int)blocks_of(na, G);
@@ -263,7 +290,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             P1.n_act_dev = w.totals + 1;
             P1.n_act = na;
             P1.D_act = w.D_act;
-            P1.L_act = w.L_act;
+            P1.LT_act = w.LT_act;
+            P1.n_rows_dev = w.totals;
             P1.Cbuf = w.Cbuf;
             P1.noms = w.noms;
             P1.gs = w.gs;
@@ -280,24 +308,24 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             P1.q = QMAX;
             P1.slice = slice;
             P1.spin_limit = 1u << 22;
+            P1.timeline = opts->timeline ? opts->timeline + 1 : nullptr;
+            P1.timeline_count = opts->timeline;
+            P1.timeline_cap = opts->timeline ? opts->timeline_cap : 0;
             void *args[] = {&P1};
             hipError_t e = hipLaunchCooperativeKernel((const void *)k_step1, dim3(G), dim3(256),
                                                       args, 0, st);
             if (e != hipSuccess)
                 return fail(CD_ERR_DEVICE, "step-1 launch (%d workgroups): %s", G,
                             hipGetErrorString(e));
-            const int gx = (int)std::min<int64_t>(16, std::max<int64_t>(1, blocks_of(mv, 256)));
-            k_gather_pivots<<<dim3(gx, (unsigned)mv), 256, 0, st>>>(
-                w.L_act, na, w.piv_slot, p.pivots, w.rows, p.n_vectors, w.Lp, mv, w.prow);
+            k_gather_pivots<<<(unsigned)mv, 256, 0, st>>>(w.LT_act, mv, w.piv_slot, p.pivots,
+                                                          w.rows, p.n_vectors, w.Lp, mv, w.prow);
             if ((s = check_launch("pivot gather"))) return s;
         }
         if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[2]), st) != hipSuccess)
             return fail(CD_ERR_INVALID_ARG, "timing event 2 could not be recorded");
         if (n > 0) {
-            k_step2<<<(unsigned)blocks_of(n, TM), 256, 0, st>>>(w.rows, n, w.prow, w.dpiv, w.Lp,
-                                                               mv, w.pivot_of_row, p.n_vectors,
-                                                               p.L, p.diag);
-            if ((s = check_launch("step 2"))) return s;
+            int64_t *tl2 = opts->timeline ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
+            if ((s = launch_step2(w, p, n, mv, di.n_cu, st, tl2, opts->timeline_cap))) return s;
         }
         if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[3]), st) != hipSuccess)
             return fail(CD_ERR_INVALID_ARG, "timing event 3 could not be recorded");
@@ -307,7 +335,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             return fail(CD_ERR_DEVICE, "stream synchronise failed");
         for (int32_t i = 0; i < count; ++i) {
             int32_t v = 0;
-            hipMemcpy(&v, probs[i].status, sizeof v, hipMemcpyDeviceToHost);
+            if (hipMemcpy(&v, probs[i].status, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "status copy failed");
             if (v != 0) return fail((cd_status)v, "problem %d: device status %d", i, v);
         }
     }
@@ -319,15 +348,50 @@ namespace {
 
 int jk_nsplit(int N, int n_cu)
 {
-    const int T = (N + TM - 1) / TM;
+    const int T = (N + 63) / 64;
     const int pairs = T * (T + 1) / 2;
     int ns = (2 * n_cu + pairs - 1) / std::max(1, pairs);
     return std::max(1, std::min(ns, 64));
 }
 
+// Unpacking of the packed vectors for the J/K and transform products: a
+// dense row map, per-function neighbour lists and the row-major copy LT.
+struct SparseWs {
+    int32_t *rowof, *deg, *nb_s, *nb_r;
+    int64_t *off;
+    double *LT;
+};
+
+SparseWs carve_sparse(Carver &c, int64_t N, int64_t n, int64_t mv)
+{
+    SparseWs w{};
+    w.rowof = c.take<int32_t>(std::max<int64_t>(1, N * N));
+    w.deg = c.take<int32_t>(std::max<int64_t>(1, N));
+    w.off = c.take<int64_t>(N + 1);
+    w.nb_s = c.take<int32_t>(std::max<int64_t>(1, 2 * n));
+    w.nb_r = c.take<int32_t>(std::max<int64_t>(1, 2 * n));
+    w.LT = c.take<double>(std::max<int64_t>(1, n * mv));
+    return w;
+}
+
+void launch_sparse_prep(const SparseWs &w, int64_t N, int64_t n, int64_t mv,
+                        const int64_t *row_pair, const double *L, const int64_t *n_vectors,
+                        hipStream_t st)
+{
+    const int64_t NN = N * N;
+    const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
+    k_fill_i32<<<fb, 256, 0, st>>>(w.rowof, NN, -1);
+    k_rowmap<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, row_pair, (int)N, w.rowof);
+    k_nbr_count<<<(unsigned)blocks_of(N, 4), 256, 0, st>>>(w.rowof, (int)N, w.deg);
+    k_scan_deg<<<1, 256, 0, st>>>(w.deg, (int)N, w.off);
+    k_nbr_fill<<<(unsigned)blocks_of(N, 4), 256, 0, st>>>(w.rowof, (int)N, w.off, w.nb_s, w.nb_r);
+    k_transpose<<<dim3((unsigned)blocks_of(n, 64), (unsigned)blocks_of(mv, 64)), 256, 0, st>>>(
+        L, n, n_vectors, w.LT, mv);
+}
+
 struct JkWs {
     double *Dm, *w, *V, *X, *Kp;
-    int32_t *rowof;
+    SparseWs sp;
     size_t bytes;
 };
 
@@ -339,7 +403,7 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
     w.Dm = c.take<double>(std::max<int64_t>(1, N * N));
     w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
     w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
-    w.rowof = c.take<int32_t>(std::max<int64_t>(1, N * N));
+    w.sp = carve_sparse(c, N, p.n_rows, p.max_vectors);
     w.X = c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_occ * N));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.bytes = c.off;
@@ -366,7 +430,8 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
 {
     if (count < 0 || (count > 0 && !probs) || !ws_bytes)
         return fail(CD_ERR_INVALID_ARG, "null argument");
-    if (prec != CD_FP64) return fail(CD_ERR_UNSUPPORTED, "precision %d not built yet", (int)prec);
+    if (prec != CD_FP64 && prec != CD_FP32 && prec != CD_BF16X3)
+        return fail(CD_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     DevInfo di;
     cd_status s = dev_info(di);
     if (s) return s;
@@ -403,18 +468,33 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         k_fill_f64<<<fb, 256, 0, st>>>(p.J, NN, 0.0);
         k_fill_f64<<<fb, 256, 0, st>>>(p.K, NN, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
-        k_fill_i32<<<fb, 256, 0, st>>>(w.rowof, NN, -1);
-        k_rowmap<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, w.rowof);
+        launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
         k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>((int)N, O, p.C, w.Dm);
         k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, w.Dm, w.w);
         k_jV<<<(unsigned)mv, 256, 0, st>>>(p.L, n, w.w, p.n_vectors, w.V);
-        k_jJ<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
-                                                          (int)N, p.J);
-        k_half<true><<<dim3((unsigned)blocks_of(N, TM), (unsigned)blocks_of(O, TN), (unsigned)mv),
-                       256, 0, st>>>(p.L, n, w.rowof, (int)N, p.C, O, p.n_vectors, 0, w.X);
-        const int T = (int)blocks_of(N, TM);
-        k_syrk<<<dim3(T * (T + 1) / 2, nsplit), 256, 0, st>>>(w.X, (int)N, p.n_vectors, O, 0, mv,
+        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, st>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
+                                                         (int)N, p.J);
+        const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
+        const int T = (int)blocks_of(N, 64);
+        const dim3 sgrid(T * (T + 1) / 2, nsplit);
+        const int64_t ldx = mv * O;
+        float *X32 = reinterpret_cast<float *>(w.X);
+        const SparseWs &q = w.sp;
+        if (prec == CD_FP64) {
+            k_half_sparse<<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+                                                 p.n_vectors, w.X, ldx);
+            k_syrk_rows<<<sgrid, 256, 0, st>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
+        } else if (prec == CD_FP32) {
+            k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
+                                                            O, p.n_vectors, X32, ldx);
+            k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, st>>>(X32, ldx, (int)N, p.n_vectors, O,
+                                                          nsplit, w.Kp);
+        } else {
+            k_half_sparse_lp<LP_BF16X3><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r,
+                                                               p.C, O, p.n_vectors, X32, ldx);
+            k_syrk_rows_lp<LP_BF16X3><<<sgrid, 256, 0, st>>>(X32, ldx, (int)N, p.n_vectors, O,
                                                              nsplit, w.Kp);
+        }
         k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
     }
@@ -437,7 +517,7 @@ cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, s
             return fail(CD_ERR_INVALID_ARG, "negative size");
         if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
         Carver c(nullptr);
-        c.take<int32_t>(std::max<int64_t>(1, (int64_t)p.n_basis * p.n_basis));
+        carve_sparse(c, p.n_basis, p.n_rows, p.max_vectors);
         c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_basis * p.q));
         tot += c.off;
     }
@@ -457,23 +537,26 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
     char *wbase = static_cast<char *>(ws);
     for (int32_t i = 0; i < count; ++i) {
         const cd_transform_problem &p = probs[i];
-        const int64_t N = p.n_basis, NN = N * N, n = p.n_rows, mv = p.max_vectors;
+        const int64_t N = p.n_basis, n = p.n_rows, mv = p.max_vectors;
         Carver c(wbase);
-        int32_t *rowof = c.take<int32_t>(std::max<int64_t>(1, NN));
+        SparseWs sp = carve_sparse(c, N, n, mv);
         double *Y = c.take<double>(std::max<int64_t>(1, mv * N * p.q));
         wbase += c.off;
         if (N == 0 || mv == 0 || p.p == 0 || p.q == 0) continue;
         if (!p.Lmo || !p.C1 || !p.C2 || !p.n_vectors || (n > 0 && (!p.L || !p.row_pair)))
             return fail(CD_ERR_INVALID_ARG, "null pointer in transform problem %d", i);
-        const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
-        k_fill_i32<<<fb, 256, 0, st>>>(rowof, NN, -1);
-        if (n > 0)
-            k_rowmap<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, rowof);
-        k_half<false><<<dim3((unsigned)blocks_of(N, TM), (unsigned)blocks_of(p.q, TN),
-                             (unsigned)mv),
-                        256, 0, st>>>(p.L, n, rowof, (int)N, p.C2, p.q, p.n_vectors, 0, Y);
-        k_tr2<<<dim3((unsigned)blocks_of(p.p, TM), (unsigned)blocks_of(p.q, TN), (unsigned)mv),
-                256, 0, st>>>(Y, (int)N, p.C1, p.p, p.q, p.n_vectors, 0, p.Lmo);
+        const int64_t ldy = mv * p.q;
+        if (n > 0) {
+            launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
+            k_half_sparse<<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
+                                 (unsigned)N),
+                            256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
+                                          p.n_vectors, Y, ldy);
+        } else {
+            k_fill_f64<<<256, 256, 0, st>>>(Y, mv * N * p.q, 0.0);
+        }
+        k_tr2<<<dim3((unsigned)blocks_of(p.p, 64), (unsigned)blocks_of(p.q, 64), (unsigned)mv),
+                256, 0, st>>>(Y, ldy, (int)N, p.C1, p.p, p.q, p.n_vectors, 0, p.Lmo);
         if ((s = check_launch("transform kernels"))) return s;
     }
     if (flags & CD_SYNC) {

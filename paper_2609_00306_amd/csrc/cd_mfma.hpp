@@ -1,8 +1,15 @@
-// FP64 matrix-core tile for gfx950: one 256-thread workgroup computes a
-// 64 x 64 block  acc[m][n] = sum_k A(k, m) B(k, n)  with both operands
-// "k-major" (for a fixed k, m or n is the fast index), staged through LDS in
-// k-chunks of 16.  Waves are arranged 2 x 2, each owning a 32 x 32 quarter as
-// 2 x 2 tiles of v_mfma_f64_16x16x4f64.
+// FP64 matrix-core GEMM engine for gfx950.
+//
+// One 256-thread workgroup (4 waves) computes a (16 RT) x 64 block
+//     acc[m][n] = sum_k A(k, m) B(k, n)
+// Wave w owns the 16 columns [16 w, 16 w + 16) and all RT row tiles, one
+// v_mfma_f64_16x16x4f64 accumulator per row tile.  Operands are staged through
+// LDS in k-chunks of TKC; the next chunk is loaded into registers while the
+// current one is multiplied (software pipelining), so global-memory latency
+// overlaps the matrix work.  Each operand is either "k-major" (for fixed k the
+// m/n index is contiguous in memory) or "k-contiguous" (for fixed m/n the k
+// index is contiguous); the global-load mapping follows the contiguous index
+// so every load is coalesced.
 //
 // Operand/result lane layout of the 16x16x4 FP64 instruction (wave64):
 //   A (16 x 4):  lane l holds A[m = l % 16][k = l / 16]
@@ -16,80 +23,229 @@ namespace cdk {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TK = 16;    // k-chunk staged in LDS
-constexpr int TM = 64;    // tile rows (m)
-constexpr int TN = 64;    // tile cols (n)
+// Row of the 16 x 16 result held by element v of 'lane'.
+__device__ __forceinline__ int mfma_row(int lane, int v) { return 4 * v + (lane >> 4); }
 
-struct TileAcc {
-    f64x4 c[2][2];
-    __device__ __forceinline__ void zero()
+template <int ROWS, int TKC, bool KMAJ>
+struct OperandStage {
+    // LDS footprint in doubles
+    static constexpr int kStride = KMAJ ? ROWS : (TKC + 1);
+    static constexpr int kSize = KMAJ ? TKC * ROWS : ROWS * (TKC + 1);
+    static constexpr int kPerThread = (ROWS * TKC + 255) / 256;
+
+    // element e of a chunk -> (k, m), following the contiguous index
+    __device__ static __forceinline__ void coord(int e, int &k, int &m)
+    {
+        if (KMAJ) {
+            k = e / ROWS;
+            m = e % ROWS;
+        } else {
+            m = e / TKC;
+            k = e % TKC;
+        }
+    }
+    __device__ static __forceinline__ int lds_index(int k, int m)
+    {
+        return KMAJ ? k * ROWS + m : m * (TKC + 1) + k;
+    }
+    template <class LD>
+    __device__ static __forceinline__ void fetch(LD ld, int64_t k0, int64_t kend, double (&r)[kPerThread])
     {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int u = 0; u < kPerThread; ++u) {
+            int e = threadIdx.x + 256 * u;
+            int k, m;
+            coord(e, k, m);
+            r[u] = (e < ROWS * TKC && k0 + k < kend) ? ld(k0 + k, m) : 0.0;
+        }
+    }
+    __device__ static __forceinline__ void put(double *s, const double (&r)[kPerThread])
+    {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) c[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < kPerThread; ++u) {
+            int e = threadIdx.x + 256 * u;
+            if (e < ROWS * TKC) {
+                int k, m;
+                coord(e, k, m);
+                s[lds_index(k, m)] = r[u];
+            }
+        }
     }
 };
 
-// sA, sB: LDS buffers of TK*TM doubles each.  la(k, m) / lb(k, n) return the
-// operand for absolute k and tile-relative m / n (returning 0 outside).
-template <class LoadA, class LoadB>
-__device__ __forceinline__ void mfma_tile_f64(int64_t kbeg, int64_t kend, LoadA la, LoadB lb,
-                                              TileAcc &acc, double *sA, double *sB)
+// acc[r] += A(k, 16 r + .) B(k, 16 w + .)  for k in [kbeg, kend).
+// rt_active <= RT row tiles are multiplied (uniform).  la(k, m), lb(k, n)
+// return the operands (k absolute, m in [0, 16 RT), n in [0, 64)); loads with
+// k >= kend are not issued.  sA, sB: LDS of OperandStage<..>::kSize doubles.
+template <int RT, int TKC, bool AK, bool BK, class LA, class LB>
+__device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, int rt_active, LA la,
+                                          LB lb, f64x4 (&acc)[RT], double *sA, double *sB)
 {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int wm = (w >> 1) * 32;
-    const int wn = (w & 1) * 32;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-#pragma unroll
-        for (int u = 0; u < (TK * TM) / 256; ++u) {
-            int e = tid + 256 * u;
-            int kk = e >> 6;
-            int mm = e & 63;
-            int64_t k = k0 + kk;
-            sA[e] = (k < kend) ? la(k, mm) : 0.0;
-            sB[e] = (k < kend) ? lb(k, mm) : 0.0;
-        }
+    using SA = OperandStage<16 * RT, TKC, AK>;
+    using SB = OperandStage<64, TKC, BK>;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    if (kbeg >= kend) return;
+    double ra[SA::kPerThread], rb[SB::kPerThread];
+    SA::fetch(la, kbeg, kend, ra);
+    SB::fetch(lb, kbeg, kend, rb);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TKC) {
+        SA::put(sA, ra);
+        SB::put(sB, rb);
         __syncthreads();
+        if (k0 + TKC < kend) {
+            SA::fetch(la, k0 + TKC, kend, ra);
+            SB::fetch(lb, k0 + TKC, kend, rb);
+        }
 #pragma unroll
-        for (int ks = 0; ks < TK; ks += 4) {
-            int kr = ks + (lane >> 4);
-            double a0 = sA[kr * TM + wm + (lane & 15)];
-            double a1 = sA[kr * TM + wm + 16 + (lane & 15)];
-            double b0 = sB[kr * TN + wn + (lane & 15)];
-            double b1 = sB[kr * TN + wn + 16 + (lane & 15)];
-            acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
-            acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
-            acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
-            acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+        for (int ks = 0; ks < TKC; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            const double b = sB[SB::lds_index(kk, 16 * w + (lane & 15))];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                if (r < rt_active) {
+                    const double a = sA[SA::lds_index(kk, 16 * r + (lane & 15))];
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+                }
+            }
         }
         __syncthreads();
     }
 }
 
-// Row of the 16 x 16 result held by element v of 'lane'.
-__device__ __forceinline__ int mfma_row(int lane, int v) { return 4 * v + (lane >> 4); }
+// ---------------------------------------------------------------- split-k form
+// Wave-parallel product for short, tall operands: every wave owns whole
+// k-chunks (chunk c goes to wave c % 4), stages them in its own LDS region
+// and keeps a full (16 RT) x 64 accumulator, so the four waves run four
+// independent load/multiply pipelines with no workgroup-wide barrier inside
+// the k loop.  Both operands are k-contiguous (for a fixed row the k index
+// is contiguous in memory).  The partial products are summed across waves
+// by wave_sum_to_lds().
+template <int RT, int TKC>
+struct SplitK {
+    static constexpr int kRows = 16 * RT;
+    static constexpr int kLd = TKC + 1;
+    static constexpr int kWaveDoubles = (kRows + 64) * kLd;     // LDS per wave
+    static constexpr int kNA = kRows * TKC / 64;                 // loads per lane
+    static constexpr int kNB = 64 * TKC / 64;
 
-// Write the accumulator into an LDS tile sT[m * ldt + n].
-__device__ __forceinline__ void tile_to_lds(const TileAcc &acc, double *sT, int ldt)
-{
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int wm = (w >> 1) * 32;
-    const int wn = (w & 1) * 32;
+    template <class LA, class LB>
+    __device__ static __forceinline__ void fetch(LA la, LB lb, int64_t k0, int64_t kend, int rows,
+                                                 double (&ra)[kNA], double (&rb)[kNB])
+    {
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int u = 0; u < kNA; ++u) {
+            const int e = lane + 64 * u, m = e / TKC, k = e % TKC;
+            ra[u] = (m < rows && k0 + k < kend) ? la(k0 + k, m) : 0.0;
+        }
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int u = 0; u < kNB; ++u) {
+            const int e = lane + 64 * u, n = e / TKC, k = e % TKC;
+            rb[u] = (k0 + k < kend) ? lb(k0 + k, n) : 0.0;
+        }
+    }
+
+    template <class LA, class LB>
+    __device__ static __forceinline__ void run(int64_t kend, int rt, int rows, LA la, LB lb,
+                                               f64x4 (&acc)[RT][4], double *sWaves)
+    {
+        const int lane = threadIdx.x & 63;
+        const int w = threadIdx.x >> 6;
+        double *sAw = sWaves + w * kWaveDoubles;
+        double *sBw = sAw + kRows * kLd;
+        double ra[kNA], rb[kNB];
+        const int64_t nch = (kend + TKC - 1) / TKC;
+        if (w >= nch) return;
+        fetch(la, lb, (int64_t)w * TKC, kend, rows, ra, rb);
+        for (int64_t c = w; c < nch; c += 4) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m = wm + 16 * i + mfma_row(lane, v);
-                int n = wn + 16 * j + (lane & 15);
-                sT[m * ldt + n] = acc.c[i][j][v];
+            for (int u = 0; u < kNA; ++u) {
+                const int e = lane + 64 * u;
+                sAw[(e / TKC) * kLd + e % TKC] = ra[u];
             }
+#pragma unroll
+            for (int u = 0; u < kNB; ++u) {
+                const int e = lane + 64 * u;
+                sBw[(e / TKC) * kLd + e % TKC] = rb[u];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (c + 4 < nch) fetch(la, lb, (c + 4) * TKC, kend, rows, ra, rb);
+#pragma unroll
+            for (int ks = 0; ks < TKC; ks += 4) {
+                const int kk = ks + (lane >> 4);
+                double b[4];
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) b[ct] = sBw[(16 * ct + (lane & 15)) * kLd + kk];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    if (r < rt) {
+                        const double a = sAw[(16 * r + (lane & 15)) * kLd + kk];
+#pragma unroll
+                        for (int ct = 0; ct < 4; ++ct)
+                            acc[r][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct], acc[r][ct],
+                                                                               0, 0, 0);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+
+    // Sum the four waves' accumulators into sOut[m * 65 + n] (m < 16 rt).
+    // Must be called by the whole workgroup; sOut may alias the wave regions.
+    __device__ static __forceinline__ void wave_sum_to_lds(const f64x4 (&acc)[RT][4], int rt,
+                                                           double *sOut)
+    {
+        const int lane = threadIdx.x & 63;
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        for (int step = 0; step < 4; ++step) {
+            if (w == step) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    if (r < rt) {
+#pragma unroll
+                        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int m = 16 * r + mfma_row(lane, v);
+                                const int n = 16 * ct + (lane & 15);
+                                double &o = sOut[m * 65 + n];
+                                o = (step == 0) ? acc[r][ct][v] : o + acc[r][ct][v];
+                            }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
+template <int RT>
+__device__ __forceinline__ void zero_acc(f64x4 (&acc)[RT])
+{
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Visit every accumulator element: f(m, n, value) with m in [0, 16 RT), n in [0, 64).
+template <int RT, class F>
+__device__ __forceinline__ void for_each_acc(const f64x4 (&acc)[RT], int rt_active, F f)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        if (r < rt_active) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f(16 * r + mfma_row(lane, v), 16 * w + (lane & 15), acc[r][v]);
+        }
+    }
 }
 
 }  // namespace cdk

@@ -56,8 +56,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(cd_molecule), sizeof(cd_decomp_opts),
          sizeof(cd_sizes), sizeof(cd_problem), sizeof(cd_jk_problem),
          sizeof(cd_transform_problem));
-  printf("%zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
-         offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
+         offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events), offsetof(cd_decomp_opts, timeline_cap));
   return 0;
 }
 '''
@@ -77,7 +77,8 @@ def test_binding_structs_match_header():
             ctypes.sizeof(cdlib.cd_sizes), ctypes.sizeof(cdlib.cd_problem),
             ctypes.sizeof(cdlib.cd_jk_problem), ctypes.sizeof(cdlib.cd_transform_problem),
             cdlib.cd_problem.status.offset, cdlib.cd_jk_problem.status.offset,
-            cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset]
+            cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset,
+            cdlib.cd_decomp_opts.timeline_cap.offset]
     assert mine == got
 
 
@@ -86,17 +87,17 @@ def test_argument_validation_without_device(lib):
     # null opts / negative count are rejected before any device work
     assert lib.cd_query(None, -1, None, None, None, None) == cdlib.CD_ERR_INVALID_ARG
     mol = cdlib.cd_molecule(-3, None, None)
-    opts = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None)
+    opts = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None, None, 0)
     caps = (ctypes.c_int64 * 1)(10)
     sizes = (cdlib.cd_sizes * 1)()
     assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(opts), caps, sizes,
                         None) == cdlib.CD_ERR_INVALID_ARG
     assert b"n_basis" in lib.cd_last_error()
-    bad = cdlib.cd_decomp_opts(-1.0, 1e-12, 0, None)
+    bad = cdlib.cd_decomp_opts(-1.0, 1e-12, 0, None, None, 0)
     mol = cdlib.cd_molecule(0, None, None)
     assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(bad), caps, sizes,
                         None) == cdlib.CD_ERR_INVALID_ARG
-    nan = cdlib.cd_decomp_opts(float("nan"), 1e-12, 0, None)
+    nan = cdlib.cd_decomp_opts(float("nan"), 1e-12, 0, None, None, 0)
     assert lib.cd_decompose(None, 0, ctypes.byref(nan), None, 0, None) == cdlib.CD_ERR_INVALID_ARG
     # an N = 0 molecule needs no device work: zero rows
     assert lib.cd_query(ctypes.byref(mol), 1, ctypes.byref(opts), caps, sizes, None) == 0

@@ -153,3 +153,26 @@ def test_transform_parity():
     out = cdlib.transform(d, C1, C2)[:M].cpu().numpy()
     exp = oracle.transform(m.n_basis, rp, ref.L, C1, C2)
     assert np.abs(out - exp).max() <= TOL_L
+
+
+# Reduced-precision J/K (FP32 and split 3xBF16 on matrix cores, FP32 inside
+# k-slabs of 32, FP64 across): J is FP64 in every mode; K and the two-electron
+# energy against the oracle's FP64 build from the oracle's vectors.
+TOL_K = {"fp32": 2e-6, "bf16x3": 1e-6}
+TOL_E2 = {"fp32": 2e-5, "bf16x3": 5e-6}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,schwarz", [("C1", 0.0), ("C2", 1e-12)])
+def test_jk_reduced_precision(name, schwarz, prec):
+    m = config_molecule(name)
+    d, M = run_gpu(m, 1e-6, schwarz)
+    rp, ref = check_against_oracle(m, 1e-6, schwarz, d, M)
+    Jr, Kr = oracle.jk_cd(m.n_basis, rp, ref.L, m.C)
+    J, K = cdlib.build_jk(d, m.C, prec)
+    J = J.cpu().numpy()
+    K = K.cpu().numpy()
+    assert np.abs(J - Jr).max() <= TOL_JK
+    assert np.abs(K - Kr).max() <= TOL_K[prec]
+    assert np.array_equal(K, K.T)
+    assert abs(oracle.e2(m.C, J, K) - oracle.e2(m.C, Jr, Kr)) <= TOL_E2[prec]
