@@ -188,6 +188,20 @@ def allocate(xyz, alpha, tau: float, schwarz: float, max_vectors: Optional[int] 
         workspace=torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=device))
 
 
+def allocate_many(mols, tau: float, schwarz: float, max_vectors=None, device="cuda",
+                  stream=None):
+    """Outputs for several molecules plus one shared workspace (batched call).
+
+    ``mols``: sequence of (xyz, alpha).  Returns (decompositions, workspace)."""
+    decs = [allocate(x, a, tau, schwarz, None if max_vectors is None else max_vectors[i],
+                     device, stream) for i, (x, a) in enumerate(mols)]
+    total = sum(int(d.workspace.numel()) for d in decs)
+    for d in decs:
+        d.workspace = torch.empty(0, dtype=torch.uint8, device=device)
+    ws = torch.empty(max(1, total), dtype=torch.uint8, device=device)
+    return decs, ws
+
+
 def problem(d: Decomposition) -> cd_problem:
     return cd_problem(molecule(d.xyz, d.alpha), d.n_rows, d.n_active, d.max_vectors,
                       _ptr(d.row_pair),
@@ -252,6 +266,24 @@ def prepare_jk(d: Decomposition, C, prec: str = "fp64") -> JK:
     _check(load().cd_query_jk(ctypes.byref(p), 1, PRECISIONS[prec], ctypes.byref(ws)))
     w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
     return JK(J, K, st, w, p, C)
+
+
+def prepare_jk_many(decs: Sequence[Decomposition], Cs, prec: str = "fp64"):
+    """J/K outputs for several decompositions plus one shared workspace."""
+    jks = [prepare_jk(d, C, prec) for d, C in zip(decs, Cs)]
+    total = sum(int(j.workspace.numel()) for j in jks)
+    dev = decs[0].L.device
+    for j in jks:
+        j.workspace = torch.empty(0, dtype=torch.uint8, device=dev)
+    return jks, torch.empty(max(1, total), dtype=torch.uint8, device=dev)
+
+
+def run_jk_many(jks: Sequence[JK], workspace: torch.Tensor, prec: str = "fp64",
+                sync: bool = False, stream=None):
+    n = len(jks)
+    arr = (cd_jk_problem * n)(*[j.problem for j in jks])
+    _check(load().cd_build_jk(arr, n, PRECISIONS[prec], CD_SYNC if sync else 0,
+                              _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
 def run_jk(jk: JK, prec: str = "fp64", sync: bool = False, stream=None):

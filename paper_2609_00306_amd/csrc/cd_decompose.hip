@@ -186,13 +186,13 @@ __device__ __forceinline__ bool eligible(double d, double tau, double floor_tol)
     return d >= tau && !(tau <= 0.0 && d <= floor_tol);
 }
 
-__device__ __forceinline__ void stamp(const Step1Params &P, int64_t batch, int what)
+__device__ __forceinline__ void stamp(const Step1Params &P, int g, int64_t batch, int what)
 {
-    if (P.timeline && batch < P.timeline_cap && blockIdx.x == 0 && threadIdx.x == 0)
+    if (P.timeline && batch < P.timeline_cap && g == 0 && threadIdx.x == 0)
         P.timeline[batch * 8 + what] = (int64_t)wall_clock64();
 }
 
-__global__ __launch_bounds__(256) void k_step1(Step1Params P)
+__global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
 {
     __shared__ double sU[S1_UNION];   // phase-dependent: nominations / GEMM staging / candidate block
     __shared__ double sD[SMAX];       // residual diagonal of this workgroup's active rows
@@ -211,8 +211,11 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
     double (*sLq)[QMAX + 1] = reinterpret_cast<double (*)[QMAX + 1]>(sU + QMAX * (QMAX + 1));
 
     const int tid = threadIdx.x;
-    const int G = gridDim.x;
-    const int g = blockIdx.x;
+    int mol = 0;
+    while (mol + 1 < B.count && (int)blockIdx.x >= B.block_begin[mol + 1]) ++mol;
+    const Step1Params &P = B.p[mol];
+    const int G = B.block_begin[mol + 1] - B.block_begin[mol];
+    const int g = (int)blockIdx.x - B.block_begin[mol];
     const int64_t n_act = P.n_act;
     const int64_t ldT = P.max_vectors;
     const int64_t s0 = (int64_t)g * P.slice;
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
     __syncthreads();
 
     for (;; ++batch) {
-        stamp(P, batch, 0);
+        stamp(P, g, batch, 0);
         // ---- this workgroup's eligible rows (compacted list)
         if (tid < 64) {
             int base = 0;
@@ -272,11 +275,11 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
         __syncthreads();
         block_sort_noms(sNom, P2);
         for (int i = tid; i <= CNOM; i += 256) P.noms[g * (CNOM + 1) + i] = sNom[i];
-        if (!grid_barrier(P.gs, G, gen, P.spin_limit)) {
+        if (!grid_barrier(P.gs, G, g, gen, P.spin_limit)) {
             status = 5;
             break;
         }
-        stamp(P, batch, 1);
+        stamp(P, g, batch, 1);
         // ---- union of nominations; bound = first row not nominated anywhere
         const int nu = G * CNOM;
         int U2 = 32;
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             sQrow[rank] = P.rows[P.act_row[me]];
         }
         __syncthreads();
-        stamp(P, batch, 2);
+        stamp(P, g, batch, 2);
 
         // ---- candidate columns on own eligible rows (FP64 MFMA):
         //      C[j][s] = (s|Q_j) - sum_{J<K} L^J_s L^J_{Q_j}
@@ -372,12 +375,12 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             }
             __syncthreads();
         }
-        stamp(P, batch, 3);
-        if (!grid_barrier(P.gs, G, gen, P.spin_limit)) {
+        stamp(P, g, batch, 3);
+        if (!grid_barrier(P.gs, G, g, gen, P.spin_limit)) {
             status = 5;
             break;
         }
-        stamp(P, batch, 4);
+        stamp(P, g, batch, 4);
 
         // ---- in-batch factorisation of the candidate block (every workgroup)
         for (int e = tid; e < nq * nq; e += 256) {
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
             }
         }
         __syncthreads();
-        stamp(P, batch, 5);
+        stamp(P, g, batch, 5);
         const int kb = s_kb;
 
         // ---- apply the accepted pivots to own eligible rows (same arithmetic
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(256) void k_step1(Step1Params P)
         }
         K += kb;
         __syncthreads();
-        stamp(P, batch, 6);
+        stamp(P, g, batch, 6);
         if (s_stop) {
             status = s_status;
             break;
@@ -516,19 +519,25 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
 __host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3 || rt == 5) ? 64 : 32; }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_step2(const RowRec *__restrict__ rows, int64_t n_rows,
-                                               const RowRec *__restrict__ prow,
-                                               const double *__restrict__ dpiv,
-                                               const double *__restrict__ Lp, int64_t ldp,
-                                               const int32_t *__restrict__ pivot_of_row,
-                                               const int64_t *__restrict__ n_vectors,
-                                               double *__restrict__ L, double *__restrict__ diag,
-                                               int64_t *__restrict__ timeline, int64_t tl_cap)
+__global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
 {
-    // optional device-clock stamps of workgroup 0, per 64-vector block
+    int mol = 0;
+    while (mol + 1 < B.count && (int)blockIdx.x >= B.tile_begin[mol + 1]) ++mol;
+    const Step2Mol &Q = B.m[mol];
+    const RowRec *__restrict__ rows = Q.rows;
+    const int64_t n_rows = Q.n_rows;
+    const RowRec *__restrict__ prow = Q.prow;
+    const double *__restrict__ dpiv = Q.dpiv;
+    const double *__restrict__ Lp = Q.Lp;
+    const int64_t ldp = Q.ldp;
+    const int32_t *__restrict__ pivot_of_row = Q.pivot_of_row;
+    double *__restrict__ L = Q.L;
+    double *__restrict__ diag = Q.diag;
+    const int tile = (int)blockIdx.x - B.tile_begin[mol];
+    // optional device-clock stamps of the last problem's first tile, per 64-vector block
+    const bool stamping = B.timeline && mol == B.count - 1 && tile == 0 && threadIdx.x == 0;
     auto mark = [&](int64_t blk, int what) {
-        if (timeline && blockIdx.x == 0 && threadIdx.x == 0 && blk < tl_cap)
-            timeline[blk * 8 + what] = (int64_t)wall_clock64();
+        if (stamping && blk < B.tl_cap) B.timeline[blk * 8 + what] = (int64_t)wall_clock64();
     };
     constexpr int R = 16 * RT;
     constexpr int TKC = s2_tkc(RT);
@@ -545,10 +554,10 @@ __global__ __launch_bounds__(256) void k_step2(const RowRec *__restrict__ rows, 
     double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
 
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t r0 = (int64_t)tile * R;
     const int rows_here = (int)min((int64_t)R, n_rows - r0);
     const int rt = (rows_here + 15) >> 4;
-    const int64_t M = *n_vectors;
+    const int64_t M = *Q.n_vectors;
     double Dfin = 0.0;
     int kp = -1;
     for (int e = tid; e < rows_here; e += 256) sRow[e] = rows[r0 + e];

@@ -118,7 +118,8 @@ __device__ __forceinline__ bool spin_until_eq(unsigned int *addr, unsigned int w
     return true;
 }
 
-__device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned int nblocks,
+// 'nblocks' workgroups take part; 'me' is this workgroup's index among them.
+__device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned int nblocks, unsigned int me,
                                              unsigned int &gen_local, unsigned int spin_limit)
 {
     __shared__ int s_ok;
@@ -127,9 +128,9 @@ __device__ __forceinline__ bool grid_barrier(GridSync *gs, unsigned int nblocks,
     if (threadIdx.x == 0) s_ok = 1;
     __syncthreads();
     if (threadIdx.x == 0)
-        __hip_atomic_store(&gs->arrive[blockIdx.x * 16], want, __ATOMIC_RELEASE,
+        __hip_atomic_store(&gs->arrive[me * 16], want, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
-    if (blockIdx.x == 0) {
+    if (me == 0) {
         for (unsigned int i = threadIdx.x; i < nblocks; i += blockDim.x)
             if (!spin_until_eq(&gs->arrive[i * 16], want, &gs->abort, spin_limit)) s_ok = 0;
         __syncthreads();

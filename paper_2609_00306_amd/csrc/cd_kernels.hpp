@@ -34,4 +34,36 @@ struct Step1Params {
     int64_t timeline_cap;
 };
 
+// Up to kStep1Batch decompositions share one cooperative launch; problem i
+// owns the workgroups [block_begin[i], block_begin[i + 1]) and its own
+// barrier, so small molecules run side by side on the GPU.
+constexpr int kStep1Batch = 16;
+struct Step1Batch {
+    int32_t count;
+    int32_t block_begin[kStep1Batch + 1];
+    Step1Params p[kStep1Batch];
+};
+
+// All-row solve of up to kStep2Batch problems in one launch.
+constexpr int kStep2Batch = 16;
+struct Step2Mol {
+    const RowRec *rows;
+    int64_t n_rows;
+    const RowRec *prow;
+    const double *dpiv;
+    const double *Lp;
+    int64_t ldp;
+    const int32_t *pivot_of_row;
+    const int64_t *n_vectors;
+    double *L;
+    double *diag;
+};
+struct Step2Batch {
+    int32_t count;
+    int32_t tile_begin[kStep2Batch + 1];
+    Step2Mol m[kStep2Batch];
+    int64_t *timeline;   // optional stamps of the last problem's first tile
+    int64_t tl_cap;
+};
+
 }  // namespace cdk

@@ -168,16 +168,18 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
 
 // Row tile of the all-row solve: the smallest 16-row multiple (2..8) that
 // gives at most one tile per compute unit, else 8 (128 rows).
-cd_status launch_step2(const DecompWs &w, const cd_problem &p, int64_t n, int64_t mv, int n_cu,
-                       hipStream_t st, int64_t *timeline, int64_t tl_cap)
+cd_status launch_step2_batch(Step2Batch &B, int64_t total_rows, int n_cu, hipStream_t st)
 {
-    int rt = (int)std::min<int64_t>(8, std::max<int64_t>(2, blocks_of(n, 16 * (int64_t)n_cu)));
-    const unsigned grid = (unsigned)blocks_of(n, 16 * rt);
-#define CD_STEP2(RT)                                                                        \
-    case RT:                                                                                \
-        k_step2<RT><<<grid, 256, 0, st>>>(w.rows, n, w.prow, w.dpiv, w.Lp, mv,               \
-                                          w.pivot_of_row, p.n_vectors, p.L, p.diag,         \
-                                          timeline, tl_cap);                                \
+    const int rt = (int)std::min<int64_t>(
+        8, std::max<int64_t>(2, blocks_of(total_rows, 16 * (int64_t)n_cu)));
+    B.tile_begin[0] = 0;
+    for (int i = 0; i < B.count; ++i)
+        B.tile_begin[i + 1] = B.tile_begin[i] + (int32_t)blocks_of(B.m[i].n_rows, 16 * rt);
+    const unsigned grid = (unsigned)B.tile_begin[B.count];
+    if (grid == 0) return CD_OK;
+#define CD_STEP2(RT)                                 \
+    case RT:                                         \
+        k_step2<RT><<<grid, 256, 0, st>>>(B);        \
         break;
     switch (rt) {
         CD_STEP2(2)
@@ -190,6 +192,40 @@ cd_status launch_step2(const DecompWs &w, const cd_problem &p, int64_t n, int64_
     }
 #undef CD_STEP2
     return check_launch("all-row solve");
+}
+
+Step1Params step1_params(const cd_problem &p, const DecompWs &w, const cd_decomp_opts *o,
+                         int slice, bool with_timeline)
+{
+    Step1Params P1{};
+    P1.rows = w.rows;
+    P1.act_row = w.act_row;
+    P1.n_act_dev = w.totals + 1;
+    P1.n_act = p.n_active;
+    P1.D_act = w.D_act;
+    P1.LT_act = w.LT_act;
+    P1.n_rows_dev = w.totals;
+    P1.Cbuf = w.Cbuf;
+    P1.noms = w.noms;
+    P1.gs = w.gs;
+    P1.pivots = p.pivots;
+    P1.piv_slot = w.piv_slot;
+    P1.dpiv = w.dpiv;
+    P1.pivot_of_row = w.pivot_of_row;
+    P1.n_vectors = p.n_vectors;
+    P1.status = p.status;
+    P1.tau = o->tau;
+    P1.d1max_bits = w.d1max;
+    P1.n_rows = p.n_rows;
+    P1.max_vectors = p.max_vectors;
+    P1.q = QMAX;
+    P1.slice = slice;
+    P1.spin_limit = 1u << 22;
+    const bool tl = with_timeline && o->timeline;
+    P1.timeline = tl ? o->timeline + 1 : nullptr;
+    P1.timeline_count = tl ? o->timeline : nullptr;
+    P1.timeline_cap = tl ? o->timeline_cap : 0;
+    return P1;
 }
 
 }  // namespace
@@ -264,72 +300,128 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     DevInfo di;
     if ((s = dev_info(di))) return s;
 
-    char *wbase = static_cast<char *>(ws);
+    auto record = [&](int k) -> cd_status {
+        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[k]), st) != hipSuccess)
+            return fail(CD_ERR_INVALID_ARG, "timing event %d could not be recorded", k);
+        return CD_OK;
+    };
+    std::vector<DecompWs> W(count);
+    {
+        char *wbase = static_cast<char *>(ws);
+        for (int32_t i = 0; i < count; ++i) {
+            const cd_problem &p = probs[i];
+            W[i] = carve_decomp(wbase, p.mol.n_basis, p.n_rows, p.n_active, p.max_vectors);
+            wbase += W[i].bytes;
+        }
+    }
+    // ---- pair table, diagonal, screening
+    if ((s = record(0))) return s;
     for (int32_t i = 0; i < count; ++i) {
         const cd_problem &p = probs[i];
-        const int64_t N = p.mol.n_basis, n = p.n_rows, na = p.n_active, mv = p.max_vectors;
-        DecompWs w = carve_decomp(wbase, N, n, na, mv);
-        wbase += w.bytes;
-        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[0]), st) != hipSuccess)
-            return fail(CD_ERR_INVALID_ARG, "timing event 0 could not be recorded");
-        k_init_decompose<<<1, 256, 0, st>>>(w.gs, p.status, p.n_vectors, w.d1max);
-        if ((s = launch_setup(p.mol, opts, w, p.row_pair, n, na, st, true))) return s;
-        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[1]), st) != hipSuccess)
-            return fail(CD_ERR_INVALID_ARG, "timing event 1 could not be recorded");
-        if (na > 0 && mv > 0) {
-            int G = (int)std::min<int64_t>(di.n_cu, std::max<int64_t>(1, blocks_of(na, 32)));
-            G = std::max<int>(G, (int)blocks_of(na, SMAX));
-            G = std::min(G, S1_MAXG);
-            const int slice = (int)blocks_of(na, G);
-            if (slice > SMAX || G > di.n_cu * std::max(1, di.coop_blocks_per_cu))
-                return fail(CD_ERR_UNSUPPORTED, "%lld active rows exceed the step-1 capacity",
-                            (long long)na);
-            Step1Params P1;
-            P1.rows = w.rows;
-            P1.act_row = w.act_row;
-            P1.n_act_dev = w.totals + 1;
-            P1.n_act = na;
-            P1.D_act = w.D_act;
-            P1.LT_act = w.LT_act;
-            P1.n_rows_dev = w.totals;
-            P1.Cbuf = w.Cbuf;
-            P1.noms = w.noms;
-            P1.gs = w.gs;
-            P1.pivots = p.pivots;
-            P1.piv_slot = w.piv_slot;
-            P1.dpiv = w.dpiv;
-            P1.pivot_of_row = w.pivot_of_row;
-            P1.n_vectors = p.n_vectors;
-            P1.status = p.status;
-            P1.tau = opts->tau;
-            P1.d1max_bits = w.d1max;
-            P1.n_rows = n;
-            P1.max_vectors = mv;
-            P1.q = QMAX;
-            P1.slice = slice;
-            P1.spin_limit = 1u << 22;
-            P1.timeline = opts->timeline ? opts->timeline + 1 : nullptr;
-            P1.timeline_count = opts->timeline;
-            P1.timeline_cap = opts->timeline ? opts->timeline_cap : 0;
-            void *args[] = {&P1};
-            hipError_t e = hipLaunchCooperativeKernel((const void *)k_step1, dim3(G), dim3(256),
-                                                      args, 0, st);
-            if (e != hipSuccess)
-                return fail(CD_ERR_DEVICE, "step-1 launch (%d workgroups): %s", G,
-                            hipGetErrorString(e));
-            k_gather_pivots<<<(unsigned)mv, 256, 0, st>>>(w.LT_act, mv, w.piv_slot, p.pivots,
-                                                          w.rows, p.n_vectors, w.Lp, mv, w.prow);
-            if ((s = check_launch("pivot gather"))) return s;
-        }
-        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[2]), st) != hipSuccess)
-            return fail(CD_ERR_INVALID_ARG, "timing event 2 could not be recorded");
-        if (n > 0) {
-            int64_t *tl2 = opts->timeline ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
-            if ((s = launch_step2(w, p, n, mv, di.n_cu, st, tl2, opts->timeline_cap))) return s;
-        }
-        if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[3]), st) != hipSuccess)
-            return fail(CD_ERR_INVALID_ARG, "timing event 3 could not be recorded");
+        k_init_decompose<<<1, 256, 0, st>>>(W[i].gs, p.status, p.n_vectors, W[i].d1max);
+        if ((s = launch_setup(p.mol, opts, W[i], p.row_pair, p.n_rows, p.n_active, st, true)))
+            return s;
     }
+    if ((s = record(1))) return s;
+
+    // ---- pivot selection: problems share cooperative launches (largest first)
+    const int capacity = std::min(di.n_cu * std::max(1, di.coop_blocks_per_cu), kMaxGridBlocks * 64);
+    const int gcap = std::min(di.n_cu, S1_MAXG);
+    std::vector<int> order;
+    for (int32_t i = 0; i < count; ++i)
+        if (probs[i].n_active > 0 && probs[i].max_vectors > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return probs[a].n_active > probs[b].n_active; });
+    auto gmin = [&](int i) { return (int)blocks_of(probs[i].n_active, SMAX); };
+    auto gmax = [&](int i) {
+        int g = (int)std::min<int64_t>(gcap, std::max<int64_t>(1, blocks_of(probs[i].n_active, 32)));
+        return std::max(g, gmin(i));
+    };
+    for (int i : order)
+        if (gmin(i) > gcap)
+            return fail(CD_ERR_UNSUPPORTED, "problem %d: %lld active rows exceed the step-1 capacity",
+                        i, (long long)probs[i].n_active);
+    size_t pos = 0;
+    while (pos < order.size()) {
+        std::vector<int> grp;
+        int sum_min = 0;
+        while (pos < order.size() && (int)grp.size() < kStep1Batch &&
+               sum_min + gmin(order[pos]) <= capacity) {
+            sum_min += gmin(order[pos]);
+            grp.push_back(order[pos++]);
+        }
+        // workgroups per problem: as many as useful, scaled down to fit the GPU
+        std::vector<int> G(grp.size());
+        int tot = 0;
+        for (size_t j = 0; j < grp.size(); ++j) tot += (G[j] = gmax(grp[j]));
+        if (tot > capacity) {
+            const int64_t want = tot;
+            for (size_t j = 0; j < grp.size(); ++j)
+                G[j] = std::max(gmin(grp[j]), (int)((int64_t)G[j] * capacity / want));
+            tot = 0;
+            for (size_t j = 0; j < grp.size(); ++j) tot += G[j];
+            while (tot > capacity) {
+                size_t big = 0;
+                for (size_t j = 0; j < grp.size(); ++j)
+                    if (G[j] - gmin(grp[j]) > G[big] - gmin(grp[big])) big = j;
+                if (G[big] <= gmin(grp[big])) break;
+                --G[big];
+                --tot;
+            }
+        }
+        Step1Batch B{};
+        B.count = (int32_t)grp.size();
+        B.block_begin[0] = 0;
+        for (size_t j = 0; j < grp.size(); ++j) {
+            const int i = grp[j];
+            const int slice = (int)blocks_of(probs[i].n_active, G[j]);
+            B.p[j] = step1_params(probs[i], W[i], opts, slice, i == count - 1);
+            B.block_begin[j + 1] = B.block_begin[j] + (int32_t)blocks_of(probs[i].n_active, slice);
+        }
+        void *args[] = {&B};
+        const int nblk = B.block_begin[B.count];
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_step1, dim3(nblk), dim3(256),
+                                                  args, 0, st);
+        if (e != hipSuccess)
+            return fail(CD_ERR_DEVICE, "pivot-selection launch (%d workgroups): %s", nblk,
+                        hipGetErrorString(e));
+        for (int i : grp) {
+            const cd_problem &p = probs[i];
+            k_gather_pivots<<<(unsigned)p.max_vectors, 256, 0, st>>>(
+                W[i].LT_act, p.max_vectors, W[i].piv_slot, p.pivots, W[i].rows, p.n_vectors,
+                W[i].Lp, p.max_vectors, W[i].prow);
+        }
+        if ((s = check_launch("pivot gather"))) return s;
+    }
+    if ((s = record(2))) return s;
+
+    // ---- all-row solve, up to kStep2Batch problems per launch
+    for (int32_t i0 = 0; i0 < count; i0 += kStep2Batch) {
+        Step2Batch B{};
+        int64_t rows = 0;
+        for (int32_t i = i0; i < count && B.count < kStep2Batch; ++i) {
+            const cd_problem &p = probs[i];
+            if (p.n_rows == 0) continue;
+            Step2Mol &q = B.m[B.count++];
+            q.rows = W[i].rows;
+            q.n_rows = p.n_rows;
+            q.prow = W[i].prow;
+            q.dpiv = W[i].dpiv;
+            q.Lp = W[i].Lp;
+            q.ldp = p.max_vectors;
+            q.pivot_of_row = W[i].pivot_of_row;
+            q.n_vectors = p.n_vectors;
+            q.L = p.L;
+            q.diag = p.diag;
+            rows += p.n_rows;
+        }
+        const bool last = (i0 + kStep2Batch >= count);
+        B.timeline = (last && opts->timeline) ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
+        B.tl_cap = opts->timeline ? opts->timeline_cap : 0;
+        if (B.count > 0 && (s = launch_step2_batch(B, rows, di.n_cu, st))) return s;
+    }
+    if ((s = record(3))) return s;
+
     if (opts->flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)
             return fail(CD_ERR_DEVICE, "stream synchronise failed");

@@ -176,3 +176,32 @@ def test_jk_reduced_precision(name, schwarz, prec):
     assert np.abs(K - Kr).max() <= TOL_K[prec]
     assert np.array_equal(K, K.T)
     assert abs(oracle.e2(m.C, J, K) - oracle.e2(m.C, Jr, Kr)) <= TOL_E2[prec]
+
+
+def test_batched_decomposition_matches_single_and_oracle():
+    # 20 molecules of uneven size in one call: more than one shared launch
+    mols = [make_molecule(3 + (7 * i) % 9, 3.0 + 0.4 * (i % 5), (0.3, 1.1, 4.0), 2, seed=500 + i)
+            for i in range(20)]
+    tau = 1e-6
+    decs, ws = cdlib.allocate_many([(m.xyz, m.alpha) for m in mols], tau, 0.0)
+    cdlib.run_decompose(decs, tau, 0.0, workspace=ws)
+    torch.cuda.synchronize()
+    for m, d in zip(mols, decs):
+        M = d.M()
+        check_against_oracle(m, tau, 0.0, d, M)
+        single, M1 = run_gpu(m, tau, 0.0)
+        assert M1 == M
+        assert torch.equal(single.pivots[:M], d.pivots[:M])
+        assert (single.L[:M] - d.L[:M]).abs().max().item() <= 1e-12
+
+
+def test_batched_jk_matches_single():
+    mols = [make_molecule(4 + i, 4.0, (0.3, 1.1, 4.0), 3, seed=700 + i) for i in range(5)]
+    decs, ws = cdlib.allocate_many([(m.xyz, m.alpha) for m in mols], 1e-6, 1e-12)
+    cdlib.run_decompose(decs, 1e-6, 1e-12, workspace=ws)
+    jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], "fp64")
+    cdlib.run_jk_many(jks, jws, "fp64")
+    torch.cuda.synchronize()
+    for m, d, jk in zip(mols, decs, jks):
+        J, K = cdlib.build_jk(d, m.C, "fp64")
+        assert torch.equal(J, jk.J) and torch.equal(K, jk.K)
