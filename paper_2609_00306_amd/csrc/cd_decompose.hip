@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
 // diagonal (R4: a row is zeroed when it is chosen as pivot).
 // k-chunk of the all-row solve: 64 where the prefetch registers still fit
 // without spilling (checked with the compiler's resource report), else 32.
-__host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3 || rt == 5) ? 64 : 32; }
+__host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3) ? 64 : 32; }
 
 template <int RT>
 __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)

@@ -234,10 +234,10 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
     gemm_tile<4, JK_TKC, true, true>(
         0, deg, 4,
         [&](int64_t k, int m) -> double {
-            return (p0 + m < M) ? LT[(int64_t)nb_r[j0 + k] * ldt + p0 + m] : 0.0;
+            return LT[(int64_t)nb_r[j0 + k] * ldt + min(p0 + m, M - 1)];
         },
         [&](int64_t k, int n) -> double {
-            return (n0 + n < ncol) ? C[(int64_t)nb_s[j0 + k] * ncol + n0 + n] : 0.0;
+            return C[(int64_t)nb_s[j0 + k] * ncol + min(n0 + n, ncol - 1)];
         },
         acc, sA, sB);
     double *out = Y + (int64_t)mu * ldy;
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
     zero_acc(acc);
     gemm_tile<4, JK_TKC, false, false>(
         kb, ke, 4,
-        [&](int64_t k, int m) -> double { return (m0 + m < N) ? X[(m0 + m) * ldx + k] : 0.0; },
-        [&](int64_t k, int n) -> double { return (n0 + n < N) ? X[(n0 + n) * ldx + k] : 0.0; },
+        [&](int64_t k, int m) -> double { return X[min(m0 + m, N - 1) * ldx + k]; },
+        [&](int64_t k, int n) -> double { return X[min(n0 + n, N - 1) * ldx + k]; },
         acc, sA, sB);
     double *out = Kp + (int64_t)s * N * N;
     for_each_acc(acc, 4, [&](int m, int n, double v) {
@@ -278,93 +278,6 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
     });
 }
 
-
-// Half transform Y^P = Lt^P C  (Lt^P the unpacked symmetric N x N vector):
-//   Y^P[mu][i] = sum_sigma Lt^P[sigma][mu] C[sigma][i]
-// tile: m = mu, n = i, k = sigma.  Output layout:
-//   TRANSPOSED: Y[(P * ncol + i) * N + mu]   (k-major rows for the K product)
-//   else      : Y[(P * N + mu) * ncol + i]
-template <bool TRANSPOSED>
-__global__ __launch_bounds__(256) void k_half(const double *__restrict__ L, int64_t n_rows,
-                                              const int32_t *__restrict__ rowof, int N,
-                                              const double *__restrict__ C, int ncol,
-                                              const int64_t *__restrict__ n_vectors,
-                                              int64_t p_base, double *__restrict__ Y)
-{
-    __shared__ double sU[(2 * JKS::kSize > 64 * 65) ? 2 * JKS::kSize : 64 * 65];
-    double *sA = sU, *sB = sU + JKS::kSize;
-    double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
-    const int64_t Pv = p_base + blockIdx.z;
-    if (Pv >= *n_vectors) return;
-    const int m0 = blockIdx.x * 64;
-    const int n0 = blockIdx.y * 64;
-    const double *Lv = L + Pv * n_rows;
-    f64x4 acc[4];
-    zero_acc(acc);
-    gemm_tile<4, JK_TKC, true, true>(
-        0, N, 4,
-        [&](int64_t k, int m) -> double {
-            int mu = m0 + m;
-            if (mu >= N) return 0.0;
-            int32_t r = rowof[k * N + mu];
-            return (r >= 0) ? Lv[r] : 0.0;
-        },
-        [&](int64_t k, int n) -> double {
-            int i = n0 + n;
-            return (i < ncol) ? C[k * ncol + i] : 0.0;
-        },
-        acc, sA, sB);
-    for_each_acc(acc, 4, [&](int m, int n, double v) { sT[m][n] = v; });
-    __syncthreads();
-    const int64_t Yb = (Pv - p_base);
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        if (TRANSPOSED) {
-            int n = e >> 6, m = e & 63;
-            if (m0 + m < N && n0 + n < ncol)
-                Y[(Yb * ncol + n0 + n) * (int64_t)N + m0 + m] = sT[m][n];
-        } else {
-            int m = e >> 6, n = e & 63;
-            if (m0 + m < N && n0 + n < ncol)
-                Y[(Yb * N + m0 + m) * (int64_t)ncol + n0 + n] = sT[m][n];
-        }
-    }
-}
-
-// Partial K over a k-slab: Kp[s][mu][nu] = sum_{k in slab s} X[k][mu] X[k][nu]
-// for lower tile pairs (tm >= tn); X is [nk][N].
-__global__ __launch_bounds__(256) void k_syrk(const double *__restrict__ X, int N,
-                                              const int64_t *__restrict__ n_vectors, int ncol,
-                                              int64_t p_base, int64_t p_count, int nsplit,
-                                              double *__restrict__ Kp)
-{
-    __shared__ double sU[2 * JKS::kSize];
-    double *sA = sU, *sB = sU + JKS::kSize;
-    int t = blockIdx.x;
-    int tm = 0;
-    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
-    int tn = t - tm * (tm + 1) / 2;
-    const int s = blockIdx.y;
-    int64_t M = *n_vectors - p_base;
-    if (M > p_count) M = p_count;
-    if (M < 0) M = 0;
-    const int64_t nk = M * ncol;
-    int64_t per = (nk + nsplit - 1) / nsplit;
-    per = (per + JK_TKC - 1) / JK_TKC * JK_TKC;
-    const int64_t kb = s * per;
-    const int64_t ke = (kb + per < nk) ? kb + per : nk;
-    f64x4 acc[4];
-    zero_acc(acc);
-    const int m0 = tm * 64, n0 = tn * 64;
-    gemm_tile<4, JK_TKC, true, true>(
-        kb, ke, 4,
-        [&](int64_t k, int m) -> double { return (m0 + m < N) ? X[k * N + m0 + m] : 0.0; },
-        [&](int64_t k, int n) -> double { return (n0 + n < N) ? X[k * N + n0 + n] : 0.0; },
-        acc, sA, sB);
-    double *out = Kp + (int64_t)s * N * N;
-    for_each_acc(acc, 4, [&](int m, int n, double v) {
-        if (m0 + m < N && n0 + n < N) out[(int64_t)(m0 + m) * N + n0 + n] = v;
-    });
-}
 
 // K[mu][nu] (+)= sum_s Kp[s][max][min]  -- exactly symmetric
 __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int accumulate,
@@ -396,8 +309,8 @@ __global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int64
     zero_acc(acc);
     gemm_tile<4, JK_TKC, true, true>(
         0, N, 4,
-        [&](int64_t k, int m) -> double { return (m0 + m < p) ? C1[k * p + m0 + m] : 0.0; },
-        [&](int64_t k, int n) -> double { return (n0 + n < q) ? Yp[k * ldy + n0 + n] : 0.0; },
+        [&](int64_t k, int m) -> double { return C1[k * p + min(m0 + m, p - 1)]; },
+        [&](int64_t k, int n) -> double { return Yp[k * ldy + min(n0 + n, q - 1)]; },
         acc, sA, sB);
     double *out = Lmo + Pv * (int64_t)p * q;
     for_each_acc(acc, 4, [&](int m, int n, double v) {

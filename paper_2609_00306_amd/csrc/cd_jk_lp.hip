@@ -42,13 +42,20 @@ __device__ __forceinline__ void split3(double x, __bf16 &b0, __bf16 &b1, __bf16 
 }
 
 // LDS staging of one k-chunk for a 64 x 64 tile.
-//  F32 : sA32[k][m], sB32[k][n]                (k-major)
+//  F32 : k-major sources   sA32[k][m], sB32[k][n]
+//        k-contiguous (KC) sA32[m][k], sB32[n][k]  (rows padded to TKC + 1)
 //  BF16: sAp[p][m][k], sBp[p][n][k] p = 0..2    (k contiguous, 8 per lane load)
+// so that the LDS writes follow the contiguous index of the global loads.
 template <int MODE, bool KC = false>
 struct LpStage {
     static constexpr int kBf16Ld = LP_TKC + 8;   // padded row (bf16 elements)
-    static constexpr int kBytes = (MODE == LP_F32) ? 2 * LP_TKC * 64 * 4
+    static constexpr int kF32Ld = LP_TKC + 1;    // padded row (KC, FP32)
+    static constexpr int kBytes = (MODE == LP_F32) ? 2 * 64 * (LP_TKC + 1) * 4
                                                    : 2 * 3 * 64 * kBf16Ld * 2;
+    __device__ static __forceinline__ int f32_index(int k, int m)
+    {
+        return KC ? m * kF32Ld + k : k * 64 + m;
+    }
     static constexpr int kPer = LP_TKC * 64 / 256;   // elements per thread per operand
 
     // element e of a chunk -> (k, m), following the operand's contiguous index:
@@ -73,8 +80,10 @@ struct LpStage {
             int k, m;
             coord(e, k, m);
             const bool ok = k0 + k < kend;
-            ra[u] = ok ? la(k0 + k, m) : 0.0;
-            rb[u] = ok ? lb(k0 + k, m) : 0.0;
+            const int64_t kk = ok ? k0 + k : kend - 1;   // always valid: load, then select
+            const double va = la(kk, m), vb = lb(kk, m);
+            ra[u] = ok ? va : 0.0;
+            rb[u] = ok ? vb : 0.0;
         }
     }
     __device__ static __forceinline__ void put(unsigned char *smem, const double (&ra)[kPer],
@@ -82,13 +91,13 @@ struct LpStage {
     {
         if (MODE == LP_F32) {
             float *sA = reinterpret_cast<float *>(smem);
-            float *sB = sA + LP_TKC * 64;
+            float *sB = sA + 64 * kF32Ld;
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 int k, m;
                 coord(threadIdx.x + 256 * u, k, m);
-                sA[k * 64 + m] = (float)ra[u];
-                sB[k * 64 + m] = (float)rb[u];
+                sA[f32_index(k, m)] = (float)ra[u];
+                sB[f32_index(k, m)] = (float)rb[u];
             }
         } else {
             __bf16 *sA = reinterpret_cast<__bf16 *>(smem);
@@ -115,14 +124,14 @@ struct LpStage {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         if (MODE == LP_F32) {
             const float *sA = reinterpret_cast<const float *>(smem);
-            const float *sB = sA + LP_TKC * 64;
+            const float *sB = sA + 64 * kF32Ld;
 #pragma unroll
             for (int ks = 0; ks < LP_TKC; ks += 4) {
                 const int kk = ks + (lane >> 4);
-                const float b = sB[kk * 64 + 16 * w + (lane & 15)];
+                const float b = sB[f32_index(kk, 16 * w + (lane & 15))];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float a = sA[kk * 64 + 16 * r + (lane & 15)];
+                    const float a = sA[f32_index(kk, 16 * r + (lane & 15))];
                     acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r], 0, 0, 0);
                 }
             }
@@ -209,10 +218,10 @@ __global__ __launch_bounds__(256) void k_half_sparse_lp(const double *__restrict
     lp_tile<MODE, false>(
         0, deg,
         [&](int64_t k, int m) -> double {
-            return (p0 + m < M) ? LT[(int64_t)nb_r[j0 + k] * ldt + p0 + m] : 0.0;
+            return LT[(int64_t)nb_r[j0 + k] * ldt + min(p0 + m, M - 1)];
         },
         [&](int64_t k, int n) -> double {
-            return (n0 + n < ncol) ? C[(int64_t)nb_s[j0 + k] * ncol + n0 + n] : 0.0;
+            return C[(int64_t)nb_s[j0 + k] * ncol + min(n0 + n, ncol - 1)];
         },
         acc, smem);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -250,12 +259,8 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
     double acc[4][4] = {};
     lp_tile<MODE, true>(
         kb, ke,
-        [&](int64_t k, int m) -> double {
-            return (m0 + m < N) ? (double)X[(m0 + m) * ldx + k] : 0.0;
-        },
-        [&](int64_t k, int n) -> double {
-            return (n0 + n < N) ? (double)X[(n0 + n) * ldx + k] : 0.0;
-        },
+        [&](int64_t k, int m) -> double { return (double)X[min(m0 + m, N - 1) * ldx + k]; },
+        [&](int64_t k, int n) -> double { return (double)X[min(n0 + n, N - 1) * ldx + k]; },
         acc, smem);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double *out = Kp + (int64_t)s * N * N;

@@ -205,3 +205,37 @@ def test_batched_jk_matches_single():
     for m, d, jk in zip(mols, decs, jks):
         J, K = cdlib.build_jk(d, m.C, "fp64")
         assert torch.equal(J, jk.J) and torch.equal(K, jk.K)
+
+
+@pytest.mark.parametrize("name", ["C5"])
+def test_large_workload_properties(name):
+    """At the 1200-function size the full oracle run is too slow for a test;
+    check what holds at any size (Sec. 2): every final residual < tau, the
+    reconstruction error of sampled integrals <= tau (Cauchy-Schwarz), and
+    each vector vanishing at earlier pivot rows; sampled rows against the
+    oracle's exact integrals."""
+    m = config_molecule(name)
+    tau = 1e-6
+    d, M = run_gpu(m, tau, 1e-12)
+    assert int(d.status.item()) == 0 and M > 0
+    rp, _ = oracle.rows(m.xyz, m.alpha, 1e-12)
+    assert np.array_equal(rp, d.row_pair.cpu().numpy())
+    diag = d.diag.cpu().numpy()
+    assert diag.max() < tau and diag.min() >= -1e-12
+    L = d.L[:M].cpu().numpy()
+    piv = d.pivots[:M].cpu().numpy()
+    assert len(np.unique(piv)) == M
+    rng = np.random.default_rng(12)
+    rows = rng.integers(0, d.n_rows, 64)
+    cols = np.concatenate([rng.integers(0, d.n_rows, 32), piv[rng.integers(0, M, 32)]])
+    for r in rows[:16]:
+        for c in cols:
+            mu, nu = oracle.unpack_pair(int(rp[r]))
+            sg, rh = oracle.unpack_pair(int(rp[c]))
+            a = oracle.eri(m.xyz, m.alpha, mu, nu, sg, rh)
+            assert abs(a - float(L[:, r] @ L[:, c])) <= tau
+    for K in rng.integers(1, M, 50):
+        assert np.abs(L[K, piv[:K]]).max() <= 1e-9
+    # the pivot values L^K at its own pivot row squared are non-increasing
+    dk = np.array([L[K, piv[K]] ** 2 for K in range(M)])
+    assert np.all(np.diff(dk) <= 1e-9 * dk[:-1])
