@@ -508,12 +508,53 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
     if (threadIdx.x == 0) prow[Kc] = rows[pivots[Kc]];
 }
 
+// Inverse-transposed pivot blocks.  For the 64 vectors K = b0 + j of one
+// block let S be the lower-triangular 64 x 64 matrix S[j][i] = L^{b0+i} at
+// pivot row P_{b0+j} (i < j) and S[j][j] = sqrt(d_{b0+j}) (the divisor of the
+// vector equation of Sec. 2).  Then the block of vectors obeys T = L_blk S^T,
+// T being the right-hand side (r|P_K) - sum over earlier blocks, so
+// L_blk = T G with G = S^{-T} (upper triangular).  Lane c solves S x = e_c by
+// forward substitution; x is row c of G.  In a ragged last block the unused
+// part of S is the identity.
+__global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__ Lp, int64_t ldp,
+                                                      const double *__restrict__ dpiv,
+                                                      const int64_t *__restrict__ n_vectors,
+                                                      double *__restrict__ G)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * 64;
+    const int64_t M = *n_vectors;
+    if (b0 >= M) return;
+    const int nb = (int)min((int64_t)64, M - b0);
+    __shared__ double sS[64][65];
+    __shared__ double sX[64][65];   // sX[j][c]: entry j of the solution for e_c
+    const int c = threadIdx.x;
+    for (int j = 0; j < 64; ++j) {
+        double v = 0.0;
+        if (c < j) {
+            if (j < nb) v = Lp[(b0 + j) * ldp + b0 + c];
+        } else if (c == j) {
+            v = (j < nb) ? sqrt(dpiv[b0 + j]) : 1.0;
+        }
+        sS[j][c] = v;
+    }
+    __syncthreads();
+    for (int j = 0; j < 64; ++j) {
+        double a = (j == c) ? 1.0 : 0.0;
+        for (int i = c; i < j; ++i) a = fma(-sS[j][i], sX[i][c], a);
+        sX[j][c] = (j < c) ? 0.0 : a / sS[j][j];
+    }
+    __syncthreads();
+    double *g = G + (int64_t)blockIdx.x * 4096;
+    for (int r = 0; r < 64; ++r) g[r * 64 + c] = sX[c][r];
+}
+
 // ---------------------------------------------------------------- step 2
 // Every row r: L[K][r] = [ (r|P_K) - sum_{J<K} L[J][r] Lp[K][J] ] / sqrt(d_K),
 // blocked over 64 vectors.  The off-block sum is an FP64 MFMA product over a
-// (16 RT)-row tile, the in-block part a substitution in 16-column panels
-// with the ERIs (r|P_K) generated in between.  Also the final residual
-// diagonal (R4: a row is zeroed when it is chosen as pivot).
+// (16 RT)-row tile; the ERIs (r|P_K) are generated into the right-hand side,
+// and the in-block triangular part is a second MFMA product with the block's
+// inverse-transposed pivot block G.  Also the final residual diagonal (R4: a
+// row is zeroed when it is chosen as pivot).
 // k-chunk of the all-row solve: 64 where the prefetch registers still fit
 // without spilling (checked with the compiler's resource report), else 32.
 __host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3) ? 64 : 32; }
@@ -527,9 +568,9 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
     const RowRec *__restrict__ rows = Q.rows;
     const int64_t n_rows = Q.n_rows;
     const RowRec *__restrict__ prow = Q.prow;
-    const double *__restrict__ dpiv = Q.dpiv;
     const double *__restrict__ Lp = Q.Lp;
     const int64_t ldp = Q.ldp;
+    const double *__restrict__ Ginv = Q.Ginv;
     const int32_t *__restrict__ pivot_of_row = Q.pivot_of_row;
     double *__restrict__ L = Q.L;
     double *__restrict__ diag = Q.diag;
@@ -545,8 +586,7 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
     using SB = OperandStage<64, TKC, false>;
     constexpr int kUnion = (SA::kSize + SB::kSize > R * 65) ? SA::kSize + SB::kSize : R * 65;
     __shared__ double sU[kUnion];
-    __shared__ double sLb[64][65];
-    __shared__ double sRs[64];
+    __shared__ double sG[64 * 64];
     __shared__ RowRec sPr[64];
     __shared__ RowRec sRow[R];
     double *sA = sU;
@@ -580,15 +620,11 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
                 return (n < nb) ? Lp[(b0 + n) * ldp + k] : 0.0;
             },
             acc, sA, sB);
-        for (int e = tid; e < 64; e += 256) {
-            if (e < nb) {
-                sPr[e] = prow[b0 + e];
-                sRs[e] = 1.0 / sqrt(dpiv[b0 + e]);
-            }
-        }
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int j = e >> 6, jj = e & 63;
-            sLb[jj][j] = (jj < j && j < nb) ? Lp[(b0 + j) * ldp + b0 + jj] : 0.0;
+        for (int e = tid; e < 64; e += 256)
+            if (e < nb) sPr[e] = prow[b0 + e];
+        {
+            const double *g = Ginv + blk * 4096;
+            for (int e = tid; e < 64 * 64; e += 256) sG[e] = g[e];
         }
         mark(blk, 1);
         for_each_acc(acc, rt, [&](int m, int n, double v) { sT[m][n] = v; });
@@ -601,39 +637,31 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
         }
         __syncthreads();
         mark(blk, 3);
-        // in-block substitution, 16-column panels
-        for (int jb = 0; jb < nb; jb += 16) {
-            const int je = min(jb + 16, nb);
-            if (tid < rows_here) {
-                double lv[16];
+        // in-block part: L_blk = T G (G upper triangular, 64 x 64)
+        {
+            zero_acc(acc);
+            const int lane = tid & 63, w = tid >> 6;
+#pragma unroll 4
+            for (int ks = 0; ks < 64; ks += 4) {
+                const int kk = ks + (lane >> 4);
+                const double b = sG[kk * 64 + 16 * w + (lane & 15)];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int j = jb + u;
-                    if (j < je) {
-                        double a = sT[tid][j];
-#pragma unroll
-                        for (int v = 0; v < u; ++v) a = fma(-lv[v], sLb[jb + v][j], a);
-                        lv[u] = a * sRs[j];
-                        sT[tid][j] = lv[u];
-                        Dfin = fma(-lv[u], lv[u], Dfin);
-                        if (b0 + j == kp) Dfin = 0.0;
+                for (int r = 0; r < RT; ++r) {
+                    if (r < rt) {
+                        const double a = sT[16 * r + (lane & 15)][kk];
+                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
                     }
                 }
             }
             __syncthreads();
-            if (je < nb) {
-                // columns beyond the panel: one column per lane, rows strided by 4
-                const int j = je + (tid & 63);
-                if (j < nb) {
-                    for (int m = tid >> 6; m < rows_here; m += 4) {
-                        double a = sT[m][j];
-#pragma unroll
-                        for (int u = 0; u < 16; ++u)
-                            if (jb + u < je) a = fma(-sT[m][jb + u], sLb[jb + u][j], a);
-                        sT[m][j] = a;
-                    }
+            for_each_acc(acc, rt, [&](int m, int n, double v) { sT[m][n] = v; });
+            __syncthreads();
+            if (tid < rows_here) {
+                for (int j = 0; j < nb; ++j) {
+                    const double l = sT[tid][j];
+                    Dfin = fma(-l, l, Dfin);
+                    if (b0 + j == kp) Dfin = 0.0;
                 }
-                __syncthreads();
             }
         }
         mark(blk, 4);

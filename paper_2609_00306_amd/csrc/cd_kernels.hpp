@@ -50,9 +50,9 @@ struct Step2Mol {
     const RowRec *rows;
     int64_t n_rows;
     const RowRec *prow;
-    const double *dpiv;
     const double *Lp;
     int64_t ldp;
+    const double *Ginv;   // [blocks][64][64] inverse-transposed pivot blocks
     const int32_t *pivot_of_row;
     const int64_t *n_vectors;
     double *L;

@@ -75,6 +75,7 @@ struct DecompWs {
     int32_t *pivot_of_row;
     double *Lp;
     RowRec *prow;
+    double *Ginv;
     size_t bytes;
 };
 
@@ -103,6 +104,7 @@ DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
     w.pivot_of_row = c.take<int32_t>(std::max<int64_t>(1, n));
     w.Lp = c.take<double>(std::max<int64_t>(1, mv * mv));
     w.prow = c.take<RowRec>(std::max<int64_t>(1, mv));
+    w.Ginv = c.take<double>(std::max<int64_t>(1, blocks_of(mv, 64)) * 64 * 64);
     w.bytes = c.off;
     return w;
 }
@@ -390,6 +392,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             k_gather_pivots<<<(unsigned)p.max_vectors, 256, 0, st>>>(
                 W[i].LT_act, p.max_vectors, W[i].piv_slot, p.pivots, W[i].rows, p.n_vectors,
                 W[i].Lp, p.max_vectors, W[i].prow);
+            k_block_inverse<<<(unsigned)blocks_of(p.max_vectors, 64), 64, 0, st>>>(
+                W[i].Lp, p.max_vectors, W[i].dpiv, p.n_vectors, W[i].Ginv);
         }
         if ((s = check_launch("pivot gather"))) return s;
     }
@@ -406,8 +410,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             q.rows = W[i].rows;
             q.n_rows = p.n_rows;
             q.prow = W[i].prow;
-            q.dpiv = W[i].dpiv;
             q.Lp = W[i].Lp;
+            q.Ginv = W[i].Ginv;
             q.ldp = p.max_vectors;
             q.pivot_of_row = W[i].pivot_of_row;
             q.n_vectors = p.n_vectors;
