@@ -27,6 +27,45 @@ if ROOT not in sys.path:
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X
 HBM_TBPS = 8.0
 
+# HBM bytes per launch of the two decomposition kernels on the default workload
+# (400 functions, tau = 1e-6), from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0` (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the same counter reads for a plain 1 GiB
+# device copy (`bench.py --copy-probe 1024`): FETCH_SIZE reads 524 302 KiB
+# there (factor 2.0), WRITE_SIZE 1 048 576 KiB (factor 1.0).  The figures
+# belong to the kernel sources they were taken on; once those change the
+# traffic is reported as null until the counters are taken again.
+KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
+                  "paper_2609_00306_amd/csrc/cd_mfma.hpp",
+                  "paper_2609_00306_amd/csrc/cd_device.hpp",
+                  "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.7, 1048576.0 / 1048576.0
+COUNTERS = {
+    "sources_sha256": "22fb6fbc55c4d0e30c53634d6b21d7589e1ce42f64857a7edfba0b1210add34f",
+    "workload": ("C2", 1e-6),
+    "fetch_kib": {"k_step2": 2348735.6, "k_step1": 160883.5},
+    "write_kib": {"k_step2": 259274.9, "k_step1": 112058.5},
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, config, tau):
+    """HBM bytes per launch of 'kernel' from the recorded counters, or None."""
+    if (config, tau) != COUNTERS["workload"]:
+        return None
+    if kernel_sources_sha256() != COUNTERS["sources_sha256"]:
+        return None
+    return 1024.0 * (COUNTERS["fetch_kib"][kernel] * FETCH_SCALE
+                     + COUNTERS["write_kib"][kernel] * WRITE_SCALE)
+
 
 def cpu_baseline(m, tau, schwarz):
     """The CPU oracle timed on the host cores: one full decomposition + FP64 J/K."""
@@ -41,6 +80,20 @@ def cpu_baseline(m, tau, schwarz):
     return {"value": ref.M / (t2 - t0), "unit": "vectors/s", "cores": cores, "kind": "oracle",
             "sample": f"one full step of the same workload: decomposition (M={ref.M}) "
                       f"{t1 - t0:.2f} s + FP64 J/K {t2 - t1:.2f} s"}
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of a known size, three times: the reference
+    against which the HBM byte counters of a profiled run are scaled."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "launches": 3}), flush=True)
 
 
 def bench_batched(args):
@@ -131,12 +184,17 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU form is design only)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.config == "C4":
         bench_batched(args)
         return
@@ -177,7 +235,6 @@ def main():
     for _ in range(args.warmup):
         step([mk() for _ in range(4)], [mk() for _ in range(3)])
     torch.cuda.synchronize()
-    assert d.M() == M and int(d.status.item()) == 0
 
     # per-batch device-clock stamps of the pivot selection (one untimed step)
     cap = 4096
@@ -207,6 +264,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    assert d.M() == M and int(d.status.item()) == 0
 
     def avg(i, j, which):
         vals = []
@@ -222,9 +280,24 @@ def main():
     t_jk = avg(0, 1, "j")
     t_tr = avg(1, 2, "j")
     w_cd = float(n) * M * (M - 1)                       # Schur / triangular-solve contraction
+    w_sel = float(d.n_active) * M * (M - 1)             # the same contraction on the active rows
     w_j = 4.0 * n * M
     w_k = 2.0 * N * N * O * M + float(N) * (N + 1) * O * M
-    achieved = w_cd / (t_solve * 1e-3) / 1e12
+    roof = {
+        "k_step2": {"kernel": "k_step2 (all-row blocked forward substitution, FP64 MFMA)",
+                    "bound": "mfma", "achieved": w_cd / (t_solve * 1e-3) / 1e12,
+                    "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                    "traffic": counter_traffic("k_step2", args.config, tau)},
+        "k_step1": {"kernel": "k_step1 (pivot selection on the active rows, one cooperative "
+                              "launch of candidate batches)",
+                    "bound": "mfma", "achieved": w_sel / (t_sel * 1e-3) / 1e12,
+                    "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                    "traffic": counter_traffic("k_step1", args.config, tau)},
+    }
+    for r in roof.values():
+        r["frac"] = r["achieved"] / r["peak"]
+    dominant = "k_step1" if t_sel > t_solve else "k_step2"
+    other = "k_step2" if dominant == "k_step1" else "k_step1"
     out = {
         "metric": "Cholesky vectors/s + J/K build TFLOP/s at tau=1e-6; mixed/batched vs plain FP64",
         "value": M / (ms * 1e-3),
@@ -252,9 +325,8 @@ def main():
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
                             "stage_us_total": breakdown},
         "all_row_solve_wg0_stage_us_total": s2_breakdown,
-        "roofline": {"kernel": "k_step2 (all-row blocked forward substitution, FP64 MFMA)",
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"], "traffic": None},
+        "roofline": roof[dominant],
+        "roofline_other_kernel": roof[other],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, tau, schwarz)

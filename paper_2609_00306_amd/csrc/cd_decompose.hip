@@ -514,8 +514,9 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
 // vector equation of Sec. 2).  Then the block of vectors obeys T = L_blk S^T,
 // T being the right-hand side (r|P_K) - sum over earlier blocks, so
 // L_blk = T G with G = S^{-T} (upper triangular).  Lane c solves S x = e_c by
-// forward substitution; x is row c of G.  In a ragged last block the unused
-// part of S is the identity.
+// forward substitution with x in registers (both loops unrolled, four partial
+// sums per row); x is row c of G.  In a ragged last block the unused part of
+// S is the identity.
 __global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__ Lp, int64_t ldp,
                                                       const double *__restrict__ dpiv,
                                                       const int64_t *__restrict__ n_vectors,
@@ -525,8 +526,7 @@ __global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__
     const int64_t M = *n_vectors;
     if (b0 >= M) return;
     const int nb = (int)min((int64_t)64, M - b0);
-    __shared__ double sS[64][65];
-    __shared__ double sX[64][65];   // sX[j][c]: entry j of the solution for e_c
+    __shared__ double sS[64][66];
     const int c = threadIdx.x;
     for (int j = 0; j < 64; ++j) {
         double v = 0.0;
@@ -538,14 +538,20 @@ __global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__
         sS[j][c] = v;
     }
     __syncthreads();
+    double x[64];
+#pragma unroll
     for (int j = 0; j < 64; ++j) {
-        double a = (j == c) ? 1.0 : 0.0;
-        for (int i = c; i < j; ++i) a = fma(-sS[j][i], sX[i][c], a);
-        sX[j][c] = (j < c) ? 0.0 : a / sS[j][j];
+        double a[4] = {(j == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < j; ++i) a[i & 3] = fma(-sS[j][i], x[i], a[i & 3]);
+        x[j] = ((a[0] + a[1]) + (a[2] + a[3])) / sS[j][j];
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 64; ++j) sS[c][j] = x[j];
+    __syncthreads();
     double *g = G + (int64_t)blockIdx.x * 4096;
-    for (int r = 0; r < 64; ++r) g[r * 64 + c] = sX[c][r];
+    for (int r = 0; r < 64; ++r) g[r * 64 + c] = sS[r][c];
 }
 
 // ---------------------------------------------------------------- step 2
