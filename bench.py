@@ -266,6 +266,22 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     assert d.M() == M and int(d.status.item()) == 0
 
+    prec_err = None
+    if args.precision != "fp64":
+        # the reduced-precision J/K of the last step against the FP64 build from
+        # the same vectors; E2 = 2 tr(DJ) - tr(DK), D = C C^T
+        J64, K64 = cdlib.build_jk(d, m.C, "fp64")
+        Ct = torch.as_tensor(m.C, device=dev)
+        Dm = Ct @ Ct.T
+
+        def e2(J, K):
+            return float(2.0 * (Dm * J).sum() - (Dm * K).sum())
+
+        prec_err = {"against": "FP64 J/K from the same vectors",
+                    "max_abs_dJ": float((jk.J - J64).abs().max()),
+                    "max_abs_dK": float((jk.K - K64).abs().max()),
+                    "abs_dE2": abs(e2(jk.J, jk.K) - e2(J64, K64))}
+
     def avg(i, j, which):
         vals = []
         for pe, je in evs:
@@ -325,6 +341,8 @@ def main():
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
                             "stage_us_total": breakdown},
         "all_row_solve_wg0_stage_us_total": s2_breakdown,
+        "jk_tflops_work": "dense-equivalent 4nM + 2N^2 O M + N(N+1) O M",
+        "precision_error": prec_err,
         "roofline": roof[dominant],
         "roofline_other_kernel": roof[other],
     }

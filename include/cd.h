@@ -13,7 +13,7 @@
  *                 and the occupied coefficients (Sec. 4.1: O(N^2 M) for J,
  *                 O(O N^2 M) for K);
  *   cd_transform  the AO->MO transform of the vectors (Sec. 4.1, CASSCF;
- *                 two-coefficient form of Sec. 9).
+ *                 two-coefficient form of Sec. 6.2).
  *
  * Conventions
  *   - Plain C, fixed-width integers; no C++ types or exceptions cross it.

@@ -21,7 +21,7 @@
  *     standard J and K with (mu nu|rho sigma) ~ sum_P L^P_{mu nu} L^P_{rho sigma}
  *     inserted), and the same J and K from exact integrals (brute force);
  *   - the AO->MO transform of the vectors (Sec. 4.1, CASSCF; two-coefficient
- *     form of Sec. 9).
+ *     form of Sec. 6.2).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   ties in the argmax go to the lowest row index; the divisor is the square

@@ -1,6 +1,6 @@
 // Coulomb/exchange builds from the Cholesky vectors (paper Sec. 4.1: J costs
 // O(N^2 M), K costs O(O N^2 M)) and the AO->MO transform of the vectors
-// (Sec. 4.1, CASSCF; two-coefficient form of Sec. 9).
+// (Sec. 4.1, CASSCF; two-coefficient form of Sec. 6.2).
 //
 //   J_{mu nu} = sum_P L^P_{mu nu} V^P,  V^P = sum_{rho sigma} L^P_{rho sigma} D_{rho sigma},  D = C C^T
 //   K_{mu nu} = sum_P sum_i X^P_{i mu} X^P_{i nu},  X^P_{i mu} = sum_sigma L^P_{mu sigma} C_{sigma i}
