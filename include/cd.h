@@ -129,7 +129,8 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
 
 /*
  * cd_decompose: decompose 'count' molecules (host array 'probs') with the
- * workspace 'ws' (device, ws_bytes >= the sum of cd_query's ws_bytes).
+ * workspace 'ws' (device, 256-byte aligned, ws_bytes >= the sum of cd_query's
+ * ws_bytes; a misaligned ws gives CD_ERR_INVALID_ARG).
  * Asynchronous and free of host synchronisation unless CD_SYNC is set.  The
  * device recounts the rows; a count that differs from n_rows / n_active
  * gives status CD_ERR_DEVICE and no vectors.

@@ -177,9 +177,11 @@ constexpr int CNOM = 4;        // nominations per workgroup
 constexpr int SMAX = 256;      // active rows per workgroup
 constexpr int NOMSORT = 1024;  // union capacity (workgroups * CNOM)
 constexpr int S1_MAXG = NOMSORT / CNOM;
-using S1K = SplitK<2, 16>;     // candidate-column product: 32 rows per pass, k-chunks of 16
-constexpr int S1_UNION = (4 * S1K::kWaveDoubles > 2 * QMAX * (QMAX + 1))
-                             ? 4 * S1K::kWaveDoubles : 2 * QMAX * (QMAX + 1);
+using S1K = SplitK<3>;         // candidate-column product: 48 rows per pass, k-chunks of 16
+constexpr int S1_LROWS = 64;      // eligible rows whose candidate columns stay in LDS
+constexpr int S1_HLD = QMAX + 2;   // row length of the in-batch history (16-byte aligned rows)
+constexpr int S1_BLOCK = QMAX * (QMAX + 1) + QMAX * S1_HLD;
+constexpr int S1_UNION = (4 * S1K::kWaveDoubles > S1_BLOCK) ? 4 * S1K::kWaveDoubles : S1_BLOCK;
 
 __device__ __forceinline__ bool eligible(double d, double tau, double floor_tol)
 {
@@ -192,11 +194,42 @@ __device__ __forceinline__ void stamp(const Step1Params &P, int g, int64_t batch
         P.timeline[batch * 8 + what] = (int64_t)wall_clock64();
 }
 
+// In-batch value before scaling: c - sum_{tp<t} own[tp] piv[tp], summed in four
+// interleaved partial sums (tp mod 4) combined as (s0 + s1) + (s2 + s3).  The
+// row update repeats exactly this arithmetic, so candidate rows agree bit for
+// bit with the block factorisation.  Reads go in chunks of 8 (16-byte loads);
+// entries past t are masked, not read into the sums.
+__device__ __forceinline__ double inbatch_value(double c, const double *__restrict__ own,
+                                                const double *__restrict__ piv, int t)
+{
+    double a[4] = {c, 0.0, 0.0, 0.0};
+    for (int tp = 0; tp < t; tp += 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+            const double2 xo = *reinterpret_cast<const double2 *>(own + tp + u);
+            const double2 yo = *reinterpret_cast<const double2 *>(piv + tp + u);
+            x[u] = xo.x;
+            x[u + 1] = xo.y;
+            y[u] = yo.x;
+            y[u + 1] = yo.y;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double f = fma(-x[u], y[u], a[u & 3]);
+            a[u & 3] = (tp + u < t) ? f : a[u & 3];
+        }
+    }
+    return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
 {
     __shared__ double sU[S1_UNION];   // phase-dependent: nominations / GEMM staging / candidate block
     __shared__ double sD[SMAX];       // residual diagonal of this workgroup's active rows
     __shared__ int sList[SMAX];       // this workgroup's eligible rows (local indices)
+    __shared__ int sCand[SMAX];       // local row -> candidate index, or -1
+    __shared__ double sC[S1_LROWS][QMAX + 1];   // candidate columns of the first eligible rows
     __shared__ int sQ[QMAX];          // candidate slots
     __shared__ RowRec sQrow[QMAX];    // candidate pair data
     __shared__ int sPiv[QMAX];        // candidate index of in-batch pivot t
@@ -208,7 +241,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
 
     Nom *sNom = reinterpret_cast<Nom *>(sU);
     double (*sS)[QMAX + 1] = reinterpret_cast<double (*)[QMAX + 1]>(sU);
-    double (*sLq)[QMAX + 1] = reinterpret_cast<double (*)[QMAX + 1]>(sU + QMAX * (QMAX + 1));
+    // sH[c][t]: in-batch value of candidate c at in-batch step t
+    double (*sH)[S1_HLD] = reinterpret_cast<double (*)[S1_HLD]>(sU + QMAX * (QMAX + 1));
 
     const int tid = threadIdx.x;
     int mol = 0;
@@ -217,7 +251,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     const int G = B.block_begin[mol + 1] - B.block_begin[mol];
     const int g = (int)blockIdx.x - B.block_begin[mol];
     const int64_t n_act = P.n_act;
-    const int64_t ldT = P.max_vectors;
+    const int64_t ldT = P.ldT;
     const int64_t s0 = (int64_t)g * P.slice;
     const int ns = (int)max((int64_t)0, min((int64_t)P.slice, n_act - s0));
     const double tau = P.tau;
@@ -265,9 +299,11 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 if (d != d || d == INFINITY) {
                     e.d = INFINITY;
                     e.idx = (int)(s0 + i);
+                    e.pad = P.act_row[s0 + i];
                 } else if (eligible(d, tau, ftol)) {
                     e.d = d;
                     e.idx = (int)(s0 + i);
+                    e.pad = P.act_row[s0 + i];    // pair row of the nominee
                 }
             }
             sNom[i] = e;
@@ -314,15 +350,18 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         }
         __syncthreads();
         block_sort_noms(sNom, U2);
+        if (tid < 64) {   // sorted: the eligible nominations come first
+            const unsigned long long ok =
+                __ballot(tid < q && tid < U2 && sNom[tid].d != -INFINITY);
+            if (tid == 0) s_nq = __popcll(ok);
+        }
         if (tid == 0) {
-            int nq = 0;
-            while (nq < q && nq < U2 && sNom[nq].d != -INFINITY) ++nq;
+            const int nq = s_nq;
             Nom nxt = (q < U2) ? sNom[q] : Nom{-INFINITY, 0x7fffffff, 0};
             if (nom_before(nxt.d, nxt.idx, s_U, s_iU)) {
                 s_U = nxt.d;
                 s_iU = nxt.idx;
             }
-            s_nq = nq;
             s_stop = 0;
             s_status = 0;
             if (nq == 0) s_stop = 1;                          // no eligible row left
@@ -341,7 +380,13 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             int rank = 0;
             for (int j = 0; j < nq; ++j) rank += (sNom[j].idx < me);
             sQ[rank] = me;
-            sQrow[rank] = P.rows[P.act_row[me]];
+            sQrow[rank] = P.rows[sNom[tid].pad];
+        }
+        for (int i = tid; i < ns; i += 256) sCand[i] = -1;
+        __syncthreads();
+        if (tid < nq) {
+            const int64_t sl = (int64_t)sQ[tid] - s0;
+            if (sl >= 0 && sl < ns) sCand[sl] = tid;
         }
         __syncthreads();
         stamp(P, g, batch, 2);
@@ -352,25 +397,35 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         for (int pb = 0; pb < cnt; pb += S1K::kRows) {
             const int rows_m = min(S1K::kRows, cnt - pb);
             const int rt = (rows_m + 15) >> 4;
-            f64x4 acc[2][4];
+            f64x4 acc[3][4];
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < 3; ++r)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-            S1K::run(
-                K, rt, rows_m,
-                [&](int64_t k, int m) -> double { return LT[(s0 + sList[pb + m]) * ldT + k]; },
-                [&](int64_t k, int n) -> double {
-                    return (n < nq) ? LT[(int64_t)sQ[n] * ldT + k] : 0.0;
-                },
-                acc, sU);
+            int64_t aoff[S1K::kNA], boff[S1K::kNB];
+#pragma unroll
+            for (int u = 0; u < S1K::kNA; ++u) {
+                const int m = S1K::row_of(u);
+                aoff[u] = (m < rows_m) ? (s0 + sList[pb + m]) * ldT : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < S1K::kNB; ++u) {
+                const int n = S1K::row_of(u);
+                boff[u] = (n < nq) ? (int64_t)sQ[n] * ldT : -1;
+            }
+            S1K::run(K, rt, LT, aoff, boff, acc, sU);
             S1K::wave_sum_to_lds(acc, rt, sU);
             for (int e = tid; e < rows_m * 64; e += 256) {
                 const int m = e >> 6, n = e & 63;
                 if (n < nq) {
-                    const int64_t slot = s0 + sList[pb + m];
+                    const int li = pb + m;
+                    const int64_t slot = s0 + sList[li];
                     const RowRec ra = P.rows[P.act_row[slot]];
-                    P.Cbuf[(int64_t)n * n_act + slot] = eri(ra, sQrow[n]) - sU[m * 65 + n];
+                    const double v = eri(ra, sQrow[n]) - sU[m * 65 + n];
+                    if (li < S1_LROWS) sC[li][n] = v;
+                    else P.Cbuf[(int64_t)n * n_act + slot] = v;
+                    const int ci = sCand[sList[li]];
+                    if (ci >= 0) P.Cblk[ci * QMAX + n] = v;   // candidate row: shared block
                 }
             }
             __syncthreads();
@@ -385,49 +440,54 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         // ---- in-batch factorisation of the candidate block (every workgroup)
         for (int e = tid; e < nq * nq; e += 256) {
             int i = e / nq, j = e % nq;
-            sS[i][j] = P.Cbuf[(int64_t)j * n_act + sQ[i]];
+            sS[i][j] = P.Cblk[i * QMAX + j];
         }
         __syncthreads();
         if (tid < 64) {
             const int i = tid;
             const bool valid = i < nq;
             double dq = valid ? P.D_act[sQ[i]] : -INFINITY;
+            const int myslot = valid ? sQ[i] : 0x7fffffff;
             bool used = !valid;
             const double U = s_U;
             const int iU = s_iU;
+            const int64_t room = P.max_vectors - K;
             int kb = 0, stop = 0, st = 0;
-            // lane i's own in-batch values live in sLq[.][i]
+            // lane t keeps the record of in-batch step t (pivot lane, value, 1/sqrt)
+            int rec_bl = 0;
+            double rec_bd = 0.0, rec_inv = 0.0;
             for (int t = 0; t < QMAX; ++t) {
                 const double val = used ? -INFINITY : dq;
                 if (__ballot(val != val)) { stop = 1; st = 4; break; }
-                const double bd = wave_max_f64(val);
-                const unsigned long long tie = __ballot(!used && val == bd);
-                if (tie == 0ull) break;                          // every candidate used
-                const int bl = __ffsll((long long)tie) - 1;      // lowest lane = lowest row
-                const int bi = sQ[bl];
-                if (!nom_before(bd, bi, U, iU)) break;           // may not be the global argmax
-                if (!eligible(bd, tau, ftol)) { stop = 1; break; }   // max D < tau: done
-                if (K + t >= P.max_vectors) { stop = 1; st = 3; break; }
+                double bd;
+                const int bl = wave_argmax_pos(val, bd);         // lowest lane = lowest row
+                if (bl < 0) break;                               // no positive residual left
+                const int bi = __builtin_amdgcn_readlane(myslot, bl);
+                const bool first = nom_before(bd, bi, U, iU);    // provably the global argmax
+                const bool elig = eligible(bd, tau, ftol);       // max D >= tau
+                if (!first || !elig || t >= room) {
+                    if (first) {
+                        stop = 1;
+                        st = elig ? 3 : 0;                       // capacity, or done
+                    }
+                    break;
+                }
                 const double inv = 1.0 / sqrt(bd);
-                double a = sS[i][bl];
-#pragma unroll 8
-                for (int tp = 0; tp < t; ++tp) a = fma(-sLq[tp][i], sLq[tp][bl], a);
-                const double lt = a * inv;
-                dq = fma(-lt, lt, dq);
-                if (i == bl) {
-                    dq = 0.0;
-                    used = true;
-                }
-                sLq[t][i] = lt;
-                if (i == 0) {
-                    sPiv[t] = bl;
-                    sDp[t] = bd;
-                    sRs[t] = inv;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const double lt = inbatch_value(sS[i][bl], sH[i], sH[bl], t) * inv;
+                dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
+                used = used || (i == bl);
+                sH[i][t] = lt;
+                rec_bl = (i == t) ? bl : rec_bl;
+                rec_bd = (i == t) ? bd : rec_bd;
+                rec_inv = (i == t) ? inv : rec_inv;
+                // LDS accesses of one wave complete in order; keep the compiler's order
+                __asm__ volatile("" ::: "memory");
                 kb = t + 1;
+            }
+            if (i < kb) {
+                sPiv[i] = rec_bl;
+                sDp[i] = rec_bd;
+                sRs[i] = rec_inv;
             }
             if (i == 0) {
                 s_kb = kb;
@@ -450,10 +510,12 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             for (int t = 0; t < QMAX; ++t) {
                 if (t < kb) {
                     const int it = sPiv[t];
-                    double a = P.Cbuf[(int64_t)it * n_act + slot];
+                    const double c = (li < S1_LROWS) ? sC[li][it]
+                                                     : P.Cbuf[(int64_t)it * n_act + slot];
+                    double a[4] = {c, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int tp = 0; tp < t; ++tp) a = fma(-l[tp], sLq[tp][it], a);
-                    l[t] = a * sRs[t];
+                    for (int tp = 0; tp < t; ++tp) a[tp & 3] = fma(-l[tp], sH[it][tp], a[tp & 3]);
+                    l[t] = ((a[0] + a[1]) + (a[2] + a[3])) * sRs[t];
                     d = fma(-l[t], l[t], d);
                     if (sQ[it] == slot) d = 0.0;
                     LT[slot * ldT + K + t] = l[t];

@@ -219,6 +219,36 @@ __device__ __forceinline__ double wave_max_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Wave-wide (64 lanes) maximum of an unsigned value with DPP max steps; the
+// result is read from lane 63.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Lowest lane holding the largest positive value (values <= 0, -inf and NaN
+// never win), or -1 if no lane holds one; 'best' receives the value.  The bit
+// pattern of a positive double orders like an unsigned integer, so the maximum
+// is taken on the high word and then on the low word among the lanes that tie
+// on the high word: exact, with 32-bit DPP steps only.
+__device__ __forceinline__ int wave_argmax_pos(double v, double &best)
+{
+    const unsigned long long key = (v > 0.0) ? (unsigned long long)__double_as_longlong(v) : 0ull;
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+    const unsigned long long top = ((unsigned long long)mh << 32) | ml;
+    best = __longlong_as_double((long long)top);
+    const unsigned long long tie = __ballot(key == top && key != 0ull);
+    return tie ? (int)__ffsll((long long)tie) - 1 : -1;
+}
+
 // Wave-wide (64 lanes) selection of the lane holding the first entry in pivot order.
 __device__ __forceinline__ void wave_best(double &d, int &idx, int &lane_of)
 {

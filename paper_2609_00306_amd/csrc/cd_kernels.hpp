@@ -11,9 +11,11 @@ struct Step1Params {
     const int64_t *n_act_dev;  // device count of active rows (must equal n_act)
     int64_t n_act;
     double *D_act;             // [n_act] residual diagonal of the active rows
-    double *LT_act;            // [n_act][max_vectors] vectors on the active rows, row-major
+    double *LT_act;            // [n_act][ldT] vectors on the active rows, row-major
+    int64_t ldT;               // row stride of LT_act (multiple of 16)
     const int64_t *n_rows_dev; // device count of rows (must equal n_rows)
-    double *Cbuf;              // [QMAX][n_act] candidate columns
+    double *Cbuf;              // [QMAX][n_act] candidate columns of rows past the LDS copy
+    double *Cblk;              // [QMAX][QMAX] candidate block, row i = candidate i
     Nom *noms;                 // [G][CNOM + 1]
     GridSync *gs;
     int64_t *pivots;           // [max_vectors] row index of each pivot

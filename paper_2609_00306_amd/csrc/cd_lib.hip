@@ -68,6 +68,7 @@ struct DecompWs {
     double *D_act;
     double *LT_act;
     double *Cbuf;
+    double *Cblk;
     Nom *noms;
     GridSync *gs;
     int32_t *piv_slot;
@@ -78,6 +79,10 @@ struct DecompWs {
     double *Ginv;
     size_t bytes;
 };
+
+// Row stride of the active-row vectors: a multiple of 16 doubles, so every
+// row starts on a 128-byte line and 16-byte loads stay aligned.
+int64_t ld_act(int64_t mv) { return (mv + 15) / 16 * 16; }
 
 DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
 {
@@ -95,8 +100,9 @@ DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
     w.rows = c.take<RowRec>(std::max<int64_t>(1, n));
     w.act_row = c.take<int32_t>(std::max<int64_t>(1, na));
     w.D_act = c.take<double>(std::max<int64_t>(1, na));
-    w.LT_act = c.take<double>(std::max<int64_t>(1, mv * na));
+    w.LT_act = c.take<double>(std::max<int64_t>(1, ld_act(mv) * na));
     w.Cbuf = c.take<double>(std::max<int64_t>(1, (int64_t)QMAX * na));
+    w.Cblk = c.take<double>((int64_t)QMAX * QMAX);
     w.noms = c.take<Nom>((size_t)S1_MAXG * (CNOM + 1));
     w.gs = c.take<GridSync>(1);
     w.piv_slot = c.take<int32_t>(std::max<int64_t>(1, mv));
@@ -206,8 +212,10 @@ Step1Params step1_params(const cd_problem &p, const DecompWs &w, const cd_decomp
     P1.n_act = p.n_active;
     P1.D_act = w.D_act;
     P1.LT_act = w.LT_act;
+    P1.ldT = ld_act(p.max_vectors);
     P1.n_rows_dev = w.totals;
     P1.Cbuf = w.Cbuf;
+    P1.Cblk = w.Cblk;
     P1.noms = w.noms;
     P1.gs = w.gs;
     P1.pivots = p.pivots;
@@ -299,6 +307,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     }
     if (need > ws_bytes || (need > 0 && !ws))
         return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(CD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     DevInfo di;
     if ((s = dev_info(di))) return s;
 
@@ -390,7 +400,7 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         for (int i : grp) {
             const cd_problem &p = probs[i];
             k_gather_pivots<<<(unsigned)p.max_vectors, 256, 0, st>>>(
-                W[i].LT_act, p.max_vectors, W[i].piv_slot, p.pivots, W[i].rows, p.n_vectors,
+                W[i].LT_act, ld_act(p.max_vectors), W[i].piv_slot, p.pivots, W[i].rows, p.n_vectors,
                 W[i].Lp, p.max_vectors, W[i].prow);
             k_block_inverse<<<(unsigned)blocks_of(p.max_vectors, 64), 64, 0, st>>>(
                 W[i].Lp, p.max_vectors, W[i].dpiv, p.n_vectors, W[i].Ginv);

@@ -115,64 +115,80 @@ __device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, int rt_act
 
 // ---------------------------------------------------------------- split-k form
 // Wave-parallel product for short, tall operands: every wave owns whole
-// k-chunks (chunk c goes to wave c % 4), stages them in its own LDS region
-// and keeps a full (16 RT) x 64 accumulator, so the four waves run four
-// independent load/multiply pipelines with no workgroup-wide barrier inside
-// the k loop.  Both operands are k-contiguous (for a fixed row the k index
-// is contiguous in memory).  The partial products are summed across waves
-// by wave_sum_to_lds().
-template <int RT, int TKC>
+// k-chunks of 16 (chunk c goes to wave c % 4), stages them in its own LDS
+// region and keeps a full (16 RT) x 64 accumulator, so the four waves run
+// four independent load/multiply pipelines with no workgroup-wide barrier
+// inside the k loop.  Both operands are rows of one row-major matrix 'base'
+// (k contiguous, rows 16-byte aligned): A rows for the 16 RT output rows, B
+// rows for the 64 output columns.  Each lane loads one 16-byte piece of 8
+// different rows per chunk (8 lanes cover a row's 128 bytes), from row
+// offsets it keeps in registers, so no index lookup precedes a load.  The
+// partial products are summed across waves by wave_sum_to_lds().
+template <int RT>
 struct SplitK {
+    static constexpr int TKC = 16;
     static constexpr int kRows = 16 * RT;
-    static constexpr int kLd = TKC + 1;
+    static constexpr int kLd = TKC + 2;                          // 16-byte aligned LDS rows
     static constexpr int kWaveDoubles = (kRows + 64) * kLd;     // LDS per wave
-    static constexpr int kNA = kRows * TKC / 64;                 // loads per lane
-    static constexpr int kNB = 64 * TKC / 64;
+    static constexpr int kNA = kRows / 8;                        // A rows per lane
+    static constexpr int kNB = 64 / 8;                           // B rows per lane
 
-    template <class LA, class LB>
-    __device__ static __forceinline__ void fetch(LA la, LB lb, int64_t k0, int64_t kend, int rows,
-                                                 double (&ra)[kNA], double (&rb)[kNB])
+    // Row handled by this lane in load slot u (A or B).
+    __device__ static __forceinline__ int row_of(int u) { return ((threadIdx.x & 63) >> 3) + 8 * u; }
+
+    template <int NR>
+    __device__ static __forceinline__ void fetch_rows(const double *__restrict__ base,
+                                                      const int64_t (&off)[NR], int64_t k0,
+                                                      int64_t kend, double2 (&v)[NR])
     {
-        const int lane = threadIdx.x & 63;
+        const int64_t k = k0 + 2 * (threadIdx.x & 7);
+        if (k0 + TKC <= kend) {
 #pragma unroll
-        for (int u = 0; u < kNA; ++u) {
-            const int e = lane + 64 * u, m = e / TKC, k = e % TKC;
-            ra[u] = (m < rows && k0 + k < kend) ? la(k0 + k, m) : 0.0;
-        }
+            for (int u = 0; u < NR; ++u)
+                v[u] = (off[u] >= 0) ? *reinterpret_cast<const double2 *>(base + off[u] + k)
+                                     : double2{0.0, 0.0};
+        } else {
 #pragma unroll
-        for (int u = 0; u < kNB; ++u) {
-            const int e = lane + 64 * u, n = e / TKC, k = e % TKC;
-            rb[u] = (k0 + k < kend) ? lb(k0 + k, n) : 0.0;
+            for (int u = 0; u < NR; ++u) {
+                v[u].x = (off[u] >= 0 && k < kend) ? base[off[u] + k] : 0.0;
+                v[u].y = (off[u] >= 0 && k + 1 < kend) ? base[off[u] + k + 1] : 0.0;
+            }
         }
     }
 
-    template <class LA, class LB>
-    __device__ static __forceinline__ void run(int64_t kend, int rt, int rows, LA la, LB lb,
+    template <int NR>
+    __device__ static __forceinline__ void put_rows(double *s, const double2 (&v)[NR])
+    {
+        const int c = 2 * (threadIdx.x & 7);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) *reinterpret_cast<double2 *>(s + row_of(u) * kLd + c) = v[u];
+    }
+
+    // aoff[u] / boff[u]: element offset of the A / B row row_of(u) in 'base', or -1
+    // for a row that is absent (read as zeros).  k runs over [0, kend).
+    __device__ static __forceinline__ void run(int64_t kend, int rt, const double *__restrict__ base,
+                                               const int64_t (&aoff)[kNA], const int64_t (&boff)[kNB],
                                                f64x4 (&acc)[RT][4], double *sWaves)
     {
         const int lane = threadIdx.x & 63;
         const int w = threadIdx.x >> 6;
         double *sAw = sWaves + w * kWaveDoubles;
         double *sBw = sAw + kRows * kLd;
-        double ra[kNA], rb[kNB];
+        double2 va[kNA], vb[kNB];
         const int64_t nch = (kend + TKC - 1) / TKC;
         if (w >= nch) return;
-        fetch(la, lb, (int64_t)w * TKC, kend, rows, ra, rb);
+        fetch_rows(base, aoff, (int64_t)w * TKC, kend, va);
+        fetch_rows(base, boff, (int64_t)w * TKC, kend, vb);
         for (int64_t c = w; c < nch; c += 4) {
-#pragma unroll
-            for (int u = 0; u < kNA; ++u) {
-                const int e = lane + 64 * u;
-                sAw[(e / TKC) * kLd + e % TKC] = ra[u];
-            }
-#pragma unroll
-            for (int u = 0; u < kNB; ++u) {
-                const int e = lane + 64 * u;
-                sBw[(e / TKC) * kLd + e % TKC] = rb[u];
-            }
+            put_rows(sAw, va);
+            put_rows(sBw, vb);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (c + 4 < nch) fetch(la, lb, (c + 4) * TKC, kend, rows, ra, rb);
+            if (c + 4 < nch) {
+                fetch_rows(base, aoff, (c + 4) * TKC, kend, va);
+                fetch_rows(base, boff, (c + 4) * TKC, kend, vb);
+            }
 #pragma unroll
             for (int ks = 0; ks < TKC; ks += 4) {
                 const int kk = ks + (lane >> 4);
@@ -181,12 +197,12 @@ struct SplitK {
                 for (int ct = 0; ct < 4; ++ct) b[ct] = sBw[(16 * ct + (lane & 15)) * kLd + kk];
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
-                    if (r < rt) {
+                    if (r < rt) {   // uniform
                         const double a = sAw[(16 * r + (lane & 15)) * kLd + kk];
 #pragma unroll
                         for (int ct = 0; ct < 4; ++ct)
-                            acc[r][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct], acc[r][ct],
-                                                                               0, 0, 0);
+                            acc[r][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct],
+                                                                               acc[r][ct], 0, 0, 0);
                     }
                 }
             }

@@ -110,6 +110,11 @@ def test_argument_validation_without_device(lib):
     p.n_active = 5
     assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(opts), None, 0,
                             None) == cdlib.CD_ERR_INVALID_ARG
+    # a workspace that is large enough but not 256-byte aligned is rejected on the host
+    p.n_active = 0
+    assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(opts), ctypes.c_void_p(0x1008),
+                            1 << 30, None) == cdlib.CD_ERR_INVALID_ARG
+    assert b"aligned" in lib.cd_last_error()
 
 
 def test_product_path_refuses_missing_library(tmp_path):
