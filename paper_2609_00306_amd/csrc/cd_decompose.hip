@@ -194,33 +194,42 @@ __device__ __forceinline__ void stamp(const Step1Params &P, int g, int64_t batch
         P.timeline[batch * 8 + what] = (int64_t)wall_clock64();
 }
 
-// In-batch value before scaling: c - sum_{tp<t} own[tp] piv[tp], summed in four
+// In-batch value: (c - sum_{tp<t} own[tp] piv[tp]) * inv, the sum taken in four
 // interleaved partial sums (tp mod 4) combined as (s0 + s1) + (s2 + s3).  The
 // row update repeats exactly this arithmetic, so candidate rows agree bit for
 // bit with the block factorisation.  Reads go in chunks of 8 (16-byte loads);
-// entries past t are masked, not read into the sums.
+// entries past t are masked, not read into the sums.  The first chunk's reads
+// are issued before 'inv' is formed, so the two overlap.
+__device__ __forceinline__ void inbatch_chunk(const double *__restrict__ own,
+                                              const double *__restrict__ piv, int tp, int t,
+                                              double (&a)[4])
+{
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+        const double2 xo = *reinterpret_cast<const double2 *>(own + tp + u);
+        const double2 yo = *reinterpret_cast<const double2 *>(piv + tp + u);
+        x[u] = xo.x;
+        x[u + 1] = xo.y;
+        y[u] = yo.x;
+        y[u + 1] = yo.y;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double f = fma(-x[u], y[u], a[u & 3]);
+        a[u & 3] = (tp + u < t) ? f : a[u & 3];
+    }
+}
+
 __device__ __forceinline__ double inbatch_value(double c, const double *__restrict__ own,
-                                                const double *__restrict__ piv, int t)
+                                                const double *__restrict__ piv, int t,
+                                                double bd, double &inv)
 {
     double a[4] = {c, 0.0, 0.0, 0.0};
-    for (int tp = 0; tp < t; tp += 8) {
-        double x[8], y[8];
-#pragma unroll
-        for (int u = 0; u < 8; u += 2) {
-            const double2 xo = *reinterpret_cast<const double2 *>(own + tp + u);
-            const double2 yo = *reinterpret_cast<const double2 *>(piv + tp + u);
-            x[u] = xo.x;
-            x[u + 1] = xo.y;
-            y[u] = yo.x;
-            y[u + 1] = yo.y;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double f = fma(-x[u], y[u], a[u & 3]);
-            a[u & 3] = (tp + u < t) ? f : a[u & 3];
-        }
-    }
-    return (a[0] + a[1]) + (a[2] + a[3]);
+    inbatch_chunk(own, piv, 0, t, a);
+    inv = rsqrt_nr(bd);
+    for (int tp = 8; tp < t; tp += 8) inbatch_chunk(own, piv, tp, t, a);
+    return ((a[0] + a[1]) + (a[2] + a[3])) * inv;
 }
 
 __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
@@ -458,7 +467,6 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             double rec_bd = 0.0, rec_inv = 0.0;
             for (int t = 0; t < QMAX; ++t) {
                 const double val = used ? -INFINITY : dq;
-                if (__ballot(val != val)) { stop = 1; st = 4; break; }
                 double bd;
                 const int bl = wave_argmax_pos(val, bd);         // lowest lane = lowest row
                 if (bl < 0) break;                               // no positive residual left
@@ -472,8 +480,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                     }
                     break;
                 }
-                const double inv = 1.0 / sqrt(bd);
-                const double lt = inbatch_value(sS[i][bl], sH[i], sH[bl], t) * inv;
+                double inv;
+                const double lt = inbatch_value(sS[i][bl], sH[i], sH[bl], t, bd, inv);
                 dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
                 used = used || (i == bl);
                 sH[i][t] = lt;
@@ -483,6 +491,12 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 // LDS accesses of one wave complete in order; keep the compiler's order
                 __asm__ volatile("" ::: "memory");
                 kb = t + 1;
+            }
+            // a candidate residual that turned NaN inside the batch ends the
+            // decomposition (lanes without a candidate carry no value)
+            if (__ballot(!used && dq != dq)) {
+                stop = 1;
+                st = 4;
             }
             if (i < kb) {
                 sPiv[i] = rec_bl;

@@ -235,18 +235,39 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v)
 // Lowest lane holding the largest positive value (values <= 0, -inf and NaN
 // never win), or -1 if no lane holds one; 'best' receives the value.  The bit
 // pattern of a positive double orders like an unsigned integer, so the maximum
-// is taken on the high word and then on the low word among the lanes that tie
-// on the high word: exact, with 32-bit DPP steps only.
+// is taken on the high word; only if several lanes share that high word is
+// the low word compared among them.  Exact, with 32-bit DPP steps only.
 __device__ __forceinline__ int wave_argmax_pos(double v, double &best)
 {
     const unsigned long long key = (v > 0.0) ? (unsigned long long)__double_as_longlong(v) : 0ull;
     const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
     const unsigned mh = wave_max_u32(hi);
-    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
-    const unsigned long long top = ((unsigned long long)mh << 32) | ml;
-    best = __longlong_as_double((long long)top);
-    const unsigned long long tie = __ballot(key == top && key != 0ull);
-    return tie ? (int)__ffsll((long long)tie) - 1 : -1;
+    const unsigned long long th = __ballot(hi == mh && key != 0ull);
+    if (th == 0ull) {
+        best = 0.0;
+        return -1;
+    }
+    unsigned long long tie = th;
+    if (th & (th - 1)) {   // several lanes share the high word
+        const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+        tie = __ballot(hi == mh && lo == ml && key != 0ull);
+    }
+    const int bl = (int)__ffsll((long long)tie) - 1;
+    const int blo = __builtin_amdgcn_readlane((int)lo, bl);
+    best = __longlong_as_double((long long)(((unsigned long long)mh << 32) | (unsigned)blo));
+    return bl;
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps y <- y + y (1/2 - (x/2) y^2), accurate to about one unit in the
+// last place.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
 }
 
 // Wave-wide (64 lanes) selection of the lane holding the first entry in pivot order.
