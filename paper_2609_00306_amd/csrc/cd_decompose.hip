@@ -308,11 +308,9 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 if (d != d || d == INFINITY) {
                     e.d = INFINITY;
                     e.idx = (int)(s0 + i);
-                    e.pad = P.act_row[s0 + i];
                 } else if (eligible(d, tau, ftol)) {
                     e.d = d;
                     e.idx = (int)(s0 + i);
-                    e.pad = P.act_row[s0 + i];    // pair row of the nominee
                 }
             }
             sNom[i] = e;
@@ -389,7 +387,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             int rank = 0;
             for (int j = 0; j < nq; ++j) rank += (sNom[j].idx < me);
             sQ[rank] = me;
-            sQrow[rank] = P.rows[sNom[tid].pad];
+            sQrow[rank] = P.rows[P.act_row[me]];
         }
         for (int i = tid; i < ns; i += 256) sCand[i] = -1;
         __syncthreads();

@@ -153,30 +153,97 @@ struct Nom {
 
 __device__ __forceinline__ bool nom_before(double da, int ia, double db, int ib)
 {
-    return (da > db) || (da == db && ia < ib);
+    // evaluated without short-circuit branches (bitwise on the two tests)
+    return (da > db) | ((da == db) & (ia < ib));
 }
 
-// In-place bitonic sort of n (power of two) entries in LDS into pivot order.
-// Must be called by all threads of the block.
+// In-place bitonic sort of n (power of two, 32 <= n <= 1024) entries in LDS
+// into pivot order, by the whole 256-thread block.  Thread t holds entries
+// 4t .. 4t+3 in registers: partners at distance 1 and 2 are in the same
+// thread, at distance 4 .. 255 in another lane of the same wave (exchanged with
+// shuffles, no barrier), and only at distance 256 and 512 in another wave
+// (through LDS, two barriers per stage).  Only d and idx are sorted; 'pad' is
+// left undefined.  Must be called by all threads of the block after the
+// entries are visible to all of them.
+__device__ __forceinline__ void nom_cmpx(double &d, int &x, double od, int ox, int e, int p, int k)
+{
+    const bool asc = (e & k) == 0;               // this run goes in pivot order
+    const bool me_first = nom_before(d, x, od, ox);
+    const bool take = ((e < p) == asc) != me_first;
+    d = take ? od : d;
+    x = take ? ox : x;
+}
+
 __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
 {
+    const int tid = threadIdx.x;
+    double d[4];
+    int x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = 4 * tid + r;
+        d[r] = (e < n) ? s[e].d : -INFINITY;
+        x[r] = (e < n) ? s[e].idx : 0x7fffffff;
+    }
     for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    Nom a = s[i], b = s[ixj];
-                    bool asc = ((i & k) == 0);   // this half goes in pivot order
-                    bool a_first = nom_before(a.d, a.idx, b.d, b.idx);
-                    if (asc ? !a_first : a_first) {
-                        s[i] = b;
-                        s[ixj] = a;
+            if (j >= 256) {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    s[4 * tid + r].d = d[r];
+                    s[4 * tid + r].idx = x[r];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = 4 * tid + r, p = e ^ j;
+                    nom_cmpx(d[r], x[r], s[p].d, s[p].idx, e, p, k);
+                }
+            } else if (j >= 4) {
+                const int lj = j >> 2;
+                double od[4];
+                int ox[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {   // all exchanges in flight before any compare
+                    od[r] = __shfl_xor(d[r], lj, 64);
+                    ox[r] = __shfl_xor(x[r], lj, 64);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = 4 * tid + r;
+                    nom_cmpx(d[r], x[r], od[r], ox[r], e, e ^ j, k);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if ((r ^ j) > r) {
+                        const int e = 4 * tid + r, p = e ^ j;
+                        const double da = d[r], db = d[r ^ j];
+                        const int xa = x[r], xb = x[r ^ j];
+                        const bool asc = (e & k) == 0;
+                        if (asc != nom_before(da, xa, db, xb)) {
+                            d[r] = db;
+                            x[r] = xb;
+                            d[r ^ j] = da;
+                            x[r ^ j] = xa;
+                        }
+                        (void)p;
                     }
                 }
             }
-            __syncthreads();
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int e = 4 * tid + r;
+        if (e < n) {
+            s[e].d = d[r];
+            s[e].idx = x[r];
+        }
+    }
+    __syncthreads();
 }
 
 // Wave-wide (64 lanes) maximum of a double, broadcast to every lane, with
