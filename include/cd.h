@@ -75,6 +75,15 @@ typedef struct {
     const double *alpha;   /* device [N], bohr^-2, > 0 */
 } cd_molecule;
 
+/* Launch shapes of the decomposition kernels (0 in a field = the built-in
+ * choice).  cd_autotune measures and returns one; cd_decompose takes one
+ * through cd_decomp_opts.tuning. */
+typedef struct {
+    int32_t step2_row_tiles;   /* all-row solve: rows per workgroup in units of 16, 2..8 */
+    int32_t step1_min_rows;    /* pivot selection: at least this many active rows per
+                                  workgroup (fewer, fuller workgroups), 16..256 */
+} cd_tuning;
+
 typedef struct {
     double tau;            /* decomposition threshold (Sec. 2): stop when max D < tau; tau >= 0.
                               tau == 0 stops at max D <= n_rows * 2^-53 * max D1 */
@@ -94,6 +103,7 @@ typedef struct {
                               block k, stage i: 0 start, 1 off-block product done, 2 staged,
                               3 integrals subtracted, 4 substitution done, 5 stored */
     int64_t timeline_cap;  /* batches / blocks the timeline can hold */
+    const cd_tuning *tuning; /* optional (may be NULL): host pointer to launch shapes */
 } cd_decomp_opts;
 
 /* Sizes of one decomposition problem, filled by cd_query. */
@@ -143,6 +153,21 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
  */
 cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                        void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * cd_autotune: choose the launch shapes of cd_decompose for these problems by
+ * measurement.  Blocking (synchronises 'stream').  It runs the decomposition
+ * once per candidate shape, timing the pivot selection and the all-row solve
+ * with HIP events: first every all-row-solve tile height (2..8 row tiles of
+ * 16) with the built-in pivot-selection shape, then pivot-selection workgroups
+ * of at least 16, 32, 48 or 64 active rows with the best tile height.  The
+ * fastest shape is written to *best (host) and a last run with it leaves the
+ * problems' outputs as cd_decompose would.  opts->tuning and opts->events are
+ * ignored.  Errors as cd_decompose; a device status other than CD_OK in any
+ * run is returned as the result.
+ */
+cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                      void *ws, size_t ws_bytes, cd_tuning *best, void *stream);
 
 /* One J/K build (all pointers DEVICE unless noted). */
 typedef struct {

@@ -30,10 +30,15 @@ class cd_molecule(ctypes.Structure):
     _fields_ = [("n_basis", ctypes.c_int32), ("xyz", _vp), ("alpha", _vp)]
 
 
+class cd_tuning(ctypes.Structure):
+    _fields_ = [("step2_row_tiles", ctypes.c_int32), ("step1_min_rows", ctypes.c_int32)]
+
+
 class cd_decomp_opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("schwarz", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("events", ctypes.POINTER(ctypes.c_void_p)),
-                ("timeline", _vp), ("timeline_cap", ctypes.c_int64)]
+                ("timeline", _vp), ("timeline_cap", ctypes.c_int64),
+                ("tuning", ctypes.POINTER(cd_tuning))]
 
 
 class cd_sizes(ctypes.Structure):
@@ -62,7 +67,7 @@ class cd_transform_problem(ctypes.Structure):
 
 
 #: every function include/cd.h declares
-EXPORTS = ("cd_query", "cd_decompose", "cd_query_jk", "cd_build_jk", "cd_query_transform",
+EXPORTS = ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
            "cd_transform", "cd_last_error", "cd_version")
 
 _lib = None
@@ -88,6 +93,8 @@ def load(path: str = LIB_PATH):
                            P(ctypes.c_int64), P(cd_sizes), _vp]
     L.cd_decompose.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp,
                                ctypes.c_size_t, _vp]
+    L.cd_autotune.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp,
+                              ctypes.c_size_t, P(cd_tuning), _vp]
     L.cd_query_jk.argtypes = [P(cd_jk_problem), ctypes.c_int32, ctypes.c_int,
                               P(ctypes.c_size_t)]
     L.cd_build_jk.argtypes = [P(cd_jk_problem), ctypes.c_int32, ctypes.c_int, ctypes.c_uint32,
@@ -96,8 +103,8 @@ def load(path: str = LIB_PATH):
                                      P(ctypes.c_size_t)]
     L.cd_transform.argtypes = [P(cd_transform_problem), ctypes.c_int32, ctypes.c_uint32, _vp,
                                ctypes.c_size_t, _vp]
-    for f in ("cd_query", "cd_decompose", "cd_query_jk", "cd_build_jk", "cd_query_transform",
-              "cd_transform"):
+    for f in ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk",
+              "cd_query_transform", "cd_transform"):
         getattr(L, f).restype = ctypes.c_int
     L.cd_last_error.restype = ctypes.c_char_p
     L.cd_last_error.argtypes = []
@@ -159,7 +166,7 @@ def query(mols: Sequence[cd_molecule], tau: float, schwarz: float,
     arr = (cd_molecule * n)(*mols)
     caps = (ctypes.c_int64 * n)(*[int(c) for c in max_vectors])
     out = (cd_sizes * n)()
-    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None, None, 0)
+    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None, None, 0, None)
     _check(L.cd_query(arr, n, ctypes.byref(opts), caps, out, _stream(stream)))
     return list(out)
 
@@ -211,11 +218,13 @@ def problem(d: Decomposition) -> cd_problem:
 
 def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, sync: bool = False,
                   stream=None, workspace: Optional[torch.Tensor] = None,
-                  events: Optional[Sequence] = None, timeline: Optional[torch.Tensor] = None):
+                  events: Optional[Sequence] = None, timeline: Optional[torch.Tensor] = None,
+                  tuning: Optional[cd_tuning] = None):
     """cd_decompose on already allocated problems (one workspace per call).
 
     ``events``: optional four torch.cuda.Event(enable_timing=True) that the
-    library records at its phase boundaries on the stream."""
+    library records at its phase boundaries on the stream.  ``tuning``: launch
+    shapes (from autotune), or None for the built-in ones."""
     L = load()
     n = len(decs)
     arr = (cd_problem * n)(*[problem(d) for d in decs])
@@ -227,13 +236,32 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
         ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
     tl, cap = (None, 0) if timeline is None else (timeline.data_ptr(),
                                                    (timeline.numel() - 1) // 16)
-    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev, tl, cap)
+    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev, tl, cap,
+                          ctypes.pointer(tuning) if tuning is not None else None)
     if workspace is None:
         if n != 1:
             raise ValueError("pass a shared workspace for more than one molecule")
         workspace = decs[0].workspace
     _check(L.cd_decompose(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
                           _stream(stream)))
+
+
+def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=None,
+             workspace: Optional[torch.Tensor] = None) -> cd_tuning:
+    """cd_autotune: measure launch shapes for these problems (blocking); the
+    outputs are left as the chosen shape's decomposition."""
+    L = load()
+    n = len(decs)
+    arr = (cd_problem * n)(*[problem(d) for d in decs])
+    opts = cd_decomp_opts(float(tau), float(schwarz), 0, None, None, 0, None)
+    if workspace is None:
+        if n != 1:
+            raise ValueError("pass a shared workspace for more than one molecule")
+        workspace = decs[0].workspace
+    best = cd_tuning(0, 0)
+    _check(L.cd_autotune(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
+                         ctypes.byref(best), _stream(stream)))
+    return best
 
 
 def decompose(xyz, alpha, tau: float, schwarz: float = 1e-12, max_vectors: Optional[int] = None,

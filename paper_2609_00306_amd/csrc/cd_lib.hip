@@ -149,6 +149,13 @@ cd_status check_opts(const cd_decomp_opts *o)
     if (!o) return fail(CD_ERR_INVALID_ARG, "null opts");
     if (!(o->tau >= 0.0) || !(o->schwarz >= 0.0))
         return fail(CD_ERR_INVALID_ARG, "tau and schwarz must be finite and >= 0");
+    if (o->tuning) {
+        const int rt = o->tuning->step2_row_tiles, mr = o->tuning->step1_min_rows;
+        if (rt != 0 && (rt < 2 || rt > 8))
+            return fail(CD_ERR_INVALID_ARG, "tuning.step2_row_tiles must be 0 or 2..8");
+        if (mr != 0 && (mr < 16 || mr > SMAX))
+            return fail(CD_ERR_INVALID_ARG, "tuning.step1_min_rows must be 0 or 16..%d", SMAX);
+    }
     return CD_OK;
 }
 
@@ -174,12 +181,15 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
     return check_launch("setup kernels");
 }
 
-// Row tile of the all-row solve: the smallest 16-row multiple (2..8) that
-// gives at most one tile per compute unit, else 8 (128 rows).
-cd_status launch_step2_batch(Step2Batch &B, int64_t total_rows, int n_cu, hipStream_t st)
+// Row tile of the all-row solve: 'rt_req' 16-row tiles if given (2..8), else
+// the smallest 16-row multiple (2..8) that gives at most one tile per compute
+// unit, else 8 (128 rows).
+cd_status launch_step2_batch(Step2Batch &B, int64_t total_rows, int n_cu, int rt_req,
+                             hipStream_t st)
 {
-    const int rt = (int)std::min<int64_t>(
-        8, std::max<int64_t>(2, blocks_of(total_rows, 16 * (int64_t)n_cu)));
+    const int rt = rt_req ? rt_req
+                          : (int)std::min<int64_t>(
+                                8, std::max<int64_t>(2, blocks_of(total_rows, 16 * (int64_t)n_cu)));
     B.tile_begin[0] = 0;
     for (int i = 0; i < B.count; ++i)
         B.tile_begin[i + 1] = B.tile_begin[i] + (int32_t)blocks_of(B.m[i].n_rows, 16 * rt);
@@ -345,8 +355,11 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return probs[a].n_active > probs[b].n_active; });
     auto gmin = [&](int i) { return (int)blocks_of(probs[i].n_active, SMAX); };
+    const int min_rows = (opts->tuning && opts->tuning->step1_min_rows) ? opts->tuning->step1_min_rows
+                                                                         : 32;
     auto gmax = [&](int i) {
-        int g = (int)std::min<int64_t>(gcap, std::max<int64_t>(1, blocks_of(probs[i].n_active, 32)));
+        int g = (int)std::min<int64_t>(gcap,
+                                       std::max<int64_t>(1, blocks_of(probs[i].n_active, min_rows)));
         return std::max(g, gmin(i));
     };
     for (int i : order)
@@ -432,7 +445,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         const bool last = (i0 + kStep2Batch >= count);
         B.timeline = (last && opts->timeline) ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
         B.tl_cap = opts->timeline ? opts->timeline_cap : 0;
-        if (B.count > 0 && (s = launch_step2_batch(B, rows, di.n_cu, st))) return s;
+        const int rt_req = opts->tuning ? opts->tuning->step2_row_tiles : 0;
+        if (B.count > 0 && (s = launch_step2_batch(B, rows, di.n_cu, rt_req, st))) return s;
     }
     if ((s = record(3))) return s;
 
@@ -447,6 +461,75 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         }
     }
     return CD_OK;
+}
+
+cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                      void *ws, size_t ws_bytes, cd_tuning *best, void *stream)
+{
+    if (!best) return fail(CD_ERR_INVALID_ARG, "null best");
+    cd_status s = check_opts(opts);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[4] = {};
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(CD_ERR_DEVICE, "hipEventCreate failed");
+        }
+    void *evp[4] = {ev[0], ev[1], ev[2], ev[3]};
+    cd_tuning t{0, 0};
+    cd_decomp_opts o = *opts;
+    o.flags = 0;
+    o.events = evp;
+    o.timeline = nullptr;
+    o.timeline_cap = 0;
+    o.tuning = &t;
+    float sel = 0.f, solve = 0.f;
+    // one decomposition with the shape in t; phase times from the events
+    auto run = [&]() -> cd_status {
+        cd_status r = cd_decompose(probs, count, &o, ws, ws_bytes, stream);
+        if (r) return r;
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "stream synchronise failed");
+        for (int32_t i = 0; i < count; ++i) {
+            int32_t v = 0;
+            if (hipMemcpy(&v, probs[i].status, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "status copy failed");
+            if (v != 0) return fail((cd_status)v, "problem %d: device status %d", i, v);
+        }
+        if (hipEventElapsedTime(&sel, ev[1], ev[2]) != hipSuccess ||
+            hipEventElapsedTime(&solve, ev[2], ev[3]) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "event timing failed");
+        return CD_OK;
+    };
+    cd_tuning pick{0, 0};
+    s = run();   // warm-up with the built-in shapes
+    float best_ms = 0.f;
+    for (int rt = 2; !s && rt <= 8; ++rt) {
+        t = cd_tuning{rt, 0};
+        if ((s = run())) break;
+        if (rt == 2 || solve < best_ms) {
+            best_ms = solve;
+            pick.step2_row_tiles = rt;
+        }
+    }
+    const int rows_opts[] = {16, 32, 48, 64};
+    for (int k = 0; !s && k < 4; ++k) {
+        t = cd_tuning{pick.step2_row_tiles, rows_opts[k]};
+        if ((s = run())) break;
+        if (k == 0 || sel < best_ms) {
+            best_ms = sel;
+            pick.step1_min_rows = rows_opts[k];
+        }
+    }
+    if (!s) {
+        t = pick;
+        s = run();   // leaves the outputs of the chosen shape
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (!s) *best = pick;
+    return s;
 }
 
 // ------------------------------------------------------------------ J / K

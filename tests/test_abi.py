@@ -58,6 +58,8 @@ int main(void) {
          sizeof(cd_transform_problem));
   printf("%zu %zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
          offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events), offsetof(cd_decomp_opts, timeline_cap));
+  printf("%zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
+         offsetof(cd_decomp_opts, tuning));
   return 0;
 }
 '''
@@ -78,7 +80,8 @@ def test_binding_structs_match_header():
             ctypes.sizeof(cdlib.cd_jk_problem), ctypes.sizeof(cdlib.cd_transform_problem),
             cdlib.cd_problem.status.offset, cdlib.cd_jk_problem.status.offset,
             cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset,
-            cdlib.cd_decomp_opts.timeline_cap.offset]
+            cdlib.cd_decomp_opts.timeline_cap.offset, ctypes.sizeof(cdlib.cd_tuning),
+            cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset]
     assert mine == got
 
 
@@ -115,6 +118,16 @@ def test_argument_validation_without_device(lib):
     assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(opts), ctypes.c_void_p(0x1008),
                             1 << 30, None) == cdlib.CD_ERR_INVALID_ARG
     assert b"aligned" in lib.cd_last_error()
+    # launch shapes outside their ranges are rejected on the host
+    for rt, mr in [(1, 0), (9, 0), (0, 8), (0, 1024)]:
+        t = cdlib.cd_tuning(rt, mr)
+        o = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None, None, 0, ctypes.pointer(t))
+        assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
+                                None) == cdlib.CD_ERR_INVALID_ARG
+        assert b"tuning" in lib.cd_last_error()
+    best = cdlib.cd_tuning()
+    assert lib.cd_autotune(None, 0, ctypes.byref(opts), None, 0, None,
+                           None) == cdlib.CD_ERR_INVALID_ARG
 
 
 def test_product_path_refuses_missing_library(tmp_path):

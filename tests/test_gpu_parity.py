@@ -217,6 +217,31 @@ def test_batched_decomposition_matches_single_and_oracle():
         assert (single.L[:M] - d.L[:M]).abs().max().item() <= 1e-12
 
 
+def test_autotune_shapes_give_the_same_decomposition():
+    # the measured launch shapes change only how rows are split over
+    # workgroups, not the arithmetic of any row
+    mols = [make_molecule(6 + 3 * i, 5.0, (0.3, 1.1, 4.0), 2, seed=900 + i) for i in range(6)]
+    tau = 1e-6
+    pairs = [(m.xyz, m.alpha) for m in mols]
+    ref, rws = cdlib.allocate_many(pairs, tau, 1e-12)
+    cdlib.run_decompose(ref, tau, 1e-12, workspace=rws)
+    decs, ws = cdlib.allocate_many(pairs, tau, 1e-12)
+    t = cdlib.autotune(decs, tau, 1e-12, workspace=ws)
+    assert 2 <= t.step2_row_tiles <= 8 and t.step1_min_rows in (16, 32, 48, 64)
+    torch.cuda.synchronize()
+    for d, r in zip(decs, ref):
+        assert d.M() == r.M() and int(d.status.item()) == 0
+        assert torch.equal(d.pivots[:d.M()], r.pivots[:r.M()])
+        assert (d.L[:d.M()] - r.L[:r.M()]).abs().max().item() <= 1e-12
+    # explicit shapes at the ends of both ranges
+    for shape in [cdlib.cd_tuning(2, 16), cdlib.cd_tuning(8, 64)]:
+        cdlib.run_decompose(decs, tau, 1e-12, workspace=ws, tuning=shape)
+        torch.cuda.synchronize()
+        for d, r in zip(decs, ref):
+            assert torch.equal(d.pivots[:d.M()], r.pivots[:r.M()])
+            assert (d.L[:d.M()] - r.L[:r.M()]).abs().max().item() <= 1e-12
+
+
 def test_batched_jk_matches_single():
     mols = [make_molecule(4 + i, 4.0, (0.3, 1.1, 4.0), 3, seed=700 + i) for i in range(5)]
     decs, ws = cdlib.allocate_many([(m.xyz, m.alpha) for m in mols], 1e-6, 1e-12)
