@@ -295,28 +295,55 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             }
             if (tid == 0) s_cnt = base;
         }
-        // ---- local nominations: first CNOM+1 own rows in pivot order
-        int P2 = 32;
-        while (P2 < ns) P2 <<= 1;
-        for (int i = tid; i < P2; i += 256) {
-            Nom e;
-            e.d = -INFINITY;
-            e.idx = 0x7fffffff;
-            e.pad = 0;
-            if (i < ns) {
-                double d = sD[i];
-                if (d != d || d == INFINITY) {
-                    e.d = INFINITY;
-                    e.idx = (int)(s0 + i);
-                } else if (eligible(d, tau, ftol)) {
-                    e.d = d;
-                    e.idx = (int)(s0 + i);
+        // ---- local nominations: the first CNOM+1 own rows in pivot order, picked
+        //      by wave 0 (lane l holds rows l, l + 64, ..; a non-finite residual
+        //      is nominated as +inf)
+        if (tid < 64) {
+            double v[4];
+            int x[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = tid + 64 * j;
+                v[j] = -INFINITY;
+                x[j] = 0x7fffffff;
+                if (i < ns) {
+                    const double d = sD[i];
+                    if (d != d || d == INFINITY) {
+                        v[j] = INFINITY;
+                        x[j] = (int)(s0 + i);
+                    } else if (eligible(d, tau, ftol)) {
+                        v[j] = d;
+                        x[j] = (int)(s0 + i);
+                    }
                 }
             }
-            sNom[i] = e;
+            for (int t = 0; t <= CNOM; ++t) {
+                // this lane's first entry (rows ascend with j, so ties keep the lower j)
+                int cj = 0;
+#pragma unroll
+                for (int j = 1; j < 4; ++j) cj = nom_before(v[j], x[j], v[cj], x[cj]) ? j : cj;
+                double cd = v[0];
+                int cx = x[0];
+#pragma unroll
+                for (int j = 1; j < 4; ++j) {
+                    cd = (cj == j) ? v[j] : cd;
+                    cx = (cj == j) ? x[j] : cx;
+                }
+                const int wl = wave_pick_first(cd, cx);
+                Nom e{-INFINITY, 0x7fffffff, 0};
+                if (wl >= 0) {
+                    e.d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(cd), wl),
+                                           __builtin_amdgcn_readlane(__double2loint(cd), wl));
+                    e.idx = __builtin_amdgcn_readlane(cx, wl);
+                    if (tid == wl) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) v[j] = (cj == j) ? -INFINITY : v[j];
+                    }
+                }
+                if (tid == 0) sNom[t] = e;
+            }
         }
         __syncthreads();
-        block_sort_noms(sNom, P2);
         for (int i = tid; i <= CNOM; i += 256) P.noms[g * (CNOM + 1) + i] = sNom[i];
         if (!grid_barrier(P.gs, G, g, gen, P.spin_limit)) {
             status = 5;
@@ -325,17 +352,11 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         stamp(P, g, batch, 1);
         // ---- union of nominations; bound = first row not nominated anywhere
         const int nu = G * CNOM;
-        int U2 = 32;
+        int U2 = 64;
         while (U2 < nu) U2 <<= 1;
         for (int i = tid; i < U2; i += 256) {
-            Nom e;
-            if (i < nu) {
-                e = P.noms[(i / CNOM) * (CNOM + 1) + (i % CNOM)];
-            } else {
-                e.d = -INFINITY;
-                e.idx = 0x7fffffff;
-                e.pad = 0;
-            }
+            Nom e{-INFINITY, 0x7fffffff, 0};
+            if (i < nu) e = P.noms[(i / CNOM) * (CNOM + 1) + (i % CNOM)];
             sNom[i] = e;
         }
         if (tid < 64) {
@@ -356,7 +377,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             }
         }
         __syncthreads();
-        block_sort_noms(sNom, U2);
+        block_sort_noms(sNom, U2);   // U2 >= q + 1 entries in pivot order
         if (tid < 64) {   // sorted: the eligible nominations come first
             const unsigned long long ok =
                 __ballot(tid < q && tid < U2 && sNom[tid].d != -INFINITY);

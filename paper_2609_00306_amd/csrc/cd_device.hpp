@@ -246,46 +246,6 @@ __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
     __syncthreads();
 }
 
-// Wave-wide (64 lanes) maximum of a double, broadcast to every lane, with
-// DPP row shifts and row broadcasts (no LDS round trips).  NaN inputs are
-// ignored (fmax), callers test for them separately.
-__device__ __forceinline__ double dpp_f64(double v, double old, int ctrl, int row_mask)
-{
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int olo = __double2loint(old), ohi = __double2hiint(old);
-    int rlo, rhi;
-    switch (ctrl) {   // the DPP control must be a compile-time constant
-    case 0x111: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x111, 0xf, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x111, 0xf, 0xf, false); break;
-    case 0x112: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x112, 0xf, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x112, 0xf, 0xf, false); break;
-    case 0x114: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x114, 0xf, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x114, 0xf, 0xf, false); break;
-    case 0x118: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x118, 0xf, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x118, 0xf, 0xf, false); break;
-    case 0x142: rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x142, 0xa, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x142, 0xa, 0xf, false); break;
-    default:    rlo = __builtin_amdgcn_update_dpp(olo, lo, 0x143, 0xc, 0xf, false);
-                rhi = __builtin_amdgcn_update_dpp(ohi, hi, 0x143, 0xc, 0xf, false); break;
-    }
-    (void)row_mask;
-    return __hiloint2double(rhi, rlo);
-}
-
-__device__ __forceinline__ double wave_max_f64(double v)
-{
-    const double ninf = -INFINITY;
-    v = fmax(v, dpp_f64(v, ninf, 0x111, 0xf));   // row_shr:1
-    v = fmax(v, dpp_f64(v, ninf, 0x112, 0xf));   // row_shr:2
-    v = fmax(v, dpp_f64(v, ninf, 0x114, 0xf));   // row_shr:4
-    v = fmax(v, dpp_f64(v, ninf, 0x118, 0xf));   // row_shr:8   -> lane 15 of each row
-    v = fmax(v, dpp_f64(v, ninf, 0x142, 0xa));   // row_bcast:15 -> lanes 31, 63
-    v = fmax(v, dpp_f64(v, ninf, 0x143, 0xc));   // row_bcast:31 -> lane 63
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-
 // Wave-wide (64 lanes) maximum of an unsigned value with DPP max steps; the
 // result is read from lane 63.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v)
@@ -323,6 +283,43 @@ __device__ __forceinline__ int wave_argmax_pos(double v, double &best)
     const int blo = __builtin_amdgcn_readlane((int)lo, bl);
     best = __longlong_as_double((long long)(((unsigned long long)mh << 32) | (unsigned)blo));
     return bl;
+}
+
+// Wave-wide (64 lanes) minimum of an unsigned value with DPP min steps; the
+// result is read from lane 63.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v)
+{
+    const int id = -1;   // 0xffffffff, the identity of the minimum
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x111, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x112, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x114, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x118, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xa, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// The lane holding the first entry in pivot order (larger d, then lower idx)
+// among lanes whose d is positive or +inf; -1 if there is none.  Exact: the
+// maximum of d is taken on its bit pattern (high word, then low word among
+// ties), and equal d are broken by the minimum idx.
+__device__ __forceinline__ int wave_pick_first(double d, int idx)
+{
+    const unsigned long long key = (d > 0.0) ? (unsigned long long)__double_as_longlong(d) : 0ull;
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(hi);
+    unsigned long long tie = __ballot(hi == mh && key != 0ull);
+    if (tie == 0ull) return -1;
+    if (tie & (tie - 1)) {
+        const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+        tie = __ballot(hi == mh && lo == ml && key != 0ull);
+        if (tie & (tie - 1)) {
+            const bool mine = (tie >> (threadIdx.x & 63)) & 1ull;
+            const unsigned mi = wave_min_u32(mine ? (unsigned)idx : 0xffffffffu);
+            tie = __ballot(mine && (unsigned)idx == mi);
+        }
+    }
+    return (int)__ffsll((long long)tie) - 1;
 }
 
 // 1 / sqrt(x) for a positive normal x: the hardware estimate refined by two

@@ -114,6 +114,7 @@ __global__ __launch_bounds__(256) void k_jJ(const double *__restrict__ L, int64_
 }
 
 constexpr int JK_TKC = 32;
+constexpr int NB_SEG = 512;   // neighbour-list entries staged in LDS at a time
 using JKS = OperandStage<64, JK_TKC, true>;
 using JKR = OperandStage<64, JK_TKC, false>;
 
@@ -213,13 +214,27 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
 // Half transform over neighbour lists (FP64):
 //   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
 // tile: m = P (64), n = i (64), k = neighbour index.
+// With PLANES the FP64 result x is written split as x = b0 + b1 + b2 into three
+// BF16 planes (b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane
+// p at Yp + p * plane, row mu at mu * ldy: the operand of the 3 x BF16 exchange
+// product, split once here instead of in every tile that reads it.
+__device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, __bf16 &b2)
+{
+    b0 = (__bf16)(float)x;
+    const double r1 = x - (double)(float)b0;
+    b1 = (__bf16)(float)r1;
+    b2 = (__bf16)(float)(r1 - (double)(float)b1);
+}
+
+template <bool PLANES>
 __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
                                                      const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ nb_s,
                                                      const int32_t *__restrict__ nb_r,
                                                      const double *__restrict__ C, int ncol,
                                                      const int64_t *__restrict__ n_vectors,
-                                                     double *__restrict__ Y, int64_t ldy)
+                                                     void *__restrict__ Yv, int64_t ldy,
+                                                     int64_t plane)
 {
     __shared__ double sU[2 * JKS::kSize];
     double *sA = sU, *sB = sU + JKS::kSize;
@@ -231,19 +246,45 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
     const int64_t j0 = off[mu], deg = off[mu + 1] - j0;
     f64x4 acc[4];
     zero_acc(acc);
-    gemm_tile<4, JK_TKC, true, true>(
-        0, deg, 4,
-        [&](int64_t k, int m) -> double {
-            return LT[(int64_t)nb_r[j0 + k] * ldt + min(p0 + m, M - 1)];
-        },
-        [&](int64_t k, int n) -> double {
-            return C[(int64_t)nb_s[j0 + k] * ncol + min(n0 + n, ncol - 1)];
-        },
-        acc, sA, sB);
-    double *out = Y + (int64_t)mu * ldy;
-    for_each_acc(acc, 4, [&](int m, int n, double v) {
-        if (p0 + m < M && n0 + n < ncol) out[(p0 + m) * ncol + n0 + n] = v;
-    });
+    // the neighbour list goes through LDS in segments, so no operand load waits
+    // on a global index load
+    __shared__ int sNs[NB_SEG], sNr[NB_SEG];
+    for (int64_t seg = 0; seg < deg; seg += NB_SEG) {
+        const int len = (int)min((int64_t)NB_SEG, deg - seg);
+        __syncthreads();
+        for (int e = threadIdx.x; e < len; e += 256) {
+            sNs[e] = nb_s[j0 + seg + e];
+            sNr[e] = nb_r[j0 + seg + e];
+        }
+        __syncthreads();
+        gemm_tile<4, JK_TKC, true, true>(
+            seg, seg + len, 4,
+            [&](int64_t k, int m) -> double {
+                return LT[(int64_t)sNr[k - seg] * ldt + min(p0 + m, M - 1)];
+            },
+            [&](int64_t k, int n) -> double {
+                return C[(int64_t)sNs[k - seg] * ncol + min(n0 + n, ncol - 1)];
+            },
+            acc, sA, sB);
+    }
+    if (!PLANES) {
+        double *out = static_cast<double *>(Yv) + (int64_t)mu * ldy;
+        for_each_acc(acc, 4, [&](int m, int n, double v) {
+            if (p0 + m < M && n0 + n < ncol) out[(p0 + m) * ncol + n0 + n] = v;
+        });
+    } else {
+        __bf16 *out = static_cast<__bf16 *>(Yv) + (int64_t)mu * ldy;
+        for_each_acc(acc, 4, [&](int m, int n, double v) {
+            if (p0 + m < M && n0 + n < ncol) {
+                __bf16 b0, b1, b2;
+                split_bf16x3(v, b0, b1, b2);
+                const int64_t e = (p0 + m) * ncol + n0 + n;
+                out[e] = b0;
+                out[plane + e] = b1;
+                out[2 * plane + e] = b2;
+            }
+        });
+    }
 }
 
 // Partial K from row-major X (row mu holds the M * ncol values X^P_{i mu}):

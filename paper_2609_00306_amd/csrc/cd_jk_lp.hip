@@ -1,11 +1,12 @@
-// Reduced-precision forms of the exchange build (K): the half transform
-// X^P = Lt^P C and the product K = sum_P X^P^T X^P on FP32 or split-BF16
-// matrix cores, with FP32 accumulation inside k-slabs of 32 and FP64
-// accumulation across slabs.  The vectors L are stored in FP64 and converted
-// on load; J is always built in FP64 (it is bound by reading L).
+// Reduced-precision forms of the exchange build (K), with FP32 accumulation
+// inside k-slabs of 32 and FP64 accumulation across slabs; J is always built
+// in FP64 (it is bound by reading L).
 //
-//   FP32  : v_mfma_f32_16x16x4f32 on operands rounded to FP32.
-//   BF16X3: every operand x is split as x = b0 + b1 + b2 (round-to-nearest
+//   FP32  : the half transform X^P = Lt^P C and the product K = sum_P X^P^T X^P
+//           both on v_mfma_f32_16x16x4f32, operands rounded to FP32 on load.
+//   BF16X3: the half transform runs in FP64 and writes X split into three BF16
+//           planes (k_half_sparse<true>); the product K reads the planes
+//           (k_syrk_rows_bf16p).  Every operand x is split as x = b0 + b1 + b2 (round-to-nearest
 //           BF16 each: b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)),
 //           and a product a*c keeps the six terms up to order 2^-16:
 //           a0c0 + a0c1 + a1c0 + a0c2 + a1c1 + a2c0  (Henry, Tang & Heinecke,
@@ -136,8 +137,17 @@ struct LpStage {
                 }
             }
         } else {
-            const __bf16 *sA = reinterpret_cast<const __bf16 *>(smem);
-            const __bf16 *sB = sA + 3 * 64 * kBf16Ld;
+            mma_planes(reinterpret_cast<const __bf16 *>(smem),
+                       reinterpret_cast<const __bf16 *>(smem) + 3 * 64 * kBf16Ld, acc);
+        }
+    }
+    // BF16 planes sA[p][m][k], sB[p][n][k] (k contiguous, rows of kBf16Ld): the
+    // six products of the 3 x BF16 split into acc[r] (rows 16 r.., columns 16 w..)
+    __device__ static __forceinline__ void mma_planes(const __bf16 *sA, const __bf16 *sB,
+                                                      f32x4 (&acc)[4])
+    {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        {
             const int kk = 8 * (lane >> 4);
             bf16x8 b[3];
 #pragma unroll
@@ -215,15 +225,25 @@ __global__ __launch_bounds__(256) void k_half_sparse_lp(const double *__restrict
     const int mu = blockIdx.z;
     const int64_t j0 = off[mu], deg = off[mu + 1] - j0;
     double acc[4][4] = {};
-    lp_tile<MODE, false>(
-        0, deg,
-        [&](int64_t k, int m) -> double {
-            return LT[(int64_t)nb_r[j0 + k] * ldt + min(p0 + m, M - 1)];
-        },
-        [&](int64_t k, int n) -> double {
-            return C[(int64_t)nb_s[j0 + k] * ncol + min(n0 + n, ncol - 1)];
-        },
-        acc, smem);
+    __shared__ int sNs[NB_SEG], sNr[NB_SEG];   // neighbour list, staged in segments
+    for (int64_t seg = 0; seg < deg; seg += NB_SEG) {
+        const int len = (int)min((int64_t)NB_SEG, deg - seg);
+        __syncthreads();
+        for (int e = threadIdx.x; e < len; e += 256) {
+            sNs[e] = nb_s[j0 + seg + e];
+            sNr[e] = nb_r[j0 + seg + e];
+        }
+        __syncthreads();
+        lp_tile<MODE, false>(
+            seg, seg + len,
+            [&](int64_t k, int m) -> double {
+                return LT[(int64_t)sNr[k - seg] * ldt + min(p0 + m, M - 1)];
+            },
+            [&](int64_t k, int n) -> double {
+                return C[(int64_t)sNs[k - seg] * ncol + min(n0 + n, ncol - 1)];
+            },
+            acc, smem);
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     float *out = Y + (int64_t)mu * ldy;
 #pragma unroll
@@ -270,6 +290,85 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
         for (int v = 0; v < 4; ++v) {
             const int m = m0 + 16 * r + lp_row(lane, v), n = n0 + 16 * w + (lane & 15);
             if (m < N && n < N) out[(int64_t)m * N + n] = acc[r][v];
+        }
+}
+
+// Partial K from X held as three BF16 planes (written by the FP64 half
+// transform): Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k] with the six
+// products of the 3 x BF16 split, FP32 inside each 32-k chunk, FP64 across.
+// Each thread loads one 16-byte piece (8 values) of one row per plane and
+// operand; ldx is a multiple of 8 so the pieces are aligned.
+__global__ __launch_bounds__(256) void k_syrk_rows_bf16p(const __bf16 *__restrict__ Xp,
+                                                         int64_t ldx, int64_t plane, int N,
+                                                         const int64_t *__restrict__ n_vectors,
+                                                         int ncol, int nsplit,
+                                                         double *__restrict__ Kp)
+{
+    using S = LpStage<LP_BF16X3, true>;
+    constexpr int LD = S::kBf16Ld;
+    __shared__ __align__(16) __bf16 sA[3 * 64 * LD];
+    __shared__ __align__(16) __bf16 sB[3 * 64 * LD];
+    const int t = blockIdx.x;
+    int tm = 0;
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    const int s = blockIdx.y;
+    const int64_t nk = *n_vectors * ncol;
+    int64_t per = (nk + nsplit - 1) / nsplit;
+    per = (per + LP_SLAB - 1) / LP_SLAB * LP_SLAB;
+    const int64_t kb = s * per;
+    const int64_t ke = (kb + per < nk) ? kb + per : nk;
+    const int m0 = tm * 64, n0 = tn * 64;
+    const int tid = threadIdx.x, row = tid >> 2, kv = 8 * (tid & 3);
+    const __bf16 *pa = Xp + (int64_t)min(m0 + row, N - 1) * ldx + kv;
+    const __bf16 *pb = Xp + (int64_t)min(n0 + row, N - 1) * ldx + kv;
+    double acc64[4][4] = {};
+    f32x4 acc[4];
+    bf16x8 va[3], vb[3];
+    auto fetch = [&](int64_t k0) {
+        if (k0 + kv + 8 <= ke) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                va[p] = *reinterpret_cast<const bf16x8 *>(pa + p * plane + k0);
+                vb[p] = *reinterpret_cast<const bf16x8 *>(pb + p * plane + k0);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool ok = k0 + kv + j < ke;
+                    va[p][j] = ok ? pa[p * plane + k0 + j] : (__bf16)0.0f;
+                    vb[p][j] = ok ? pb[p * plane + k0 + j] : (__bf16)0.0f;
+                }
+        }
+    };
+    if (kb < ke) fetch(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += LP_TKC) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            *reinterpret_cast<bf16x8 *>(&sA[(p * 64 + row) * LD + kv]) = va[p];
+            *reinterpret_cast<bf16x8 *>(&sB[(p * 64 + row) * LD + kv]) = vb[p];
+        }
+        __syncthreads();
+        if (k0 + LP_TKC < ke) fetch(k0 + LP_TKC);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+        S::mma_planes(sA, sB, acc);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[r][v] += (double)acc[r][v];
+    }
+    const int lane = tid & 63, w = tid >> 6;
+    double *out = Kp + (int64_t)s * N * N;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = m0 + 16 * r + lp_row(lane, v), n = n0 + 16 * w + (lane & 15);
+            if (m < N && n < N) out[(int64_t)m * N + n] = acc64[r][v];
         }
 }
 

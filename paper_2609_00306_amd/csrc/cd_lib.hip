@@ -584,6 +584,10 @@ struct JkWs {
     size_t bytes;
 };
 
+// Row stride (in values) of the BF16 planes of X: a multiple of 8, so every
+// row starts 16-byte aligned.
+int64_t bf16_ld(int64_t n) { return (n + 7) / 8 * 8; }
+
 JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
 {
     JkWs w{};
@@ -593,7 +597,11 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
     w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
     w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
     w.sp = carve_sparse(c, N, p.n_rows, p.max_vectors);
-    w.X = c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_occ * N));
+    // X: FP64 [N][M O], FP32 in the same space, or three BF16 planes of rows of
+    // bf16_ld(M O) values
+    const int64_t xf = p.max_vectors * (int64_t)p.n_occ * N;
+    const int64_t xb = (3 * N * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
+    w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.bytes = c.off;
     return w;
@@ -670,8 +678,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
         if (prec == CD_FP64) {
-            k_half_sparse<<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
-                                                 p.n_vectors, w.X, ldx);
+            k_half_sparse<false><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+                                                        p.n_vectors, w.X, ldx, 0);
             k_syrk_rows<<<sgrid, 256, 0, st>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
@@ -679,10 +687,14 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, st>>>(X32, ldx, (int)N, p.n_vectors, O,
                                                           nsplit, w.Kp);
         } else {
-            k_half_sparse_lp<LP_BF16X3><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r,
-                                                               p.C, O, p.n_vectors, X32, ldx);
-            k_syrk_rows_lp<LP_BF16X3><<<sgrid, 256, 0, st>>>(X32, ldx, (int)N, p.n_vectors, O,
-                                                             nsplit, w.Kp);
+            // X in FP64 (matrix cores), written split into three BF16 planes; the
+            // exchange product then runs on BF16 matrix cores from the planes
+            const int64_t ldb = bf16_ld(ldx), plane = N * ldb;
+            __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
+            k_half_sparse<true><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+                                                       p.n_vectors, Xp, ldb, plane);
+            k_syrk_rows_bf16p<<<sgrid, 256, 0, st>>>(Xp, ldb, plane, (int)N, p.n_vectors, O,
+                                                     nsplit, w.Kp);
         }
         k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
@@ -737,10 +749,10 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
         const int64_t ldy = mv * p.q;
         if (n > 0) {
             launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
-            k_half_sparse<<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
-                                 (unsigned)N),
-                            256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
-                                          p.n_vectors, Y, ldy);
+            k_half_sparse<false><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
+                                        (unsigned)N),
+                                   256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
+                                                 p.n_vectors, Y, ldy, 0);
         } else {
             k_fill_f64<<<256, 256, 0, st>>>(Y, mv * N * p.q, 0.0);
         }
