@@ -41,10 +41,10 @@ KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.7, 1048576.0 / 1048576.0
 COUNTERS = {
-    "sources_sha256": "22fb6fbc55c4d0e30c53634d6b21d7589e1ce42f64857a7edfba0b1210add34f",
+    "sources_sha256": "b421c99d3422cadc23ca740036940bca9ed7bad129c6b931d57b561d378403f7",
     "workload": ("C2", 1e-6),
-    "fetch_kib": {"k_step2": 2348735.6, "k_step1": 160883.5},
-    "write_kib": {"k_step2": 259274.9, "k_step1": 112058.5},
+    "fetch_kib": {"k_step2": 2348735.1, "k_step1": 73919.5},
+    "write_kib": {"k_step2": 259273.6, "k_step1": 29445.0},
 }
 
 
