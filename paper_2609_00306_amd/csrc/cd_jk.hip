@@ -287,6 +287,21 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
     }
 }
 
+// Work item of a split-k exchange product launched as a 1-D grid of
+// pairs x nsplit workgroups (nsplit a multiple of 8).  Workgroups are dealt to
+// the 8 XCDs round robin, so workgroup g runs on XCD g % 8; giving every k-split
+// to one XCD (all tile pairs of split s on XCD s % 8, dispatched together)
+// lets the pairs that read the same rows of X share that XCD's L2, and each
+// k-chunk of X comes from memory once per split instead of once per pair.
+__device__ __forceinline__ void syrk_tile_split(int N, int nsplit, int &t, int &s)
+{
+    const int T = (N + 63) / 64, pairs = T * (T + 1) / 2;
+    const int g = blockIdx.x, xcd = g & 7, j = g >> 3;
+    s = xcd + 8 * (j / pairs);
+    t = j % pairs;
+    (void)nsplit;
+}
+
 // Partial K from row-major X (row mu holds the M * ncol values X^P_{i mu}):
 //   Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k]   (lower tile pairs)
 __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X, int64_t ldx,
@@ -295,11 +310,11 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
 {
     __shared__ double sU[2 * JKR::kSize];
     double *sA = sU, *sB = sU + JKR::kSize;
-    const int t = blockIdx.x;
+    int t, s;
+    syrk_tile_split(N, nsplit, t, s);
     int tm = 0;
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
-    const int s = blockIdx.y;
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
     per = (per + JK_TKC - 1) / JK_TKC * JK_TKC;

@@ -265,11 +265,11 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
                                                       double *__restrict__ Kp)
 {
     __shared__ __align__(16) unsigned char smem[LpStage<MODE, true>::kBytes];
-    const int t = blockIdx.x;
+    int t, s;
+    syrk_tile_split(N, nsplit, t, s);
     int tm = 0;
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
-    const int s = blockIdx.y;
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
     per = (per + LP_SLAB - 1) / LP_SLAB * LP_SLAB;
@@ -308,11 +308,11 @@ __global__ __launch_bounds__(256) void k_syrk_rows_bf16p(const __bf16 *__restric
     constexpr int LD = S::kBf16Ld;
     __shared__ __align__(16) __bf16 sA[3 * 64 * LD];
     __shared__ __align__(16) __bf16 sB[3 * 64 * LD];
-    const int t = blockIdx.x;
+    int t, s;
+    syrk_tile_split(N, nsplit, t, s);
     int tm = 0;
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     const int tn = t - tm * (tm + 1) / 2;
-    const int s = blockIdx.y;
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
     per = (per + LP_SLAB - 1) / LP_SLAB * LP_SLAB;

@@ -535,12 +535,15 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
 // ------------------------------------------------------------------ J / K
 namespace {
 
+// k-splits of the exchange product: a multiple of 8 (one XCD per split, see
+// syrk_tile_split) giving at least two workgroups per compute unit.
 int jk_nsplit(int N, int n_cu)
 {
     const int T = (N + 63) / 64;
     const int pairs = T * (T + 1) / 2;
     int ns = (2 * n_cu + pairs - 1) / std::max(1, pairs);
-    return std::max(1, std::min(ns, 64));
+    ns = (ns + 7) / 8 * 8;
+    return std::max(8, std::min(ns, 64));
 }
 
 // Unpacking of the packed vectors for the J/K and transform products: a
@@ -673,7 +676,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                                                          (int)N, p.J);
         const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
         const int T = (int)blocks_of(N, 64);
-        const dim3 sgrid(T * (T + 1) / 2, nsplit);
+        const unsigned sgrid = (unsigned)(T * (T + 1) / 2 * nsplit);   // see syrk_tile_split
         const int64_t ldx = mv * O;
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
