@@ -174,6 +174,20 @@ __device__ __forceinline__ void nom_cmpx(double &d, int &x, double od, int ox, i
     x = take ? ox : x;
 }
 
+// Compare-exchange of register entries a < b (compile-time indices) of one
+// thread; e is the element index of entry a.
+__device__ __forceinline__ void nom_cmpx_regs(double (&d)[4], int (&x)[4], int a, int b, int e, int k)
+{
+    const bool asc = (e & k) == 0;
+    const bool swap = asc != nom_before(d[a], x[a], d[b], x[b]);
+    const double da = d[a], db = d[b];
+    const int xa = x[a], xb = x[b];
+    d[a] = swap ? db : da;
+    x[a] = swap ? xb : xa;
+    d[b] = swap ? da : db;
+    x[b] = swap ? xa : xb;
+}
+
 __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
 {
     const int tid = threadIdx.x;
@@ -214,23 +228,12 @@ __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
                     const int e = 4 * tid + r;
                     nom_cmpx(d[r], x[r], od[r], ox[r], e, e ^ j, k);
                 }
+            } else if (j == 2) {
+                nom_cmpx_regs(d, x, 0, 2, 4 * tid, k);
+                nom_cmpx_regs(d, x, 1, 3, 4 * tid + 1, k);
             } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if ((r ^ j) > r) {
-                        const int e = 4 * tid + r, p = e ^ j;
-                        const double da = d[r], db = d[r ^ j];
-                        const int xa = x[r], xb = x[r ^ j];
-                        const bool asc = (e & k) == 0;
-                        if (asc != nom_before(da, xa, db, xb)) {
-                            d[r] = db;
-                            x[r] = xb;
-                            d[r ^ j] = da;
-                            x[r ^ j] = xa;
-                        }
-                        (void)p;
-                    }
-                }
+                nom_cmpx_regs(d, x, 0, 1, 4 * tid, k);
+                nom_cmpx_regs(d, x, 2, 3, 4 * tid + 2, k);
             }
         }
     }
