@@ -240,6 +240,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     __shared__ int sCand[SMAX];       // local row -> candidate index, or -1
     __shared__ double sC[S1_LROWS][QMAX + 1];   // candidate columns of the first eligible rows
     __shared__ int sQ[QMAX];          // candidate slots
+    __shared__ double sQd[QMAX];      // candidate residual diagonals
+    __shared__ RowRec sRow[SMAX];     // pair data of this workgroup's active rows
     __shared__ RowRec sQrow[QMAX];    // candidate pair data
     __shared__ int sPiv[QMAX];        // candidate index of in-batch pivot t
     __shared__ double sDp[QMAX];      // pivot values
@@ -274,7 +276,10 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         if (g == 0 && tid == 0) *P.status = 5;  // CD_ERR_DEVICE: device and host counts differ
         return;
     }
-    for (int i = tid; i < ns; i += 256) sD[i] = P.D_act[s0 + i];
+    for (int i = tid; i < ns; i += 256) {
+        sD[i] = P.D_act[s0 + i];
+        sRow[i] = P.rows[P.act_row[s0 + i]];
+    }
     int64_t K = 0;
     int64_t batch = 0;
     int status = 0;
@@ -408,6 +413,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             int rank = 0;
             for (int j = 0; j < nq; ++j) rank += (sNom[j].idx < me);
             sQ[rank] = me;
+            sQd[rank] = sNom[tid].d;     // the residual diagonal as nominated (= D_act)
             sQrow[rank] = P.rows[P.act_row[me]];
         }
         for (int i = tid; i < ns; i += 256) sCand[i] = -1;
@@ -448,8 +454,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 if (n < nq) {
                     const int li = pb + m;
                     const int64_t slot = s0 + sList[li];
-                    const RowRec ra = P.rows[P.act_row[slot]];
-                    const double v = eri(ra, sQrow[n]) - sU[m * 65 + n];
+                    const double v = eri(sRow[sList[li]], sQrow[n]) - sU[m * 65 + n];
                     if (li < S1_LROWS) sC[li][n] = v;
                     else P.Cbuf[(int64_t)n * n_act + slot] = v;
                     const int ci = sCand[sList[li]];
@@ -466,15 +471,26 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         stamp(P, g, batch, 4);
 
         // ---- in-batch factorisation of the candidate block (every workgroup)
-        for (int e = tid; e < nq * nq; e += 256) {
-            int i = e / nq, j = e % nq;
-            sS[i][j] = P.Cblk[i * QMAX + j];
+        {
+            // the whole [QMAX][QMAX] block in 16-byte loads, all issued before
+            // the first use (rows and columns past nq are read, not kept)
+            constexpr int NV = QMAX * QMAX / (2 * 256);
+            const double2 *src = reinterpret_cast<const double2 *>(P.Cblk);
+            double2 v[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) v[u] = src[tid + 256 * u];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int e = 2 * (tid + 256 * u), i = e / QMAX, j = e % QMAX;
+                if (i < nq && j < nq) sS[i][j] = v[u].x;
+                if (i < nq && j + 1 < nq) sS[i][j + 1] = v[u].y;
+            }
         }
         __syncthreads();
         if (tid < 64) {
             const int i = tid;
             const bool valid = i < nq;
-            double dq = valid ? P.D_act[sQ[i]] : -INFINITY;
+            double dq = valid ? sQd[i] : -INFINITY;
             const int myslot = valid ? sQ[i] : 0x7fffffff;
             bool used = !valid;
             const double U = s_U;
