@@ -194,42 +194,28 @@ __device__ __forceinline__ void stamp(const Step1Params &P, int g, int64_t batch
         P.timeline[batch * 8 + what] = (int64_t)wall_clock64();
 }
 
-// In-batch value: (c - sum_{tp<t} own[tp] piv[tp]) * inv, the sum taken in four
-// interleaved partial sums (tp mod 4) combined as (s0 + s1) + (s2 + s3).  The
-// row update repeats exactly this arithmetic, so candidate rows agree bit for
-// bit with the block factorisation.  Reads go in chunks of 8 (16-byte loads);
-// entries past t are masked, not read into the sums.  The first chunk's reads
-// are issued before 'inv' is formed, so the two overlap.
-__device__ __forceinline__ void inbatch_chunk(const double *__restrict__ own,
-                                              const double *__restrict__ piv, int tp, int t,
-                                              double (&a)[4])
+// In-batch value of step t: (c - sum_{tp<t} own[tp] piv[tp]) / sqrt(pivot), the
+// sum taken in four interleaved partial sums a[tp mod 4], each in increasing
+// tp, combined as (a0 + a1) + (a2 + a3).  The row update repeats exactly this
+// arithmetic, so candidate rows agree bit for bit with the block
+// factorisation.  The steps run in groups of 8: earlier full groups are read
+// from LDS (16-byte loads, no masking), the current group's own values sit in
+// registers at compile-time indices.
+__device__ __forceinline__ void inbatch_group(const double *__restrict__ own,
+                                              const double *__restrict__ piv, double (&a)[4])
 {
     double x[8], y[8];
 #pragma unroll
     for (int u = 0; u < 8; u += 2) {
-        const double2 xo = *reinterpret_cast<const double2 *>(own + tp + u);
-        const double2 yo = *reinterpret_cast<const double2 *>(piv + tp + u);
+        const double2 xo = *reinterpret_cast<const double2 *>(own + u);
+        const double2 yo = *reinterpret_cast<const double2 *>(piv + u);
         x[u] = xo.x;
         x[u + 1] = xo.y;
         y[u] = yo.x;
         y[u + 1] = yo.y;
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const double f = fma(-x[u], y[u], a[u & 3]);
-        a[u & 3] = (tp + u < t) ? f : a[u & 3];
-    }
-}
-
-__device__ __forceinline__ double inbatch_value(double c, const double *__restrict__ own,
-                                                const double *__restrict__ piv, int t,
-                                                double bd, double &inv)
-{
-    double a[4] = {c, 0.0, 0.0, 0.0};
-    inbatch_chunk(own, piv, 0, t, a);
-    inv = rsqrt_nr(bd);
-    for (int tp = 8; tp < t; tp += 8) inbatch_chunk(own, piv, tp, t, a);
-    return ((a[0] + a[1]) + (a[2] + a[3])) * inv;
+    for (int u = 0; u < 8; ++u) a[u & 3] = fma(-x[u], y[u], a[u & 3]);
 }
 
 __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
@@ -500,32 +486,49 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             // lane t keeps the record of in-batch step t (pivot lane, value, 1/sqrt)
             int rec_bl = 0;
             double rec_bd = 0.0, rec_inv = 0.0;
-            for (int t = 0; t < QMAX; ++t) {
-                const double val = used ? -INFINITY : dq;
-                double bd;
-                const int bl = wave_argmax_pos(val, bd);         // lowest lane = lowest row
-                if (bl < 0) break;                               // no positive residual left
-                const int bi = __builtin_amdgcn_readlane(myslot, bl);
-                const bool first = nom_before(bd, bi, U, iU);    // provably the global argmax
-                const bool elig = eligible(bd, tau, ftol);       // max D >= tau
-                if (!first || !elig || t >= room) {
-                    if (first) {
-                        stop = 1;
-                        st = elig ? 3 : 0;                       // capacity, or done
+            double cur[8];   // this lane's values of the current group of 8 steps
+            bool done = false;
+            for (int c = 0; c < QMAX / 8 && !done; ++c) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = 8 * c + u;
+                    const double val = used ? -INFINITY : dq;
+                    double bd;
+                    const int bl = wave_argmax_pos(val, bd);     // lowest lane = lowest row
+                    if (bl < 0) {                                // no positive residual left
+                        done = true;
+                        break;
                     }
-                    break;
+                    const int bi = __builtin_amdgcn_readlane(myslot, bl);
+                    const bool first = nom_before(bd, bi, U, iU);   // provably the global argmax
+                    const bool elig = eligible(bd, tau, ftol);      // max D >= tau
+                    if (!first || !elig || t >= room) {
+                        if (first) {
+                            stop = 1;
+                            st = elig ? 3 : 0;                   // capacity, or done
+                        }
+                        done = true;
+                        break;
+                    }
+                    const double *pv = sH[bl];
+                    double a[4] = {sS[i][bl], 0.0, 0.0, 0.0};
+                    for (int cp = 0; cp < c; ++cp) inbatch_group(sH[i] + 8 * cp, pv + 8 * cp, a);
+#pragma unroll
+                    for (int up = 0; up < u; ++up)
+                        a[up & 3] = fma(-cur[up], pv[8 * c + up], a[up & 3]);
+                    const double inv = rsqrt_nr(bd);
+                    const double lt = ((a[0] + a[1]) + (a[2] + a[3])) * inv;
+                    cur[u] = lt;
+                    dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
+                    used = used || (i == bl);
+                    sH[i][t] = lt;
+                    rec_bl = (i == t) ? bl : rec_bl;
+                    rec_bd = (i == t) ? bd : rec_bd;
+                    rec_inv = (i == t) ? inv : rec_inv;
+                    // LDS accesses of one wave complete in order; keep the compiler's order
+                    __asm__ volatile("" ::: "memory");
+                    kb = t + 1;
                 }
-                double inv;
-                const double lt = inbatch_value(sS[i][bl], sH[i], sH[bl], t, bd, inv);
-                dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
-                used = used || (i == bl);
-                sH[i][t] = lt;
-                rec_bl = (i == t) ? bl : rec_bl;
-                rec_bd = (i == t) ? bd : rec_bd;
-                rec_inv = (i == t) ? inv : rec_inv;
-                // LDS accesses of one wave complete in order; keep the compiler's order
-                __asm__ volatile("" ::: "memory");
-                kb = t + 1;
             }
             // a candidate residual that turned NaN inside the batch ends the
             // decomposition (lanes without a candidate carry no value)
