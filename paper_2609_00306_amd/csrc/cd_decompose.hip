@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     __shared__ int sPiv[QMAX];        // candidate index of in-batch pivot t
     __shared__ double sDp[QMAX];      // pivot values
     __shared__ double sRs[QMAX];      // 1 / sqrt of pivot values
-    __shared__ int s_nq, s_kb, s_stop, s_status, s_cnt;
+    __shared__ int s_nq, s_kb, s_stop, s_status, s_cnt, s_ns;
     __shared__ double s_U;
     __shared__ int s_iU;
 
@@ -341,14 +341,21 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             break;
         }
         stamp(P, g, batch, 1);
-        // ---- union of nominations; bound = first row not nominated anywhere
+        // ---- union of nominations; bound U = first row not nominated anywhere
+        //      (the best (CNOM+1)-th nomination over workgroups).  A nomination
+        //      that does not come before U can never be accepted in this batch
+        //      (its residual only decreases, and the block factorisation stops
+        //      at the first pivot that does not come before U), so only the
+        //      nominations before U are kept; they are a prefix of the full
+        //      union in pivot order, so the candidates and the bound are those
+        //      of the full union with the never-accepted rows left out.
         const int nu = G * CNOM;
-        int U2 = 64;
-        while (U2 < nu) U2 <<= 1;
-        for (int i = tid; i < U2; i += 256) {
-            Nom e{-INFINITY, 0x7fffffff, 0};
-            if (i < nu) e = P.noms[(i / CNOM) * (CNOM + 1) + (i % CNOM)];
-            sNom[i] = e;
+        Nom mine[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = tid + 256 * r;
+            mine[r] = Nom{-INFINITY, 0x7fffffff, 0};
+            if (i < nu) mine[r] = P.noms[(i / CNOM) * (CNOM + 1) + (i % CNOM)];
         }
         if (tid < 64) {
             double bd = -INFINITY;
@@ -365,10 +372,30 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             if (tid == 0) {
                 s_U = bd;
                 s_iU = bi;
+                s_ns = 0;
             }
         }
         __syncthreads();
-        block_sort_noms(sNom, U2);   // U2 >= q + 1 entries in pivot order
+        {
+            const double U = s_U;
+            const int iU = s_iU;
+            const int lane = tid & 63;
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool keep = nom_before(mine[r].d, mine[r].idx, U, iU);
+                const unsigned long long m = __ballot(keep);
+                int base = 0;
+                if (lane == 0 && m) base = atomicAdd(&s_ns, __popcll(m));
+                base = __shfl(base, 0, 64);
+                if (keep) sNom[base + __popcll(m & below)] = mine[r];
+            }
+        }
+        __syncthreads();
+        const int n_keep = s_ns;
+        int U2 = 32;
+        while (U2 < n_keep) U2 <<= 1;
+        block_sort_noms(sNom, U2, n_keep);   // entries past n_keep sort as fillers
         if (tid < 64) {   // sorted: the eligible nominations come first
             const unsigned long long ok =
                 __ballot(tid < q && tid < U2 && sNom[tid].d != -INFINITY);

@@ -158,7 +158,8 @@ __device__ __forceinline__ bool nom_before(double da, int ia, double db, int ib)
 }
 
 // In-place bitonic sort of n (power of two, 32 <= n <= 1024) entries in LDS
-// into pivot order, by the whole 256-thread block.  Thread t holds entries
+// into pivot order, by the whole 256-thread block; entries at 'valid' and past
+// it are not read and sort as fillers (-inf, largest index).  Thread t holds entries
 // 4t .. 4t+3 in registers: partners at distance 1 and 2 are in the same
 // thread, at distance 4 .. 255 in another lane of the same wave (exchanged with
 // shuffles, no barrier), and only at distance 256 and 512 in another wave
@@ -188,7 +189,7 @@ __device__ __forceinline__ void nom_cmpx_regs(double (&d)[4], int (&x)[4], int a
     x[b] = swap ? xa : xb;
 }
 
-__device__ __forceinline__ void block_sort_noms(Nom *s, int n)
+__device__ __forceinline__ void block_sort_noms(Nom *s, int n, int valid)
 {
     const int tid = threadIdx.x;
     double d[4];
@@ -196,8 +197,8 @@ __device__ __forceinline__ void block_sort_noms(Nom *s, int n)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int e = 4 * tid + r;
-        d[r] = (e < n) ? s[e].d : -INFINITY;
-        x[r] = (e < n) ? s[e].idx : 0x7fffffff;
+        d[r] = (e < valid) ? s[e].d : -INFINITY;
+        x[r] = (e < valid) ? s[e].idx : 0x7fffffff;
     }
     for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
