@@ -198,9 +198,9 @@ __device__ __forceinline__ void stamp(const Step1Params &P, int g, int64_t batch
 // sum taken in four interleaved partial sums a[tp mod 4], each in increasing
 // tp, combined as (a0 + a1) + (a2 + a3).  The row update repeats exactly this
 // arithmetic, so candidate rows agree bit for bit with the block
-// factorisation.  The steps run in groups of 8: earlier full groups are read
-// from LDS (16-byte loads, no masking), the current group's own values sit in
-// registers at compile-time indices.
+// factorisation.  The steps run in groups of 8 (the step within the group is
+// a compile-time index): earlier full groups are read with 16-byte loads and
+// the current group's first entries at fixed offsets, so nothing is masked.
 __device__ __forceinline__ void inbatch_group(const double *__restrict__ own,
                                               const double *__restrict__ piv, double (&a)[4])
 {
@@ -360,11 +360,18 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         if (tid < 64) {
             double bd = -INFINITY;
             int bi = 0x7fffffff;
-            for (int h = tid; h < G; h += 64) {
-                Nom e = P.noms[h * (CNOM + 1) + CNOM];
-                if (nom_before(e.d, e.idx, bd, bi)) {
-                    bd = e.d;
-                    bi = e.idx;
+            Nom e[S1_MAXG / 64];   // all loads in flight before the first compare
+#pragma unroll
+            for (int r = 0; r < S1_MAXG / 64; ++r) {
+                const int h = tid + 64 * r;
+                e[r] = Nom{-INFINITY, 0x7fffffff, 0};
+                if (h < G) e[r] = P.noms[h * (CNOM + 1) + CNOM];
+            }
+#pragma unroll
+            for (int r = 0; r < S1_MAXG / 64; ++r) {
+                if (nom_before(e[r].d, e[r].idx, bd, bi)) {
+                    bd = e[r].d;
+                    bi = e[r].idx;
                 }
             }
             int lo;
@@ -513,7 +520,6 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             // lane t keeps the record of in-batch step t (pivot lane, value, 1/sqrt)
             int rec_bl = 0;
             double rec_bd = 0.0, rec_inv = 0.0;
-            double cur[8];   // this lane's values of the current group of 8 steps
             bool done = false;
             for (int c = 0; c < QMAX / 8 && !done; ++c) {
 #pragma unroll
@@ -540,12 +546,12 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                     const double *pv = sH[bl];
                     double a[4] = {sS[i][bl], 0.0, 0.0, 0.0};
                     for (int cp = 0; cp < c; ++cp) inbatch_group(sH[i] + 8 * cp, pv + 8 * cp, a);
+                    const double *ow = sH[i] + 8 * c;
 #pragma unroll
                     for (int up = 0; up < u; ++up)
-                        a[up & 3] = fma(-cur[up], pv[8 * c + up], a[up & 3]);
+                        a[up & 3] = fma(-ow[up], pv[8 * c + up], a[up & 3]);
                     const double inv = rsqrt_nr(bd);
                     const double lt = ((a[0] + a[1]) + (a[2] + a[3])) * inv;
-                    cur[u] = lt;
                     dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
                     used = used || (i == bl);
                     sH[i][t] = lt;
