@@ -161,11 +161,12 @@ __device__ __forceinline__ bool nom_before(double da, int ia, double db, int ib)
 // into pivot order, by the whole 256-thread block; entries at 'valid' and past
 // it are not read and sort as fillers (-inf, largest index).  Thread t holds entries
 // 4t .. 4t+3 in registers: partners at distance 1 and 2 are in the same
-// thread, at distance 4 .. 255 in another lane of the same wave (exchanged with
-// shuffles, no barrier), and only at distance 256 and 512 in another wave
-// (through LDS, two barriers per stage).  Only d and idx are sorted; 'pad' is
-// left undefined.  Must be called by all threads of the block after the
-// entries are visible to all of them.
+// thread, at distance 4 .. 255 in another lane of the same wave (exchanged
+// with DPP, swizzles or lane permutes chosen per stage at compile time, no
+// barrier), and only at distance 256 and 512 in another wave (through LDS, two
+// barriers per stage); up to 256 entries are sorted by wave 0 alone.  Only d
+// and idx are sorted; 'pad' is left undefined.  Must be called by all threads
+// of the block after the entries are visible to all of them.
 __device__ __forceinline__ void nom_cmpx(double &d, int &x, double od, int ox, int e, int p, int k)
 {
     const bool asc = (e & k) == 0;               // this run goes in pivot order
@@ -189,9 +190,87 @@ __device__ __forceinline__ void nom_cmpx_regs(double (&d)[4], int (&x)[4], int a
     x[b] = swap ? xa : xb;
 }
 
+// Value of lane (l ^ m) for a compile-time lane mask m < 64: DPP quad
+// permutes for m = 1, 2, swizzles inside 32-lane halves for m = 4, 8, 16, and a
+// lane permute for m = 32.
+template <int M>
+__device__ __forceinline__ int lane_xor(int v)
+{
+    if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+    else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+    else if constexpr (M == 4 || M == 8 || M == 16) return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1f);
+    else return __shfl_xor(v, M, 64);
+}
+
+template <int M>
+__device__ __forceinline__ double lane_xor_d(double v)
+{
+    return __hiloint2double(lane_xor<M>(__double2hiint(v)), lane_xor<M>(__double2loint(v)));
+}
+
+// One bitonic stage (run length K, partner distance J, both compile-time) on
+// the four register entries of every thread (entries 4t .. 4t+3).
+template <int K, int J>
+__device__ __forceinline__ void nom_stage(double (&d)[4], int (&x)[4], Nom *s)
+{
+    const int tid = threadIdx.x;
+    if constexpr (J == 1) {
+        nom_cmpx_regs(d, x, 0, 1, 4 * tid, K);
+        nom_cmpx_regs(d, x, 2, 3, 4 * tid + 2, K);
+    } else if constexpr (J == 2) {
+        nom_cmpx_regs(d, x, 0, 2, 4 * tid, K);
+        nom_cmpx_regs(d, x, 1, 3, 4 * tid + 1, K);
+    } else if constexpr (J < 256) {
+        double od[4];
+        int ox[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {   // all exchanges in flight before any compare
+            od[r] = lane_xor_d<J / 4>(d[r]);
+            ox[r] = lane_xor<J / 4>(x[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = 4 * tid + r;
+            nom_cmpx(d[r], x[r], od[r], ox[r], e, e ^ J, K);
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s[4 * tid + r].d = d[r];
+            s[4 * tid + r].idx = x[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = 4 * tid + r, p = e ^ J;
+            nom_cmpx(d[r], x[r], s[p].d, s[p].idx, e, p, K);
+        }
+    }
+}
+
+// All stages of run length K (partner distances K/2 .. 1).
+template <int K, int J>
+__device__ __forceinline__ void nom_merge(double (&d)[4], int (&x)[4], Nom *s)
+{
+    nom_stage<K, J>(d, x, s);
+    if constexpr (J > 1) nom_merge<K, J / 2>(d, x, s);
+}
+
+// Run lengths K .. KMAX, stopping at the first one above n (uniform).
+template <int K, int KMAX>
+__device__ __forceinline__ void nom_sort_from(double (&d)[4], int (&x)[4], Nom *s, int n)
+{
+    if (K > n) return;
+    nom_merge<K, K / 2>(d, x, s);
+    if constexpr (K < KMAX) nom_sort_from<2 * K, KMAX>(d, x, s, n);
+}
+
 __device__ __forceinline__ void block_sort_noms(Nom *s, int n, int valid)
 {
     const int tid = threadIdx.x;
+    // up to 256 entries live in wave 0 alone (no barrier inside the sort)
+    const bool active = n > 256 || tid < 64;
     double d[4];
     int x[4];
 #pragma unroll
@@ -200,44 +279,8 @@ __device__ __forceinline__ void block_sort_noms(Nom *s, int n, int valid)
         d[r] = (e < valid) ? s[e].d : -INFINITY;
         x[r] = (e < valid) ? s[e].idx : 0x7fffffff;
     }
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= 256) {
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    s[4 * tid + r].d = d[r];
-                    s[4 * tid + r].idx = x[r];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int e = 4 * tid + r, p = e ^ j;
-                    nom_cmpx(d[r], x[r], s[p].d, s[p].idx, e, p, k);
-                }
-            } else if (j >= 4) {
-                const int lj = j >> 2;
-                double od[4];
-                int ox[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {   // all exchanges in flight before any compare
-                    od[r] = __shfl_xor(d[r], lj, 64);
-                    ox[r] = __shfl_xor(x[r], lj, 64);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int e = 4 * tid + r;
-                    nom_cmpx(d[r], x[r], od[r], ox[r], e, e ^ j, k);
-                }
-            } else if (j == 2) {
-                nom_cmpx_regs(d, x, 0, 2, 4 * tid, k);
-                nom_cmpx_regs(d, x, 1, 3, 4 * tid + 1, k);
-            } else {
-                nom_cmpx_regs(d, x, 0, 1, 4 * tid, k);
-                nom_cmpx_regs(d, x, 2, 3, 4 * tid + 2, k);
-            }
-        }
-    }
+    if (n > 256) nom_sort_from<2, 1024>(d, x, s, n);
+    else if (active) nom_sort_from<2, 256>(d, x, s, n);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
