@@ -765,7 +765,7 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
         f64x4 acc[RT];
         zero_acc(acc);
         gemm_tile<RT, TKC, true, false>(
-            0, b0, rt,
+            0, b0,
             [&](int64_t k, int m) -> double {
                 return (m < rows_here) ? L[k * n_rows + r0 + m] : 0.0;
             },
@@ -798,12 +798,12 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
             for (int ks = 0; ks < 64; ks += 4) {
                 const int kk = ks + (lane >> 4);
                 const double b = sG[kk * 64 + 16 * w + (lane & 15)];
+                // every row tile (rows past rows_here are never stored; an
+                // output row depends only on its own row of T)
 #pragma unroll
                 for (int r = 0; r < RT; ++r) {
-                    if (r < rt) {
-                        const double a = sT[16 * r + (lane & 15)][kk];
-                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
-                    }
+                    const double a = sT[16 * r + (lane & 15)][kk];
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
                 }
             }
             __syncthreads();

@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
         }
         __syncthreads();
         gemm_tile<4, JK_TKC, true, true>(
-            seg, seg + len, 4,
+            seg, seg + len,
             [&](int64_t k, int m) -> double {
                 return LT[(int64_t)sNr[k - seg] * ldt + min(p0 + m, M - 1)];
             },
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
     f64x4 acc[4];
     zero_acc(acc);
     gemm_tile<4, JK_TKC, false, false>(
-        kb, ke, 4,
+        kb, ke,
         [&](int64_t k, int m) -> double { return X[min(m0 + m, N - 1) * ldx + k]; },
         [&](int64_t k, int n) -> double { return X[min(n0 + n, N - 1) * ldx + k]; },
         acc, sA, sB);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int64
     f64x4 acc[4];
     zero_acc(acc);
     gemm_tile<4, JK_TKC, true, true>(
-        0, N, 4,
+        0, N,
         [&](int64_t k, int m) -> double { return C1[k * p + min(m0 + m, p - 1)]; },
         [&](int64_t k, int n) -> double { return Yp[k * ldy + min(n0 + n, q - 1)]; },
         acc, sA, sB);

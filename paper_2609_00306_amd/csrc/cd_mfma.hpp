@@ -73,13 +73,16 @@ struct OperandStage {
     }
 };
 
-// acc[r] += A(k, 16 r + .) B(k, 16 w + .)  for k in [kbeg, kend).
-// rt_active <= RT row tiles are multiplied (uniform).  la(k, m), lb(k, n)
-// return the operands (k absolute, m in [0, 16 RT), n in [0, 64)); loads with
-// k >= kend are not issued.  sA, sB: LDS of OperandStage<..>::kSize doubles.
+// acc[r] += A(k, 16 r + .) B(k, 16 w + .)  for k in [kbeg, kend), all RT row
+// tiles (rows a caller does not need read zeros from its loader; updating every
+// accumulator unconditionally keeps them out of control flow, which the
+// register allocator otherwise answers with accumulator copies).  la(k, m),
+// lb(k, n) return the operands (k absolute, m in [0, 16 RT), n in [0, 64));
+// loads with k >= kend are not issued.  sA, sB: LDS of OperandStage<..>::kSize
+// doubles.
 template <int RT, int TKC, bool AK, bool BK, class LA, class LB>
-__device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, int rt_active, LA la,
-                                          LB lb, f64x4 (&acc)[RT], double *sA, double *sB)
+__device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, LA la, LB lb,
+                                          f64x4 (&acc)[RT], double *sA, double *sB)
 {
     using SA = OperandStage<16 * RT, TKC, AK>;
     using SB = OperandStage<64, TKC, BK>;
@@ -103,10 +106,8 @@ __device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, int rt_act
             const double b = sB[SB::lds_index(kk, 16 * w + (lane & 15))];
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                if (r < rt_active) {
-                    const double a = sA[SA::lds_index(kk, 16 * r + (lane & 15))];
-                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
-                }
+                const double a = sA[SA::lds_index(kk, 16 * r + (lane & 15))];
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
             }
         }
         __syncthreads();
