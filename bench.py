@@ -41,10 +41,10 @@ KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.7, 1048576.0 / 1048576.0
 COUNTERS = {
-    "sources_sha256": "b421c99d3422cadc23ca740036940bca9ed7bad129c6b931d57b561d378403f7",
+    "sources_sha256": "58a41b1039219a78ccd6f12396725aa91ac563d493aa960304377d98e2124d20",
     "workload": ("C2", 1e-6),
-    "fetch_kib": {"k_step2": 2348735.1, "k_step1": 73919.5},
-    "write_kib": {"k_step2": 259273.6, "k_step1": 29445.0},
+    "fetch_kib": {"k_step2": 2348664.7, "k_step1": 73041.3},
+    "write_kib": {"k_step2": 259274.9, "k_step1": 29520.2},
 }
 
 

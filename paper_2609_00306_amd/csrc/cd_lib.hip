@@ -184,12 +184,31 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
 // Row tile of the all-row solve: 'rt_req' 16-row tiles if given (2..8), else
 // the smallest 16-row multiple (2..8) that gives at most one tile per compute
 // unit, else 8 (128 rows).
-cd_status launch_step2_batch(Step2Batch &B, int64_t total_rows, int n_cu, int rt_req,
-                             hipStream_t st)
+// Built-in tile height of the all-row solve.  One workgroup runs per compute
+// unit, so the solve takes ceil(tiles / n_cu) rounds of one tile each; a tile
+// of 16 RT rows costs about RT (1 + 0.04 (8 - RT)) units (taller tiles reuse
+// each pivot-row operand over more rows; the factor is a fit to measured
+// 400-, 1000- and 1200-function solves).  The cheapest RT wins, the taller on
+// ties.
+int step2_rows_default(const Step2Batch &B, int n_cu)
 {
-    const int rt = rt_req ? rt_req
-                          : (int)std::min<int64_t>(
-                                8, std::max<int64_t>(2, blocks_of(total_rows, 16 * (int64_t)n_cu)));
+    int best = 8;
+    double best_cost = 0.0;
+    for (int rt = 8; rt >= 2; --rt) {
+        int64_t tiles = 0;
+        for (int i = 0; i < B.count; ++i) tiles += blocks_of(B.m[i].n_rows, 16 * rt);
+        const double cost = (double)blocks_of(tiles, std::max(1, n_cu)) * rt * (1.0 + 0.04 * (8 - rt));
+        if (rt == 8 || cost < best_cost) {
+            best = rt;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st)
+{
+    const int rt = rt_req ? rt_req : step2_rows_default(B, n_cu);
     B.tile_begin[0] = 0;
     for (int i = 0; i < B.count; ++i)
         B.tile_begin[i + 1] = B.tile_begin[i] + (int32_t)blocks_of(B.m[i].n_rows, 16 * rt);
@@ -425,7 +444,6 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     // ---- all-row solve, up to kStep2Batch problems per launch
     for (int32_t i0 = 0; i0 < count; i0 += kStep2Batch) {
         Step2Batch B{};
-        int64_t rows = 0;
         for (int32_t i = i0; i < count && B.count < kStep2Batch; ++i) {
             const cd_problem &p = probs[i];
             if (p.n_rows == 0) continue;
@@ -440,13 +458,12 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             q.n_vectors = p.n_vectors;
             q.L = p.L;
             q.diag = p.diag;
-            rows += p.n_rows;
         }
         const bool last = (i0 + kStep2Batch >= count);
         B.timeline = (last && opts->timeline) ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
         B.tl_cap = opts->timeline ? opts->timeline_cap : 0;
         const int rt_req = opts->tuning ? opts->tuning->step2_row_tiles : 0;
-        if (B.count > 0 && (s = launch_step2_batch(B, rows, di.n_cu, rt_req, st))) return s;
+        if (B.count > 0 && (s = launch_step2_batch(B, di.n_cu, rt_req, st))) return s;
     }
     if ((s = record(3))) return s;
 
