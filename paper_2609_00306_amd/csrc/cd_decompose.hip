@@ -233,6 +233,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     __shared__ double sDp[QMAX];      // pivot values
     __shared__ double sRs[QMAX];      // 1 / sqrt of pivot values
     __shared__ int s_nq, s_kb, s_stop, s_status, s_cnt, s_ns;
+    __shared__ int s_prog, s_kbfin, s_lost;   // in-batch pivots published / final count / wait lost
     __shared__ double s_U;
     __shared__ int s_iU;
 
@@ -506,7 +507,17 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 if (i < nq && j + 1 < nq) sS[i][j + 1] = v[u].y;
             }
         }
+        if (tid == 0) {
+            s_prog = 0;
+            s_kbfin = -1;
+            s_lost = 0;
+        }
         __syncthreads();
+        // Wave 0 factors the candidate block and publishes every accepted pivot
+        // (candidate, value, 1/sqrt, its in-batch values) as soon as it is
+        // formed; waves 1-3 apply the pivots to this workgroup's eligible rows
+        // one step behind, with the same arithmetic, so candidate rows agree
+        // bit for bit.
         if (tid < 64) {
             const int i = tid;
             const bool valid = i < nq;
@@ -517,9 +528,6 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             const int iU = s_iU;
             const int64_t room = P.max_vectors - K;
             int kb = 0, stop = 0, st = 0;
-            // lane t keeps the record of in-batch step t (pivot lane, value, 1/sqrt)
-            int rec_bl = 0;
-            double rec_bd = 0.0, rec_inv = 0.0;
             bool done = false;
             for (int c = 0; c < QMAX / 8 && !done; ++c) {
 #pragma unroll
@@ -555,11 +563,16 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                     dq = (i == bl) ? 0.0 : fma(-lt, lt, dq);
                     used = used || (i == bl);
                     sH[i][t] = lt;
-                    rec_bl = (i == t) ? bl : rec_bl;
-                    rec_bd = (i == t) ? bd : rec_bd;
-                    rec_inv = (i == t) ? inv : rec_inv;
+                    if (i == 0) {
+                        sPiv[t] = bl;
+                        sDp[t] = bd;
+                        sRs[t] = inv;
+                    }
                     // LDS accesses of one wave complete in order; keep the compiler's order
                     __asm__ volatile("" ::: "memory");
+                    if (i == 0)
+                        __hip_atomic_store(&s_prog, t + 1, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                     kb = t + 1;
                 }
             }
@@ -569,45 +582,67 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 stop = 1;
                 st = 4;
             }
-            if (i < kb) {
-                sPiv[i] = rec_bl;
-                sDp[i] = rec_bd;
-                sRs[i] = rec_inv;
-            }
             if (i == 0) {
                 s_kb = kb;
                 s_stop = stop;
                 s_status = st;
+                __hip_atomic_store(&s_kbfin, kb, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            // ---- apply the accepted pivots to own eligible rows as they appear
+            for (int li = tid - 64; li < cnt; li += 192) {
+                const int sl = sList[li];
+                const int64_t slot = s0 + sl;
+                double d = sD[sl];
+                double l[QMAX];
+                bool fin = false;
+#pragma unroll
+                for (int t = 0; t < QMAX; ++t) {
+                    if (!fin) {
+                        // step t published, or the factorisation ended before it
+                        // (bounded: wave 0 always publishes the final count)
+                        const uint64_t t0 = wall_clock64();
+                        for (;;) {
+                            if (__hip_atomic_load(&s_prog, __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP) > t)
+                                break;
+                            const int kf = __hip_atomic_load(&s_kbfin, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+                            if (kf >= 0 && kf <= t) {
+                                fin = true;
+                                break;
+                            }
+                            if (wall_clock64() - t0 > 100000000ull) {   // 1 s
+                                s_lost = 1;
+                                fin = true;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    if (!fin) {
+                        const int it = sPiv[t];
+                        const double c = (li < S1_LROWS) ? sC[li][it]
+                                                         : P.Cbuf[(int64_t)it * n_act + slot];
+                        double a[4] = {c, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int tp = 0; tp < t; ++tp) a[tp & 3] = fma(-l[tp], sH[it][tp], a[tp & 3]);
+                        l[t] = ((a[0] + a[1]) + (a[2] + a[3])) * sRs[t];
+                        d = fma(-l[t], l[t], d);
+                        if (sQ[it] == slot) d = 0.0;
+                        LT[slot * ldT + K + t] = l[t];
+                    }
+                }
+                sD[sl] = d;
+                P.D_act[slot] = d;
             }
         }
         __syncthreads();
         stamp(P, g, batch, 5);
         const int kb = s_kb;
-
-        // ---- apply the accepted pivots to own eligible rows (same arithmetic
-        //      as the candidate block, so candidate rows agree bit for bit)
-        for (int li = tid; li < cnt; li += 256) {
-            const int sl = sList[li];
-            const int64_t slot = s0 + sl;
-            double d = sD[sl];
-            double l[QMAX];
-#pragma unroll
-            for (int t = 0; t < QMAX; ++t) {
-                if (t < kb) {
-                    const int it = sPiv[t];
-                    const double c = (li < S1_LROWS) ? sC[li][it]
-                                                     : P.Cbuf[(int64_t)it * n_act + slot];
-                    double a[4] = {c, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int tp = 0; tp < t; ++tp) a[tp & 3] = fma(-l[tp], sH[it][tp], a[tp & 3]);
-                    l[t] = ((a[0] + a[1]) + (a[2] + a[3])) * sRs[t];
-                    d = fma(-l[t], l[t], d);
-                    if (sQ[it] == slot) d = 0.0;
-                    LT[slot * ldT + K + t] = l[t];
-                }
-            }
-            sD[sl] = d;
-            P.D_act[slot] = d;
+        if (s_lost) {   // a row-update wait ran out of time: CD_ERR_DEVICE
+            status = 5;
+            break;
         }
         if (g == 0) {
             for (int t = tid; t < kb; t += 256) {
