@@ -469,13 +469,21 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 boff[u] = (n < nq) ? (int64_t)sQ[n] * ldT : -1;
             }
             S1K::run(K, rt, LT, aoff, boff, acc, sU);
-            S1K::wave_sum_to_lds(acc, rt, sU);
+            // up to 32 rows: the four waves' partial sums side by side, added
+            // below in wave order (the same order as the in-place sum)
+            constexpr int PR = 32 * 65;
+            static_assert(4 * PR <= S1_UNION, "partial sums do not fit");
+            if (rt <= 2) S1K::wave_store_partials(acc, rt, sU, PR);
+            else S1K::wave_sum_to_lds(acc, rt, sU);
             for (int e = tid; e < rows_m * 64; e += 256) {
                 const int m = e >> 6, n = e & 63;
                 if (n < nq) {
                     const int li = pb + m;
                     const int64_t slot = s0 + sList[li];
-                    const double v = eri(sRow[sList[li]], sQrow[n]) - sU[m * 65 + n];
+                    const int o = m * 65 + n;
+                    const double sum =
+                        (rt <= 2) ? ((sU[o] + sU[o + PR]) + sU[o + 2 * PR]) + sU[o + 3 * PR] : sU[o];
+                    const double v = eri(sRow[sList[li]], sQrow[n]) - sum;
                     if (li < S1_LROWS) sC[li][n] = v;
                     else P.Cbuf[(int64_t)n * n_act + slot] = v;
                     const int ci = sCand[sList[li]];

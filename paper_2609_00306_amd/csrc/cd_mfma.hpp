@@ -213,6 +213,30 @@ struct SplitK {
         }
     }
 
+    // Each wave stores its accumulators into its own region,
+    // sOut[w * region + m * 65 + n] (m < 16 rt): no read-modify-write, the
+    // reader sums the four regions.  Must be called by the whole workgroup;
+    // sOut may alias the wave regions.
+    __device__ static __forceinline__ void wave_store_partials(const f64x4 (&acc)[RT][4], int rt,
+                                                               double *sOut, int region)
+    {
+        const int lane = threadIdx.x & 63;
+        const int w = threadIdx.x >> 6;
+        double *o = sOut + w * region;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            if (r < rt) {
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        o[(16 * r + mfma_row(lane, v)) * 65 + 16 * ct + (lane & 15)] = acc[r][ct][v];
+            }
+        }
+        __syncthreads();
+    }
+
     // Sum the four waves' accumulators into sOut[m * 65 + n] (m < 16 rt).
     // Must be called by the whole workgroup; sOut may alias the wave regions.
     __device__ static __forceinline__ void wave_sum_to_lds(const f64x4 (&acc)[RT][4], int rt,
