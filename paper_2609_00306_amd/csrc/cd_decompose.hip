@@ -576,10 +576,13 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                         sDp[t] = bd;
                         sRs[t] = inv;
                     }
-                    // LDS accesses of one wave complete in order; keep the compiler's order
+                    // LDS operations of one wave are performed in issue order, so a
+                    // wave that reads the new count also reads the pivot data
+                    // written before it (no wait for the writes is needed here);
+                    // the compiler barrier keeps the program order
                     __asm__ volatile("" ::: "memory");
                     if (i == 0)
-                        __hip_atomic_store(&s_prog, t + 1, __ATOMIC_RELEASE,
+                        __hip_atomic_store(&s_prog, t + 1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                     kb = t + 1;
                 }
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 s_kb = kb;
                 s_stop = stop;
                 s_status = st;
-                __hip_atomic_store(&s_kbfin, kb, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(&s_kbfin, kb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         } else {
             // ---- apply the accepted pivots to own eligible rows as they appear
@@ -611,10 +614,10 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                         // (bounded: wave 0 always publishes the final count)
                         const uint64_t t0 = wall_clock64();
                         for (;;) {
-                            if (__hip_atomic_load(&s_prog, __ATOMIC_ACQUIRE,
+                            if (__hip_atomic_load(&s_prog, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP) > t)
                                 break;
-                            const int kf = __hip_atomic_load(&s_kbfin, __ATOMIC_ACQUIRE,
+                            const int kf = __hip_atomic_load(&s_kbfin, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
                             if (kf >= 0 && kf <= t) {
                                 fin = true;
@@ -627,6 +630,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                             }
                             __builtin_amdgcn_s_sleep(1);
                         }
+                        // the pivot data are read after the count (program order)
+                        __asm__ volatile("" ::: "memory");
                     }
                     if (!fin) {
                         const int it = sPiv[t];
