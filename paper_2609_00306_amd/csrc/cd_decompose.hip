@@ -761,7 +761,7 @@ __global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__
 __host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3) ? 64 : 32; }
 
 template <int RT>
-__global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
+__global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
 {
     int mol = 0;
     while (mol + 1 < B.count && (int)blockIdx.x >= B.tile_begin[mol + 1]) ++mol;
@@ -783,8 +783,8 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
     };
     constexpr int R = 16 * RT;
     constexpr int TKC = s2_tkc(RT);
-    using SA = OperandStage<R, TKC, true>;
-    using SB = OperandStage<64, TKC, false>;
+    using SA = OperandStage<R, TKC, true, 512>;
+    using SB = OperandStage<64, TKC, false, 512>;
     constexpr int kUnion = (SA::kSize + SB::kSize > R * 65) ? SA::kSize + SB::kSize : R * 65;
     __shared__ double sU[kUnion];
     __shared__ double sG[64 * 64];
@@ -795,24 +795,46 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
     double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int cw = w & 3, h = w >> 2;   // column group, k half (waves w and w + 4 share a SIMD)
     const int64_t r0 = (int64_t)tile * R;
     const int rows_here = (int)min((int64_t)R, n_rows - r0);
-    const int rt = (rows_here + 15) >> 4;
     const int64_t M = *Q.n_vectors;
     double Dfin = 0.0;
     int kp = -1;
-    for (int e = tid; e < rows_here; e += 256) sRow[e] = rows[r0 + e];
+    for (int e = tid; e < rows_here; e += 512) sRow[e] = rows[r0 + e];
     if (tid < rows_here) {
         Dfin = rows[r0 + tid].d1;
         kp = pivot_of_row[r0 + tid];
     }
+    // T[m][n] = (half 0) + (half 1) of the accumulators (rows of a partial last
+    // tile past rows_here hold values that are never stored)
+    auto halves_to_T = [&](const f64x4 (&acc)[RT]) {
+        if (h == 1) {
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sT[16 * r + mfma_row(lane, v)][16 * cw + (lane & 15)] = acc[r][v];
+        }
+        __syncthreads();
+        if (h == 0) {
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double &o = sT[16 * r + mfma_row(lane, v)][16 * cw + (lane & 15)];
+                    o = acc[r][v] + o;
+                }
+        }
+        __syncthreads();
+    };
     for (int64_t b0 = 0; b0 < M; b0 += 64) {
         const int nb = (int)min((int64_t)64, M - b0);
         const int64_t blk = b0 >> 6;
         mark(blk, 0);
         f64x4 acc[RT];
         zero_acc(acc);
-        gemm_tile<RT, TKC, true, false>(
+        gemm_tile_2w<RT, TKC, true, false>(
             0, b0,
             [&](int64_t k, int m) -> double {
                 return (m < rows_here) ? L[k * n_rows + r0 + m] : 0.0;
@@ -821,52 +843,46 @@ __global__ __launch_bounds__(256) void k_step2(const Step2Batch B)
                 return (n < nb) ? Lp[(b0 + n) * ldp + k] : 0.0;
             },
             acc, sA, sB);
-        for (int e = tid; e < 64; e += 256)
+        for (int e = tid; e < 64; e += 512)
             if (e < nb) sPr[e] = prow[b0 + e];
         {
             const double *g = Ginv + blk * 4096;
-            for (int e = tid; e < 64 * 64; e += 256) sG[e] = g[e];
+            for (int e = tid; e < 64 * 64; e += 512) sG[e] = g[e];
         }
         mark(blk, 1);
-        for_each_acc(acc, rt, [&](int m, int n, double v) { sT[m][n] = v; });
-        __syncthreads();
+        halves_to_T(acc);
         mark(blk, 2);
         // right-hand side: (r|P_K) - off-block sum
-        for (int e = tid; e < R * 64; e += 256) {
+        for (int e = tid; e < R * 64; e += 512) {
             const int m = e >> 6, j = e & 63;
             if (m < rows_here && j < nb) sT[m][j] = eri(sRow[m], sPr[j]) - sT[m][j];
         }
         __syncthreads();
         mark(blk, 3);
-        // in-block part: L_blk = T G (G upper triangular, 64 x 64)
-        {
-            zero_acc(acc);
-            const int lane = tid & 63, w = tid >> 6;
+        // in-block part: L_blk = T G (G upper triangular, 64 x 64), the k-steps
+        // split between the two halves like the off-block product
+        zero_acc(acc);
 #pragma unroll 4
-            for (int ks = 0; ks < 64; ks += 4) {
-                const int kk = ks + (lane >> 4);
-                const double b = sG[kk * 64 + 16 * w + (lane & 15)];
-                // every row tile (rows past rows_here are never stored; an
-                // output row depends only on its own row of T)
+        for (int ks = 0; ks < 64; ks += 8) {
+            const int kk = ks + 4 * h + (lane >> 4);
+            const double b = sG[kk * 64 + 16 * cw + (lane & 15)];
 #pragma unroll
-                for (int r = 0; r < RT; ++r) {
-                    const double a = sT[16 * r + (lane & 15)][kk];
-                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
-                }
+            for (int r = 0; r < RT; ++r) {
+                const double a = sT[16 * r + (lane & 15)][kk];
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
             }
-            __syncthreads();
-            for_each_acc(acc, rt, [&](int m, int n, double v) { sT[m][n] = v; });
-            __syncthreads();
-            if (tid < rows_here) {
-                for (int j = 0; j < nb; ++j) {
-                    const double l = sT[tid][j];
-                    Dfin = fma(-l, l, Dfin);
-                    if (b0 + j == kp) Dfin = 0.0;
-                }
+        }
+        __syncthreads();
+        halves_to_T(acc);
+        if (tid < rows_here) {
+            for (int j = 0; j < nb; ++j) {
+                const double l = sT[tid][j];
+                Dfin = fma(-l, l, Dfin);
+                if (b0 + j == kp) Dfin = 0.0;
             }
         }
         mark(blk, 4);
-        for (int e = tid; e < nb * R; e += 256) {
+        for (int e = tid; e < nb * R; e += 512) {
             const int j = e / R, m = e % R;
             if (m < rows_here) L[(b0 + j) * n_rows + r0 + m] = sT[m][j];
         }

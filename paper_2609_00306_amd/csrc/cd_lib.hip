@@ -186,21 +186,22 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
 // unit, else 8 (128 rows).
 // Built-in tile height of the all-row solve.  One workgroup runs per compute
 // unit, so the solve takes ceil(tiles / n_cu) rounds of one tile each; a tile
-// of 16 RT rows costs about RT (1 + 0.04 (8 - RT)) units (taller tiles reuse
-// each pivot-row operand over more rows; the factor is a fit to measured
-// 400-, 1000- and 1200-function solves).  The cheapest RT wins, the taller on
-// ties.
+// of 16 RT rows costs about RT * cost[RT] units (taller tiles reuse each
+// pivot-row operand over more rows until the 8-tile kernel runs out of
+// registers; the factors are fitted to measured 400-, 1000- and 1200-function
+// solves).  The cheapest RT wins, the taller on ties.
 int step2_rows_default(const Step2Batch &B, int n_cu)
 {
+    static const double cost[9] = {0.0, 0.0, 1.28, 1.16, 1.05, 1.0, 1.0, 0.98, 1.09};
     int best = 8;
     double best_cost = 0.0;
     for (int rt = 8; rt >= 2; --rt) {
         int64_t tiles = 0;
         for (int i = 0; i < B.count; ++i) tiles += blocks_of(B.m[i].n_rows, 16 * rt);
-        const double cost = (double)blocks_of(tiles, std::max(1, n_cu)) * rt * (1.0 + 0.04 * (8 - rt));
-        if (rt == 8 || cost < best_cost) {
+        const double c = (double)blocks_of(tiles, std::max(1, n_cu)) * rt * cost[rt];
+        if (rt == 8 || c < best_cost) {
             best = rt;
-            best_cost = cost;
+            best_cost = c;
         }
     }
     return best;
@@ -216,7 +217,7 @@ cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st
     if (grid == 0) return CD_OK;
 #define CD_STEP2(RT)                                 \
     case RT:                                         \
-        k_step2<RT><<<grid, 256, 0, st>>>(B);        \
+        k_step2<RT><<<grid, 512, 0, st>>>(B);        \
         break;
     switch (rt) {
         CD_STEP2(2)
