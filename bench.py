@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--tau", type=float, default=1e-6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--eta", type=float, default=1.0,
+                    help="span factor of the pivot selection (1 = exact pivoting)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
@@ -224,7 +226,7 @@ def main():
     N, O = m.n_basis, m.n_occ
 
     # size the outputs with the measured number of vectors
-    probe = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz)
+    probe = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, eta=args.eta)
     M = probe.M()
     assert int(probe.status.item()) == 0
     del probe
@@ -235,7 +237,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(phase_ev, jk_ev):
-        cdlib.run_decompose([d], tau, schwarz, events=phase_ev)
+        cdlib.run_decompose([d], tau, schwarz, events=phase_ev, eta=args.eta)
         jk_ev[0].record(stream)
         cdlib.run_jk(jk, args.precision)
         jk_ev[1].record(stream)
@@ -250,7 +252,7 @@ def main():
     # per-batch device-clock stamps of the pivot selection (one untimed step)
     cap = 4096
     timeline = torch.zeros(1 + 16 * cap, dtype=torch.int64, device=dev)
-    cdlib.run_decompose([d], tau, schwarz, timeline=timeline)
+    cdlib.run_decompose([d], tau, schwarz, timeline=timeline, eta=args.eta)
     torch.cuda.synchronize()
     tl = timeline.cpu().numpy()
     nbatch = int(tl[0])
@@ -342,7 +344,7 @@ def main():
                                f"{cfg['box']:.1f} A box, {len(cfg['exponents'])} exponents), "
                                f"tau={tau:g}, Schwarz {schwarz:g}, O={O}",
                    "n_basis": N, "n_rows": n, "n_active": d.n_active, "n_vectors": M,
-                   "tau": tau, "n_occ": O, "jk_precision": args.precision},
+                   "tau": tau, "n_occ": O, "jk_precision": args.precision, "eta": args.eta},
         "cd_ms": t_cd,
         "cd_vectors_per_s": M / (t_cd * 1e-3),
         "jk_ms": t_jk,

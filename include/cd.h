@@ -104,6 +104,13 @@ typedef struct {
                               3 integrals subtracted, 4 substitution done, 5 stored */
     int64_t timeline_cap;  /* batches / blocks the timeline can hold */
     const cd_tuning *tuning; /* optional (may be NULL): host pointer to launch shapes */
+    double eta;            /* span factor of the two-step first step (Sec. 3, Table 1), in [0, 1].
+                              0 or 1: exact pivoting (Sec. 2: every pivot is the row of largest
+                              residual).  0 < eta < 1: within a candidate batch a candidate is
+                              also accepted while it is the largest remaining candidate and its
+                              residual is >= eta times the batch's first pivot (the qualified set
+                              of Table 1); the pivot sequence then differs from Sec. 2, every
+                              final residual is still < tau */
 } cd_decomp_opts;
 
 /* Sizes of one decomposition problem, filled by cd_query. */

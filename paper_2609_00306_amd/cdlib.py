@@ -38,7 +38,7 @@ class cd_decomp_opts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("schwarz", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("events", ctypes.POINTER(ctypes.c_void_p)),
                 ("timeline", _vp), ("timeline_cap", ctypes.c_int64),
-                ("tuning", ctypes.POINTER(cd_tuning))]
+                ("tuning", ctypes.POINTER(cd_tuning)), ("eta", ctypes.c_double)]
 
 
 class cd_sizes(ctypes.Structure):
@@ -219,12 +219,13 @@ def problem(d: Decomposition) -> cd_problem:
 def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, sync: bool = False,
                   stream=None, workspace: Optional[torch.Tensor] = None,
                   events: Optional[Sequence] = None, timeline: Optional[torch.Tensor] = None,
-                  tuning: Optional[cd_tuning] = None):
+                  tuning: Optional[cd_tuning] = None, eta: float = 1.0):
     """cd_decompose on already allocated problems (one workspace per call).
 
     ``events``: optional four torch.cuda.Event(enable_timing=True) that the
     library records at its phase boundaries on the stream.  ``tuning``: launch
-    shapes (from autotune), or None for the built-in ones."""
+    shapes (from autotune), or None for the built-in ones.  ``eta``: span
+    factor of the two-step first step (1 = exact pivoting)."""
     L = load()
     n = len(decs)
     arr = (cd_problem * n)(*[problem(d) for d in decs])
@@ -237,7 +238,7 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
     tl, cap = (None, 0) if timeline is None else (timeline.data_ptr(),
                                                    (timeline.numel() - 1) // 16)
     opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev, tl, cap,
-                          ctypes.pointer(tuning) if tuning is not None else None)
+                          ctypes.pointer(tuning) if tuning is not None else None, float(eta))
     if workspace is None:
         if n != 1:
             raise ValueError("pass a shared workspace for more than one molecule")
@@ -265,9 +266,9 @@ def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=N
 
 
 def decompose(xyz, alpha, tau: float, schwarz: float = 1e-12, max_vectors: Optional[int] = None,
-              sync: bool = True, device="cuda", stream=None) -> Decomposition:
+              sync: bool = True, device="cuda", stream=None, eta: float = 1.0) -> Decomposition:
     d = allocate(xyz, alpha, tau, schwarz, max_vectors, device, stream)
-    run_decompose([d], tau, schwarz, sync=sync, stream=stream)
+    run_decompose([d], tau, schwarz, sync=sync, stream=stream, eta=eta)
     return d
 
 

@@ -349,7 +349,9 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         //      at the first pivot that does not come before U), so only the
         //      nominations before U are kept; they are a prefix of the full
         //      union in pivot order, so the candidates and the bound are those
-        //      of the full union with the never-accepted rows left out.
+        //      of the full union with the never-accepted rows left out.  With a
+        //      span factor eta < 1 every nomination is kept (step 3 may then
+        //      accept rows that do not come before U).
         const int nu = G * CNOM;
         Nom mine[4];
 #pragma unroll
@@ -389,9 +391,11 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             const int iU = s_iU;
             const int lane = tid & 63;
             const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            const bool span = P.eta < 1.0;   // qualified-set acceptance: keep every nomination
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const bool keep = nom_before(mine[r].d, mine[r].idx, U, iU);
+                const bool keep = span ? (mine[r].d != -INFINITY)
+                                       : nom_before(mine[r].d, mine[r].idx, U, iU);
                 const unsigned long long m = __ballot(keep);
                 int base = 0;
                 if (lane == 0 && m) base = atomicAdd(&s_ns, __popcll(m));
@@ -537,6 +541,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             const int64_t room = P.max_vectors - K;
             int kb = 0, stop = 0, st = 0;
             bool done = false;
+            const double eta = P.eta;
+            double dmax0 = 0.0;   // the batch's first pivot: the global maximum residual
             for (int c = 0; c < QMAX / 8 && !done; ++c) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -549,10 +555,18 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                         break;
                     }
                     const int bi = __builtin_amdgcn_readlane(myslot, bl);
-                    const bool first = nom_before(bd, bi, U, iU);   // provably the global argmax
-                    const bool elig = eligible(bd, tau, ftol);      // max D >= tau
-                    if (!first || !elig || t >= room) {
-                        if (first) {
+                    dmax0 = (t == 0) ? bd : dmax0;
+                    // provably the global argmax, or (span factor < 1) qualified:
+                    // residual >= eta times the batch's first pivot
+                    const bool first = nom_before(bd, bi, U, iU);
+                    const bool qualified = first || (eta < 1.0 && bd >= eta * dmax0);
+                    const bool elig = eligible(bd, tau, ftol);      // D >= tau
+                    if (!qualified || !elig || t >= room) {
+                        // the decomposition ends when the global maximum is below tau,
+                        // or when a pivot it needs finds no room (capacity); a qualified
+                        // candidate below tau that is not the global maximum only ends
+                        // the batch
+                        if (first || (qualified && elig)) {
                             stop = 1;
                             st = elig ? 3 : 0;                   // capacity, or done
                         }

@@ -28,6 +28,7 @@ struct Step1Params {
     const unsigned long long *d1max_bits;  // max D1 (bit pattern)
     int64_t n_rows;            // tau == 0: stop at max D <= n_rows 2^-53 max D1
     int64_t max_vectors;
+    double eta;                // span factor: 1 = exact pivoting, < 1 = qualified-set acceptance
     int32_t q;                 // candidate batch size (<= QMAX)
     int32_t slice;             // active rows per workgroup
     uint32_t spin_limit;

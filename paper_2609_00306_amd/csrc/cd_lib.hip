@@ -149,6 +149,8 @@ cd_status check_opts(const cd_decomp_opts *o)
     if (!o) return fail(CD_ERR_INVALID_ARG, "null opts");
     if (!(o->tau >= 0.0) || !(o->schwarz >= 0.0))
         return fail(CD_ERR_INVALID_ARG, "tau and schwarz must be finite and >= 0");
+    if (!(o->eta >= 0.0 && o->eta <= 1.0))
+        return fail(CD_ERR_INVALID_ARG, "eta must be in [0, 1]");
     if (o->tuning) {
         const int rt = o->tuning->step2_row_tiles, mr = o->tuning->step1_min_rows;
         if (rt != 0 && (rt < 2 || rt > 8))
@@ -259,6 +261,7 @@ Step1Params step1_params(const cd_problem &p, const DecompWs &w, const cd_decomp
     P1.n_rows = p.n_rows;
     P1.max_vectors = p.max_vectors;
     P1.q = QMAX;
+    P1.eta = (o->eta > 0.0 && o->eta < 1.0) ? o->eta : 1.0;
     P1.slice = slice;
     P1.spin_limit = 1u << 22;
     const bool tl = with_timeline && o->timeline;

@@ -58,8 +58,8 @@ int main(void) {
          sizeof(cd_transform_problem));
   printf("%zu %zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
          offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events), offsetof(cd_decomp_opts, timeline_cap));
-  printf("%zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
-         offsetof(cd_decomp_opts, tuning));
+  printf("%zu %zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
+         offsetof(cd_decomp_opts, tuning), offsetof(cd_decomp_opts, eta));
   return 0;
 }
 '''
@@ -81,7 +81,8 @@ def test_binding_structs_match_header():
             cdlib.cd_problem.status.offset, cdlib.cd_jk_problem.status.offset,
             cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset,
             cdlib.cd_decomp_opts.timeline_cap.offset, ctypes.sizeof(cdlib.cd_tuning),
-            cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset]
+            cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset,
+            cdlib.cd_decomp_opts.eta.offset]
     assert mine == got
 
 
@@ -125,6 +126,12 @@ def test_argument_validation_without_device(lib):
         assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
                                 None) == cdlib.CD_ERR_INVALID_ARG
         assert b"tuning" in lib.cd_last_error()
+    # span factors outside [0, 1] (or NaN) are rejected on the host
+    for eta in [-0.1, 1.5, float("nan")]:
+        o = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None, None, 0, None, eta)
+        assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
+                                None) == cdlib.CD_ERR_INVALID_ARG
+        assert b"eta" in lib.cd_last_error()
     best = cdlib.cd_tuning()
     assert lib.cd_autotune(None, 0, ctypes.byref(opts), None, 0, None,
                            None) == cdlib.CD_ERR_INVALID_ARG

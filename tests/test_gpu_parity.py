@@ -200,6 +200,46 @@ def test_jk_reduced_precision_c3():
         assert abs(e2(J, K) - e2(J64, K64)) <= TOL_E2[prec]
 
 
+@pytest.mark.parametrize("name,eta", [("C1", 0.5), ("C1", 0.05), ("ragged", 0.1), ("C2", 0.1)])
+def test_span_factor_gives_a_valid_decomposition(name, eta):
+    """Span factor eta < 1 (Sec. 3, Table 1): pivots are taken from the qualified
+    set without the exact argmax, so the pivot sequence differs from Sec. 2.
+    Checked by what holds for every valid pivoted CD: all final residuals < tau;
+    the residual matrix R = A - L L^T is positive semidefinite, so on any block of
+    rows its diagonal is the reported residual and |R_rs| <= sqrt(R_rr R_ss);
+    a pivot row vanishes in every later vector; and the rank stays close to
+    exact pivoting's (greedy exact pivoting does not minimise the rank, so it
+    can come out a little above or below)."""
+    if name == "ragged":
+        m, tau, schwarz = make_molecule(37, 6.0, (0.5,), 3, seed=77), 1e-8, 1e-12
+    else:
+        m, tau, schwarz = config_molecule(name), 1e-6, (0.0 if name == "C1" else 1e-12)
+    d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, sync=False, eta=eta)
+    ex = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, sync=False)
+    torch.cuda.synchronize()
+    assert int(d.status.item()) == 0 and int(ex.status.item()) == 0
+    M, Mx = d.M(), ex.M()
+    assert 0.8 * Mx - 8 <= M <= 1.25 * Mx + 8
+    L = d.L[:M].cpu().numpy()
+    D = d.diag.cpu().numpy()
+    piv = d.pivots[:M].cpu().numpy()
+    assert D.max() < tau
+    assert len(set(piv.tolist())) == M
+    for k in range(M):
+        assert L[k, piv[k]] > 0.0
+        if k + 1 < M:
+            assert np.abs(L[k + 1:, piv[k]]).max() <= 1e-9
+    rp = d.row_pair.cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.arange(len(rp)) if len(rp) <= 800 else np.sort(rng.choice(len(rp), 400, replace=False))
+    A = oracle.eri_matrix(m.xyz, m.alpha, rp[idx])
+    Ls = L[:, idx]
+    R = A - Ls.T @ Ls
+    assert np.abs(np.diag(R) - D[idx]).max() <= 1e-10
+    Dp = np.maximum(D[idx], 0.0)
+    assert (np.abs(R) - np.sqrt(np.outer(Dp, Dp))).max() <= 1e-10
+
+
 def test_batched_decomposition_matches_single_and_oracle():
     # 20 molecules of uneven size in one call: more than one shared launch
     mols = [make_molecule(3 + (7 * i) % 9, 3.0 + 0.4 * (i % 5), (0.3, 1.1, 4.0), 2, seed=500 + i)
