@@ -65,6 +65,11 @@ def lib():
         L.or_jk_exact.argtypes = [ctypes.c_int, _d, _d, _d, ctypes.c_int, _d, _d]
         L.or_e2.restype = ctypes.c_double
         L.or_e2.argtypes = [ctypes.c_int, _d, ctypes.c_int, _d, _d]
+        L.or_mp2_pair.restype = ctypes.c_double
+        L.or_mp2_pair.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _d, _d, _d,
+                                  ctypes.c_int, ctypes.c_int]
+        L.or_mp2.restype = ctypes.c_double
+        L.or_mp2.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _d, _d, _d, _d]
         L.or_transform.restype = None
         L.or_transform.argtypes = [ctypes.c_int, ctypes.c_int64, _i64, _d, ctypes.c_int64, _d,
                                    ctypes.c_int, _d, ctypes.c_int, _d]
@@ -195,3 +200,20 @@ def transform(N: int, row_pair, L, C1, C2) -> np.ndarray:
     lib().or_transform(N, rp.shape[0], _p(rp, _i64), _p(L, _d), M, _p(C1, _d), p, _p(C2, _d),
                        q, _p(out, _d))
     return out
+
+
+def mp2(B, e_occ, e_virt):
+    """Closed-shell second-order energy from transformed vectors B [M][O][V]
+    (CD-based MP2, Secs. 5 and 7): returns (E, pair energies [O][O])."""
+    B, eo, ev = _f64(B), _f64(e_occ), _f64(e_virt)
+    M, O, V = B.shape
+    pair = np.zeros((max(1, O), max(1, O)))
+    e = lib().or_mp2(M, O, V, _p(B, _d), _p(eo, _d), _p(ev, _d), _p(pair, _d))
+    return e, pair[:O, :O].copy()
+
+
+def mp2_pair(B, e_occ, e_virt, i: int, j: int) -> float:
+    """One pair energy e_ij of ``mp2``."""
+    B, eo, ev = _f64(B), _f64(e_occ), _f64(e_virt)
+    M, O, V = B.shape
+    return lib().or_mp2_pair(M, O, V, _p(B, _d), _p(eo, _d), _p(ev, _d), int(i), int(j))

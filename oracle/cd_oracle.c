@@ -21,7 +21,9 @@
  *     standard J and K with (mu nu|rho sigma) ~ sum_P L^P_{mu nu} L^P_{rho sigma}
  *     inserted), and the same J and K from exact integrals (brute force);
  *   - the AO->MO transform of the vectors (Sec. 4.1, CASSCF; two-coefficient
- *     form of Sec. 6.2).
+ *     form of Sec. 6.2);
+ *   - the closed-shell second-order (MP2) energy from transformed vectors
+ *     (CD-based MP2 of Secs. 5 and 7; the textbook energy expression).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   ties in the argmax go to the lowest row index; the divisor is the square
@@ -363,4 +365,48 @@ void or_transform(int N, int64_t n, const int64_t *row_pair, const double *L, in
         }
         free(S); free(T);
     }
+}
+
+/* Closed-shell second-order (MP2) pair energy from transformed vectors,
+ * B[P][i][a] = sum_{mu nu} C_occ[mu][i] L^P_{mu nu} C_virt[nu][a] (the
+ * CD-based MP2 of Secs. 5 and 7 of the paper; the energy expression is the
+ * textbook closed-shell one, not printed in the paper):
+ *   (ia|jb) = sum_P B[P][i][a] B[P][j][b],
+ *   e_ij = sum_{ab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b).
+ * The total energy is sum over all ordered pairs (i, j). */
+double or_mp2_pair(int64_t M, int O, int V, const double *B, const double *eo,
+                   const double *ev, int i, int j)
+{
+    if (V <= 0) return 0.0;
+    double *W = (double *)malloc(sizeof(double) * (size_t)V * V);
+#pragma omp parallel for schedule(static)
+    for (int a = 0; a < V; ++a)
+        for (int b = 0; b < V; ++b) {
+            double s = 0.0;
+            for (int64_t P = 0; P < M; ++P)
+                s += B[(P * O + i) * V + a] * B[(P * O + j) * V + b];
+            W[a * V + b] = s;
+        }
+    double e = 0.0;
+    for (int a = 0; a < V; ++a)
+        for (int b = 0; b < V; ++b) {
+            const double w = W[a * V + b];
+            e += w * (2.0 * w - W[b * V + a]) / (eo[i] + eo[j] - ev[a] - ev[b]);
+        }
+    free(W);
+    return e;
+}
+
+/* All pair energies (pair[i * O + j]) and their sum. */
+double or_mp2(int64_t M, int O, int V, const double *B, const double *eo, const double *ev,
+              double *pair)
+{
+    double e = 0.0;
+    for (int i = 0; i < O; ++i)
+        for (int j = 0; j < O; ++j) {
+            const double s = or_mp2_pair(M, O, V, B, eo, ev, i, j);
+            if (pair) pair[i * O + j] = s;
+            e += s;
+        }
+    return e;
 }

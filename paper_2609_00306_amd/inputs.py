@@ -18,6 +18,11 @@ thresholds):
   of an N x O matrix of standard normal deviates, drawn after the centres from
   the same generator.
 * The generator is ``numpy.random.Generator(PCG64(seed))``.
+* For the second-order energy (``mp2_orbitals``): virtual coefficients are
+  columns O .. O+V-1 of the Q factor of [C | G], G an N x V matrix of standard
+  normal deviates (so they are orthonormal and orthogonal to C); orbital
+  energies are sorted uniform deviates, occupied in [-1.5, -0.3] and virtual
+  in [0.2, 2.5] hartree; all from ``PCG64(seed + 7919)``.
 """
 from __future__ import annotations
 
@@ -134,3 +139,19 @@ def batch_c4(count: int | None = None) -> List[Molecule]:
         mols.append(make_molecule(c, 16.0 * (c / 100.0) ** (1.0 / 3.0), b["exponents"],
                                   nb // 8, seed, name=f"C4_{i}", rng=rng))
     return mols
+
+
+def mp2_orbitals(m: Molecule, n_virt: int | None = None):
+    """Synthetic orbitals for the second-order energy of molecule ``m``:
+    (C_occ [N][O], C_virt [N][V], e_occ [O], e_virt [V]); V defaults to N - O."""
+    n, o = m.n_basis, m.n_occ
+    v = n - o if n_virt is None else int(n_virt)
+    if v < 0 or o + v > n:
+        raise ValueError("need n_occ + n_virt <= n_basis")
+    rng = np.random.Generator(np.random.PCG64(m.seed + 7919))
+    g = rng.standard_normal((n, v))
+    q, _ = np.linalg.qr(np.concatenate([m.C, g], axis=1))
+    c_virt = np.ascontiguousarray(q[:, o:o + v])
+    e_occ = np.sort(rng.uniform(-1.5, -0.3, o))
+    e_virt = np.sort(rng.uniform(0.2, 2.5, v))
+    return np.ascontiguousarray(m.C), c_virt, e_occ, e_virt

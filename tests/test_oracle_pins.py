@@ -11,6 +11,9 @@ fix, independent of the oracle's own formulas.
   chol(A[B,B])^-T), and for the invariants of Sec. 2 (stop rule, error
   bound, non-increasing pivots, prefix property in tau).
 * J/K against brute force from exact integrals and closed cases.
+* The second-order (MP2) energy from transformed vectors against the
+  spin-orbital form of the same energy, its sign and scaling, and at tau = 0
+  against exact integrals.
 """
 import math
 
@@ -363,3 +366,79 @@ def test_transform_identity_and_orthogonal(orc):
     out = orc.transform(N, rp, cd.L, C1, C2)
     ref = np.matmul(np.matmul(C1.T[None], S), C2[None])
     assert np.abs(out - ref).max() <= 1e-13
+
+
+# ---------------------------------------------------------------- MP2 energy
+def _spin_orbital_mp2(g, eo, ev):
+    """(1/4) sum_{IJAB} |<IJ||AB>|^2 / (e_I + e_J - e_A - e_B) over spin orbitals,
+    <IJ|AB> = (ia|jb) delta(s_I, s_A) delta(s_J, s_B), from the chemists'
+    integrals g[i, a, j, b] = (ia|jb): a different route to the closed-shell
+    energy."""
+    O, V = g.shape[0], g.shape[1]
+    e = 0.0
+    for I in range(2 * O):
+        i, si = divmod(I, 2)
+        for J in range(2 * O):
+            j, sj = divmod(J, 2)
+            for A in range(2 * V):
+                a, sa = divmod(A, 2)
+                for Bb in range(2 * V):
+                    b, sb = divmod(Bb, 2)
+                    direct = g[i, a, j, b] if (si == sa and sj == sb) else 0.0
+                    exch = g[i, b, j, a] if (si == sb and sj == sa) else 0.0
+                    v = direct - exch
+                    e += v * v / (eo[i] + eo[j] - ev[a] - ev[b])
+    return 0.25 * e
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mp2_matches_spin_orbital_form(orc, seed):
+    rng = np.random.default_rng(seed)
+    M, O, V = 5, 3, 4
+    B = rng.standard_normal((M, O, V))
+    eo = np.sort(rng.uniform(-1.5, -0.3, O))
+    ev = np.sort(rng.uniform(0.2, 2.5, V))
+    E, pair = orc.mp2(B, eo, ev)
+    ref = _spin_orbital_mp2(np.einsum("Pia,Pjb->iajb", B, B), eo, ev)
+    assert abs(E - ref) <= 1e-12 * abs(ref)
+    assert abs(pair.sum() - E) <= 1e-14 * abs(E)
+    assert np.allclose(pair, pair.T, rtol=1e-13, atol=0.0)   # e_ij = e_ji
+    assert orc.mp2_pair(B, eo, ev, 1, 2) == pair[1, 2]
+
+
+def test_mp2_sign_scaling_and_permutation(orc):
+    rng = np.random.default_rng(7)
+    M, O, V = 6, 4, 5
+    B = rng.standard_normal((M, O, V))
+    eo = np.sort(rng.uniform(-1.5, -0.3, O))
+    ev = np.sort(rng.uniform(0.2, 2.5, V))
+    E, _ = orc.mp2(B, eo, ev)
+    assert E < 0.0                                   # every (a, b) + (b, a) term is <= 0
+    assert abs(orc.mp2(2.0 * B, eo, ev)[0] - 16.0 * E) <= 1e-12 * abs(E)
+    po, pv = rng.permutation(O), rng.permutation(V)
+    Ep, _ = orc.mp2(B[:, po][:, :, pv], eo[po], ev[pv])
+    assert abs(Ep - E) <= 1e-12 * abs(E)
+    # no vectors, or no virtuals: zero
+    assert orc.mp2(np.zeros((0, O, V)), eo, ev)[0] == 0.0
+    assert orc.mp2(np.zeros((M, O, 0)), eo, np.zeros(0))[0] == 0.0
+
+
+def test_mp2_at_tau_zero_equals_exact_integrals(orc):
+    from paper_2609_00306_amd.inputs import mp2_orbitals
+    m = random_small(11, n_centres=3, exps=(0.4, 1.6), n_occ=2)
+    N = m.n_basis
+    Co, Cv, eo, ev = mp2_orbitals(m)
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    cd = orc.decompose(m.xyz, m.alpha, rp, 0.0)
+    B = orc.transform(N, rp, cd.L, Co, Cv)
+    E, _ = orc.mp2(B, eo, ev)
+    # exact (ia|jb) from the full four-index integrals, transformed with einsum
+    g4 = np.empty((N, N, N, N))
+    for mu in range(N):
+        for nu in range(N):
+            for sg in range(N):
+                for rh in range(N):
+                    g4[mu, nu, sg, rh] = orc.eri(m.xyz, m.alpha, mu, nu, sg, rh)
+    g = np.einsum("mi,na,mnsr,sj,rb->iajb", Co, Cv, g4, Co, Cv)
+    Eex = _spin_orbital_mp2(g, eo, ev)
+    assert abs(E - Eex) <= 1e-10 * abs(Eex)
