@@ -13,7 +13,9 @@
  *                 and the occupied coefficients (Sec. 4.1: O(N^2 M) for J,
  *                 O(O N^2 M) for K);
  *   cd_transform  the AO->MO transform of the vectors (Sec. 4.1, CASSCF;
- *                 two-coefficient form of Sec. 6.2).
+ *                 two-coefficient form of Sec. 6.2);
+ *   cd_mp2_energy the second-order energy from transformed vectors (CD-based
+ *                 MP2, Secs. 5 and 7).
  *
  * Conventions
  *   - Plain C, fixed-width integers; no C++ types or exceptions cross it.
@@ -223,6 +225,37 @@ cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, s
 
 cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_t flags,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Second-order (MP2) energy from transformed vectors.  The CD-based MP2 of
+ * Secs. 5 and 7 transforms the vectors to the molecular-orbital basis
+ * (cd_transform with C1 = occupied, C2 = virtual coefficients) and contracts
+ * them:
+ *     (ia|jb) = sum_P B[P][i][a] B[P][j][b],
+ *     e_ij = sum_{ab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b),
+ *     E = sum_{ij} e_ij
+ * (the textbook closed-shell energy; the denominators must not vanish).
+ * FP64 throughout.  Asynchronous; cd_query_mp2 gives the workspace size.
+ * Device status: CD_ERR_INVALID_ARG when *n_vectors is outside
+ * [0, max_vectors] (then E = 0).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_occ;             /* O >= 0 */
+    int32_t n_virt;            /* V >= 0 */
+    int64_t max_vectors;       /* leading dimension of B */
+    const int64_t *n_vectors;  /* [1] M (e.g. written by cd_decompose) */
+    const double *B;           /* [max_vectors][O][V] transformed vectors (cd_transform's Lmo) */
+    const double *e_occ;       /* [O] occupied orbital energies, hartree */
+    const double *e_virt;      /* [V] virtual orbital energies, hartree */
+    double *energy;            /* [1] out: E */
+    double *pair_energy;       /* optional (may be NULL) [O][O] out: e_ij */
+    int32_t *status;           /* [1] */
+} cd_mp2_problem;
+
+cd_status cd_query_mp2(const cd_mp2_problem *probs, int32_t count, size_t *ws_bytes);
+
+cd_status cd_mp2_energy(const cd_mp2_problem *probs, int32_t count, uint32_t flags, void *ws,
+                        size_t ws_bytes, void *stream);
 
 /* Thread-local message describing the last error returned on this thread. */
 const char *cd_last_error(void);

@@ -66,9 +66,15 @@ class cd_transform_problem(ctypes.Structure):
                 ("C2", _vp), ("Lmo", _vp), ("status", _vp)]
 
 
+class cd_mp2_problem(ctypes.Structure):
+    _fields_ = [("n_occ", ctypes.c_int32), ("n_virt", ctypes.c_int32),
+                ("max_vectors", ctypes.c_int64), ("n_vectors", _vp), ("B", _vp), ("e_occ", _vp),
+                ("e_virt", _vp), ("energy", _vp), ("pair_energy", _vp), ("status", _vp)]
+
+
 #: every function include/cd.h declares
 EXPORTS = ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
-           "cd_transform", "cd_last_error", "cd_version")
+           "cd_transform", "cd_query_mp2", "cd_mp2_energy", "cd_last_error", "cd_version")
 
 _lib = None
 
@@ -103,8 +109,11 @@ def load(path: str = LIB_PATH):
                                      P(ctypes.c_size_t)]
     L.cd_transform.argtypes = [P(cd_transform_problem), ctypes.c_int32, ctypes.c_uint32, _vp,
                                ctypes.c_size_t, _vp]
+    L.cd_query_mp2.argtypes = [P(cd_mp2_problem), ctypes.c_int32, P(ctypes.c_size_t)]
+    L.cd_mp2_energy.argtypes = [P(cd_mp2_problem), ctypes.c_int32, ctypes.c_uint32, _vp,
+                                ctypes.c_size_t, _vp]
     for f in ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk",
-              "cd_query_transform", "cd_transform"):
+              "cd_query_transform", "cd_transform", "cd_query_mp2", "cd_mp2_energy"):
         getattr(L, f).restype = ctypes.c_int
     L.cd_last_error.restype = ctypes.c_char_p
     L.cd_last_error.argtypes = []
@@ -343,3 +352,35 @@ def transform(d: Decomposition, C1, C2, sync: bool = True, stream=None) -> torch
     _check(L.cd_transform(ctypes.byref(prob), 1, CD_SYNC if sync else 0, _ptr(w), w.numel(),
                           _stream(stream)))
     return out
+
+
+def mp2_energy(B, n_vectors, e_occ, e_virt, pair_energy: bool = False, sync: bool = True,
+               stream=None):
+    """Closed-shell second-order energy from transformed vectors B[max_vectors][O][V].
+
+    ``n_vectors`` is a device int64 tensor of one element (a decomposition's
+    count).  Returns the energy as a device tensor of one element and, when
+    asked, the pair energies e_ij as an [O][O] device tensor.
+    """
+    dev = B.device
+    if B.dtype != torch.float64 or B.dim() != 3 or not B.is_contiguous():
+        raise ValueError("B must be a contiguous float64 [max_vectors][O][V] tensor")
+    mv, O, V = (int(x) for x in B.shape)
+    eo = _dev_f64(e_occ, dev)
+    ev = _dev_f64(e_virt, dev)
+    if eo.numel() != O or ev.numel() != V:
+        raise ValueError("orbital energies do not match B's shape")
+    if n_vectors.dtype != torch.int64 or n_vectors.device != dev:
+        raise ValueError("n_vectors must be an int64 tensor on B's device")
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    pe = torch.empty((O, O), dtype=torch.float64, device=dev) if pair_energy else None
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    prob = cd_mp2_problem(O, V, mv, _ptr(n_vectors), _ptr(B), _ptr(eo), _ptr(ev), _ptr(E),
+                          _ptr(pe), _ptr(st))
+    ws = ctypes.c_size_t()
+    L = load()
+    _check(L.cd_query_mp2(ctypes.byref(prob), 1, ctypes.byref(ws)))
+    w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    _check(L.cd_mp2_energy(ctypes.byref(prob), 1, CD_SYNC if sync else 0, _ptr(w), w.numel(),
+                           _stream(stream)))
+    return (E, pe) if pair_energy else E

@@ -14,6 +14,7 @@
 #include "cd_decompose.hip"
 #include "cd_jk.hip"
 #include "cd_jk_lp.hip"
+#include "cd_mp2.hip"
 
 using namespace cdk;
 
@@ -787,6 +788,81 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
     if (flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)
             return fail(CD_ERR_DEVICE, "stream synchronise failed");
+    }
+    return CD_OK;
+}
+
+cd_status cd_query_mp2(const cd_mp2_problem *probs, int32_t count, size_t *ws_bytes)
+{
+    if (count < 0 || (count > 0 && !probs) || !ws_bytes)
+        return fail(CD_ERR_INVALID_ARG, "null argument");
+    size_t tot = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_mp2_problem &p = probs[i];
+        if (p.n_occ < 0 || p.n_virt < 0 || p.max_vectors < 0)
+            return fail(CD_ERR_INVALID_ARG, "negative size");
+        Carver c(nullptr);
+        c.take<double>(mp2_ws_doubles(p.n_occ, p.n_virt));
+        tot += c.off;
+    }
+    *ws_bytes = tot;
+    return CD_OK;
+}
+
+cd_status cd_mp2_energy(const cd_mp2_problem *probs, int32_t count, uint32_t flags, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    cd_status s = cd_query_mp2(probs, count, &need);
+    if (s) return s;
+    if (need > ws_bytes || (need > 0 && !ws))
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *wbase = static_cast<char *>(ws);
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_mp2_problem &p = probs[i];
+        Carver c(wbase);
+        double *w = c.take<double>(mp2_ws_doubles(p.n_occ, p.n_virt));
+        wbase += c.off;
+        if (!p.energy || !p.status || !p.n_vectors)
+            return fail(CD_ERR_INVALID_ARG, "null pointer in mp2 problem %d", i);
+        if (p.n_occ > 0 && p.n_virt > 0 && (!p.B || !p.e_occ || !p.e_virt))
+            return fail(CD_ERR_INVALID_ARG, "null pointer in mp2 problem %d", i);
+        Mp2Params Q{};
+        Q.B = p.B;
+        Q.max_vectors = p.max_vectors;
+        Q.n_vectors = p.n_vectors;
+        Q.O = p.n_occ;
+        Q.V = p.n_virt;
+        Q.eo = p.e_occ;
+        Q.ev = p.e_virt;
+        const int64_t T = blocks_of(p.n_virt, 64), TP = T * (T + 1) / 2;
+        const int64_t NP = (int64_t)p.n_occ * (p.n_occ + 1) / 2;
+        if (NP * TP > ((int64_t)1 << 31) - 8 || NP > ((int64_t)1 << 31) - 1)
+            return fail(CD_ERR_UNSUPPORTED, "mp2 problem %d too large", i);
+        Q.T = (int32_t)T;
+        Q.TP = (int32_t)TP;
+        Q.NP = (int32_t)NP;
+        Q.per_xcd = blocks_of(NP * TP, 8);
+        Q.partial = w;
+        Q.pair_e = w + NP * TP;
+        Q.pair_out = p.pair_energy;
+        Q.energy = p.energy;
+        Q.status = p.status;
+        if (NP * TP > 0) k_mp2_tiles<<<(unsigned)(8 * Q.per_xcd), 256, 0, st>>>(Q);
+        if (NP > 0) k_mp2_pairs<<<(unsigned)NP, 64, 0, st>>>(Q);
+        k_mp2_total<<<1, 256, 0, st>>>(Q);
+        if ((s = check_launch("mp2 kernels"))) return s;
+    }
+    if (flags & CD_SYNC) {
+        if (hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "stream synchronise failed");
+        for (int32_t i = 0; i < count; ++i) {
+            int32_t v = 0;
+            if (hipMemcpy(&v, probs[i].status, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "status copy failed");
+            if (v != 0) return fail((cd_status)v, "mp2 problem %d: device status %d", i, v);
+        }
     }
     return CD_OK;
 }

@@ -23,6 +23,10 @@ thresholds):
   normal deviates (so they are orthonormal and orthogonal to C); orbital
   energies are sorted uniform deviates, occupied in [-1.5, -0.3] and virtual
   in [0.2, 2.5] hartree; all from ``PCG64(seed + 7919)``.
+* Stand-alone transformed vectors for the second-order energy
+  (``random_mo_vectors``): B[P][i][a] standard normal deviates scaled by
+  sqrt(d_P), d_P falling geometrically from 1 to 1e-6 over P (the shape of a
+  decomposition's pivot values), from ``PCG64(seed)``.
 """
 from __future__ import annotations
 
@@ -155,3 +159,13 @@ def mp2_orbitals(m: Molecule, n_virt: int | None = None):
     e_occ = np.sort(rng.uniform(-1.5, -0.3, o))
     e_virt = np.sort(rng.uniform(0.2, 2.5, v))
     return np.ascontiguousarray(m.C), c_virt, e_occ, e_virt
+
+
+def random_mo_vectors(n_vectors: int, n_occ: int, n_virt: int, seed: int) -> np.ndarray:
+    """Seeded stand-in for transformed vectors B [n_vectors][n_occ][n_virt]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = rng.standard_normal((n_vectors, n_occ, n_virt))
+    if n_vectors > 0:
+        d = np.geomspace(1.0, 1e-6, n_vectors)
+        b *= np.sqrt(d)[:, None, None]
+    return np.ascontiguousarray(b)

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "cd.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(cd_[a-z_]+)\s*\(", text)
+    names = re.findall(r"\b(cd_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -60,6 +60,8 @@ int main(void) {
          offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events), offsetof(cd_decomp_opts, timeline_cap));
   printf("%zu %zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
          offsetof(cd_decomp_opts, tuning), offsetof(cd_decomp_opts, eta));
+  printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
+         offsetof(cd_mp2_problem, status));
   return 0;
 }
 '''
@@ -82,7 +84,8 @@ def test_binding_structs_match_header():
             cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset,
             cdlib.cd_decomp_opts.timeline_cap.offset, ctypes.sizeof(cdlib.cd_tuning),
             cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset,
-            cdlib.cd_decomp_opts.eta.offset]
+            cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
+            cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset]
     assert mine == got
 
 
@@ -132,6 +135,19 @@ def test_argument_validation_without_device(lib):
         assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
                                 None) == cdlib.CD_ERR_INVALID_ARG
         assert b"eta" in lib.cd_last_error()
+    # second-order energy: negative sizes, null pointers, a short workspace
+    ws = ctypes.c_size_t()
+    assert lib.cd_query_mp2(None, 1, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
+    mp = cdlib.cd_mp2_problem(-1, 4, 8)
+    assert lib.cd_query_mp2(ctypes.byref(mp), 1, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
+    mp = cdlib.cd_mp2_problem(3, 70, 8)
+    assert lib.cd_query_mp2(ctypes.byref(mp), 1, ctypes.byref(ws)) == 0
+    # 6 occupied pairs x 3 virtual tile pairs of partials, 6 pair sums, 1 total
+    assert ws.value >= (6 * 3 + 6 + 1) * 8
+    assert lib.cd_mp2_energy(ctypes.byref(mp), 1, 0, None, 0, None) == cdlib.CD_ERR_WORKSPACE
+    assert lib.cd_mp2_energy(ctypes.byref(mp), 1, 0, ctypes.c_void_p(0x1000), ws.value,
+                             None) == cdlib.CD_ERR_INVALID_ARG
+    assert b"null pointer" in lib.cd_last_error()
     best = cdlib.cd_tuning()
     assert lib.cd_autotune(None, 0, ctypes.byref(opts), None, 0, None,
                            None) == cdlib.CD_ERR_INVALID_ARG

@@ -335,3 +335,93 @@ def test_large_workload_properties(name):
     LB = np.ascontiguousarray(L[:, piv].T)
     X = solve_triangular(LB, A[:M, M:], lower=True)
     assert np.abs(X - L[:, sel]).max() <= 1e-9
+
+
+# Second-order energy from transformed vectors (CD-based MP2, Secs. 5 and 7).
+# Both sides add the same terms in different orders (FP64 matrix-core
+# products over P, tile-wise sums over a, b): with |terms| summed in S, the
+# rounding difference is below (M + V^2) * 2^-52 * S; 1e-10 relative to the
+# largest magnitude covers it for every shape here.
+TOL_MP2 = 1e-10
+
+
+def _mp2_gpu(B, M, eo, ev, dev, pad_rows=0):
+    """GPU energy and pairs for B [M][O][V], padded with NaN rows the kernels
+    must not read."""
+    M0, O, V = B.shape
+    Bd = torch.full((M0 + pad_rows, O, V), float("nan"), dtype=torch.float64, device=dev)
+    Bd[:M0] = torch.from_numpy(B).to(dev)
+    nv = torch.tensor([M], dtype=torch.int64, device=dev)
+    E, pe = cdlib.mp2_energy(Bd, nv, eo, ev, pair_energy=True)
+    return float(E.item()), pe.cpu().numpy()
+
+
+@pytest.mark.parametrize("M,O,V", [(37, 5, 50), (70, 9, 130), (64, 1, 64), (200, 12, 200),
+                                   (5, 3, 1), (0, 4, 70), (16, 0, 40), (16, 3, 0)])
+def test_mp2_parity(gpu, M, O, V):
+    """Several virtual tiles with a ragged tail, one exact tile, a single
+    virtual, and the empty cases (no vectors: E = 0; no occupied or no
+    virtual orbitals: E = 0)."""
+    from paper_2609_00306_amd.inputs import random_mo_vectors
+    B = random_mo_vectors(M, O, V, seed=100 + M + O + V)
+    rng = np.random.default_rng(M * 7 + O)
+    eo = np.sort(rng.uniform(-1.5, -0.3, O))
+    ev = np.sort(rng.uniform(0.2, 2.5, V))
+    E, pe = _mp2_gpu(B, M, eo, ev, gpu, pad_rows=3)
+    Er, per = oracle.mp2(B, eo, ev)
+    scale = max(1e-300, np.abs(per).max() if per.size else 0.0)
+    assert abs(E - Er) <= TOL_MP2 * max(abs(Er), scale)
+    assert pe.shape == (O, O)
+    if O > 0:
+        assert np.abs(pe - per).max() <= TOL_MP2 * scale
+        assert np.array_equal(pe, pe.T)
+    if M == 0 or O == 0 or V == 0:
+        assert E == 0.0
+
+
+def test_mp2_chain_c1(gpu):
+    """Decomposition, transform with the occupied and virtual orbitals, and
+    the energy, all on the GPU, against the same chain in the oracle.  The
+    vectors agree to 1e-10 absolute, so the integrals (ia|jb) agree to about
+    2 M 1e-10 max|B|; 1e-7 relative on E covers that bound."""
+    from paper_2609_00306_amd.inputs import mp2_orbitals
+    m = config_molecule("C1")
+    d, M = run_gpu(m, 1e-6, 0.0)
+    rp, ref = check_against_oracle(m, 1e-6, 0.0, d, M)
+    Co, Cv, eo, ev = mp2_orbitals(m)
+    Bg = cdlib.transform(d, Co, Cv)
+    E = float(cdlib.mp2_energy(Bg, d.n_vectors, eo, ev).item())
+    Br = oracle.transform(m.n_basis, rp, ref.L, Co, Cv)
+    Er, _ = oracle.mp2(Br, eo, ev)
+    assert Er < 0.0
+    assert abs(E - Er) <= 1e-7 * abs(Er)
+
+
+def test_mp2_c2_shape_sampled_pairs(gpu):
+    """The 400-function workload's shape at tau = 1e-6 (M = 1930 vectors,
+    O = 50, V = 350): sampled pair energies against the oracle's pair by
+    pair, and E against the sum of the GPU's own pairs."""
+    from paper_2609_00306_amd.inputs import random_mo_vectors
+    M, O, V = 1930, 50, 350
+    B = random_mo_vectors(M, O, V, seed=2)
+    rng = np.random.default_rng(22)
+    eo = np.sort(rng.uniform(-1.5, -0.3, O))
+    ev = np.sort(rng.uniform(0.2, 2.5, V))
+    E, pe = _mp2_gpu(B, M, eo, ev, gpu)
+    for i, j in [(0, 0), (O - 1, O - 1), (0, O - 1), (17, 33), (25, 26)]:
+        r = oracle.mp2_pair(B, eo, ev, i, j)
+        assert abs(pe[i, j] - r) <= TOL_MP2 * abs(r)
+        assert pe[j, i] == pe[i, j]
+    iu = np.triu_indices(O, 1)
+    s = np.trace(pe) + 2.0 * pe[iu].sum()
+    assert abs(E - s) <= 1e-12 * abs(s)
+
+
+def test_mp2_rejects_bad_vector_count(gpu):
+    """A vector count above the buffer's capacity is reported through the
+    status word (the kernels then read no vectors)."""
+    B = torch.zeros((4, 2, 3), dtype=torch.float64, device=gpu)
+    nv = torch.tensor([5], dtype=torch.int64, device=gpu)
+    with pytest.raises(cdlib.CDError) as e:
+        cdlib.mp2_energy(B, nv, [-1.0, -0.5], [0.5, 1.0, 2.0])
+    assert e.value.status == cdlib.CD_ERR_INVALID_ARG
