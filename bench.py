@@ -295,6 +295,27 @@ def main():
                     "max_abs_dK": float((jk.K - K64).abs().max()),
                     "abs_dE2": abs(e2(jk.J, jk.K) - e2(J64, K64))}
 
+    # second-order energy from the step's vectors (outside the step): the
+    # transform with occupied and virtual orbitals, then the contraction
+    from paper_2609_00306_amd.inputs import mp2_orbitals
+    Co, Cv, eo, ev = mp2_orbitals(m)
+    V = Cv.shape[1]
+    Bmo = cdlib.transform(d, Co, Cv)
+    E_mp2 = cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev)
+    mp2_ev = [mk() for _ in range(args.steps + 1)]
+    mp2_ev[0].record(stream)
+    for k in range(args.steps):
+        cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev, sync=False)
+        mp2_ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    t_mp2 = mp2_ev[0].elapsed_time(mp2_ev[-1]) / args.steps
+    w_mp2 = O * (O + 1) / 2.0 * V * V * 2.0 * M   # (ia|jb), i <= j, all a, b
+    mp2 = {"ms": t_mp2, "energy": float(E_mp2.item()), "n_virt": V,
+           "tflops": w_mp2 / (t_mp2 * 1e-3) / 1e12,
+           "frac_fp64_peak": w_mp2 / (t_mp2 * 1e-3) / 1e12 / PEAK["fp64"],
+           "work": "O(O+1)/2 V^2 2M (integrals of pairs i <= j)"}
+    del Bmo
+
     def avg(i, j, which):
         vals = []
         for pe, je in evs:
@@ -350,6 +371,7 @@ def main():
         "jk_ms": t_jk,
         "jk_tflops": (w_j + w_k) / (t_jk * 1e-3) / 1e12,
         "transform_ms": t_tr,
+        "mp2": mp2,
         "phases_ms": {"setup": t_setup, "pivot_selection": t_sel, "all_row_solve": t_solve},
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
                             "stage_us_total": breakdown},
