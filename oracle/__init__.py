@@ -57,7 +57,7 @@ def lib():
         L.or_decompose.restype = ctypes.c_int
         L.or_decompose.argtypes = [_d, _d, ctypes.c_int64, _i64, ctypes.c_double, ctypes.c_int64,
                                    _d, _i64, _d, _d, _i64, _i64, ctypes.c_int64,
-                                   ctypes.c_double, _i64]
+                                   ctypes.c_double, _i64, ctypes.c_void_p]
         L.or_jk_cd.restype = None
         L.or_jk_cd.argtypes = [ctypes.c_int, ctypes.c_int64, _i64, _d, ctypes.c_int64, _d,
                                ctypes.c_int, _d, _d]
@@ -138,11 +138,26 @@ class CD(NamedTuple):
     bad: int             # replay: first pivot that was not a valid argmax (or -1)
 
 
+def candidate_rows(row_pair, pivot_fn) -> np.ndarray:
+    """Row mask of restricted-candidate pivoting (Sec. 6.2): row (mu nu) may be
+    a pivot iff both functions are flagged in ``pivot_fn`` [N]."""
+    fn = np.asarray(pivot_fn).astype(bool)
+    out = np.zeros(len(row_pair), dtype=np.uint8)
+    for r, pq in enumerate(np.asarray(row_pair, dtype=np.int64)):
+        mu, nu = unpack_pair(int(pq))
+        out[r] = 1 if (fn[mu] and fn[nu]) else 0
+    return out
+
+
 def decompose(xyz, alpha, row_pair, tau: float, max_vectors: Optional[int] = None,
-              given: Optional[np.ndarray] = None, tie_tol: float = 0.0) -> CD:
+              given: Optional[np.ndarray] = None, tie_tol: float = 0.0,
+              pivot_fn=None) -> CD:
+    """Sec. 2 decomposition over the given rows.  With ``pivot_fn`` (flags per
+    function) only rows of two flagged functions may be pivots (Sec. 6.2)."""
     xyz, alpha = _f64(xyz), _f64(alpha)
     rp = np.ascontiguousarray(row_pair, dtype=np.int64)
     n = rp.shape[0]
+    cand = None if pivot_fn is None else candidate_rows(rp, pivot_fn)
     if max_vectors is None:
         max_vectors = n
     L = np.zeros((max(1, max_vectors), max(1, n)))
@@ -158,7 +173,8 @@ def decompose(xyz, alpha, row_pair, tau: float, max_vectors: Optional[int] = Non
         g, gp, ng = None, None, 0
     rc = lib().or_decompose(_p(xyz, _d), _p(alpha, _d), n, _p(rp, _i64), float(tau),
                             int(max_vectors), _p(L, _d), _p(piv, _i64), _p(dp, _d), _p(D, _d),
-                            ctypes.byref(M), gp, ng, float(tie_tol), ctypes.byref(bad))
+                            ctypes.byref(M), gp, ng, float(tie_tol), ctypes.byref(bad),
+                            None if cand is None else cand.ctypes.data)
     m = M.value
     return CD(rc, m, L[:m, :n].copy(), piv[:m].copy(), dp[:m].copy(), D[:n].copy(), bad.value)
 

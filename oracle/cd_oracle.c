@@ -169,13 +169,19 @@ void or_eri_matrix(const double *xyz, const double *alpha, int64_t n,
  * first violation is written to *bad (or -1).  Replay stops after n_given
  * pivots or at the threshold, whichever comes first.
  *
+ * If 'cand' is non-NULL, only rows with cand[r] != 0 may become pivots
+ * (restricted candidates, Sec. 6.2: the Cholesky basis chosen from one block
+ * of rows only): the argmax and the stop test run over those rows, and every
+ * row still gets its elements of each vector and its residual D.
+ *
  * Returns 0 on success, 1 if max_vectors was reached before the threshold,
  * 2 if a pivot value was not positive and finite.
  */
 int or_decompose(const double *xyz, const double *alpha, int64_t n, const int64_t *row_pair,
                  double tau, int64_t max_vectors, double *L, int64_t *pivots,
                  double *dpiv, double *D, int64_t *M_out,
-                 const int64_t *given, int64_t n_given, double tie_tol, int64_t *bad)
+                 const int64_t *given, int64_t n_given, double tie_tol, int64_t *bad,
+                 const unsigned char *cand)
 {
     int rc = 0;
     int64_t M = 0;
@@ -191,13 +197,13 @@ int or_decompose(const double *xyz, const double *alpha, int64_t n, const int64_
         int64_t piv = -1;
         double d = -INFINITY;
         for (int64_t r = 0; r < n; ++r)
-            if (D[r] > d) { d = D[r]; piv = r; }
+            if ((!cand || cand[r]) && D[r] > d) { d = D[r]; piv = r; }
         if (n == 0 || d < tau) break;
         if (tau <= 0.0 && d <= floor_tol) break;
         if (given) {
             if (M >= n_given) break;
             int64_t g = given[M];
-            if (g < 0 || g >= n) { if (bad && *bad < 0) *bad = M; break; }
+            if (g < 0 || g >= n || (cand && !cand[g])) { if (bad && *bad < 0) *bad = M; break; }
             if (D[g] < d - tie_tol && bad && *bad < 0) *bad = M;
             piv = g;
             d = D[g];

@@ -442,3 +442,87 @@ def test_mp2_at_tau_zero_equals_exact_integrals(orc):
     g = np.einsum("mi,na,mnsr,sj,rb->iajb", Co, Cv, g4, Co, Cv)
     Eex = _spin_orbital_mp2(g, eo, ev)
     assert abs(E - Eex) <= 1e-10 * abs(Eex)
+
+
+# ---------------------------------------------------------------- restricted candidates
+# Sec. 6.2: the Cholesky basis is taken from one block of rows only (the LL,LL
+# block of the four-component matrix); every row still gets its vectors.  The
+# stand-in block: rows whose two functions both carry a flagged exponent.
+def _restricted_c1(orc, flagged=(0, 1)):
+    m = config_molecule("C1")
+    n_exp = 3
+    fn = np.array([(k % n_exp) in flagged for k in range(m.n_basis)], dtype=np.uint8)
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    A = orc.eri_matrix(m.xyz, m.alpha, rp)
+    cand = orc.candidate_rows(rp, fn).astype(bool)
+    return m, fn, rp, A, cand
+
+
+def test_candidate_rows_rule(orc):
+    m, fn, rp, A, cand = _restricted_c1(orc)
+    for r in range(0, len(rp), 37):
+        mu, nu = orc.unpack_pair(int(rp[r]))
+        assert cand[r] == bool(fn[mu] and fn[nu])
+
+
+def test_restricted_block_matches_lapack_dpstrf(orc):
+    """On the candidate block the restricted decomposition is the pivoted
+    Cholesky of A[cand][cand]: LAPACK dpstrf gives the same rank, pivots and
+    factor."""
+    m, fn, rp, A, cand = _restricted_c1(orc)
+    tau = 1e-6
+    cd = orc.decompose(m.xyz, m.alpha, rp, tau, pivot_fn=fn)
+    idx = np.nonzero(cand)[0]
+    Ab = A[np.ix_(idx, idx)]
+    c, piv, rank, info = lapack.dpstrf(Ab.copy(), tol=tau, lower=1)
+    piv = piv - 1
+    assert cd.rc == 0 and rank == cd.M
+    assert np.array_equal(idx[piv[:rank]], cd.pivots)
+    assert np.abs(np.tril(c)[:, :rank] - cd.L[:, idx].T[piv]).max() <= 1e-12
+
+
+def test_restricted_rows_follow_the_fitting_identity(orc):
+    """Every row, candidate or not, carries L = A[:, B] M^-T with S = A[B,B] =
+    M M^T (Sec. 3), and its final residual is diag(A) minus the squares; the
+    residual is below tau on candidate rows only."""
+    m, fn, rp, A, cand = _restricted_c1(orc)
+    tau = 1e-6
+    cd = orc.decompose(m.xyz, m.alpha, rp, tau, pivot_fn=fn)
+    B = cd.pivots
+    Mf = np.linalg.cholesky(A[np.ix_(B, B)])
+    Ldf = scipy.linalg.solve_triangular(Mf, A[:, B].T, lower=True)
+    assert np.abs(Ldf - cd.L).max() <= 1e-10
+    assert np.abs(np.diag(A) - (cd.L ** 2).sum(axis=0) - cd.D).max() <= 1e-12
+    assert cd.D[cand].max() < tau
+    # the excluded tight functions keep residuals far above tau: the
+    # restriction matters, and the unrestricted basis differs
+    assert cd.D[~cand].max() > 1e3 * tau
+    full = orc.decompose(m.xyz, m.alpha, rp, tau)
+    assert not np.all(cand[full.pivots])
+    # on the candidate block the reconstruction still meets the Sec. 2 bound
+    R = A - cd.L.T @ cd.L
+    assert np.abs(R[np.ix_(cand, cand)]).max() <= tau
+
+
+def test_restricted_all_flags_and_no_flags(orc):
+    m, fn, rp, A, cand = _restricted_c1(orc)
+    tau = 1e-6
+    full = orc.decompose(m.xyz, m.alpha, rp, tau)
+    every = orc.decompose(m.xyz, m.alpha, rp, tau, pivot_fn=np.ones(m.n_basis, np.uint8))
+    assert every.M == full.M and np.array_equal(every.pivots, full.pivots)
+    assert np.array_equal(every.L, full.L)
+    none = orc.decompose(m.xyz, m.alpha, rp, tau, pivot_fn=np.zeros(m.n_basis, np.uint8))
+    assert none.rc == 0 and none.M == 0
+    assert np.array_equal(none.D, np.diag(A))
+
+
+def test_restricted_replay_flags_a_non_candidate(orc):
+    m, fn, rp, A, cand = _restricted_c1(orc)
+    full = orc.decompose(m.xyz, m.alpha, rp, 1e-6)
+    ok = cand[full.pivots]
+    assert not ok.all()
+    first_bad = int(np.argmin(ok))
+    # the unrestricted pivots are global maxima, so each one up to the first
+    # non-candidate is a valid restricted argmax; that one is flagged
+    rep = orc.decompose(m.xyz, m.alpha, rp, 1e-6, given=full.pivots, pivot_fn=fn)
+    assert rep.bad == first_bad and rep.M == first_bad
