@@ -75,6 +75,12 @@ typedef struct {
     int32_t n_basis;       /* N >= 0 */
     const double *xyz;     /* device [N][3], bohr */
     const double *alpha;   /* device [N], bohr^-2, > 0 */
+    const uint8_t *pivot_fn; /* optional (may be NULL) device [N]: restricted candidates
+                              (Sec. 6.2, the Cholesky basis taken from one block of rows).
+                              When set, row (mu nu) may become a pivot only if pivot_fn[mu]
+                              and pivot_fn[nu] are both nonzero; every row still gets its
+                              vector elements and final residual, and the stop test runs over
+                              the candidate rows only */
 } cd_molecule;
 
 /* Launch shapes of the decomposition kernels (0 in a field = the built-in
@@ -118,7 +124,8 @@ typedef struct {
 /* Sizes of one decomposition problem, filled by cd_query. */
 typedef struct {
     int64_t n_rows;        /* rows kept after screening */
-    int64_t n_active;      /* rows with D1 >= tau (the only possible pivots) */
+    int64_t n_active;      /* rows with D1 >= tau that may be pivots (the only possible pivots;
+                              candidate rows only when pivot_fn is set) */
     size_t ws_bytes;       /* device workspace cd_decompose needs for this problem
                               at the max_vectors passed to cd_query */
 } cd_sizes;
@@ -154,7 +161,8 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
  * device recounts the rows; a count that differs from n_rows / n_active
  * gives status CD_ERR_DEVICE and no vectors.
  * The pivots follow Sec. 2 exactly: the pivot is the row of largest residual
- * diagonal (lowest row index among equal values), the vector is
+ * diagonal (lowest row index among equal values; among the candidate rows when
+ * the molecule's pivot_fn is set), the vector is
  * [(r|P) - sum_J L^J_r L^J_P] / sqrt(d_P) with d_P the tracked diagonal, the
  * pivot's own residual is set to zero, and the loop ends when max D < tau.
  * Rows whose D1 < tau can never be pivots and are only solved for at the

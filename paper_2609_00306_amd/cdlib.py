@@ -27,7 +27,7 @@ _vp = ctypes.c_void_p
 
 
 class cd_molecule(ctypes.Structure):
-    _fields_ = [("n_basis", ctypes.c_int32), ("xyz", _vp), ("alpha", _vp)]
+    _fields_ = [("n_basis", ctypes.c_int32), ("xyz", _vp), ("alpha", _vp), ("pivot_fn", _vp)]
 
 
 class cd_tuning(ctypes.Structure):
@@ -159,13 +159,24 @@ class Decomposition:
     n_vectors: torch.Tensor  # [1] int64
     status: torch.Tensor     # [1] int32
     workspace: torch.Tensor
+    pivot_fn: Optional[torch.Tensor] = None   # [N] uint8 restricted candidates, or None
 
     def M(self) -> int:
         return int(self.n_vectors.item())
 
 
-def molecule(xyz: torch.Tensor, alpha: torch.Tensor) -> cd_molecule:
-    return cd_molecule(int(alpha.shape[0]), _ptr(xyz), _ptr(alpha))
+def molecule(xyz: torch.Tensor, alpha: torch.Tensor,
+             pivot_fn: Optional[torch.Tensor] = None) -> cd_molecule:
+    return cd_molecule(int(alpha.shape[0]), _ptr(xyz), _ptr(alpha), _ptr(pivot_fn))
+
+
+def _dev_flags(pivot_fn, n: int, device) -> Optional[torch.Tensor]:
+    if pivot_fn is None:
+        return None
+    f = torch.as_tensor(pivot_fn).reshape(-1).to(device=device)
+    if f.numel() != n:
+        raise ValueError("pivot_fn needs one flag per basis function")
+    return (f != 0).to(torch.uint8).contiguous()
 
 
 def query(mols: Sequence[cd_molecule], tau: float, schwarz: float,
@@ -181,17 +192,19 @@ def query(mols: Sequence[cd_molecule], tau: float, schwarz: float,
 
 
 def allocate(xyz, alpha, tau: float, schwarz: float, max_vectors: Optional[int] = None,
-             device="cuda", stream=None) -> Decomposition:
+             device="cuda", stream=None, pivot_fn=None) -> Decomposition:
     """Allocate outputs and workspace for one molecule (sizes from cd_query).
 
     Without ``max_vectors`` the capacity is the number of active rows, which
-    bounds the number of vectors (every pivot is an active row)."""
+    bounds the number of vectors (every pivot is an active row).  ``pivot_fn``:
+    optional per-function flags of restricted-candidate pivoting (Sec. 6.2)."""
     xyz = _dev_f64(xyz, device).reshape(-1, 3)
     alpha = _dev_f64(alpha, device).reshape(-1)
+    fn = _dev_flags(pivot_fn, int(alpha.shape[0]), device)
     if max_vectors is None:
-        sz = query([molecule(xyz, alpha)], tau, schwarz, [0], stream)[0]
+        sz = query([molecule(xyz, alpha, fn)], tau, schwarz, [0], stream)[0]
         max_vectors = max(1, int(sz.n_active))
-    sz = query([molecule(xyz, alpha)], tau, schwarz, [max_vectors], stream)[0]
+    sz = query([molecule(xyz, alpha, fn)], tau, schwarz, [max_vectors], stream)[0]
     n, mv = int(sz.n_rows), int(max_vectors)
     i64 = dict(dtype=torch.int64, device=device)
     f64 = dict(dtype=torch.float64, device=device)
@@ -201,7 +214,8 @@ def allocate(xyz, alpha, tau: float, schwarz: float, max_vectors: Optional[int] 
         row_pair=torch.empty(n, **i64), L=torch.empty((mv, n), **f64),
         pivots=torch.empty(mv, **i64), diag=torch.empty(n, **f64),
         n_vectors=torch.zeros(1, **i64), status=torch.zeros(1, dtype=torch.int32, device=device),
-        workspace=torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=device))
+        workspace=torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=device),
+        pivot_fn=fn)
 
 
 def allocate_many(mols, tau: float, schwarz: float, max_vectors=None, device="cuda",
@@ -219,7 +233,7 @@ def allocate_many(mols, tau: float, schwarz: float, max_vectors=None, device="cu
 
 
 def problem(d: Decomposition) -> cd_problem:
-    return cd_problem(molecule(d.xyz, d.alpha), d.n_rows, d.n_active, d.max_vectors,
+    return cd_problem(molecule(d.xyz, d.alpha, d.pivot_fn), d.n_rows, d.n_active, d.max_vectors,
                       _ptr(d.row_pair),
                       _ptr(d.L), _ptr(d.pivots), _ptr(d.diag), _ptr(d.n_vectors),
                       _ptr(d.status))
@@ -275,8 +289,9 @@ def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=N
 
 
 def decompose(xyz, alpha, tau: float, schwarz: float = 1e-12, max_vectors: Optional[int] = None,
-              sync: bool = True, device="cuda", stream=None, eta: float = 1.0) -> Decomposition:
-    d = allocate(xyz, alpha, tau, schwarz, max_vectors, device, stream)
+              sync: bool = True, device="cuda", stream=None, eta: float = 1.0,
+              pivot_fn=None) -> Decomposition:
+    d = allocate(xyz, alpha, tau, schwarz, max_vectors, device, stream, pivot_fn)
     run_decompose([d], tau, schwarz, sync=sync, stream=stream, eta=eta)
     return d
 

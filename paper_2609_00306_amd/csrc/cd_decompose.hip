@@ -4,7 +4,8 @@
 //
 //   setup   : pair table, diagonal D1 = (r|r), screening, compaction of the
 //             rows and of the "active" rows (D1 >= tau: the only possible
-//             pivots, since D never increases -- Sec. 3).
+//             pivots, since D never increases -- Sec. 3; with restricted
+//             candidates, Sec. 6.2, also both functions flagged).
 //   step 1  : one persistent cooperative kernel selects the pivots on the
 //             active rows only.  Per batch it takes the top-q active rows as
 //             candidates, forms their Schur-complement columns in one pass
@@ -51,17 +52,29 @@ __global__ __launch_bounds__(256) void k_diag_all(int N, const double *__restric
     }
 }
 
+// keep: the row survives screening; act: it may become a pivot (D1 >= tau
+// and, with restricted candidates, both functions flagged -- Sec. 6.2).
 __device__ __forceinline__ void row_flags(double d1, double mx, double schwarz, double tau,
-                                          bool &keep, bool &act)
+                                          bool cand, bool &keep, bool &act)
 {
     keep = sqrt(d1 * mx) >= schwarz;
-    act = keep && (d1 >= tau);
+    act = keep && cand && (d1 >= tau);
+}
+
+// Row k may be a pivot under the per-function flags (null: every row).
+__device__ __forceinline__ bool pair_is_candidate(int64_t k, const uint8_t *__restrict__ pivot_fn)
+{
+    if (!pivot_fn) return true;
+    int mu, nu;
+    unpack_pair(k, mu, nu);
+    return pivot_fn[mu] != 0 && pivot_fn[nu] != 0;
 }
 
 // Per-256-pair block counts of kept and active rows.
 __global__ __launch_bounds__(256) void k_count(int64_t npairs, const double *__restrict__ D1all,
                                                const unsigned long long *d1max_bits,
                                                double schwarz, double tau,
+                                               const uint8_t *__restrict__ pivot_fn,
                                                int32_t *__restrict__ cnt_rows,
                                                int32_t *__restrict__ cnt_act)
 {
@@ -69,7 +82,7 @@ __global__ __launch_bounds__(256) void k_count(int64_t npairs, const double *__r
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double mx = __longlong_as_double((long long)*d1max_bits);
     bool keep = false, act = false;
-    if (k < npairs) row_flags(D1all[k], mx, schwarz, tau, keep, act);
+    if (k < npairs) row_flags(D1all[k], mx, schwarz, tau, pair_is_candidate(k, pivot_fn), keep, act);
     unsigned long long bk = __ballot(keep);
     unsigned long long ba = __ballot(act);
     if ((threadIdx.x & 63) == 0) {
@@ -133,7 +146,7 @@ __global__ __launch_bounds__(256) void k_scan(int32_t nblk, const int32_t *__res
 __global__ __launch_bounds__(256) void k_scatter(
     int N, const double *__restrict__ xyz, const double *__restrict__ alpha, int64_t npairs,
     const double *__restrict__ D1all, const unsigned long long *d1max_bits, double schwarz,
-    double tau, const int64_t *__restrict__ off_rows, const int64_t *__restrict__ off_act,
+    double tau, const uint8_t *__restrict__ pivot_fn, const int64_t *__restrict__ off_rows, const int64_t *__restrict__ off_act,
     int64_t n_cap, int64_t na_cap, int64_t *__restrict__ row_pair, RowRec *__restrict__ rows, int32_t *__restrict__ act_row,
     double *__restrict__ D_act, int32_t *__restrict__ pivot_of_row)
 {
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(256) void k_scatter(
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double mx = __longlong_as_double((long long)*d1max_bits);
     bool keep = false, act = false;
-    if (k < npairs) row_flags(D1all[k], mx, schwarz, tau, keep, act);
+    if (k < npairs) row_flags(D1all[k], mx, schwarz, tau, pair_is_candidate(k, pivot_fn), keep, act);
     unsigned long long bk = __ballot(keep);
     unsigned long long ba = __ballot(act);
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -172,13 +172,14 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
     const int64_t nblk = blocks_of(np, 256);
     if (np == 0) return CD_OK;
     k_diag_all<<<(unsigned)nblk, 256, 0, st>>>(m.n_basis, m.xyz, m.alpha, np, w.D1all, w.d1max);
-    k_count<<<(unsigned)nblk, 256, 0, st>>>(np, w.D1all, w.d1max, o->schwarz, o->tau, w.cnt_rows,
-                                            w.cnt_act);
+    k_count<<<(unsigned)nblk, 256, 0, st>>>(np, w.D1all, w.d1max, o->schwarz, o->tau,
+                                            m.pivot_fn, w.cnt_rows, w.cnt_act);
     k_scan<<<1, 256, 0, st>>>((int32_t)nblk, w.cnt_rows, w.cnt_act, w.off_rows, w.off_act,
                               w.totals);
     if (scatter)
         k_scatter<<<(unsigned)nblk, 256, 0, st>>>(m.n_basis, m.xyz, m.alpha, np, w.D1all,
-                                                  w.d1max, o->schwarz, o->tau, w.off_rows,
+                                                  w.d1max, o->schwarz, o->tau, m.pivot_fn,
+                                                  w.off_rows,
                                                   w.off_act, n_cap, na_cap, row_pair, w.rows,
                                                   w.act_row, w.D_act, w.pivot_of_row);
     return check_launch("setup kernels");

@@ -161,6 +161,18 @@ def mp2_orbitals(m: Molecule, n_virt: int | None = None):
     return np.ascontiguousarray(m.C), c_virt, e_occ, e_virt
 
 
+def exponent_block(m: Molecule, flagged: Sequence[int]) -> np.ndarray:
+    """Per-function flags [N] (uint8): 1 for the functions whose exponent index
+    (position within their centre) is in ``flagged``.  A stand-in for one block
+    of a larger basis (restricted-candidate pivoting)."""
+    n = m.n_basis
+    n_exp = 1
+    while n_exp < n and np.array_equal(m.xyz[n_exp], m.xyz[0]):   # functions on centre 0
+        n_exp += 1
+    keep = set(int(f) for f in flagged)
+    return np.array([1 if (k % n_exp) in keep else 0 for k in range(m.n_basis)], dtype=np.uint8)
+
+
 def random_mo_vectors(n_vectors: int, n_occ: int, n_virt: int, seed: int) -> np.ndarray:
     """Seeded stand-in for transformed vectors B [n_vectors][n_occ][n_virt]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -41,14 +41,16 @@ def run_gpu(m, tau, schwarz, max_vectors=None):
 _ORACLE_CACHE = {}
 
 
-def oracle_cd(m, rp, tau, cap):
-    key = (m.name, m.seed, m.n_basis, tau, len(rp), cap)
+def oracle_cd(m, rp, tau, cap, pivot_fn=None):
+    fk = None if pivot_fn is None else bytes(np.asarray(pivot_fn, dtype=np.uint8))
+    key = (m.name, m.seed, m.n_basis, tau, len(rp), cap, fk)
     if key not in _ORACLE_CACHE:
-        _ORACLE_CACHE[key] = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=cap)
+        _ORACLE_CACHE[key] = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=cap,
+                                              pivot_fn=pivot_fn)
     return _ORACLE_CACHE[key]
 
 
-def check_against_oracle(m, tau, schwarz, d, M, expect_status=0):
+def check_against_oracle(m, tau, schwarz, d, M, expect_status=0, pivot_fn=None):
     """Compare one GPU decomposition with the oracle; returns the oracle result used."""
     assert int(d.status.item()) == expect_status
     rp, _ = oracle.rows(m.xyz, m.alpha, schwarz)
@@ -56,11 +58,11 @@ def check_against_oracle(m, tau, schwarz, d, M, expect_status=0):
     assert np.array_equal(rp, rp_g), "screened row sets differ"
     piv = d.pivots[:M].cpu().numpy()
     cap = d.max_vectors
-    ref = oracle_cd(m, rp, tau, cap)
+    ref = oracle_cd(m, rp, tau, cap, pivot_fn)
     if not (ref.M == M and np.array_equal(ref.pivots, piv)):
         D1max = float(np.max(oracle.diagonal_all(m.xyz, m.alpha))) if m.n_basis else 0.0
         ref = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=cap, given=piv,
-                               tie_tol=1e-12 * D1max)
+                               tie_tol=1e-12 * D1max, pivot_fn=pivot_fn)
         assert ref.bad == -1, f"GPU pivot {ref.bad} is not a valid argmax"
         assert ref.M == M
     L = d.L[:M].cpu().numpy()
@@ -425,3 +427,44 @@ def test_mp2_rejects_bad_vector_count(gpu):
     with pytest.raises(cdlib.CDError) as e:
         cdlib.mp2_energy(B, nv, [-1.0, -0.5], [0.5, 1.0, 2.0])
     assert e.value.status == cdlib.CD_ERR_INVALID_ARG
+
+
+# Restricted candidates (Sec. 6.2): the Cholesky basis from the rows of two
+# flagged functions only (stand-in for the LL,LL block: the functions of the
+# flagged exponents); every row still gets its vectors and final residual.
+@pytest.mark.parametrize("name,schwarz,flagged", [("C1", 0.0, (0, 1)), ("C1", 0.0, (1, 2)),
+                                                  ("C2", 1e-12, (0, 1, 2))])
+def test_restricted_candidates_parity(name, schwarz, flagged):
+    from paper_2609_00306_amd.inputs import exponent_block
+    m = config_molecule(name)
+    fn = exponent_block(m, flagged)
+    tau = 1e-6
+    d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, pivot_fn=fn, sync=False)
+    torch.cuda.synchronize()
+    M = d.M()
+    rp, ref = check_against_oracle(m, tau, schwarz, d, M, pivot_fn=fn)
+    cand = oracle.candidate_rows(rp, fn).astype(bool)
+    D1 = oracle.diagonal_all(m.xyz, m.alpha)[rp]
+    assert d.n_active == int(np.count_nonzero(cand & (D1 >= tau)))
+    piv = d.pivots[:M].cpu().numpy()
+    assert cand[piv].all()
+    diag = d.diag.cpu().numpy()
+    assert diag[cand].max() < tau
+    assert diag[~cand].max() > tau        # the restriction leaves large residuals elsewhere
+
+
+def test_restricted_candidates_edge_flags():
+    """All functions flagged: the unrestricted decomposition, bit for bit.
+    None flagged: no active rows, no vectors, the residual is the diagonal."""
+    m = make_molecule(37, 6.0, (0.5, 2.0), 3, seed=78)
+    tau = 1e-8
+    d0, M0 = run_gpu(m, tau, 1e-12)
+    d1 = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=1e-12,
+                         pivot_fn=np.ones(m.n_basis, np.uint8))
+    assert d1.M() == M0 and torch.equal(d1.pivots[:M0], d0.pivots[:M0])
+    assert torch.equal(d1.L[:M0], d0.L[:M0]) and torch.equal(d1.diag, d0.diag)
+    dz = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=1e-12,
+                         pivot_fn=np.zeros(m.n_basis, np.uint8), max_vectors=4)
+    assert dz.n_active == 0 and dz.M() == 0 and int(dz.status.item()) == 0
+    check_against_oracle(m, tau, 1e-12, dz, 0, pivot_fn=np.zeros(m.n_basis, np.uint8))
+
