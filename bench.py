@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--eta", type=float, default=1.0,
                     help="span factor of the pivot selection (1 = exact pivoting)")
+    ap.add_argument("--pivot-block", default=None, metavar="I,J,..",
+                    help="restricted candidates (Sec. 6.2): pivots only from rows of two "
+                         "functions whose exponent index is listed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
@@ -225,13 +228,18 @@ def main():
     tau, schwarz = args.tau, cfg["schwarz"]
     N, O = m.n_basis, m.n_occ
 
+    fn = None
+    if args.pivot_block is not None:
+        from paper_2609_00306_amd.inputs import exponent_block
+        fn = exponent_block(m, [int(x) for x in args.pivot_block.split(",") if x != ""])
+
     # size the outputs with the measured number of vectors
-    probe = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, eta=args.eta)
+    probe = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz, eta=args.eta, pivot_fn=fn)
     M = probe.M()
     assert int(probe.status.item()) == 0
     del probe
     torch.cuda.empty_cache()
-    d = cdlib.allocate(m.xyz, m.alpha, tau, schwarz, max(1, M), device=dev)
+    d = cdlib.allocate(m.xyz, m.alpha, tau, schwarz, max(1, M), device=dev, pivot_fn=fn)
     n = d.n_rows
     jk = cdlib.prepare_jk(d, m.C, args.precision)
     stream = torch.cuda.current_stream()
@@ -294,6 +302,23 @@ def main():
                     "max_abs_dJ": float((jk.J - J64).abs().max()),
                     "max_abs_dK": float((jk.K - K64).abs().max()),
                     "abs_dE2": abs(e2(jk.J, jk.K) - e2(J64, K64))}
+
+    restricted = None
+    if fn is not None:
+        # against the unrestricted decomposition of the same molecule: the
+        # residual left outside the candidate block and the J/K energy change
+        full = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz)
+        Jf, Kf = cdlib.build_jk(full, m.C, "fp64")
+        Jr, Kr = cdlib.build_jk(d, m.C, "fp64")
+        Ct = torch.as_tensor(m.C, device=dev)
+        Dm = Ct @ Ct.T
+        e2f = float(2.0 * (Dm * Jf).sum() - (Dm * Kf).sum())
+        e2r = float(2.0 * (Dm * Jr).sum() - (Dm * Kr).sum())
+        restricted = {"flagged_functions": int(fn.sum()), "n_active": d.n_active,
+                      "n_active_unrestricted": full.n_active, "M_unrestricted": full.M(),
+                      "max_residual": float(d.diag.max()),
+                      "abs_dE2_vs_unrestricted": abs(e2r - e2f), "E2": e2r}
+        del full, Jf, Kf, Jr, Kr
 
     # second-order energy from the step's vectors (outside the step): the
     # transform with occupied and virtual orbitals, then the contraction
@@ -365,13 +390,15 @@ def main():
                                f"{cfg['box']:.1f} A box, {len(cfg['exponents'])} exponents), "
                                f"tau={tau:g}, Schwarz {schwarz:g}, O={O}",
                    "n_basis": N, "n_rows": n, "n_active": d.n_active, "n_vectors": M,
-                   "tau": tau, "n_occ": O, "jk_precision": args.precision, "eta": args.eta},
+                   "tau": tau, "n_occ": O, "jk_precision": args.precision, "eta": args.eta,
+                   "pivot_block": args.pivot_block},
         "cd_ms": t_cd,
         "cd_vectors_per_s": M / (t_cd * 1e-3),
         "jk_ms": t_jk,
         "jk_tflops": (w_j + w_k) / (t_jk * 1e-3) / 1e12,
         "transform_ms": t_tr,
         "mp2": mp2,
+        "restricted_candidates": restricted,
         "phases_ms": {"setup": t_setup, "pivot_selection": t_sel, "all_row_solve": t_solve},
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
                             "stage_us_total": breakdown},
