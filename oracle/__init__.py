@@ -54,6 +54,10 @@ def lib():
         L.or_rows.argtypes = [ctypes.c_int, _d, _d, ctypes.c_double, _i64, _d]
         L.or_eri_matrix.restype = None
         L.or_eri_matrix.argtypes = [_d, _d, ctypes.c_int64, _i64, _d]
+        L.or_one_electron.restype = None
+        L.or_one_electron.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, _d, _d, _d, _d, _d]
+        L.or_charge_repulsion.restype = ctypes.c_double
+        L.or_charge_repulsion.argtypes = [ctypes.c_int, _d, _d]
         L.or_decompose.restype = ctypes.c_int
         L.or_decompose.argtypes = [_d, _d, ctypes.c_int64, _i64, ctypes.c_double, ctypes.c_int64,
                                    _d, _i64, _d, _d, _i64, _i64, ctypes.c_int64,
@@ -233,3 +237,60 @@ def mp2_pair(B, e_occ, e_virt, i: int, j: int) -> float:
     B, eo, ev = _f64(B), _f64(e_occ), _f64(e_virt)
     M, O, V = B.shape
     return lib().or_mp2_pair(M, O, V, _p(B, _d), _p(eo, _d), _p(ev, _d), int(i), int(j))
+
+
+def one_electron(xyz, alpha, charge_xyz, charge):
+    """Overlap S, kinetic T and point-charge attraction V, each [N][N]."""
+    xyz, alpha = _f64(xyz), _f64(alpha)
+    cx, Z = _f64(np.reshape(charge_xyz, (-1, 3))), _f64(charge)
+    N, nc = alpha.shape[0], Z.shape[0]
+    S, T, V = (np.zeros((max(1, N), max(1, N))) for _ in range(3))
+    lib().or_one_electron(N, _p(xyz, _d), _p(alpha, _d), nc, _p(cx, _d), _p(Z, _d),
+                          _p(S, _d), _p(T, _d), _p(V, _d))
+    return S[:N, :N].copy(), T[:N, :N].copy(), V[:N, :N].copy()
+
+
+def charge_repulsion(charge_xyz, charge) -> float:
+    cx, Z = _f64(np.reshape(charge_xyz, (-1, 3))), _f64(charge)
+    return lib().or_charge_repulsion(Z.shape[0], _p(cx, _d), _p(Z, _d))
+
+
+class SCF(NamedTuple):
+    energies: np.ndarray     # E_k for k = 0, 1, .. (density D_k, Fock matrix F(D_k))
+    C: np.ndarray            # [N][O] occupied orbitals of the last density
+    eps: np.ndarray          # orbital energies of the last Fock matrix
+    F: np.ndarray
+    D: np.ndarray
+    converged: bool
+
+
+def scf(S, H, e_charges: float, n_occ: int, jk, max_iter: int = 100,
+        e_tol: float = 1e-10, d_tol: float = 1e-8) -> SCF:
+    """Closed-shell Roothaan-Hall SCF (Sec. 4.1 builds its J and K from the
+    Cholesky vectors).  ``jk(C)`` returns J and K of D = C C^T.
+
+    D_0 is the projector on the n_occ lowest solutions of H C = S C e (core
+    guess).  Iteration k: F_k = H + 2 J(D_k) - K(D_k),
+    E_k = tr(D_k (H + F_k)) + e_charges, and D_{k+1} from the n_occ lowest
+    solutions of F_k C = S C e.  Stops when |E_k - E_{k-1}| < e_tol and the
+    largest element of F_k D_k S - S D_k F_k is below d_tol."""
+    import scipy.linalg
+    e, V = scipy.linalg.eigh(H, S)
+    C = np.ascontiguousarray(V[:, :n_occ])
+    energies = []
+    conv = False
+    F = H.copy()
+    for _ in range(max_iter):
+        D = C @ C.T
+        J, K = jk(C)
+        F = H + 2.0 * J - K
+        E = float(np.sum(D * (H + F))) + e_charges
+        energies.append(E)
+        comm = F @ D @ S - S @ D @ F
+        if len(energies) > 1 and abs(E - energies[-2]) < e_tol and np.abs(comm).max() < d_tol:
+            conv = True
+            break
+        e, V = scipy.linalg.eigh(F, S)
+        C = np.ascontiguousarray(V[:, :n_occ])
+    return SCF(np.array(energies), C, e, F, C @ C.T, conv)
+

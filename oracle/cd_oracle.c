@@ -23,7 +23,11 @@
  *   - the AO->MO transform of the vectors (Sec. 4.1, CASSCF; two-coefficient
  *     form of Sec. 6.2);
  *   - the closed-shell second-order (MP2) energy from transformed vectors
- *     (CD-based MP2 of Secs. 5 and 7; the textbook energy expression).
+ *     (CD-based MP2 of Secs. 5 and 7; the textbook energy expression);
+ *   - one-electron integrals over the same functions (overlap, kinetic
+ *     energy, attraction to point charges) and the repulsion of the charges,
+ *     the ingredients of the SCF of Sec. 4.1 besides J and K (textbook
+ *     closed forms for s functions).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   ties in the argmax go to the lowest row index; the divisor is the square
@@ -416,3 +420,55 @@ double or_mp2(int64_t M, int O, int V, const double *B, const double *eo, const 
         }
     return e;
 }
+
+/* ---- one-electron integrals (SCF, Sec. 4.1) ------------------------------ */
+/* For normalised s primitives a, b (exponents x_a, x_b, centres A, B):
+ *   S_ab = N_a N_b (pi/p)^{3/2} exp(-x_a x_b / p |A-B|^2),   p = x_a + x_b
+ *   T_ab = m (3 - 2 m |A-B|^2) S_ab,                          m = x_a x_b / p
+ *   V_ab = -sum_C Z_C (2 pi / p) N_a N_b exp(-m |A-B|^2) F0(p |P-C|^2)
+ * with P the Gaussian product centre.  Outputs are [N][N] row-major. */
+void or_one_electron(int N, const double *xyz, const double *alpha, int nc,
+                     const double *cxyz, const double *Z, double *S, double *T, double *V)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int a = 0; a < N; ++a)
+        for (int b = 0; b < N; ++b) {
+            double p, P[3], E;
+            pair_data(xyz, alpha, a, b, &p, P, &E);
+            double m = alpha[a] * alpha[b] / p, r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double d = xyz[3 * a + k] - xyz[3 * b + k];
+                r2 += d * d;
+            }
+            double s = E * pow(M_PI / p, 1.5);
+            double v = 0.0;
+            for (int c = 0; c < nc; ++c) {
+                double pc2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double d = P[k] - cxyz[3 * c + k];
+                    pc2 += d * d;
+                }
+                v -= Z[c] * 2.0 * M_PI / p * E * or_boys0(p * pc2);
+            }
+            S[a * N + b] = s;
+            T[a * N + b] = m * (3.0 - 2.0 * m * r2) * s;
+            V[a * N + b] = v;
+        }
+}
+
+/* Repulsion of the point charges, sum_{C<D} Z_C Z_D / |C - D|. */
+double or_charge_repulsion(int nc, const double *cxyz, const double *Z)
+{
+    double e = 0.0;
+    for (int c = 0; c < nc; ++c)
+        for (int d = 0; d < c; ++d) {
+            double r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double t = cxyz[3 * c + k] - cxyz[3 * d + k];
+                r2 += t * t;
+            }
+            e += Z[c] * Z[d] / sqrt(r2);
+        }
+    return e;
+}
+

@@ -23,6 +23,9 @@ thresholds):
   normal deviates (so they are orthonormal and orthogonal to C); orbital
   energies are sorted uniform deviates, occupied in [-1.5, -0.3] and virtual
   in [0.2, 2.5] hartree; all from ``PCG64(seed + 7919)``.
+* Point charges for the SCF (``scf_charges``): charge 2 on each of the first O
+  centres, none on the others (their functions are ghost functions), so the
+  2 O electrons fill closed-shell He-like sites.
 * Stand-alone transformed vectors for the second-order energy
   (``random_mo_vectors``): B[P][i][a] standard normal deviates scaled by
   sqrt(d_P), d_P falling geometrically from 1 to 1e-6 over P (the shape of a
@@ -171,6 +174,22 @@ def exponent_block(m: Molecule, flagged: Sequence[int]) -> np.ndarray:
         n_exp += 1
     keep = set(int(f) for f in flagged)
     return np.array([1 if (k % n_exp) in keep else 0 for k in range(m.n_basis)], dtype=np.uint8)
+
+
+def scf_charges(m: Molecule, n_occ: int | None = None):
+    """Synthetic point charges for the SCF: charge 2 on each of the first
+    ``n_occ`` centres (closed-shell He-like sites, 2 n_occ electrons in all)
+    and none on the rest, whose functions stay as ghost functions.
+    Returns (charge_xyz [n_occ][3], charge [n_occ])."""
+    o = m.n_occ if n_occ is None else int(n_occ)
+    n = m.n_basis
+    n_exp = 1
+    while n_exp < n and np.array_equal(m.xyz[n_exp], m.xyz[0]):   # functions on centre 0
+        n_exp += 1
+    centres = m.xyz[::n_exp]
+    if o > centres.shape[0]:
+        raise ValueError("more occupied orbitals than centres")
+    return np.ascontiguousarray(centres[:o]), np.full(o, 2.0)
 
 
 def random_mo_vectors(n_vectors: int, n_occ: int, n_virt: int, seed: int) -> np.ndarray:

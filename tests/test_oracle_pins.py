@@ -526,3 +526,105 @@ def test_restricted_replay_flags_a_non_candidate(orc):
     # non-candidate is a valid restricted argmax; that one is flagged
     rep = orc.decompose(m.xyz, m.alpha, rp, 1e-6, given=full.pivots, pivot_fn=fn)
     assert rep.bad == first_bad and rep.M == first_bad
+
+
+# ---------------------------------------------------------------- SCF (Sec. 4.1)
+def _g1(x, c, a):
+    return (2.0 * a / math.pi) ** 0.25 * np.exp(-a * (x - c) ** 2)
+
+
+def _one_electron_numerical(A, a, B, b, Cc):
+    """S, T and the attraction to a unit charge at Cc by 1-D grid quadrature of
+    the plain Gaussians per axis (no product theorem, no Boys function):
+    T = 1/2 int grad g_a . grad g_b, and 1/r = 2/sqrt(pi) int_0^inf exp(-u^2 r^2) du."""
+    x = np.linspace(-12.0, 12.0, 24001)
+    dx = x[1] - x[0]
+    ov, kin = [], []
+    for k in range(3):
+        ga, gb = _g1(x, A[k], a), _g1(x, B[k], b)
+        dga, dgb = -2.0 * a * (x - A[k]) * ga, -2.0 * b * (x - B[k]) * gb
+        ov.append(np.sum(ga * gb) * dx)
+        kin.append(np.sum(dga * dgb) * dx)
+    S = ov[0] * ov[1] * ov[2]
+    T = 0.5 * sum(kin[k] * np.prod([ov[j] for j in range(3) if j != k]) for k in range(3))
+
+    def f(u):
+        out = 1.0
+        for k in range(3):
+            out *= np.sum(_g1(x, A[k], a) * _g1(x, B[k], b) * np.exp(-u * u * (x - Cc[k]) ** 2)) * dx
+        return out
+    V = -2.0 / math.sqrt(math.pi) * scipy.integrate.quad(f, 0.0, np.inf, limit=200)[0]
+    return S, T, V
+
+
+def test_one_electron_matches_numerical_route(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        A, B, Cc = rng.uniform(-1.5, 1.5, (3, 3))
+        a, b = rng.uniform(0.3, 2.5, 2)
+        S, T, V = orc.one_electron(np.array([A, B]), np.array([a, b]), Cc[None], [1.0])
+        Sn, Tn, Vn = _one_electron_numerical(A, a, B, b, Cc)
+        assert S[0, 1] == pytest.approx(Sn, rel=1e-9, abs=1e-12)
+        assert T[0, 1] == pytest.approx(Tn, rel=1e-8, abs=1e-11)
+        assert V[0, 1] == pytest.approx(Vn, rel=1e-8, abs=1e-11)
+        assert S[0, 1] == S[1, 0] and T[0, 1] == pytest.approx(T[1, 0], rel=1e-15)
+
+
+def test_single_gaussian_helium_closed_form(orc):
+    """One normalised Gaussian on a charge-2 nucleus holding two electrons:
+    E(a) = 3a - 8 sqrt(2a/pi) + 2 sqrt(a/pi) (two kinetic terms, two
+    attractions, one repulsion 2 sqrt(a/pi)); its minimum is
+    -(8 sqrt 2 - 2)^2 / (12 pi) = -2.3010 Eh."""
+    a_opt = ((8.0 * math.sqrt(2.0) - 2.0) / (6.0 * math.sqrt(math.pi))) ** 2
+    for a in (0.5, a_opt, 2.0):
+        xyz, al = np.zeros((1, 3)), np.array([a])
+        S, T, V = orc.one_electron(xyz, al, np.zeros((1, 3)), [2.0])
+        res = orc.scf(S, T + V, 0.0, 1, lambda C: orc.jk_exact(xyz, al, C))
+        exact = 3.0 * a - 8.0 * math.sqrt(2.0 * a / math.pi) + 2.0 * math.sqrt(a / math.pi)
+        assert res.converged and res.energies[-1] == pytest.approx(exact, rel=1e-13)
+    assert exact > -(8.0 * math.sqrt(2.0) - 2.0) ** 2 / (12.0 * math.pi)
+    assert res.energies[-1] > -2.30103
+
+
+def test_charge_repulsion_and_point_charge_symmetry(orc):
+    cx = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 2.0], [0.0, 3.0, 0.0]])
+    Z = np.array([2.0, 1.0, 3.0])
+    assert orc.charge_repulsion(cx, Z) == pytest.approx(2.0 / 2.0 + 6.0 / 3.0 + 3.0 / math.sqrt(13.0),
+                                                         rel=1e-15)
+    # the attraction matrix is linear in the charges
+    m = make_molecule(3, 3.0, (0.5, 2.0), 1, seed=9)
+    _, _, V1 = orc.one_electron(m.xyz, m.alpha, cx, Z)
+    _, _, V2 = orc.one_electron(m.xyz, m.alpha, cx, 2.0 * Z)
+    assert np.abs(V2 - 2.0 * V1).max() <= 1e-13 * np.abs(V1).max()
+
+
+@pytest.fixture(scope="module")
+def c1_scf(orc):
+    from paper_2609_00306_amd.inputs import scf_charges
+    m = config_molecule("C1")
+    cx, Z = scf_charges(m)
+    S, T, V = orc.one_electron(m.xyz, m.alpha, cx, Z)
+    en = orc.charge_repulsion(cx, Z)
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    cd0 = orc.decompose(m.xyz, m.alpha, rp, 0.0)
+    exact = orc.scf(S, T + V, en, m.n_occ, lambda C: orc.jk_exact(m.xyz, m.alpha, C))
+    cd = orc.scf(S, T + V, en, m.n_occ, lambda C: orc.jk_cd(m.n_basis, rp, cd0.L, C))
+    return m, S, T + V, exact, cd
+
+
+def test_scf_converged_invariants(orc, c1_scf):
+    """Brillouin condition (F D S = S D F), idempotency D S D = D, tr(D S) = O,
+    and the converged energy below the core-guess energy."""
+    m, S, H, exact, cd = c1_scf
+    for r in (exact, cd):
+        assert r.converged
+        D, F = r.D, r.F
+        assert np.abs(F @ D @ S - S @ D @ F).max() < 1e-7
+        assert np.abs(D @ S @ D - D).max() < 1e-12
+        assert np.trace(D @ S) == pytest.approx(m.n_occ, abs=1e-10)
+        assert r.energies[-1] < r.energies[0]
+
+
+def test_scf_at_tau_zero_equals_exact_integrals(orc, c1_scf):
+    m, S, H, exact, cd = c1_scf
+    assert abs(cd.energies[-1] - exact.energies[-1]) <= 1e-9 * abs(exact.energies[-1])
