@@ -15,7 +15,8 @@
  *   cd_transform  the AO->MO transform of the vectors (Sec. 4.1, CASSCF;
  *                 two-coefficient form of Sec. 6.2);
  *   cd_mp2_energy the second-order energy from transformed vectors (CD-based
- *                 MP2, Secs. 5 and 7).
+ *                 MP2, Secs. 5 and 7);
+ *   cd_one_electron, cd_scf  the SCF on Cholesky J/K (Sec. 4.1).
  *
  * Conventions
  *   - Plain C, fixed-width integers; no C++ types or exceptions cross it.
@@ -264,6 +265,65 @@ cd_status cd_query_mp2(const cd_mp2_problem *probs, int32_t count, size_t *ws_by
 
 cd_status cd_mp2_energy(const cd_mp2_problem *probs, int32_t count, uint32_t flags, void *ws,
                         size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * SCF on Cholesky J/K (Sec. 4.1): the one-electron integrals and a
+ * closed-shell Roothaan-Hall loop whose J and K come from cd_build_jk.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    cd_molecule mol;           /* the basis (pivot_fn is ignored) */
+    int32_t n_charges;         /* point charges, >= 0 */
+    const double *charge_xyz;  /* device [n_charges][3], bohr */
+    const double *charge;      /* device [n_charges] */
+    double *S;                 /* out, device [N][N]: overlap */
+    double *H;                 /* out, device [N][N]: kinetic energy + attraction to the charges */
+} cd_one_electron_problem;
+
+/* S and H in closed form for normalised s functions (textbook formulas with
+ * F0).  Asynchronous unless flags has CD_SYNC. */
+cd_status cd_one_electron(const cd_one_electron_problem *p, uint32_t flags, void *stream);
+
+typedef struct {
+    /* Cholesky vectors, as in cd_jk_problem (device) */
+    int32_t n_basis;
+    int64_t n_rows;
+    int64_t max_vectors;
+    const int64_t *row_pair;
+    const double *L;
+    const int64_t *n_vectors;
+    int32_t n_occ;             /* O doubly occupied orbitals, 1 <= O <= N */
+    const double *S;           /* device [N][N] overlap */
+    const double *H;           /* device [N][N] one-electron Hamiltonian */
+    double e_charges;          /* host value added to every energy (charge repulsion) */
+    int32_t max_iter;          /* >= 1 */
+    double e_tol;              /* converged when |E_k - E_(k-1)| < e_tol ... */
+    double d_tol;              /* ... and max |F D S - S D F| < d_tol */
+    double *C;                 /* out, device [N][O]: D = C C^T (pivoted Cholesky factor of D) */
+    double *D;                 /* out, device [N][N]: density of the last iteration */
+    double *F;                 /* out, device [N][N]: F(D) = H + 2 J(D) - K(D) */
+    double *energies;          /* out, device [max_iter]: E_k = tr(D_k (H + F_k)) + e_charges */
+    int32_t *status;           /* device [1] */
+    int32_t n_iter;            /* out (host field): energies written */
+    int32_t converged;         /* out (host field): 1 if the tolerances were met */
+} cd_scf_problem;
+
+/* Workspace bytes of cd_scf (host-side, no device work). */
+cd_status cd_query_scf(const cd_scf_problem *p, cd_precision prec, size_t *ws_bytes);
+
+/*
+ * cd_scf: D_0 projects on the O lowest solutions of H C = S C e (core
+ * guess); iteration k builds J and K of D_k = C_k C_k^T from the vectors at
+ * precision 'prec', F_k = H + 2 J - K and E_k, and stops on convergence;
+ * otherwise D_(k+1) projects on the O lowest solutions of F_k C = S C e.  The
+ * projector comes from trace-correcting purification of X F X with
+ * X = S^(-1/2) (Newton-Schulz), not from a diagonalisation.  Blocking: the
+ * host reads the convergence figures.  Errors: CD_ERR_INVALID_ARG (sizes,
+ * pointers), CD_ERR_NOT_PSD (the orthogonaliser does not converge: S is not
+ * positive definite to working precision), CD_ERR_UNSUPPORTED (purification
+ * does not converge: no gap between the O-th and (O+1)-th level), and the
+ * errors of cd_build_jk.
+ */
+cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes, void *stream);
 
 /* Thread-local message describing the last error returned on this thread. */
 const char *cd_last_error(void);

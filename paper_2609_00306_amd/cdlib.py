@@ -72,9 +72,26 @@ class cd_mp2_problem(ctypes.Structure):
                 ("e_virt", _vp), ("energy", _vp), ("pair_energy", _vp), ("status", _vp)]
 
 
+
+class cd_one_electron_problem(ctypes.Structure):
+    _fields_ = [("mol", cd_molecule), ("n_charges", ctypes.c_int32), ("charge_xyz", _vp),
+                ("charge", _vp), ("S", _vp), ("H", _vp)]
+
+
+class cd_scf_problem(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
+                ("n_vectors", _vp), ("n_occ", ctypes.c_int32), ("S", _vp), ("H", _vp),
+                ("e_charges", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("e_tol", ctypes.c_double), ("d_tol", ctypes.c_double), ("C", _vp), ("D", _vp),
+                ("F", _vp), ("energies", _vp), ("status", _vp), ("n_iter", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+
 #: every function include/cd.h declares
 EXPORTS = ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
-           "cd_transform", "cd_query_mp2", "cd_mp2_energy", "cd_last_error", "cd_version")
+           "cd_transform", "cd_query_mp2", "cd_mp2_energy", "cd_one_electron", "cd_query_scf",
+           "cd_scf", "cd_last_error", "cd_version")
 
 _lib = None
 
@@ -112,8 +129,12 @@ def load(path: str = LIB_PATH):
     L.cd_query_mp2.argtypes = [P(cd_mp2_problem), ctypes.c_int32, P(ctypes.c_size_t)]
     L.cd_mp2_energy.argtypes = [P(cd_mp2_problem), ctypes.c_int32, ctypes.c_uint32, _vp,
                                 ctypes.c_size_t, _vp]
+    L.cd_one_electron.argtypes = [P(cd_one_electron_problem), ctypes.c_uint32, _vp]
+    L.cd_query_scf.argtypes = [P(cd_scf_problem), ctypes.c_int, P(ctypes.c_size_t)]
+    L.cd_scf.argtypes = [P(cd_scf_problem), ctypes.c_int, _vp, ctypes.c_size_t, _vp]
     for f in ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk",
-              "cd_query_transform", "cd_transform", "cd_query_mp2", "cd_mp2_energy"):
+              "cd_query_transform", "cd_transform", "cd_query_mp2", "cd_mp2_energy",
+              "cd_one_electron", "cd_query_scf", "cd_scf"):
         getattr(L, f).restype = ctypes.c_int
     L.cd_last_error.restype = ctypes.c_char_p
     L.cd_last_error.argtypes = []
@@ -399,3 +420,55 @@ def mp2_energy(B, n_vectors, e_occ, e_virt, pair_energy: bool = False, sync: boo
     _check(L.cd_mp2_energy(ctypes.byref(prob), 1, CD_SYNC if sync else 0, _ptr(w), w.numel(),
                            _stream(stream)))
     return (E, pe) if pair_energy else E
+
+
+def one_electron(xyz, alpha, charge_xyz, charge, device="cuda", sync: bool = True, stream=None):
+    """Overlap S and one-electron Hamiltonian H (kinetic + point-charge
+    attraction) as device [N][N] tensors."""
+    xyz = _dev_f64(xyz, device).reshape(-1, 3)
+    alpha = _dev_f64(alpha, device).reshape(-1)
+    cx = _dev_f64(charge_xyz, device).reshape(-1, 3)
+    Z = _dev_f64(charge, device).reshape(-1)
+    N = int(alpha.shape[0])
+    S = torch.empty((N, N), dtype=torch.float64, device=device)
+    H = torch.empty((N, N), dtype=torch.float64, device=device)
+    prob = cd_one_electron_problem(molecule(xyz, alpha), int(Z.numel()), _ptr(cx), _ptr(Z),
+                                   _ptr(S), _ptr(H))
+    _check(load().cd_one_electron(ctypes.byref(prob), CD_SYNC if sync else 0, _stream(stream)))
+    return S, H
+
+
+@dataclasses.dataclass
+class SCFResult:
+    energies: torch.Tensor   # [n_iter] E_k
+    C: torch.Tensor          # [N][O], D = C C^T
+    D: torch.Tensor
+    F: torch.Tensor
+    converged: bool
+
+
+def scf(d: Decomposition, S: torch.Tensor, H: torch.Tensor, n_occ: int, e_charges: float,
+        prec: str = "fp64", max_iter: int = 100, e_tol: float = 1e-10, d_tol: float = 1e-8,
+        stream=None) -> SCFResult:
+    """Closed-shell SCF on the decomposition's J/K (cd_scf; blocking)."""
+    dev = d.L.device
+    N = d.n_basis
+    f64 = dict(dtype=torch.float64, device=dev)
+    C = torch.empty((N, n_occ), **f64)
+    D = torch.empty((N, N), **f64)
+    F = torch.empty((N, N), **f64)
+    E = torch.zeros(max_iter, **f64)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    S = S.contiguous()
+    H = H.contiguous()
+    prob = cd_scf_problem(N, d.n_rows, d.max_vectors, _ptr(d.row_pair), _ptr(d.L),
+                          _ptr(d.n_vectors), int(n_occ), _ptr(S), _ptr(H), float(e_charges),
+                          int(max_iter), float(e_tol), float(d_tol), _ptr(C), _ptr(D), _ptr(F),
+                          _ptr(E), _ptr(st), 0, 0)
+    L = load()
+    ws = ctypes.c_size_t()
+    _check(L.cd_query_scf(ctypes.byref(prob), PRECISIONS[prec], ctypes.byref(ws)))
+    w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
+    _check(L.cd_scf(ctypes.byref(prob), PRECISIONS[prec], _ptr(w), w.numel(), _stream(stream)))
+    return SCFResult(E[:prob.n_iter].clone(), C, D, F, bool(prob.converged))
+

@@ -15,6 +15,7 @@
 #include "cd_jk.hip"
 #include "cd_jk_lp.hip"
 #include "cd_mp2.hip"
+#include "cd_scf.hip"
 
 using namespace cdk;
 
@@ -789,6 +790,251 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
     if (flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)
             return fail(CD_ERR_DEVICE, "stream synchronise failed");
+    }
+    return CD_OK;
+}
+
+cd_status cd_one_electron(const cd_one_electron_problem *p, uint32_t flags, void *stream)
+{
+    if (!p) return fail(CD_ERR_INVALID_ARG, "null problem");
+    cd_status s = check_mol(p->mol);
+    if (s) return s;
+    const int N = p->mol.n_basis;
+    if (p->n_charges < 0) return fail(CD_ERR_INVALID_ARG, "n_charges < 0");
+    if (p->n_charges > 0 && (!p->charge_xyz || !p->charge))
+        return fail(CD_ERR_INVALID_ARG, "null charges");
+    if (N > 0 && (!p->S || !p->H)) return fail(CD_ERR_INVALID_ARG, "null S/H");
+    if ((int64_t)N * N > ((int64_t)1 << 40)) return fail(CD_ERR_UNSUPPORTED, "basis too large");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n2 = (int64_t)N * N;
+    if (n2 > 0)
+        k_one_electron<<<(unsigned)blocks_of(n2, 256), 256, 0, st>>>(
+            N, p->mol.xyz, p->mol.alpha, p->n_charges, p->charge_xyz, p->charge, p->S, p->H);
+    if ((s = check_launch("one-electron kernel"))) return s;
+    if ((flags & CD_SYNC) && hipStreamSynchronize(st) != hipSuccess)
+        return fail(CD_ERR_DEVICE, "stream synchronise failed");
+    return CD_OK;
+}
+
+// Device workspace of cd_scf: eight N x N matrices, the Cholesky scratch, the
+// reduction results, and the J/K workspace.
+struct ScfWs {
+    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red;
+    void *jk;
+    size_t jk_bytes;
+};
+
+static cd_jk_problem scf_jk_problem(const cd_scf_problem &p, double *J, double *K)
+{
+    cd_jk_problem q{};
+    q.n_basis = p.n_basis;
+    q.n_rows = p.n_rows;
+    q.max_vectors = p.max_vectors;
+    q.row_pair = p.row_pair;
+    q.L = p.L;
+    q.n_vectors = p.n_vectors;
+    q.n_occ = p.n_occ;
+    q.C = p.C;
+    q.J = J;
+    q.K = K;
+    q.status = p.status;
+    return q;
+}
+
+static cd_status scf_carve(const cd_scf_problem &p, cd_precision prec, void *base, ScfWs &w,
+                           size_t &bytes)
+{
+    const int64_t n2 = std::max<int64_t>(1, (int64_t)p.n_basis * p.n_basis);
+    Carver c(base);
+    w.X = c.take<double>(n2);
+    w.A = c.take<double>(n2);
+    w.B = c.take<double>(n2);
+    w.T = c.take<double>(n2);
+    w.W1 = c.take<double>(n2);
+    w.W2 = c.take<double>(n2);
+    w.J = c.take<double>(n2);
+    w.K = c.take<double>(n2);
+    w.dres = c.take<double>(std::max(1, p.n_basis));
+    w.red = c.take<double>(8);
+    // the J/K workspace depends on the sizes only; the size query is given
+    // placeholder addresses that it never dereferences
+    static double placeholder[1];
+    cd_jk_problem q = scf_jk_problem(p, placeholder, placeholder);
+    q.row_pair = reinterpret_cast<const int64_t *>(placeholder);
+    q.L = placeholder;
+    q.n_vectors = reinterpret_cast<const int64_t *>(placeholder);
+    q.C = placeholder;
+    q.status = reinterpret_cast<int32_t *>(placeholder);
+    size_t jb = 0;
+    cd_status s = cd_query_jk(&q, 1, prec, &jb);
+    if (s) return s;
+    w.jk = c.take<char>(std::max<size_t>(1, jb));
+    w.jk_bytes = std::max<size_t>(1, jb);
+    bytes = c.off;
+    return CD_OK;
+}
+
+static cd_status check_scf(const cd_scf_problem *p)
+{
+    if (!p) return fail(CD_ERR_INVALID_ARG, "null problem");
+    if (p->n_basis < 1 || p->n_occ < 1 || p->n_occ > p->n_basis)
+        return fail(CD_ERR_INVALID_ARG, "need 1 <= n_occ <= n_basis");
+    if (p->max_iter < 1) return fail(CD_ERR_INVALID_ARG, "max_iter < 1");
+    if (!(p->e_tol >= 0.0) || !(p->d_tol >= 0.0))
+        return fail(CD_ERR_INVALID_ARG, "tolerances must be >= 0");
+    if ((int64_t)p->n_basis * p->n_basis > ((int64_t)1 << 31))
+        return fail(CD_ERR_UNSUPPORTED, "basis too large");
+    return CD_OK;
+}
+
+cd_status cd_query_scf(const cd_scf_problem *p, cd_precision prec, size_t *ws_bytes)
+{
+    if (!ws_bytes) return fail(CD_ERR_INVALID_ARG, "null ws_bytes");
+    cd_status s = check_scf(p);
+    if (s) return s;
+    ScfWs w{};
+    return scf_carve(*p, prec, nullptr, w, *ws_bytes);
+}
+
+cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes, void *stream)
+{
+    cd_status s = check_scf(p);
+    if (s) return s;
+    if (!p->S || !p->H || !p->C || !p->D || !p->F || !p->energies || !p->status ||
+        !p->n_vectors || (p->n_rows > 0 && (!p->row_pair || !p->L)))
+        return fail(CD_ERR_INVALID_ARG, "null pointer in SCF problem");
+    ScfWs w{};
+    size_t need = 0;
+    if ((s = scf_carve(*p, prec, nullptr, w, need))) return s;
+    if (need > ws_bytes || !ws)
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if ((s = scf_carve(*p, prec, ws, w, need))) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int N = p->n_basis, O = p->n_occ;
+    const int64_t n2 = (int64_t)N * N;
+    const unsigned eb = (unsigned)blocks_of(n2, 256);
+    const dim3 gg((unsigned)blocks_of(N, 64), (unsigned)blocks_of(N, 64));
+    p->n_iter = 0;
+    p->converged = 0;
+
+    auto gemm = [&](const double *A, const double *B, double *C) {
+        k_gemm_nn<<<gg, 256, 0, st>>>(N, A, B, C);
+    };
+    auto lincomb = [&](double *out, double a, const double *X, double b, const double *Y,
+                       double c) { k_lincomb<<<eb, 256, 0, st>>>(N, out, a, X, b, Y, c); };
+    // read 'n' reduction results back (synchronises the stream)
+    double h[8];
+    auto read = [&](int n) -> cd_status {
+        cd_status r = check_launch("SCF kernels");
+        if (r) return r;
+        if (hipMemcpyAsync(h, w.red, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "SCF read-back failed");
+        return CD_OK;
+    };
+
+    k_fill_i32<<<1, 64, 0, st>>>(p->status, 1, 0);
+
+    // ---- X = S^{-1/2}: coupled Newton-Schulz from Y = S / c, Z = I
+    k_gershgorin<<<1, 256, 0, st>>>(N, p->S, w.red);
+    if ((s = read(2))) return s;
+    const double c = h[1];
+    if (!(c > 0.0) || !std::isfinite(c)) return fail(CD_ERR_NOT_PSD, "overlap bound %g", c);
+    double *Y = w.A, *Z = w.B;
+    lincomb(Y, 1.0 / c, p->S, 0.0, nullptr, 0.0);
+    lincomb(Z, 0.0, p->S, 0.0, nullptr, 1.0);
+    bool ns_ok = false;
+    double prev = INFINITY;
+    for (int it = 0; it < 200; ++it) {
+        gemm(Z, Y, w.W1);
+        k_maxabs<<<1, 256, 0, st>>>(N, w.W1, 1, w.red);
+        if ((s = read(1))) return s;
+        const double err = h[0];
+        if (!std::isfinite(err)) break;
+        if (err < 1e-13 || (err < 1e-9 && err >= 0.5 * prev)) {
+            ns_ok = true;
+            break;
+        }
+        prev = err;
+        lincomb(w.T, -0.5, w.W1, 0.0, nullptr, 1.5);
+        gemm(Y, w.T, w.W2);
+        std::swap(Y, w.W2);
+        gemm(w.T, Z, w.W2);
+        std::swap(Z, w.W2);
+    }
+    if (!ns_ok) return fail(CD_ERR_NOT_PSD, "Newton-Schulz for S^-1/2 did not converge");
+    lincomb(w.X, 1.0 / std::sqrt(c), Z, 0.0, nullptr, 0.0);
+    // the scratch pointers may have been swapped: keep A, B, W2 distinct from X
+    double *bufs[3] = {Y, Z, w.W2};
+    w.A = bufs[0];
+    w.B = bufs[1];
+    w.W2 = bufs[2];
+
+    // ---- projector on the O lowest levels of Fm (in the S metric) into p->D
+    auto purify = [&](const double *Fm) -> cd_status {
+        double *Fo = w.A, *P = w.B, *P2 = w.T;
+        gemm(w.X, Fm, w.W1);
+        gemm(w.W1, w.X, Fo);
+        k_gershgorin<<<1, 256, 0, st>>>(N, Fo, w.red);
+        cd_status r = read(2);
+        if (r) return r;
+        const double lo = h[0], hi = h[1];
+        if (!(hi > lo)) return fail(CD_ERR_UNSUPPORTED, "degenerate Fock spectrum bounds");
+        lincomb(P, -1.0 / (hi - lo), Fo, 0.0, nullptr, hi / (hi - lo));
+        bool ok = false;
+        double last = INFINITY;
+        for (int it = 0; it < 400; ++it) {
+            gemm(P, P, P2);
+            k_traces<<<1, 256, 0, st>>>(N, P, P2, w.red);
+            if ((r = read(2))) return r;
+            const double t1 = h[0], t2 = h[1], e = std::fabs(t1 - t2);
+            if (!std::isfinite(e)) break;
+            if (e < 1e-13 * O || (e < 1e-9 && e >= 0.5 * last)) {
+                ok = true;
+                break;
+            }
+            last = e;
+            if (t1 > (double)O)
+                std::swap(P, P2);                       // P <- P^2
+            else
+                lincomb(P, 2.0, P, -1.0, P2, 0.0);      // P <- 2 P - P^2
+        }
+        if (!ok) return fail(CD_ERR_UNSUPPORTED, "purification did not converge (no gap?)");
+        gemm(w.X, P, w.W1);
+        gemm(w.W1, w.X, p->D);
+        // keep the scratch roles consistent after the swaps
+        w.B = P;
+        w.T = P2;
+        return CD_OK;
+    };
+
+    if ((s = purify(p->H))) return s;
+    cd_jk_problem q = scf_jk_problem(*p, w.J, w.K);
+    double e_prev = 0.0;
+    for (int k = 0; k < p->max_iter; ++k) {
+        k_density_cholesky<<<1, 256, 0, st>>>(N, O, p->D, p->C, w.dres, p->status);
+        if ((s = check_launch("density Cholesky"))) return s;
+        if ((s = cd_build_jk(&q, 1, prec, 0, w.jk, w.jk_bytes, stream))) return s;
+        k_fock_energy<<<1, 256, 0, st>>>(N, p->H, w.J, w.K, p->D, p->e_charges, p->F,
+                                         p->energies + k);
+        gemm(p->F, p->D, w.W1);
+        gemm(w.W1, p->S, w.W2);
+        k_maxabs<<<1, 256, 0, st>>>(N, w.W2, 0, w.red);
+        if ((s = read(1))) return s;
+        const double comm = h[0];
+        double E = 0.0;
+        int32_t dst = 0;
+        if (hipMemcpy(&E, p->energies + k, sizeof E, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&dst, p->status, sizeof dst, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "SCF read-back failed");
+        if (dst != 0) return fail((cd_status)dst, "SCF iteration %d: device status %d", k, dst);
+        p->n_iter = k + 1;
+        if (k > 0 && std::fabs(E - e_prev) < p->e_tol && comm < p->d_tol) {
+            p->converged = 1;
+            break;
+        }
+        e_prev = E;
+        if (k + 1 < p->max_iter && (s = purify(p->F))) return s;
     }
     return CD_OK;
 }

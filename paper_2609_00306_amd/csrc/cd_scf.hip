@@ -1,0 +1,292 @@
+// Closed-shell SCF on Cholesky J/K (Sec. 4.1): the one-electron integrals
+// over the s functions, and the dense N x N building blocks of a
+// diagonalisation-free Roothaan-Hall step.
+//
+//   one-electron : S, T and the attraction to point charges in closed form
+//                  (textbook s-function formulas with the Boys function F0);
+//   orthogonaliser: X = S^{-1/2} by the coupled Newton-Schulz iteration
+//                  Y <- Y T, Z <- T Z, T = (3 I - Z Y) / 2 from Y = S / c,
+//                  Z = I (c bounds the spectrum of S from above);
+//   density      : the projector on the O lowest solutions of F C = S C e,
+//                  by trace-correcting purification of X F X (Niklasson,
+//                  Phys. Rev. B 66, 155115 (2002)): P <- P^2 when tr P > O,
+//                  else 2 P - P^2, from P0 = (l_max - X F X) / (l_max - l_min)
+//                  with Gershgorin bounds; D = X P X;
+//   orbitals     : D = C C^T with C [N][O] from a pivoted Cholesky
+//                  decomposition of the rank-O density (any such C gives the
+//                  same J and K, which depend on D only).
+// Every product is an FP64 matrix-core GEMM (the shared tile engine); every
+// sum over matrix elements runs in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cd_device.hpp"
+#include "cd_mfma.hpp"
+
+namespace cdk {
+
+// ---------------------------------------------------------------- one-electron
+// S_ab = N_a N_b (pi/p)^{3/2} exp(-m R^2), T_ab = m (3 - 2 m R^2) S_ab,
+// V_ab = -sum_C Z_C 2 pi / p N_a N_b exp(-m R^2) F0(p |P - C|^2),
+// p = a + b, m = a b / p, P = (a A + b B) / p, N = (2 x / pi)^{3/4}.
+__global__ __launch_bounds__(256) void k_one_electron(int N, const double *__restrict__ xyz,
+                                                      const double *__restrict__ alpha, int nc,
+                                                      const double *__restrict__ cxyz,
+                                                      const double *__restrict__ Z,
+                                                      double *__restrict__ S,
+                                                      double *__restrict__ H)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int a = (int)(e / N), b = (int)(e % N);
+    const double xa = alpha[a], xb = alpha[b];
+    const double p = xa + xb, m = xa * xb / p;
+    double r2 = 0.0, P[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double A = xyz[3 * a + k], B = xyz[3 * b + k];
+        r2 += (A - B) * (A - B);
+        P[k] = (xa * A + xb * B) / p;
+    }
+    const double nn = pow(2.0 * xa / kPi, 0.75) * pow(2.0 * xb / kPi, 0.75);
+    const double E = nn * exp(-m * r2);
+    const double s = E * pow(kPi / p, 1.5);
+    double v = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double pc2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double d = P[k] - cxyz[3 * c + k];
+            pc2 += d * d;
+        }
+        v -= Z[c] * (2.0 * kPi / p) * E * boys0(p * pc2);
+    }
+    S[e] = s;
+    H[e] = m * (3.0 - 2.0 * m * r2) * s + v;
+}
+
+// ---------------------------------------------------------------- dense GEMM
+// C = A B for row-major N x N matrices: one 64 x 64 tile per workgroup.
+constexpr int SCF_TKC = 32;
+__global__ __launch_bounds__(256) void k_gemm_nn(int N, const double *__restrict__ A,
+                                                 const double *__restrict__ B,
+                                                 double *__restrict__ C)
+{
+    using SA = OperandStage<64, SCF_TKC, false>;
+    using SB = OperandStage<64, SCF_TKC, true>;
+    __shared__ double sA[SA::kSize];
+    __shared__ double sB[SB::kSize];
+    const int r0 = 64 * blockIdx.y, c0 = 64 * blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    f64x4 acc[4];
+    zero_acc(acc);
+    gemm_tile<4, SCF_TKC, false, true>(
+        0, N,
+        [&](int64_t k, int m) -> double {
+            const int r = r0 + m;
+            return (r < N) ? A[(int64_t)r * N + k] : 0.0;
+        },
+        [&](int64_t k, int n) -> double {
+            const int c = c0 + n;
+            return (c < N) ? B[k * N + c] : 0.0;
+        },
+        acc, sA, sB);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = r0 + 16 * r + mfma_row(lane, v), col = c0 + 16 * w + (lane & 15);
+            if (row < N && col < N) C[(int64_t)row * N + col] = acc[r][v];
+        }
+}
+
+// out = a X + b Y + c I (Y may be null when b == 0)
+// (out may be X or Y: each element is read before it is written by the same thread)
+__global__ __launch_bounds__(256) void k_lincomb(int N, double *out, double a, const double *X,
+                                                 double b, const double *Y, double c)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    double v = a * X[e];
+    if (Y) v += b * Y[e];
+    if (e / N == e % N) v += c;
+    out[e] = v;
+}
+
+// Fixed-order sum and max of one value per thread of a 256-thread workgroup
+// (valid in thread 0).
+__device__ __forceinline__ double scf_block_sum(double v, double *s)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+    s[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) s[tid] = s[tid] + s[tid + w];
+        __syncthreads();
+    }
+    return s[0];
+}
+
+__device__ __forceinline__ double scf_block_max(double v, double *s)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+    s[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) s[tid] = fmax(s[tid], s[tid + w]);
+        __syncthreads();
+    }
+    return s[0];
+}
+
+// out[0] = tr X, out[1] = tr Y (one workgroup)
+__global__ __launch_bounds__(256) void k_traces(int N, const double *__restrict__ X,
+                                                const double *__restrict__ Y,
+                                                double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        a += X[(int64_t)i * N + i];
+        b += Y[(int64_t)i * N + i];
+    }
+    const double ta = scf_block_sum(a, s);
+    const double tb = scf_block_sum(b, s);
+    if (threadIdx.x == 0) {
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
+// Gershgorin bounds of a symmetric matrix: out[0] <= every eigenvalue <= out[1]
+// (one workgroup).
+__global__ __launch_bounds__(256) void k_gershgorin(int N, const double *__restrict__ A,
+                                                    double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        double r = 0.0;
+        for (int j = 0; j < N; ++j)
+            if (j != i) r += fabs(A[(int64_t)i * N + j]);
+        const double d = A[(int64_t)i * N + i];
+        lo = fmin(lo, d - r);
+        hi = fmax(hi, d + r);
+    }
+    const double mlo = scf_block_max(-lo, s);
+    const double mhi = scf_block_max(hi, s);
+    if (threadIdx.x == 0) {
+        out[0] = -mlo;
+        out[1] = mhi;
+    }
+}
+
+// out[0] = max |G - G^T| (the commutator F D S - S D F with G = F D S for
+// symmetric F, D, S), or with 'minus_identity' max |G - I| (one workgroup per
+// call; N^2 elements).
+__global__ __launch_bounds__(256) void k_maxabs(int N, const double *__restrict__ G,
+                                                int minus_identity, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double m = 0.0;
+    const int64_t n2 = (int64_t)N * N;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+        const int i = (int)(e / N), j = (int)(e % N);
+        const double v = minus_identity ? G[e] - (i == j ? 1.0 : 0.0)
+                                        : G[e] - G[(int64_t)j * N + i];
+        m = fmax(m, fabs(v));
+    }
+    const double r = scf_block_max(m, s);
+    if (threadIdx.x == 0) out[0] = r;
+}
+
+// F = H + 2 J - K and E = sum D o (H + F) + e_charges (one workgroup for the
+// sum; the Fock matrix elementwise by the same threads).
+__global__ __launch_bounds__(256) void k_fock_energy(int N, const double *__restrict__ H,
+                                                     const double *__restrict__ J,
+                                                     const double *__restrict__ K,
+                                                     const double *__restrict__ D, double e_charges,
+                                                     double *__restrict__ F,
+                                                     double *__restrict__ energy)
+{
+    __shared__ double s[256];
+    double acc = 0.0;
+    const int64_t n2 = (int64_t)N * N;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+        const double f = H[e] + 2.0 * J[e] - K[e];
+        F[e] = f;
+        acc += D[e] * (H[e] + f);
+    }
+    const double t = scf_block_sum(acc, s);
+    if (threadIdx.x == 0) energy[0] = t + e_charges;
+}
+
+// C [N][O] with C C^T = D for the rank-O density D: a pivoted Cholesky
+// decomposition taking the O largest residual diagonals in turn (lowest index
+// on ties).  'dres' [N] is scratch.  One workgroup; status 4 when a pivot is
+// not positive.
+__global__ __launch_bounds__(256) void k_density_cholesky(int N, int O,
+                                                          const double *__restrict__ D,
+                                                          double *__restrict__ C,
+                                                          double *__restrict__ dres,
+                                                          int32_t *__restrict__ status)
+{
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    __shared__ int s_piv;
+    __shared__ double s_d;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += 256) dres[i] = D[(int64_t)i * N + i];
+    __syncthreads();
+    for (int k = 0; k < O; ++k) {
+        double bv = -INFINITY;
+        int bi = N;
+        for (int i = tid; i < N; i += 256) {
+            const double d = dres[i];
+            if (d > bv) {   // ascending i per thread: the first maximum stays
+                bv = d;
+                bi = i;
+            }
+        }
+        sv[tid] = bv;
+        si[tid] = bi;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+                const double ov = sv[tid + w];
+                const int oi = si[tid + w];
+                if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) {
+                    sv[tid] = ov;
+                    si[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            s_piv = si[0];
+            s_d = sv[0];
+        }
+        __syncthreads();
+        const int p = s_piv;
+        const double dp = s_d;
+        if (!(dp > 0.0) || p >= N) {
+            if (tid == 0) status[0] = 4;
+            for (int e = tid; e < N * (O - k); e += 256) C[(int64_t)(e / (O - k)) * O + k + e % (O - k)] = 0.0;
+            return;
+        }
+        const double inv = 1.0 / sqrt(dp);
+        for (int i = tid; i < N; i += 256) {
+            double v = D[(int64_t)i * N + p];
+            for (int j = 0; j < k; ++j) v -= C[(int64_t)i * O + j] * C[(int64_t)p * O + j];
+            v *= inv;
+            C[(int64_t)i * O + k] = v;
+            dres[i] = (i == p) ? -INFINITY : dres[i] - v * v;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace cdk

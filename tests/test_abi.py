@@ -62,6 +62,9 @@ int main(void) {
          offsetof(cd_decomp_opts, tuning), offsetof(cd_decomp_opts, eta));
   printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
          offsetof(cd_mp2_problem, status));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(cd_one_electron_problem),
+         offsetof(cd_one_electron_problem, H), sizeof(cd_scf_problem),
+         offsetof(cd_scf_problem, e_tol), offsetof(cd_scf_problem, converged));
   return 0;
 }
 '''
@@ -85,7 +88,10 @@ def test_binding_structs_match_header():
             cdlib.cd_decomp_opts.timeline_cap.offset, ctypes.sizeof(cdlib.cd_tuning),
             cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset,
             cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
-            cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset]
+            cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset,
+            ctypes.sizeof(cdlib.cd_one_electron_problem), cdlib.cd_one_electron_problem.H.offset,
+            ctypes.sizeof(cdlib.cd_scf_problem), cdlib.cd_scf_problem.e_tol.offset,
+            cdlib.cd_scf_problem.converged.offset]
     assert mine == got
 
 
@@ -148,6 +154,16 @@ def test_argument_validation_without_device(lib):
     assert lib.cd_mp2_energy(ctypes.byref(mp), 1, 0, ctypes.c_void_p(0x1000), ws.value,
                              None) == cdlib.CD_ERR_INVALID_ARG
     assert b"null pointer" in lib.cd_last_error()
+    # SCF: sizes and pointers are checked on the host
+    sp = cdlib.cd_scf_problem(n_basis=4, n_occ=5, max_iter=10)
+    assert lib.cd_query_scf(ctypes.byref(sp), 0, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
+    sp = cdlib.cd_scf_problem(n_basis=4, n_occ=2, max_iter=0)
+    assert lib.cd_query_scf(ctypes.byref(sp), 0, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
+    sp = cdlib.cd_scf_problem(n_basis=4, n_occ=2, max_iter=5)
+    assert lib.cd_scf(ctypes.byref(sp), 0, None, 0, None) == cdlib.CD_ERR_INVALID_ARG
+    assert b"null pointer" in lib.cd_last_error()
+    op = cdlib.cd_one_electron_problem(cdlib.cd_molecule(2, None, None))
+    assert lib.cd_one_electron(ctypes.byref(op), 0, None) == cdlib.CD_ERR_INVALID_ARG
     best = cdlib.cd_tuning()
     assert lib.cd_autotune(None, 0, ctypes.byref(opts), None, 0, None,
                            None) == cdlib.CD_ERR_INVALID_ARG

@@ -468,3 +468,83 @@ def test_restricted_candidates_edge_flags():
     assert dz.n_active == 0 and dz.M() == 0 and int(dz.status.item()) == 0
     check_against_oracle(m, tau, 1e-12, dz, 0, pivot_fn=np.zeros(m.n_basis, np.uint8))
 
+
+# SCF on Cholesky J/K (Sec. 4.1).  Both sides take the same steps (core guess,
+# then F_k = H + 2J - K, E_k = tr(D_k (H + F_k)) + charge repulsion, D_(k+1)
+# the projector on the O lowest levels of F_k); the GPU reaches the projector
+# by purification, the oracle by diagonalisation.  J and K agree to 1e-10
+# elementwise, so each E_k agrees to about 3e-10 sum|D|; the projectors agree
+# to the purification's idempotency tolerance.
+def _scf_case(m, tau, schwarz, prec="fp64", e_tol=1e-10, d_tol=1e-8):
+    from paper_2609_00306_amd.inputs import scf_charges
+    cx, Z = scf_charges(m)
+    d, M = run_gpu(m, tau, schwarz)
+    S, H = cdlib.one_electron(m.xyz, m.alpha, cx, Z)
+    e_ch = oracle.charge_repulsion(cx, Z)
+    res = cdlib.scf(d, S, H, m.n_occ, e_ch, prec=prec, e_tol=e_tol, d_tol=d_tol)
+    return d, M, cx, Z, S, H, e_ch, res
+
+
+def test_one_electron_parity():
+    from paper_2609_00306_amd.inputs import scf_charges
+    for m in (config_molecule("C1"), make_molecule(13, 5.0, (0.3, 1.2, 6.0), 6, seed=31)):
+        cx, Z = scf_charges(m)
+        S, H = cdlib.one_electron(m.xyz, m.alpha, cx, Z)
+        Sr, Tr, Vr = oracle.one_electron(m.xyz, m.alpha, cx, Z)
+        Hr = Tr + Vr
+        assert np.abs(S.cpu().numpy() - Sr).max() <= 1e-14 * np.abs(Sr).max()
+        assert np.abs(H.cpu().numpy() - Hr).max() <= 1e-13 * np.abs(Hr).max()
+
+
+@pytest.mark.parametrize("case", ["C1", "ragged"])
+def test_scf_parity(case):
+    if case == "C1":
+        m, tau, schwarz = config_molecule("C1"), 1e-6, 0.0
+    else:
+        m, tau, schwarz = make_molecule(13, 5.0, (0.3, 1.2, 6.0), 6, seed=31), 1e-7, 1e-12
+    d, M, cx, Z, S, H, e_ch, res = _scf_case(m, tau, schwarz)
+    rp, ref = check_against_oracle(m, tau, schwarz, d, M)
+    Sr, Tr, Vr = oracle.one_electron(m.xyz, m.alpha, cx, Z)
+    exp = oracle.scf(Sr, Tr + Vr, e_ch, m.n_occ,
+                     lambda C: oracle.jk_cd(m.n_basis, rp, ref.L, C))
+    assert res.converged and exp.converged
+    E = res.energies.cpu().numpy()
+    assert len(E) == len(exp.energies)
+    tol = 3e-10 * np.abs(exp.D).sum() + 1e-12 * abs(exp.energies[-1])
+    assert np.abs(E - exp.energies).max() <= tol
+    D = res.D.cpu().numpy()
+    assert np.abs(D - exp.D).max() <= 1e-8
+    C = res.C.cpu().numpy()
+    assert np.abs(C @ C.T - D).max() <= 1e-12
+    # converged-SCF invariants on the GPU's own result
+    Sn = S.cpu().numpy()
+    assert np.trace(D @ Sn) == pytest.approx(m.n_occ, abs=1e-9)
+    F = res.F.cpu().numpy()
+    assert np.abs(F @ D @ Sn - Sn @ D @ F).max() < 1e-8
+
+
+def test_scf_reduced_precision_energy_error():
+    """FP32 and 3xBF16 K in the SCF: the converged energy moves by at most
+    1e-5 Eh from the FP64 one (the J/K energy bar).  The energy change per
+    iteration and the commutator cannot fall below what the K rounding leaves
+    (about 1e-7 here), so both tolerances are 1e-6."""
+    m = config_molecule("C1")
+    base = _scf_case(m, 1e-6, 0.0)[-1]
+    for prec in ("fp32", "bf16x3"):
+        r = _scf_case(m, 1e-6, 0.0, prec, e_tol=1e-6, d_tol=1e-6)[-1]
+        assert r.converged
+        assert abs(float(r.energies[-1]) - float(base.energies[-1])) <= 1e-5
+
+
+def test_scf_rejects_a_singular_overlap():
+    """Two identical functions make S singular: the orthogonaliser does not
+    converge and the call says so (no vectors of the SCF are touched)."""
+    m = make_molecule(5, 4.0, (0.5, 2.0), 2, seed=41)
+    xyz = np.concatenate([m.xyz, m.xyz[:1]])
+    alpha = np.concatenate([m.alpha, m.alpha[:1]])
+    d = cdlib.decompose(xyz, alpha, 1e-8, schwarz=1e-12)
+    S, H = cdlib.one_electron(xyz, alpha, m.xyz[:2], [2.0, 2.0])
+    with pytest.raises(cdlib.CDError) as e:
+        cdlib.scf(d, S, H, 2, 0.0, max_iter=5)
+    assert e.value.status == cdlib.CD_ERR_NOT_PSD
+
