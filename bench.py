@@ -186,6 +186,50 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_scf(cdlib, d, m, prec, e_tol=1e-10, d_tol=1e-8):
+    """One converged SCF on decomposition d; returns (result, ms)."""
+    import torch
+    from paper_2609_00306_amd.inputs import scf_charges
+    cx, Z = scf_charges(m)
+    S, H = cdlib.one_electron(m.xyz, m.alpha, cx, Z)
+    e_ch = float(sum(Z[i] * Z[j] / ((((cx[i] - cx[j]) ** 2).sum()) ** 0.5)
+                     for i in range(len(Z)) for j in range(i)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = cdlib.scf(d, S, H, m.n_occ, e_ch, prec=prec, e_tol=e_tol, d_tol=d_tol)
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) * 1e3
+
+
+def scf_sweep(args):
+    """Converged SCF energies on the workload over tau and J/K precision; the
+    error is taken against the FP64 SCF at the smallest tau."""
+    import torch
+
+    from paper_2609_00306_amd import cdlib
+    from paper_2609_00306_amd.inputs import CONFIGS, config_molecule
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[args.config]
+    m = config_molecule(args.config)
+    taus = [1e-3, 1e-4, 1e-5, 1e-6, 1e-8]
+    rows = []
+    ref = None
+    for tau in reversed(taus):
+        d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=cfg["schwarz"])
+        for prec in ("fp64", "fp32", "bf16x3"):
+            tol = (1e-10, 1e-8) if prec == "fp64" else (1e-6, 1e-6)
+            r, ms = run_scf(cdlib, d, m, prec, *tol)
+            E = float(r.energies[-1])
+            if ref is None:
+                ref = E
+            rows.append({"tau": tau, "precision": prec, "M": d.M(), "iterations": len(r.energies),
+                         "converged": r.converged, "energy": E, "error_vs_fp64_tau1e-8": E - ref,
+                         "ms": ms})
+        del d
+    print(json.dumps({"scf_sweep": args.config, "n_basis": m.n_basis, "n_occ": m.n_occ,
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +243,9 @@ def main():
     ap.add_argument("--pivot-block", default=None, metavar="I,J,..",
                     help="restricted candidates (Sec. 6.2): pivots only from rows of two "
                          "functions whose exponent index is listed")
+    ap.add_argument("--scf-sweep", action="store_true",
+                    help="only run converged SCFs over tau and J/K precision and print the "
+                         "energy errors (one JSON line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
@@ -213,6 +260,9 @@ def main():
         return
     if args.config == "C4":
         bench_batched(args)
+        return
+    if args.scf_sweep:
+        scf_sweep(args)
         return
 
     import numpy as np
@@ -302,6 +352,14 @@ def main():
                     "max_abs_dJ": float((jk.J - J64).abs().max()),
                     "max_abs_dK": float((jk.K - K64).abs().max()),
                     "abs_dE2": abs(e2(jk.J, jk.K) - e2(J64, K64))}
+
+    # a converged SCF on the step's vectors (outside the step)
+    scf_res, scf_ms = run_scf(cdlib, d, m, args.precision,
+                              *((1e-10, 1e-8) if args.precision == "fp64" else (1e-6, 1e-6)))
+    scf = {"ms": scf_ms, "iterations": len(scf_res.energies), "converged": scf_res.converged,
+           "ms_per_iteration": scf_ms / max(1, len(scf_res.energies)),
+           "energy": float(scf_res.energies[-1]), "jk_precision": args.precision}
+    del scf_res
 
     restricted = None
     if fn is not None:
@@ -398,6 +456,7 @@ def main():
         "jk_tflops": (w_j + w_k) / (t_jk * 1e-3) / 1e12,
         "transform_ms": t_tr,
         "mp2": mp2,
+        "scf": scf,
         "restricted_candidates": restricted,
         "phases_ms": {"setup": t_setup, "pivot_selection": t_sel, "all_row_solve": t_solve},
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),

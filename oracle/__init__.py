@@ -265,21 +265,26 @@ class SCF(NamedTuple):
 
 
 def scf(S, H, e_charges: float, n_occ: int, jk, max_iter: int = 100,
-        e_tol: float = 1e-10, d_tol: float = 1e-8) -> SCF:
+        e_tol: float = 1e-10, d_tol: float = 1e-8, diis: int = 8) -> SCF:
     """Closed-shell Roothaan-Hall SCF (Sec. 4.1 builds its J and K from the
     Cholesky vectors).  ``jk(C)`` returns J and K of D = C C^T.
 
     D_0 is the projector on the n_occ lowest solutions of H C = S C e (core
     guess).  Iteration k: F_k = H + 2 J(D_k) - K(D_k),
-    E_k = tr(D_k (H + F_k)) + e_charges, and D_{k+1} from the n_occ lowest
-    solutions of F_k C = S C e.  Stops when |E_k - E_{k-1}| < e_tol and the
-    largest element of F_k D_k S - S D_k F_k is below d_tol."""
+    E_k = tr(D_k (H + F_k)) + e_charges, e_k = F_k D_k S - S D_k F_k.  Stops
+    when |E_k - E_{k-1}| < e_tol and max |e_k| < d_tol.  Otherwise D_{k+1}
+    comes from the n_occ lowest solutions of F C = S C e, with F = F_k
+    (``diis`` = 0) or Pulay's extrapolation over the last ``diis`` iterations
+    (Chem. Phys. Lett. 73, 393 (1980)): F = sum_i c_i F_i with sum_i c_i = 1
+    minimising |sum_i c_i e_i| (Frobenius), i.e. the bordered system
+    [B 1; 1^T 0] [c; -l] = [0; 1] with B_ij = sum e_i o e_j."""
     import scipy.linalg
     e, V = scipy.linalg.eigh(H, S)
     C = np.ascontiguousarray(V[:, :n_occ])
     energies = []
     conv = False
     F = H.copy()
+    Fs, es = [], []
     for _ in range(max_iter):
         D = C @ C.T
         J, K = jk(C)
@@ -290,7 +295,25 @@ def scf(S, H, e_charges: float, n_occ: int, jk, max_iter: int = 100,
         if len(energies) > 1 and abs(E - energies[-2]) < e_tol and np.abs(comm).max() < d_tol:
             conv = True
             break
-        e, V = scipy.linalg.eigh(F, S)
+        Fx = F
+        if diis > 0:
+            Fs.append(F)
+            es.append(comm)
+            if len(Fs) > diis:
+                Fs.pop(0)
+                es.pop(0)
+            n = len(Fs)
+            A = np.zeros((n + 1, n + 1))
+            for i in range(n):
+                for j in range(n):
+                    A[i, j] = float(np.sum(es[i] * es[j]))
+            A[:n, n] = 1.0
+            A[n, :n] = 1.0
+            rhs = np.zeros(n + 1)
+            rhs[n] = 1.0
+            c = np.linalg.solve(A, rhs)[:n]
+            Fx = sum(ci * Fi for ci, Fi in zip(c, Fs))
+        e, V = scipy.linalg.eigh(Fx, S)
         C = np.ascontiguousarray(V[:, :n_occ])
     return SCF(np.array(energies), C, e, F, C @ C.T, conv)
 

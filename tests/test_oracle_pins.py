@@ -628,3 +628,18 @@ def test_scf_converged_invariants(orc, c1_scf):
 def test_scf_at_tau_zero_equals_exact_integrals(orc, c1_scf):
     m, S, H, exact, cd = c1_scf
     assert abs(cd.energies[-1] - exact.energies[-1]) <= 1e-9 * abs(exact.energies[-1])
+
+
+def test_scf_diis_reaches_the_plain_fixed_point(orc, c1_scf):
+    """Pulay's extrapolation changes the path, not the solution: plain
+    Roothaan iterations end at the same energy and density, in no fewer
+    iterations."""
+    from paper_2609_00306_amd.inputs import scf_charges
+    m, S, H, exact, cd = c1_scf
+    cx, Z = scf_charges(m)
+    plain = orc.scf(S, H, orc.charge_repulsion(cx, Z), m.n_occ,
+                    lambda C: orc.jk_exact(m.xyz, m.alpha, C), diis=0)
+    assert plain.converged
+    assert plain.energies[-1] == pytest.approx(exact.energies[-1], abs=1e-9)
+    assert np.abs(plain.D - exact.D).max() < 1e-7
+    assert len(plain.energies) >= len(exact.energies)
