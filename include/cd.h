@@ -298,6 +298,8 @@ typedef struct {
     int32_t max_iter;          /* >= 1 */
     double e_tol;              /* converged when |E_k - E_(k-1)| < e_tol ... */
     double d_tol;              /* ... and max |F D S - S D F| < d_tol */
+    int32_t diis;              /* Pulay extrapolation over the last 'diis' Fock matrices, 0..8
+                                  (0: plain Roothaan steps) */
     double *C;                 /* out, device [N][O]: D = C C^T (pivoted Cholesky factor of D) */
     double *D;                 /* out, device [N][N]: density of the last iteration */
     double *F;                 /* out, device [N][N]: F(D) = H + 2 J(D) - K(D) */
@@ -314,7 +316,9 @@ cd_status cd_query_scf(const cd_scf_problem *p, cd_precision prec, size_t *ws_by
  * cd_scf: D_0 projects on the O lowest solutions of H C = S C e (core
  * guess); iteration k builds J and K of D_k = C_k C_k^T from the vectors at
  * precision 'prec', F_k = H + 2 J - K and E_k, and stops on convergence;
- * otherwise D_(k+1) projects on the O lowest solutions of F_k C = S C e.  The
+ * otherwise D_(k+1) projects on the O lowest solutions of F C = S C e, where F
+ * is F_k or, with diis > 0, Pulay's extrapolation sum_i c_i F_i (sum c_i = 1,
+ * minimal |sum c_i e_i| over the stored commutators e_i).  The
  * projector comes from trace-correcting purification of X F X with
  * X = S^(-1/2) (Newton-Schulz), not from a diagonalisation.  Blocking: the
  * host reads the convergence figures.  Errors: CD_ERR_INVALID_ARG (sizes,

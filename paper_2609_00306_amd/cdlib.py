@@ -83,7 +83,8 @@ class cd_scf_problem(ctypes.Structure):
                 ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
                 ("n_vectors", _vp), ("n_occ", ctypes.c_int32), ("S", _vp), ("H", _vp),
                 ("e_charges", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("e_tol", ctypes.c_double), ("d_tol", ctypes.c_double), ("C", _vp), ("D", _vp),
+                ("e_tol", ctypes.c_double), ("d_tol", ctypes.c_double),
+                ("diis", ctypes.c_int32), ("C", _vp), ("D", _vp),
                 ("F", _vp), ("energies", _vp), ("status", _vp), ("n_iter", ctypes.c_int32),
                 ("converged", ctypes.c_int32)]
 
@@ -449,7 +450,7 @@ class SCFResult:
 
 def scf(d: Decomposition, S: torch.Tensor, H: torch.Tensor, n_occ: int, e_charges: float,
         prec: str = "fp64", max_iter: int = 100, e_tol: float = 1e-10, d_tol: float = 1e-8,
-        stream=None) -> SCFResult:
+        diis: int = 8, stream=None) -> SCFResult:
     """Closed-shell SCF on the decomposition's J/K (cd_scf; blocking)."""
     dev = d.L.device
     N = d.n_basis
@@ -463,7 +464,8 @@ def scf(d: Decomposition, S: torch.Tensor, H: torch.Tensor, n_occ: int, e_charge
     H = H.contiguous()
     prob = cd_scf_problem(N, d.n_rows, d.max_vectors, _ptr(d.row_pair), _ptr(d.L),
                           _ptr(d.n_vectors), int(n_occ), _ptr(S), _ptr(H), float(e_charges),
-                          int(max_iter), float(e_tol), float(d_tol), _ptr(C), _ptr(D), _ptr(F),
+                          int(max_iter), float(e_tol), float(d_tol), int(diis), _ptr(C),
+                          _ptr(D), _ptr(F),
                           _ptr(E), _ptr(st), 0, 0)
     L = load()
     ws = ctypes.c_size_t()

@@ -819,7 +819,7 @@ cd_status cd_one_electron(const cd_one_electron_problem *p, uint32_t flags, void
 // Device workspace of cd_scf: eight N x N matrices, the Cholesky scratch, the
 // reduction results, and the J/K workspace.
 struct ScfWs {
-    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red;
+    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red, *Fh, *Eh;
     void *jk;
     size_t jk_bytes;
 };
@@ -856,6 +856,8 @@ static cd_status scf_carve(const cd_scf_problem &p, cd_precision prec, void *bas
     w.K = c.take<double>(n2);
     w.dres = c.take<double>(std::max(1, p.n_basis));
     w.red = c.take<double>(8);
+    w.Fh = c.take<double>(n2 * std::max(1, p.diis));
+    w.Eh = c.take<double>(n2 * std::max(1, p.diis));
     // the J/K workspace depends on the sizes only; the size query is given
     // placeholder addresses that it never dereferences
     static double placeholder[1];
@@ -880,6 +882,7 @@ static cd_status check_scf(const cd_scf_problem *p)
     if (p->n_basis < 1 || p->n_occ < 1 || p->n_occ > p->n_basis)
         return fail(CD_ERR_INVALID_ARG, "need 1 <= n_occ <= n_basis");
     if (p->max_iter < 1) return fail(CD_ERR_INVALID_ARG, "max_iter < 1");
+    if (p->diis < 0 || p->diis > SCF_DIIS) return fail(CD_ERR_INVALID_ARG, "diis must be 0..%d", SCF_DIIS);
     if (!(p->e_tol >= 0.0) || !(p->d_tol >= 0.0))
         return fail(CD_ERR_INVALID_ARG, "tolerances must be >= 0");
     if ((int64_t)p->n_basis * p->n_basis > ((int64_t)1 << 31))
@@ -1008,6 +1011,57 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
         return CD_OK;
     };
 
+    // Pulay extrapolation: history slots in age order and their error overlaps
+    std::vector<int> order;
+    double Bm[SCF_DIIS][SCF_DIIS] = {};
+    auto extrapolate = [&](const double *G, double *Fx) -> cd_status {
+        int slot;
+        if ((int)order.size() < p->diis) {
+            slot = (int)order.size();
+        } else {
+            slot = order.front();
+            order.erase(order.begin());
+        }
+        order.push_back(slot);
+        k_diis_store<<<eb, 256, 0, st>>>(N, G, p->F, w.Eh + slot * n2, w.Fh + slot * n2);
+        DiisCoef co{};
+        co.n = (int)order.size();
+        for (int b = 0; b < co.n; ++b) co.slot[b] = order[b];
+        k_diis_dots<<<(unsigned)co.n, 256, 0, st>>>(n2, w.Eh + slot * n2, w.Eh, co, w.red);
+        cd_status r = read(co.n);
+        if (r) return r;
+        for (int b = 0; b < co.n; ++b) Bm[slot][order[b]] = Bm[order[b]][slot] = h[b];
+        // [B 1; 1^T 0] [c; -l] = [0; 1] by Gaussian elimination with partial pivoting
+        const int n = co.n, m1 = n + 1;
+        double A[SCF_DIIS + 1][SCF_DIIS + 2];
+        for (int i = 0; i < m1; ++i) {
+            for (int j = 0; j < m1; ++j)
+                A[i][j] = (i < n && j < n) ? Bm[order[i]][order[j]] : (i == n && j == n ? 0.0 : 1.0);
+            A[i][m1] = (i == n) ? 1.0 : 0.0;
+        }
+        for (int col = 0; col < m1; ++col) {
+            int piv = col;
+            for (int i = col + 1; i < m1; ++i)
+                if (std::fabs(A[i][col]) > std::fabs(A[piv][col])) piv = i;
+            if (A[piv][col] == 0.0) return fail(CD_ERR_UNSUPPORTED, "singular DIIS system");
+            if (piv != col)
+                for (int j = 0; j <= m1; ++j) std::swap(A[piv][j], A[col][j]);
+            for (int i = col + 1; i < m1; ++i) {
+                const double f = A[i][col] / A[col][col];
+                for (int j = col; j <= m1; ++j) A[i][j] -= f * A[col][j];
+            }
+        }
+        double x[SCF_DIIS + 1];
+        for (int i = m1 - 1; i >= 0; --i) {
+            double v = A[i][m1];
+            for (int j = i + 1; j < m1; ++j) v -= A[i][j] * x[j];
+            x[i] = v / A[i][i];
+        }
+        for (int b = 0; b < n; ++b) co.c[b] = x[b];
+        k_diis_combine<<<eb, 256, 0, st>>>(n2, w.Fh, co, Fx);
+        return check_launch("DIIS kernels");
+    };
+
     if ((s = purify(p->H))) return s;
     cd_jk_problem q = scf_jk_problem(*p, w.J, w.K);
     double e_prev = 0.0;
@@ -1034,7 +1088,13 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
             break;
         }
         e_prev = E;
-        if (k + 1 < p->max_iter && (s = purify(p->F))) return s;
+        if (k + 1 == p->max_iter) break;
+        if (p->diis > 0) {
+            if ((s = extrapolate(w.W2, w.W2))) return s;
+            if ((s = purify(w.W2))) return s;
+        } else if ((s = purify(p->F))) {
+            return s;
+        }
     }
     return CD_OK;
 }

@@ -14,7 +14,10 @@
 //                  with Gershgorin bounds; D = X P X;
 //   orbitals     : D = C C^T with C [N][O] from a pivoted Cholesky
 //                  decomposition of the rank-O density (any such C gives the
-//                  same J and K, which depend on D only).
+//                  same J and K, which depend on D only);
+//   extrapolation: Pulay's DIIS over the last 8 Fock matrices with the
+//                  commutators F D S - S D F as error vectors (the small
+//                  bordered system is solved on the host).
 // Every product is an FP64 matrix-core GEMM (the shared tile engine); every
 // sum over matrix elements runs in a fixed order.
 #pragma once
@@ -222,6 +225,56 @@ __global__ __launch_bounds__(256) void k_fock_energy(int N, const double *__rest
     }
     const double t = scf_block_sum(acc, s);
     if (threadIdx.x == 0) energy[0] = t + e_charges;
+}
+
+// Pulay extrapolation (DIIS) of the Fock matrix over stored iterations.
+constexpr int SCF_DIIS = 8;
+struct DiisCoef {
+    double c[SCF_DIIS];
+    int slot[SCF_DIIS];
+    int n;
+};
+
+// e = G - G^T (the commutator F D S - S D F for G = F D S); also copies F into
+// the history slot
+__global__ __launch_bounds__(256) void k_diis_store(int N, const double *__restrict__ G,
+                                                    const double *__restrict__ F,
+                                                    double *__restrict__ e_out,
+                                                    double *__restrict__ f_out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int i = (int)(e / N), j = (int)(e % N);
+    e_out[e] = G[e] - G[(int64_t)j * N + i];
+    f_out[e] = F[e];
+}
+
+// out[b] = sum e_new o hist[slot[b]] over the N^2 elements, one workgroup per
+// stored iteration, fixed order
+__global__ __launch_bounds__(256) void k_diis_dots(int64_t n2, const double *__restrict__ e_new,
+                                                   const double *__restrict__ hist,
+                                                   const DiisCoef slots,
+                                                   double *__restrict__ out)
+{
+    __shared__ double s[256];
+    const int b = blockIdx.x;
+    if (b >= slots.n) return;
+    const double *h = hist + (int64_t)slots.slot[b] * n2;
+    double a = 0.0;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) a += e_new[e] * h[e];
+    const double t = scf_block_sum(a, s);
+    if (threadIdx.x == 0) out[b] = t;
+}
+
+// F = sum_b c[b] hist[slot[b]]
+__global__ __launch_bounds__(256) void k_diis_combine(int64_t n2, const double *__restrict__ hist,
+                                                      const DiisCoef co, double *__restrict__ F)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n2) return;
+    double v = 0.0;
+    for (int b = 0; b < co.n; ++b) v += co.c[b] * hist[(int64_t)co.slot[b] * n2 + e];
+    F[e] = v;
 }
 
 // C [N][O] with C C^T = D for the rank-O density D: a pivoted Cholesky

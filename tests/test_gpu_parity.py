@@ -475,13 +475,13 @@ def test_restricted_candidates_edge_flags():
 # by purification, the oracle by diagonalisation.  J and K agree to 1e-10
 # elementwise, so each E_k agrees to about 3e-10 sum|D|; the projectors agree
 # to the purification's idempotency tolerance.
-def _scf_case(m, tau, schwarz, prec="fp64", e_tol=1e-10, d_tol=1e-8):
+def _scf_case(m, tau, schwarz, prec="fp64", e_tol=1e-10, d_tol=1e-8, diis=8):
     from paper_2609_00306_amd.inputs import scf_charges
     cx, Z = scf_charges(m)
     d, M = run_gpu(m, tau, schwarz)
     S, H = cdlib.one_electron(m.xyz, m.alpha, cx, Z)
     e_ch = oracle.charge_repulsion(cx, Z)
-    res = cdlib.scf(d, S, H, m.n_occ, e_ch, prec=prec, e_tol=e_tol, d_tol=d_tol)
+    res = cdlib.scf(d, S, H, m.n_occ, e_ch, prec=prec, e_tol=e_tol, d_tol=d_tol, diis=diis)
     return d, M, cx, Z, S, H, e_ch, res
 
 
@@ -496,17 +496,17 @@ def test_one_electron_parity():
         assert np.abs(H.cpu().numpy() - Hr).max() <= 1e-13 * np.abs(Hr).max()
 
 
-@pytest.mark.parametrize("case", ["C1", "ragged"])
-def test_scf_parity(case):
+@pytest.mark.parametrize("case,diis", [("C1", 8), ("C1", 0), ("ragged", 8)])
+def test_scf_parity(case, diis):
     if case == "C1":
         m, tau, schwarz = config_molecule("C1"), 1e-6, 0.0
     else:
         m, tau, schwarz = make_molecule(13, 5.0, (0.3, 1.2, 6.0), 6, seed=31), 1e-7, 1e-12
-    d, M, cx, Z, S, H, e_ch, res = _scf_case(m, tau, schwarz)
+    d, M, cx, Z, S, H, e_ch, res = _scf_case(m, tau, schwarz, diis=diis)
     rp, ref = check_against_oracle(m, tau, schwarz, d, M)
     Sr, Tr, Vr = oracle.one_electron(m.xyz, m.alpha, cx, Z)
     exp = oracle.scf(Sr, Tr + Vr, e_ch, m.n_occ,
-                     lambda C: oracle.jk_cd(m.n_basis, rp, ref.L, C))
+                     lambda C: oracle.jk_cd(m.n_basis, rp, ref.L, C), diis=diis)
     assert res.converged and exp.converged
     E = res.energies.cpu().numpy()
     assert len(E) == len(exp.energies)
@@ -521,6 +521,24 @@ def test_scf_parity(case):
     assert np.trace(D @ Sn) == pytest.approx(m.n_occ, abs=1e-9)
     F = res.F.cpu().numpy()
     assert np.abs(F @ D @ Sn - Sn @ D @ F).max() < 1e-8
+
+
+def test_scf_c2_converges_with_valid_density():
+    """The 400-function workload (50 charge-2 sites, 50 ghost centres): the
+    oracle's SCF takes minutes here, so the converged result is checked for
+    what holds at any size (idempotency in the S metric, electron count,
+    Brillouin condition, D = C C^T)."""
+    m = config_molecule("C2")
+    d, M, cx, Z, S, H, e_ch, res = _scf_case(m, 1e-6, 1e-12)
+    assert res.converged and len(res.energies) <= 40
+    Sn = S.cpu().numpy()
+    D = res.D.cpu().numpy()
+    F = res.F.cpu().numpy()
+    C = res.C.cpu().numpy()
+    assert np.abs(D @ Sn @ D - D).max() < 1e-9
+    assert np.trace(D @ Sn) == pytest.approx(m.n_occ, abs=1e-9)
+    assert np.abs(F @ D @ Sn - Sn @ D @ F).max() < 1e-8
+    assert np.abs(C @ C.T - D).max() < 1e-12
 
 
 def test_scf_reduced_precision_energy_error():
