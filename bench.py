@@ -39,12 +39,12 @@ KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_mfma.hpp",
                   "paper_2609_00306_amd/csrc/cd_device.hpp",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.7, 1048576.0 / 1048576.0
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.2, 1048576.0 / 1048576.0
 COUNTERS = {
-    "sources_sha256": "c6c55d0afb9b2b9fc3a98c0bf81a6757f04a82b129b20dd8d4e2843d01fe6f9a",
+    "sources_sha256": "508111cb07413e1628b7d801a32edce4019a1418b74543291ffdd52577efedc8",
     "workload": ("C2", 1e-6),
-    "fetch_kib": {"k_step2": 2348620.8, "k_step1": 73093.3},
-    "write_kib": {"k_step2": 259291.9, "k_step1": 30159.5},
+    "fetch_kib": {"k_step2": 2348584.3, "k_step1": 73114.7},
+    "write_kib": {"k_step2": 259292.3, "k_step1": 30159.5},
 }
 
 
