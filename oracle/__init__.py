@@ -58,6 +58,9 @@ def lib():
         L.or_one_electron.argtypes = [ctypes.c_int, _d, _d, ctypes.c_int, _d, _d, _d, _d, _d]
         L.or_charge_repulsion.restype = ctypes.c_double
         L.or_charge_repulsion.argtypes = [ctypes.c_int, _d, _d]
+        L.or_zdecompose.restype = ctypes.c_int
+        L.or_zdecompose.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_int64, _d,
+                                    _i64, _d, _i64]
         L.or_decompose.restype = ctypes.c_int
         L.or_decompose.argtypes = [_d, _d, ctypes.c_int64, _i64, ctypes.c_double, ctypes.c_int64,
                                    _d, _i64, _d, _d, _i64, _i64, ctypes.c_int64,
@@ -316,4 +319,29 @@ def scf(S, H, e_charges: float, n_occ: int, jk, max_iter: int = 100,
         e, V = scipy.linalg.eigh(Fx, S)
         C = np.ascontiguousarray(V[:, :n_occ])
     return SCF(np.array(energies), C, e, F, C @ C.T, conv)
+
+
+class ZCD(NamedTuple):
+    rc: int
+    M: int
+    L: np.ndarray        # [M][n] complex
+    pivots: np.ndarray   # [M]
+    D: np.ndarray        # [n] final residual diagonal (real)
+
+
+def zdecompose(A, tau: float, max_vectors: Optional[int] = None) -> ZCD:
+    """Pivoted Cholesky decomposition of a Hermitian PSD matrix (Sec. 2 in
+    complex algebra, the finite-field case of Sec. 7): A ~ sum_K L_K L_K^H."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    if max_vectors is None:
+        max_vectors = n
+    L = np.zeros((max(1, max_vectors), max(1, n)), dtype=np.complex128)
+    piv = np.zeros(max(1, max_vectors), dtype=np.int64)
+    D = np.zeros(max(1, n))
+    M = ctypes.c_int64()
+    rc = lib().or_zdecompose(n, A.ctypes.data_as(_d), float(tau), int(max_vectors),
+                             L.ctypes.data_as(_d), _p(piv, _i64), _p(D, _d), ctypes.byref(M))
+    m = M.value
+    return ZCD(rc, m, L[:m, :n].copy(), piv[:m].copy(), D[:n].copy())
 

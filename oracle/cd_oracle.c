@@ -24,6 +24,10 @@
  *     form of Sec. 6.2);
  *   - the closed-shell second-order (MP2) energy from transformed vectors
  *     (CD-based MP2 of Secs. 5 and 7; the textbook energy expression);
+ *   - the threshold-truncated, fully pivoted Cholesky decomposition of a
+ *     complex Hermitian positive semidefinite matrix (the finite-field case
+ *     of Sec. 7: complex integrals, a real diagonal, complex vectors with
+ *     A ~ sum_K L_K L_K^H), given the matrix explicitly;
  *   - one-electron integrals over the same functions (overlap, kinetic
  *     energy, attraction to point charges) and the repulsion of the charges,
  *     the ingredients of the SCF of Sec. 4.1 besides J and K (textbook
@@ -38,6 +42,7 @@
  *   sqrt(D^1_row * max D^1) >= schwarz, in ascending packed order
  *   pq = mu(mu+1)/2 + nu (mu >= nu).
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -470,5 +475,53 @@ double or_charge_repulsion(int nc, const double *cxyz, const double *Z)
             e += Z[c] * Z[d] / sqrt(r2);
         }
     return e;
+}
+
+/* ---- Hermitian decomposition (Sec. 7) ----------------------------------- */
+/*
+ * A: [n][n] complex, Hermitian positive semidefinite (row-major).  Sec. 2
+ * with complex algebra:
+ *   D_r = A_rr (real);  P_K = argmax_r D_r (lowest r on ties);  d_K = D_{P_K}
+ *   stop if d_K < tau (or d_K <= n 2^-53 max D when tau <= 0)
+ *   L^K_r = [ A_{r P_K} - sum_{J<K} L^J_r conj(L^J_{P_K}) ] / sqrt(d_K)
+ *   D_r -= |L^K_r|^2;  D_{P_K} = 0
+ * so that A_rs ~ sum_K L^K_r conj(L^K_s).  L is vector-major [K][n].
+ * Returns 0, or 1 at capacity, 2 for a non-positive / non-finite pivot.
+ */
+int or_zdecompose(int64_t n, const double complex *A, double tau, int64_t max_vectors,
+                  double complex *L, int64_t *pivots, double *D, int64_t *M_out)
+{
+    int rc = 0;
+    int64_t M = 0;
+    double dmax = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        D[r] = creal(A[r * n + r]);
+        if (D[r] > dmax) dmax = D[r];
+    }
+    const double floor_tol = (double)n * ldexp(1.0, -53) * dmax;
+    for (;;) {
+        int64_t piv = -1;
+        double d = -INFINITY;
+        for (int64_t r = 0; r < n; ++r)
+            if (D[r] > d) { d = D[r]; piv = r; }
+        if (n == 0 || d < tau) break;
+        if (tau <= 0.0 && d <= floor_tol) break;
+        if (M >= max_vectors) { rc = 1; break; }
+        if (!(d > 0.0) || !isfinite(d)) { rc = 2; break; }
+        const double s = sqrt(d);
+        double complex *LK = L + M * n;
+#pragma omp parallel for schedule(static)
+        for (int64_t r = 0; r < n; ++r) {
+            double complex v = A[r * n + piv];
+            for (int64_t J = 0; J < M; ++J) v -= L[J * n + r] * conj(L[J * n + piv]);
+            LK[r] = v / s;
+        }
+        for (int64_t r = 0; r < n; ++r) D[r] -= creal(LK[r]) * creal(LK[r]) + cimag(LK[r]) * cimag(LK[r]);
+        D[piv] = 0.0;
+        pivots[M] = piv;
+        ++M;
+    }
+    *M_out = M;
+    return rc;
 }
 

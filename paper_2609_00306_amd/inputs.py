@@ -26,6 +26,10 @@ thresholds):
 * Point charges for the SCF (``scf_charges``): charge 2 on each of the first O
   centres, none on the others (their functions are ghost functions), so the
   2 O electrons fill closed-shell He-like sites.
+* Complex Hermitian stand-in for finite-field integrals (``hermitian_gram``):
+  the Gram matrix F F^H of complex Gaussians with London-like plane-wave
+  phases, F[r][q] = s_q exp(-b_q |P_r - c_q|^2) exp(i k_q . P_r) with
+  k_q = (B x c_q) / 2; see the function for the distributions.
 * Stand-alone transformed vectors for the second-order energy
   (``random_mo_vectors``): B[P][i][a] standard normal deviates scaled by
   sqrt(d_P), d_P falling geometrically from 1 to 1e-6 over P (the shape of a
@@ -190,6 +194,27 @@ def scf_charges(m: Molecule, n_occ: int | None = None):
     if o > centres.shape[0]:
         raise ValueError("more occupied orbitals than centres")
     return np.ascontiguousarray(centres[:o]), np.full(o, 2.0)
+
+
+def hermitian_gram(n_rows: int, n_fun: int, seed: int, field: float = 0.5,
+                   box_bohr: float = 20.0) -> np.ndarray:
+    """Seeded complex Hermitian positive semidefinite stand-in for the integral
+    matrix of a finite magnetic field: A = F F^H with
+    F[r][q] = s_q exp(-b_q |P_r - c_q|^2) exp(i k_q . P_r), k_q = (B x c_q) / 2
+    for a field B = (0, 0, field): row "pair centres" P_r and function centres
+    c_q uniform in the box, exponents b_q uniform in [0.05, 0.5] bohr^-2,
+    weights s_q falling geometrically from 1 to 1e-4.  Returns [n][n] complex128."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = rng.uniform(0.0, box_bohr, (n_rows, 3))
+    c = rng.uniform(0.0, box_bohr, (n_fun, 3))
+    b = rng.uniform(0.05, 0.5, n_fun)
+    s = np.geomspace(1.0, 1e-4, n_fun) if n_fun > 0 else np.zeros(0)
+    k = 0.5 * np.cross(np.array([0.0, 0.0, field]), c)
+    d2 = ((P[:, None, :] - c[None, :, :]) ** 2).sum(axis=2)
+    F = s[None, :] * np.exp(-b[None, :] * d2) * np.exp(1j * (P @ k.T))
+    A = F @ F.conj().T
+    A = 0.5 * (A + A.conj().T)            # exactly Hermitian in floating point
+    return np.ascontiguousarray(A)
 
 
 def random_mo_vectors(n_vectors: int, n_occ: int, n_virt: int, seed: int) -> np.ndarray:

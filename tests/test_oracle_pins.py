@@ -643,3 +643,68 @@ def test_scf_diis_reaches_the_plain_fixed_point(orc, c1_scf):
     assert plain.energies[-1] == pytest.approx(exact.energies[-1], abs=1e-9)
     assert np.abs(plain.D - exact.D).max() < 1e-7
     assert len(plain.energies) >= len(exact.energies)
+
+
+# ---------------------------------------------------------------- Hermitian (Sec. 7)
+def _zfactor(A, cd):
+    return cd.L.T @ cd.L.conj()          # sum_K L_K L_K^H
+
+
+@pytest.mark.parametrize("tau", [1e-6, 1e-9])
+def test_zdecompose_matches_lapack_zpstrf(orc, tau):
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(300, 250, seed=11)
+    cd = orc.zdecompose(A, tau)
+    c, piv, rank, info = lapack.zpstrf(A.copy(), tol=tau, lower=1)
+    piv = piv - 1
+    assert cd.rc == 0 and rank == cd.M
+    assert np.array_equal(piv[:rank], cd.pivots)
+    # rounding in the residual is divided by sqrt(d_K): compare L_K sqrt(d_K)
+    dk = np.array([cd.L[K, cd.pivots[K]].real for K in range(cd.M)])
+    err = np.abs(np.tril(c)[:, :rank] - cd.L.T[piv]) * dk[None, :]
+    assert err.max() <= 1e-13 * np.abs(A).max()
+
+
+def test_zdecompose_invariants(orc):
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(400, 300, seed=12)
+    tau = 1e-7
+    cd = orc.zdecompose(A, tau)
+    assert cd.rc == 0 and cd.D.max() < tau
+    R = A - _zfactor(A, cd)
+    assert np.abs(R).max() <= tau                         # Cauchy-Schwarz for PSD R
+    assert np.abs(np.diag(R).real - cd.D).max() <= 1e-12
+    dp = np.array([cd.L[K, cd.pivots[K]] for K in range(cd.M)])
+    assert np.abs(dp.imag).max() == 0.0 and np.all(dp.real > 0)
+    assert np.all(np.diff(dp.real ** 2) <= 1e-12)         # non-increasing pivot values
+    for K in range(1, cd.M, 7):
+        assert np.abs(cd.L[K, cd.pivots[:K]]).max() <= 1e-12
+
+
+def test_zdecompose_real_matrix_reduces_to_the_real_case(orc):
+    """With no field the matrix is real symmetric: the same pivots and factor
+    as LAPACK dpstrf, and real vectors."""
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(300, 250, seed=13, field=0.0)
+    assert np.abs(A.imag).max() == 0.0
+    cd = orc.zdecompose(A, 1e-7)
+    c, piv, rank, info = lapack.dpstrf(A.real.copy(), tol=1e-7, lower=1)
+    piv = piv - 1
+    assert rank == cd.M and np.array_equal(piv[:rank], cd.pivots)
+    assert np.abs(cd.L.imag).max() == 0.0
+    assert np.abs(np.tril(c)[:, :rank] - cd.L.real.T[piv]).max() <= 1e-12
+
+
+def test_zdecompose_phase_similarity(orc):
+    """A' = U A U^H with U = diag(exp(i theta)) has the same pivots, and
+    L'_K(r) = exp(i (theta_r - theta_(P_K))) L_K(r) (each pivot entry stays
+    real and positive)."""
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(250, 200, seed=14)
+    th = np.random.default_rng(3).uniform(0, 2 * np.pi, A.shape[0])
+    u = np.exp(1j * th)
+    A2 = u[:, None] * A * u.conj()[None, :]
+    cd, cd2 = orc.zdecompose(A, 1e-8), orc.zdecompose(A2, 1e-8)
+    assert cd.M == cd2.M and np.array_equal(cd.pivots, cd2.pivots)
+    ph = np.exp(1j * (th[None, :] - th[cd.pivots][:, None]))
+    assert np.abs(cd2.L - ph * cd.L).max() <= 1e-10
