@@ -16,7 +16,8 @@
  *                 two-coefficient form of Sec. 6.2);
  *   cd_mp2_energy the second-order energy from transformed vectors (CD-based
  *                 MP2, Secs. 5 and 7);
- *   cd_one_electron, cd_scf  the SCF on Cholesky J/K (Sec. 4.1).
+ *   cd_one_electron, cd_scf  the SCF on Cholesky J/K (Sec. 4.1);
+ *   cd_zdecompose the decomposition of a complex Hermitian matrix (Sec. 7).
  *
  * Conventions
  *   - Plain C, fixed-width integers; no C++ types or exceptions cross it.
@@ -328,6 +329,39 @@ cd_status cd_query_scf(const cd_scf_problem *p, cd_precision prec, size_t *ws_by
  * errors of cd_build_jk.
  */
 cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Hermitian decomposition (Sec. 7, finite magnetic field): the integrals over
+ * field-dependent orbitals are complex and the matrix is Hermitian positive
+ * semidefinite with a real diagonal.  Sec. 2 in complex algebra, on a matrix
+ * given explicitly:
+ *     P_K = argmax_r D_r (lowest r on ties), d_K = D_(P_K), stop when d_K < tau
+ *     (tau == 0: also when d_K <= n 2^-53 max_r A_rr),
+ *     L^K_r = [A_(r P_K) - sum_(J<K) L^J_r conj(L^J_(P_K))] / sqrt(d_K),
+ *     D_r -= |L^K_r|^2, D_(P_K) = 0,
+ * so A_rs ~ sum_K L^K_r conj(L^K_s).  Complex values are (re, im) pairs of
+ * doubles.  Device status: CD_ERR_CAPACITY (max_vectors reached before the
+ * threshold), CD_ERR_NOT_PSD (a non-finite or non-positive pivot),
+ * CD_ERR_DEVICE (a device-side wait exceeded its bound).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;                 /* rows, 0 <= n < 2^31 (and n <= 256 x the resident workgroups) */
+    const void *A;             /* device [n][n] complex double, Hermitian (only A read) */
+    int64_t max_vectors;       /* capacity of L and pivots */
+    void *L;                   /* out, device [max_vectors][n] complex double */
+    int64_t *pivots;           /* out, device [max_vectors] */
+    double *diag;              /* out, device [n] final residual diagonal */
+    int64_t *n_vectors;        /* out, device [1] */
+    int32_t *status;           /* out, device [1] */
+} cd_zproblem;
+
+/* Workspace bytes of cd_zdecompose (host-side). */
+cd_status cd_query_zdecompose(const cd_zproblem *p, size_t *ws_bytes);
+
+/* One persistent cooperative launch; asynchronous unless flags has CD_SYNC.
+ * ws: device, 256-byte aligned, at least cd_query_zdecompose's bytes. */
+cd_status cd_zdecompose(const cd_zproblem *p, double tau, uint32_t flags, void *ws,
+                        size_t ws_bytes, void *stream);
 
 /* Thread-local message describing the last error returned on this thread. */
 const char *cd_last_error(void);

@@ -89,10 +89,16 @@ class cd_scf_problem(ctypes.Structure):
                 ("converged", ctypes.c_int32)]
 
 
+
+class cd_zproblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("A", _vp), ("max_vectors", ctypes.c_int64), ("L", _vp),
+                ("pivots", _vp), ("diag", _vp), ("n_vectors", _vp), ("status", _vp)]
+
+
 #: every function include/cd.h declares
 EXPORTS = ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
            "cd_transform", "cd_query_mp2", "cd_mp2_energy", "cd_one_electron", "cd_query_scf",
-           "cd_scf", "cd_last_error", "cd_version")
+           "cd_scf", "cd_query_zdecompose", "cd_zdecompose", "cd_last_error", "cd_version")
 
 _lib = None
 
@@ -133,9 +139,13 @@ def load(path: str = LIB_PATH):
     L.cd_one_electron.argtypes = [P(cd_one_electron_problem), ctypes.c_uint32, _vp]
     L.cd_query_scf.argtypes = [P(cd_scf_problem), ctypes.c_int, P(ctypes.c_size_t)]
     L.cd_scf.argtypes = [P(cd_scf_problem), ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+    L.cd_query_zdecompose.argtypes = [P(cd_zproblem), P(ctypes.c_size_t)]
+    L.cd_zdecompose.argtypes = [P(cd_zproblem), ctypes.c_double, ctypes.c_uint32, _vp,
+                                ctypes.c_size_t, _vp]
     for f in ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk",
               "cd_query_transform", "cd_transform", "cd_query_mp2", "cd_mp2_energy",
-              "cd_one_electron", "cd_query_scf", "cd_scf"):
+              "cd_one_electron", "cd_query_scf", "cd_scf", "cd_query_zdecompose",
+              "cd_zdecompose"):
         getattr(L, f).restype = ctypes.c_int
     L.cd_last_error.restype = ctypes.c_char_p
     L.cd_last_error.argtypes = []
@@ -473,4 +483,46 @@ def scf(d: Decomposition, S: torch.Tensor, H: torch.Tensor, n_occ: int, e_charge
     w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
     _check(L.cd_scf(ctypes.byref(prob), PRECISIONS[prec], _ptr(w), w.numel(), _stream(stream)))
     return SCFResult(E[:prob.n_iter].clone(), C, D, F, bool(prob.converged))
+
+
+@dataclasses.dataclass
+class ZDecomposition:
+    """Device-resident result of cd_zdecompose."""
+    L: torch.Tensor          # [max_vectors][n] complex128
+    pivots: torch.Tensor     # [max_vectors] int64
+    diag: torch.Tensor       # [n] float64
+    n_vectors: torch.Tensor  # [1] int64
+    status: torch.Tensor     # [1] int32
+    workspace: Optional[torch.Tensor] = None
+
+    def M(self) -> int:
+        return int(self.n_vectors.item())
+
+
+def zdecompose(A: torch.Tensor, tau: float, max_vectors: Optional[int] = None,
+               sync: bool = True, stream=None) -> ZDecomposition:
+    """Pivoted Cholesky decomposition of a Hermitian PSD complex128 device
+    matrix [n][n] (Sec. 7): A ~ sum_K L_K L_K^H."""
+    if A.dtype != torch.complex128 or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be a square complex128 tensor")
+    A = A.contiguous()
+    dev = A.device
+    n = int(A.shape[0])
+    mv = n if max_vectors is None else int(max_vectors)
+    out = ZDecomposition(L=torch.empty((max(1, mv), max(1, n)), dtype=torch.complex128, device=dev),
+                         pivots=torch.empty(max(1, mv), dtype=torch.int64, device=dev),
+                         diag=torch.empty(max(1, n), dtype=torch.float64, device=dev),
+                         n_vectors=torch.zeros(1, dtype=torch.int64, device=dev),
+                         status=torch.zeros(1, dtype=torch.int32, device=dev))
+    prob = cd_zproblem(n, _ptr(A), mv, _ptr(out.L), _ptr(out.pivots), _ptr(out.diag),
+                       _ptr(out.n_vectors), _ptr(out.status))
+    L = load()
+    ws = ctypes.c_size_t()
+    _check(L.cd_query_zdecompose(ctypes.byref(prob), ctypes.byref(ws)))
+    w = torch.empty(max(1, ws.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-w.data_ptr()) % 256
+    _check(L.cd_zdecompose(ctypes.byref(prob), float(tau), CD_SYNC if sync else 0,
+                           w.data_ptr() + off, w.numel() - off, _stream(stream)))
+    out.workspace = w
+    return out
 

@@ -16,6 +16,7 @@
 #include "cd_jk_lp.hip"
 #include "cd_mp2.hip"
 #include "cd_scf.hip"
+#include "cd_zcd.hip"
 
 using namespace cdk;
 
@@ -1095,6 +1096,90 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
         } else if ((s = purify(p->F))) {
             return s;
         }
+    }
+    return CD_OK;
+}
+
+// Workgroups and rows per workgroup of the Hermitian decomposition.
+static cd_status zcd_shape(int64_t n, int &G, int &R)
+{
+    DevInfo di;
+    cd_status s = dev_info(di);
+    if (s) return s;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_zcd, 256, 0) != hipSuccess)
+        return fail(CD_ERR_DEVICE, "occupancy query failed");
+    const int cap = std::min(kMaxGridBlocks, di.n_cu * std::max(1, nb));
+    R = 1;
+    while ((int64_t)R * cap < n && R < 256) R *= 2;
+    if ((int64_t)R * cap < n) return fail(CD_ERR_UNSUPPORTED, "n = %lld rows exceed %d", (long long)n, R * cap);
+    G = (int)std::max<int64_t>(1, blocks_of(n, R));
+    return CD_OK;
+}
+
+static size_t zcd_ws_bytes()
+{
+    Carver c(nullptr);
+    c.take<GridSync>(1);
+    c.take<Nom>(2 * kMaxGridBlocks);
+    return c.off;
+}
+
+cd_status cd_query_zdecompose(const cd_zproblem *p, size_t *ws_bytes)
+{
+    if (!p || !ws_bytes) return fail(CD_ERR_INVALID_ARG, "null argument");
+    if (p->n < 0 || p->max_vectors < 0) return fail(CD_ERR_INVALID_ARG, "negative size");
+    if (p->n > ((int64_t)1 << 31) - 1) return fail(CD_ERR_UNSUPPORTED, "n too large");
+    *ws_bytes = zcd_ws_bytes();
+    return CD_OK;
+}
+
+cd_status cd_zdecompose(const cd_zproblem *p, double tau, uint32_t flags, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    cd_status s = cd_query_zdecompose(p, &need);
+    if (s) return s;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(CD_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    if (need > ws_bytes || !ws) return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CD_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (!p->n_vectors || !p->status) return fail(CD_ERR_INVALID_ARG, "null n_vectors/status");
+    if (p->n > 0 && (!p->A || !p->diag || (p->max_vectors > 0 && (!p->L || !p->pivots))))
+        return fail(CD_ERR_INVALID_ARG, "null pointer in Hermitian problem");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws);
+    GridSync *gs = c.take<GridSync>(1);
+    Nom *part = c.take<Nom>(2 * kMaxGridBlocks);
+    k_zcd_init<<<1, 256, 0, st>>>(gs, p->status, p->n_vectors);
+    if ((s = check_launch("Hermitian init"))) return s;
+    if (p->n > 0) {
+        int G = 0, R = 0;
+        if ((s = zcd_shape(p->n, G, R))) return s;
+        ZcdParams Z{};
+        Z.n = p->n;
+        Z.A = static_cast<const double2 *>(p->A);
+        Z.tau = tau;
+        Z.max_vectors = p->max_vectors;
+        Z.L = static_cast<double2 *>(p->L);
+        Z.pivots = p->pivots;
+        Z.D = p->diag;
+        Z.n_vectors = p->n_vectors;
+        Z.status = p->status;
+        Z.gs = gs;
+        Z.part = part;
+        Z.G = G;
+        Z.R = R;
+        Z.spin_limit = 1u << 22;
+        void *args[] = {&Z};
+        if (hipLaunchCooperativeKernel((const void *)k_zcd, dim3(G), dim3(256), args, 0, st) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "Hermitian decomposition launch (%d workgroups) failed", G);
+    }
+    if (flags & CD_SYNC) {
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(CD_ERR_DEVICE, "stream synchronise failed");
+        int32_t v = 0;
+        if (hipMemcpy(&v, p->status, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "status copy failed");
+        if (v != 0) return fail((cd_status)v, "Hermitian decomposition: device status %d", v);
     }
     return CD_OK;
 }

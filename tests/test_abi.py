@@ -62,6 +62,7 @@ int main(void) {
          offsetof(cd_decomp_opts, tuning), offsetof(cd_decomp_opts, eta));
   printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
          offsetof(cd_mp2_problem, status));
+  printf("%zu %zu\n", sizeof(cd_zproblem), offsetof(cd_zproblem, status));
   printf("%zu %zu %zu %zu %zu\n", sizeof(cd_one_electron_problem),
          offsetof(cd_one_electron_problem, H), sizeof(cd_scf_problem),
          offsetof(cd_scf_problem, e_tol), offsetof(cd_scf_problem, converged));
@@ -89,6 +90,7 @@ def test_binding_structs_match_header():
             cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset,
             cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
             cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset,
+            ctypes.sizeof(cdlib.cd_zproblem), cdlib.cd_zproblem.status.offset,
             ctypes.sizeof(cdlib.cd_one_electron_problem), cdlib.cd_one_electron_problem.H.offset,
             ctypes.sizeof(cdlib.cd_scf_problem), cdlib.cd_scf_problem.e_tol.offset,
             cdlib.cd_scf_problem.converged.offset]
@@ -154,6 +156,18 @@ def test_argument_validation_without_device(lib):
     assert lib.cd_mp2_energy(ctypes.byref(mp), 1, 0, ctypes.c_void_p(0x1000), ws.value,
                              None) == cdlib.CD_ERR_INVALID_ARG
     assert b"null pointer" in lib.cd_last_error()
+    # Hermitian decomposition: sizes, tau, workspace and pointers on the host
+    zp = cdlib.cd_zproblem(-1)
+    assert lib.cd_query_zdecompose(ctypes.byref(zp), ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
+    zp = cdlib.cd_zproblem(10, None, 5)
+    assert lib.cd_query_zdecompose(ctypes.byref(zp), ctypes.byref(ws)) == 0 and ws.value > 0
+    assert lib.cd_zdecompose(ctypes.byref(zp), float("nan"), 0, None, 0,
+                             None) == cdlib.CD_ERR_INVALID_ARG
+    assert lib.cd_zdecompose(ctypes.byref(zp), 1e-6, 0, None, 0, None) == cdlib.CD_ERR_WORKSPACE
+    assert lib.cd_zdecompose(ctypes.byref(zp), 1e-6, 0, ctypes.c_void_p(0x1008), ws.value,
+                             None) == cdlib.CD_ERR_INVALID_ARG
+    assert lib.cd_zdecompose(ctypes.byref(zp), 1e-6, 0, ctypes.c_void_p(0x1000), ws.value,
+                             None) == cdlib.CD_ERR_INVALID_ARG
     # SCF: sizes and pointers are checked on the host
     sp = cdlib.cd_scf_problem(n_basis=4, n_occ=5, max_iter=10)
     assert lib.cd_query_scf(ctypes.byref(sp), 0, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG

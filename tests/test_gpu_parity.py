@@ -566,3 +566,66 @@ def test_scf_rejects_a_singular_overlap():
         cdlib.scf(d, S, H, 2, 0.0, max_iter=5)
     assert e.value.status == cdlib.CD_ERR_NOT_PSD
 
+
+# Hermitian decomposition (Sec. 7) on the seeded stand-in for finite-field
+# integrals.  The pivot sequences must be equal; rounding in a residual is
+# divided by sqrt(d_K) in vector K, so vectors are compared as L_K sqrt(d_K)
+# (1e-13 of max|A|), residual diagonals to 1e-12 of max|A|.
+def _zcheck(A, tau, max_vectors=None, expect_status=0):
+    Ad = torch.from_numpy(A).to("cuda")
+    z = cdlib.zdecompose(Ad, tau, max_vectors=max_vectors, sync=False)
+    torch.cuda.synchronize()
+    assert int(z.status.item()) == expect_status
+    M = z.M()
+    ref = oracle.zdecompose(A, tau, max_vectors=max_vectors)
+    assert M == ref.M
+    piv = z.pivots[:M].cpu().numpy()
+    assert np.array_equal(piv, ref.pivots)
+    L = z.L[:M].cpu().numpy()
+    amax = np.abs(A).max()
+    if M:
+        dk = np.array([ref.L[K, ref.pivots[K]].real for K in range(M)])
+        assert (np.abs(L - ref.L) * dk[:, None]).max() <= 1e-13 * amax
+    assert np.abs(z.diag.cpu().numpy()[:A.shape[0]] - ref.D).max() <= 1e-12 * amax
+    return z, ref
+
+
+@pytest.mark.parametrize("n,q,tau,field", [(300, 250, 1e-6, 0.5), (1200, 900, 1e-8, 0.5),
+                                           (777, 500, 1e-6, 0.0), (64, 80, 0.0, 0.3)])
+def test_zdecompose_parity(n, q, tau, field):
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(n, q, seed=n + q, field=field)
+    z, ref = _zcheck(A, tau)
+    assert ref.rc == 0
+
+
+def test_zdecompose_capacity_and_single_row():
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(500, 400, seed=21)
+    _zcheck(A, 1e-8, max_vectors=50, expect_status=cdlib.CD_ERR_CAPACITY)
+    one = np.array([[2.25 + 0.0j]])
+    z = cdlib.zdecompose(torch.from_numpy(one).to("cuda"), 1e-6)
+    assert z.M() == 1 and z.L[0, 0].item() == 1.5 + 0.0j
+
+
+def test_zdecompose_large_properties():
+    """4096 rows (the measured size): every final residual < tau, sampled
+    entries of A - sum L L^H within tau, pivot rows vanishing in later
+    vectors, distinct pivots."""
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    A = hermitian_gram(4096, 2048, seed=5)
+    tau = 1e-6
+    z = cdlib.zdecompose(torch.from_numpy(A).to("cuda"), tau)
+    M = z.M()
+    assert int(z.status.item()) == 0 and M > 500
+    assert float(z.diag.max()) < tau
+    L = z.L[:M].cpu().numpy()
+    piv = z.pivots[:M].cpu().numpy()
+    assert len(np.unique(piv)) == M
+    rng = np.random.default_rng(4)
+    rows, cols = rng.integers(0, 4096, 200), rng.integers(0, 4096, 200)
+    rec = np.einsum("kr,kr->r", L[:, rows], L[:, cols].conj())
+    assert np.abs(A[rows, cols] - rec).max() <= tau
+    for K in rng.integers(1, M, 40):
+        assert np.abs(L[K, piv[:K]]).max() <= 1e-9
+
