@@ -230,6 +230,44 @@ def scf_sweep(args):
                       "rows": rows}), flush=True)
 
 
+def bench_hermitian(args):
+    """The Hermitian decomposition of the seeded finite-field stand-in
+    (n rows, n/2 Gaussians) at tau: time per decomposition (HIP events on the
+    launch stream), vectors/s, and the bandwidth of the reads it must make
+    (each vector K re-reads the K earlier vectors of every row)."""
+    import torch
+
+    from paper_2609_00306_amd import cdlib
+    from paper_2609_00306_amd.inputs import hermitian_gram
+    torch.cuda.set_device(0)
+    n = args.hermitian
+    A = torch.from_numpy(hermitian_gram(n, n // 2, seed=5)).to("cuda")
+    tau = args.tau
+    z = cdlib.zdecompose(A, tau)
+    M = z.M()
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        cdlib.zdecompose(A, tau, sync=False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    for _ in range(args.steps):
+        cdlib.zdecompose(A, tau, sync=False)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    # algorithmic bytes: earlier vectors of every row (16 n K for vector K),
+    # the pivot row of A, the new vector and the residual update
+    traffic = 16.0 * n * M * (M - 1) / 2.0 + M * n * (16.0 + 16.0 + 16.0)
+    print(json.dumps({"hermitian": {"n": n, "n_fun": n // 2, "tau": tau, "n_vectors": M,
+                                    "ms": ms, "vectors_per_s": M / (ms * 1e-3),
+                                    "roofline": {"bound": "hbm",
+                                                 "achieved": traffic / (ms * 1e-3) / 1e9,
+                                                 "peak": HBM_TBPS * 1e3, "unit": "GB/s",
+                                                 "frac": traffic / (ms * 1e-3) / 1e9 / (HBM_TBPS * 1e3)},
+                                    "steps": args.steps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +284,9 @@ def main():
     ap.add_argument("--scf-sweep", action="store_true",
                     help="only run converged SCFs over tau and J/K precision and print the "
                          "energy errors (one JSON line)")
+    ap.add_argument("--hermitian", type=int, default=0, metavar="N",
+                    help="only time the Hermitian (finite-field) decomposition of the N-row "
+                         "stand-in matrix (one JSON line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
@@ -263,6 +304,9 @@ def main():
         return
     if args.scf_sweep:
         scf_sweep(args)
+        return
+    if args.hermitian:
+        bench_hermitian(args)
         return
 
     import numpy as np
