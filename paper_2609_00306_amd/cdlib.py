@@ -56,7 +56,7 @@ class cd_jk_problem(ctypes.Structure):
     _fields_ = [("n_basis", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
                 ("n_vectors", _vp), ("n_occ", ctypes.c_int32), ("C", _vp), ("J", _vp),
-                ("K", _vp), ("status", _vp)]
+                ("K", _vp), ("status", _vp), ("Lmo", _vp)]
 
 
 class cd_transform_problem(ctypes.Structure):
@@ -336,21 +336,26 @@ class JK:
     workspace: torch.Tensor
     problem: cd_jk_problem
     C: torch.Tensor
+    Lmo: Optional[torch.Tensor] = None   # [max_vectors][O][O] when asked for
 
 
-def prepare_jk(d: Decomposition, C, prec: str = "fp64") -> JK:
+def prepare_jk(d: Decomposition, C, prec: str = "fp64", lmo: bool = False) -> JK:
+    """Outputs and workspace of one J/K build; with ``lmo`` the build also
+    writes C^T L^P C from its half transform (FP64 only)."""
     dev = d.L.device
     C = _dev_f64(C, dev)
     N = d.n_basis
     J = torch.empty((N, N), dtype=torch.float64, device=dev)
     K = torch.empty((N, N), dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
+    O = int(C.shape[1]) if C.ndim == 2 else 0
+    Lmo = (torch.empty((d.max_vectors, O, O), dtype=torch.float64, device=dev) if lmo else None)
     p = cd_jk_problem(N, d.n_rows, d.max_vectors, _ptr(d.row_pair), _ptr(d.L), _ptr(d.n_vectors),
-                      int(C.shape[1]) if C.ndim == 2 else 0, _ptr(C), _ptr(J), _ptr(K), _ptr(st))
+                      O, _ptr(C), _ptr(J), _ptr(K), _ptr(st), _ptr(Lmo))
     ws = ctypes.c_size_t()
     _check(load().cd_query_jk(ctypes.byref(p), 1, PRECISIONS[prec], ctypes.byref(ws)))
     w = torch.empty(max(1, ws.value), dtype=torch.uint8, device=dev)
-    return JK(J, K, st, w, p, C)
+    return JK(J, K, st, w, p, C, Lmo)
 
 
 def prepare_jk_many(decs: Sequence[Decomposition], Cs, prec: str = "fp64"):

@@ -672,6 +672,9 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
 cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
                       uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
+    for (int32_t i = 0; i < count && probs; ++i)
+        if (probs[i].Lmo && prec != CD_FP64)
+            return fail(CD_ERR_INVALID_ARG, "problem %d: Lmo needs FP64 precision", i);
     size_t need = 0;
     cd_status s = cd_query_jk(probs, count, prec, &need);
     if (s) return s;
@@ -692,6 +695,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
         k_fill_f64<<<fb, 256, 0, st>>>(p.J, NN, 0.0);
         k_fill_f64<<<fb, 256, 0, st>>>(p.K, NN, 0.0);
+        if (p.Lmo && n == 0 && O > 0 && mv > 0)
+            k_fill_f64<<<256, 256, 0, st>>>(p.Lmo, mv * O * O, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
         launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
         k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>((int)N, O, p.C, w.Dm);
@@ -709,6 +714,9 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             k_half_sparse<false><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                         p.n_vectors, w.X, ldx, 0);
             k_syrk_rows<<<sgrid, 256, 0, st>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
+            if (p.Lmo)   // the second half of the transform on the same X
+                k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv),
+                        256, 0, st>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
         } else if (prec == CD_FP32) {
             k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
                                                             O, p.n_vectors, X32, ldx);

@@ -63,6 +63,7 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
          offsetof(cd_mp2_problem, status));
   printf("%zu %zu\n", sizeof(cd_zproblem), offsetof(cd_zproblem, status));
+  printf("%zu\n", offsetof(cd_jk_problem, Lmo));
   printf("%zu %zu %zu %zu %zu\n", sizeof(cd_one_electron_problem),
          offsetof(cd_one_electron_problem, H), sizeof(cd_scf_problem),
          offsetof(cd_scf_problem, e_tol), offsetof(cd_scf_problem, converged));
@@ -91,6 +92,7 @@ def test_binding_structs_match_header():
             cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
             cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset,
             ctypes.sizeof(cdlib.cd_zproblem), cdlib.cd_zproblem.status.offset,
+            cdlib.cd_jk_problem.Lmo.offset,
             ctypes.sizeof(cdlib.cd_one_electron_problem), cdlib.cd_one_electron_problem.H.offset,
             ctypes.sizeof(cdlib.cd_scf_problem), cdlib.cd_scf_problem.e_tol.offset,
             cdlib.cd_scf_problem.converged.offset]

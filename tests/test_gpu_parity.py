@@ -146,6 +146,25 @@ def test_jk_fp64_parity(name, schwarz):
     assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
 
 
+def test_jk_with_fused_transform():
+    """The FP64 J/K build with the optional MO-basis output: J and K as
+    without it, and C^T L^P C equal to the stand-alone transform with
+    C1 = C2 = C and to the oracle's."""
+    m = config_molecule("C2")
+    d, M = run_gpu(m, 1e-6, 1e-12)
+    rp, ref = check_against_oracle(m, 1e-6, 1e-12, d, M)
+    jk = cdlib.prepare_jk(d, m.C, "fp64", lmo=True)
+    cdlib.run_jk(jk, "fp64", sync=True)
+    J0, K0 = cdlib.build_jk(d, m.C, "fp64")
+    assert torch.equal(jk.J, J0) and torch.equal(jk.K, K0)
+    T = cdlib.transform(d, m.C, m.C)
+    assert torch.equal(jk.Lmo[:M], T[:M])
+    exp = oracle.transform(m.n_basis, rp, ref.L, m.C, m.C)
+    assert np.abs(jk.Lmo[:M].cpu().numpy() - exp).max() <= TOL_L
+    with pytest.raises(cdlib.CDError):
+        cdlib.run_jk(cdlib.prepare_jk(d, m.C, "fp64", lmo=True), "fp32", sync=True)
+
+
 def test_transform_parity():
     m = config_molecule("C1")
     d, M = run_gpu(m, 1e-6, 0.0)
