@@ -11,7 +11,9 @@
 // One workgroup per (pair i <= j, virtual tile pair TA <= TB of 64 x 64):
 // W1 = B_i(:, TA)^T B_j(:, TB) and, off the tile diagonal, W2 =
 // B_i(:, TB)^T B_j(:, TA), both FP64 MFMA products over P (k-major operands,
-// the shared gemm_tile engine).  The epilogue adds the terms of every ordered
+// the shared gemm_tile engine).  When the last tile TB holds at most 32
+// virtuals, both products take it as their row side with 2 row tiles, which
+// halves the matrix work spent on its zero padding.  The epilogue adds the terms of every ordered
 // (a, b) with a in TA, b in TB and, off the diagonal, (b, a); a fixed-order
 // reduction leaves one partial per workgroup.  Then one workgroup per pair
 // adds its tile pairs, and one workgroup adds the pairs (i == j once, i < j
@@ -91,10 +93,11 @@ __global__ __launch_bounds__(256) void k_mp2_tiles(const Mp2Params Q)
     double *sW2 = sStage;   // [64][64] once the second product is done
     const int lane = tid & 63, w = tid >> 6;
 
-    // acc[r] = B_x(:, 64 tr + 16 r + .)^T B_y(:, 64 tc + 16 w + .)
-    auto product = [&](int x, int tr, int y, int tc, f64x4 (&acc)[4]) {
+    // acc[r] = B_x(:, 64 tr + 16 r + .)^T B_y(:, 64 tc + 16 w + .), RT row tiles
+    auto product = [&](int x, int tr, int y, int tc, auto &acc) {
+        constexpr int RT = sizeof(acc) / sizeof(acc[0]);
         zero_acc(acc);
-        gemm_tile<4, MP2_TKC, true, true>(
+        gemm_tile<RT, MP2_TKC, true, true>(
             0, M,
             [&](int64_t k, int m) -> double {
                 const int a = 64 * tr + m;
@@ -106,19 +109,42 @@ __global__ __launch_bounds__(256) void k_mp2_tiles(const Mp2Params Q)
             },
             acc, sA, sB);
     };
-    f64x4 acc[4];
-    product(i, TA, j, TB, acc);
+    // acc element (row m, column n) -> W1[a][b] or W2[b][a] in LDS; 'swap' when
+    // the product was formed with the tiles exchanged (rows from TB)
+    auto store = [&](const auto &acc, double *dst, int ld, bool swap) {
+        constexpr int RT = sizeof(acc) / sizeof(acc[0]);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sW1[16 * r + mfma_row(lane, v)][16 * w + (lane & 15)] = acc[r][v];
-    if (TA != TB) {
-        product(i, TB, j, TA, acc);   // ends with a barrier: the staging is free
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                sW2[(16 * r + mfma_row(lane, v)) * 64 + 16 * w + (lane & 15)] = acc[r][v];
+            for (int v = 0; v < 4; ++v) {
+                const int m = 16 * r + mfma_row(lane, v), n = 16 * w + (lane & 15);
+                if (swap) dst[n * ld + m] = acc[r][v];
+                else dst[m * ld + n] = acc[r][v];
+            }
+    };
+    // A last virtual tile with at most 32 columns in use is taken as the row
+    // side of both products (2 row tiles instead of 4): W1 is then formed as
+    // W1^T = B_j(:, TB)^T B_i(:, TA) and stored transposed.
+    const bool short_tb = (TB == Q.T - 1) && (V - 64 * TB <= 32);
+    if (!short_tb) {
+        f64x4 acc[4];
+        product(i, TA, j, TB, acc);
+        store(acc, &sW1[0][0], 65, false);
+        if (TA != TB) {
+            product(i, TB, j, TA, acc);   // ends with a barrier: the staging is free
+            store(acc, sW2, 64, false);
+        }
+    } else {
+        f64x4 acc[2];
+        if (TA != TB) {
+            product(j, TB, i, TA, acc);   // W1^T
+            store(acc, &sW1[0][0], 65, true);
+            product(i, TB, j, TA, acc);   // W2
+            store(acc, sW2, 64, false);
+        } else {
+            product(i, TA, j, TB, acc);   // rows and columns both in the short tile
+            store(acc, &sW1[0][0], 65, false);
+        }
     }
     __syncthreads();
     const double ei = Q.eo[i], ej = Q.eo[j];
