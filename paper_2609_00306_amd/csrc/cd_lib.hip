@@ -828,7 +828,7 @@ cd_status cd_one_electron(const cd_one_electron_problem *p, uint32_t flags, void
 // Device workspace of cd_scf: eight N x N matrices, the Cholesky scratch, the
 // reduction results, and the J/K workspace.
 struct ScfWs {
-    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red, *Fh, *Eh;
+    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red, *Fh, *Eh, *part;
     void *jk;
     size_t jk_bytes;
 };
@@ -865,6 +865,7 @@ static cd_status scf_carve(const cd_scf_problem &p, cd_precision prec, void *bas
     w.K = c.take<double>(n2);
     w.dres = c.take<double>(std::max(1, p.n_basis));
     w.red = c.take<double>(8);
+    w.part = c.take<double>(SCF_DIIS * 256);
     w.Fh = c.take<double>(n2 * std::max(1, p.diis));
     w.Eh = c.take<double>(n2 * std::max(1, p.diis));
     // the J/K workspace depends on the sizes only; the size query is given
@@ -946,10 +947,29 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
     };
 
     k_fill_i32<<<1, 64, 0, st>>>(p->status, 1, 0);
+    // grid-wide reductions: a fixed grid (the partition of the N^2 elements,
+    // and so every sum, is the same on every call)
+    const unsigned rb = (unsigned)std::min<int64_t>(256, blocks_of(n2, 256));
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(w.red);
+    auto gershgorin = [&](const double *A) -> cd_status {
+        k_gershgorin_init<<<1, 1, 0, st>>>(keys);
+        k_gershgorin<<<(unsigned)blocks_of(N, 4), 256, 0, st>>>(N, A, keys);
+        cd_status r = read(2);
+        if (r) return r;
+        unsigned long long kk[2];
+        std::memcpy(kk, h, sizeof kk);
+        h[0] = key_value(kk[0]);
+        h[1] = key_value(kk[1]);
+        return CD_OK;
+    };
+    auto maxabs = [&](const double *G, int minus_identity) -> cd_status {
+        k_fill_f64<<<1, 64, 0, st>>>(w.red, 1, 0.0);
+        k_maxabs<<<rb, 256, 0, st>>>(N, G, minus_identity, w.red);
+        return read(1);
+    };
 
     // ---- X = S^{-1/2}: coupled Newton-Schulz from Y = S / c, Z = I
-    k_gershgorin<<<1, 256, 0, st>>>(N, p->S, w.red);
-    if ((s = read(2))) return s;
+    if ((s = gershgorin(p->S))) return s;
     const double c = h[1];
     if (!(c > 0.0) || !std::isfinite(c)) return fail(CD_ERR_NOT_PSD, "overlap bound %g", c);
     double *Y = w.A, *Z = w.B;
@@ -959,8 +979,7 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
     double prev = INFINITY;
     for (int it = 0; it < 200; ++it) {
         gemm(Z, Y, w.W1);
-        k_maxabs<<<1, 256, 0, st>>>(N, w.W1, 1, w.red);
-        if ((s = read(1))) return s;
+        if ((s = maxabs(w.W1, 1))) return s;
         const double err = h[0];
         if (!std::isfinite(err)) break;
         if (err < 1e-13 || (err < 1e-9 && err >= 0.5 * prev)) {
@@ -987,8 +1006,7 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
         double *Fo = w.A, *P = w.B, *P2 = w.T;
         gemm(w.X, Fm, w.W1);
         gemm(w.W1, w.X, Fo);
-        k_gershgorin<<<1, 256, 0, st>>>(N, Fo, w.red);
-        cd_status r = read(2);
+        cd_status r = gershgorin(Fo);
         if (r) return r;
         const double lo = h[0], hi = h[1];
         if (!(hi > lo)) return fail(CD_ERR_UNSUPPORTED, "degenerate Fock spectrum bounds");
@@ -1036,7 +1054,9 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
         DiisCoef co{};
         co.n = (int)order.size();
         for (int b = 0; b < co.n; ++b) co.slot[b] = order[b];
-        k_diis_dots<<<(unsigned)co.n, 256, 0, st>>>(n2, w.Eh + slot * n2, w.Eh, co, w.red);
+        k_diis_dots<<<dim3(rb, (unsigned)co.n), 256, 0, st>>>(n2, w.Eh + slot * n2, w.Eh, co,
+                                                              w.part);
+        k_sum_partials<<<(unsigned)co.n, 256, 0, st>>>((int)rb, w.part, 0.0, w.red);
         cd_status r = read(co.n);
         if (r) return r;
         for (int b = 0; b < co.n; ++b) Bm[slot][order[b]] = Bm[order[b]][slot] = h[b];
@@ -1075,15 +1095,14 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
     cd_jk_problem q = scf_jk_problem(*p, w.J, w.K);
     double e_prev = 0.0;
     for (int k = 0; k < p->max_iter; ++k) {
-        k_density_cholesky<<<1, 256, 0, st>>>(N, O, p->D, p->C, w.dres, p->status);
+        k_density_cholesky<<<1, DCH_T, 0, st>>>(N, O, p->D, w.W1, p->C, w.dres, p->status);
         if ((s = check_launch("density Cholesky"))) return s;
         if ((s = cd_build_jk(&q, 1, prec, 0, w.jk, w.jk_bytes, stream))) return s;
-        k_fock_energy<<<1, 256, 0, st>>>(N, p->H, w.J, w.K, p->D, p->e_charges, p->F,
-                                         p->energies + k);
+        k_fock_energy<<<rb, 256, 0, st>>>(N, p->H, w.J, w.K, p->D, p->F, w.part);
+        k_sum_partials<<<1, 256, 0, st>>>((int)rb, w.part, p->e_charges, p->energies + k);
         gemm(p->F, p->D, w.W1);
         gemm(w.W1, p->S, w.W2);
-        k_maxabs<<<1, 256, 0, st>>>(N, w.W2, 0, w.red);
-        if ((s = read(1))) return s;
+        if ((s = maxabs(w.W2, 0))) return s;
         const double comm = h[0];
         double E = 0.0;
         int32_t dst = 0;

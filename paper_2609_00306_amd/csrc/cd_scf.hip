@@ -23,6 +23,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "cd_device.hpp"
 #include "cd_mfma.hpp"
@@ -164,67 +165,105 @@ __global__ __launch_bounds__(256) void k_traces(int N, const double *__restrict_
     }
 }
 
-// Gershgorin bounds of a symmetric matrix: out[0] <= every eigenvalue <= out[1]
-// (one workgroup).
-__global__ __launch_bounds__(256) void k_gershgorin(int N, const double *__restrict__ A,
-                                                    double *__restrict__ out)
-{
-    __shared__ double s[256];
-    double lo = INFINITY, hi = -INFINITY;
-    for (int i = threadIdx.x; i < N; i += 256) {
-        double r = 0.0;
-        for (int j = 0; j < N; ++j)
-            if (j != i) r += fabs(A[(int64_t)i * N + j]);
-        const double d = A[(int64_t)i * N + i];
-        lo = fmin(lo, d - r);
-        hi = fmax(hi, d + r);
-    }
-    const double mlo = scf_block_max(-lo, s);
-    const double mhi = scf_block_max(hi, s);
-    if (threadIdx.x == 0) {
-        out[0] = -mlo;
-        out[1] = mhi;
-    }
-}
-
-// out[0] = max |G - G^T| (the commutator F D S - S D F with G = F D S for
-// symmetric F, D, S), or with 'minus_identity' max |G - I| (one workgroup per
-// call; N^2 elements).
+// *out = max |G - G^T| (the commutator F D S - S D F with G = F D S for
+// symmetric F, D, S), or with 'minus_identity' max |G - I|.  Grid-stride over
+// the N^2 elements; the maximum of non-negative doubles is taken on their bit
+// patterns (which order like the values), so the result does not depend on
+// the order.  *out must hold +0.0 before the launch.
 __global__ __launch_bounds__(256) void k_maxabs(int N, const double *__restrict__ G,
                                                 int minus_identity, double *__restrict__ out)
 {
-    __shared__ double s[256];
-    double m = 0.0;
     const int64_t n2 = (int64_t)N * N;
-    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+    double m = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
+         e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / N), j = (int)(e % N);
         const double v = minus_identity ? G[e] - (i == j ? 1.0 : 0.0)
                                         : G[e] - G[(int64_t)j * N + i];
-        m = fmax(m, fabs(v));
+        m = (v != v) ? INFINITY : fmax(m, fabs(v));   // a NaN reads as unbounded
     }
-    const double r = scf_block_max(m, s);
-    if (threadIdx.x == 0) out[0] = r;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(out),
+                  (unsigned long long)__double_as_longlong(m));
 }
 
-// F = H + 2 J - K and E = sum D o (H + F) + e_charges (one workgroup for the
-// sum; the Fock matrix elementwise by the same threads).
+// Fixed-order sums of 'nb' partials per row: out[b] = sum_k part[b * nb + k]
+// (one workgroup per row b), plus 'add'.
+__global__ __launch_bounds__(256) void k_sum_partials(int nb, const double *__restrict__ part,
+                                                      double add, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) a += part[(int64_t)blockIdx.x * nb + k];
+    const double t = scf_block_sum(a, s);
+    if (threadIdx.x == 0) out[blockIdx.x] = t + add;
+}
+
+// Gershgorin bounds of a symmetric matrix, one wave per row: keys[0] and
+// keys[1] collect, on order-preserving integer keys, the smallest d - r and
+// the largest d + r (d the diagonal element, r the off-diagonal absolute row
+// sum).  keys[0] must start at all ones and keys[1] at zero.
+__device__ __forceinline__ unsigned long long order_key(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__host__ __device__ inline double key_value(unsigned long long k)
+{
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double x;
+    memcpy(&x, &b, sizeof x);
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_gershgorin(int N, const double *__restrict__ A,
+                                                    unsigned long long *__restrict__ keys)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (row >= N) return;
+    double r = 0.0;
+    for (int j = lane; j < N; j += 64)
+        if (j != row) r += fabs(A[(int64_t)row * N + j]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off, 64);
+    if (lane == 0) {
+        const double d = A[(int64_t)row * N + row];
+        atomicMin(&keys[0], order_key(d - r));
+        atomicMax(&keys[1], order_key(d + r));
+    }
+}
+
+__global__ void k_gershgorin_init(unsigned long long *keys)
+{
+    keys[0] = ~0ull;
+    keys[1] = 0ull;
+}
+
+// F = H + 2 J - K, and per workgroup the fixed-order partial sum of
+// D o (H + F) (grid-stride over the N^2 elements with a fixed grid, so the
+// partition, and with k_sum_partials the energy, is the same on every run).
 __global__ __launch_bounds__(256) void k_fock_energy(int N, const double *__restrict__ H,
                                                      const double *__restrict__ J,
                                                      const double *__restrict__ K,
-                                                     const double *__restrict__ D, double e_charges,
+                                                     const double *__restrict__ D,
                                                      double *__restrict__ F,
-                                                     double *__restrict__ energy)
+                                                     double *__restrict__ part)
 {
     __shared__ double s[256];
     double acc = 0.0;
     const int64_t n2 = (int64_t)N * N;
-    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
+         e += (int64_t)gridDim.x * blockDim.x) {
         const double f = H[e] + 2.0 * J[e] - K[e];
         F[e] = f;
         acc += D[e] * (H[e] + f);
     }
     const double t = scf_block_sum(acc, s);
-    if (threadIdx.x == 0) energy[0] = t + e_charges;
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // Pulay extrapolation (DIIS) of the Fock matrix over stored iterations.
@@ -249,21 +288,24 @@ __global__ __launch_bounds__(256) void k_diis_store(int N, const double *__restr
     f_out[e] = F[e];
 }
 
-// out[b] = sum e_new o hist[slot[b]] over the N^2 elements, one workgroup per
-// stored iteration, fixed order
+// part[b * gridDim.x + x] = the fixed-order partial sum, over workgroup x's
+// share of the N^2 elements, of e_new o hist[slot[b]] (grid: x, b); the
+// overlaps follow from k_sum_partials
 __global__ __launch_bounds__(256) void k_diis_dots(int64_t n2, const double *__restrict__ e_new,
                                                    const double *__restrict__ hist,
                                                    const DiisCoef slots,
-                                                   double *__restrict__ out)
+                                                   double *__restrict__ part)
 {
     __shared__ double s[256];
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     if (b >= slots.n) return;
     const double *h = hist + (int64_t)slots.slot[b] * n2;
     double a = 0.0;
-    for (int64_t e = threadIdx.x; e < n2; e += 256) a += e_new[e] * h[e];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
+         e += (int64_t)gridDim.x * blockDim.x)
+        a += e_new[e] * h[e];
     const double t = scf_block_sum(a, s);
-    if (threadIdx.x == 0) out[b] = t;
+    if (threadIdx.x == 0) part[(int64_t)b * gridDim.x + blockIdx.x] = t;
 }
 
 // F = sum_b c[b] hist[slot[b]]
@@ -279,25 +321,29 @@ __global__ __launch_bounds__(256) void k_diis_combine(int64_t n2, const double *
 
 // C [N][O] with C C^T = D for the rank-O density D: a pivoted Cholesky
 // decomposition taking the O largest residual diagonals in turn (lowest index
-// on ties).  'dres' [N] is scratch.  One workgroup; status 4 when a pivot is
+// on ties).  One 1024-thread workgroup; the columns are formed in 'Ct' [O][N]
+// (so each is written and read with consecutive rows on consecutive threads)
+// and copied to C at the end; 'dres' [N] is scratch.  Status 4 when a pivot is
 // not positive.
-__global__ __launch_bounds__(256) void k_density_cholesky(int N, int O,
-                                                          const double *__restrict__ D,
-                                                          double *__restrict__ C,
-                                                          double *__restrict__ dres,
-                                                          int32_t *__restrict__ status)
+constexpr int DCH_T = 1024;
+__global__ __launch_bounds__(DCH_T) void k_density_cholesky(int N, int O,
+                                                            const double *__restrict__ D,
+                                                            double *__restrict__ Ct,
+                                                            double *__restrict__ C,
+                                                            double *__restrict__ dres,
+                                                            int32_t *__restrict__ status)
 {
-    __shared__ double sv[256];
-    __shared__ int si[256];
-    __shared__ int s_piv;
-    __shared__ double s_d;
+    __shared__ double sv[DCH_T];
+    __shared__ int si[DCH_T];
+    __shared__ double sp[1024];   // Ct[j][p] for the current pivot, j < k (chunks of 1024)
     const int tid = threadIdx.x;
-    for (int i = tid; i < N; i += 256) dres[i] = D[(int64_t)i * N + i];
+    for (int i = tid; i < N; i += DCH_T) dres[i] = D[(int64_t)i * N + i];
     __syncthreads();
+    int kdone = O;
     for (int k = 0; k < O; ++k) {
         double bv = -INFINITY;
         int bi = N;
-        for (int i = tid; i < N; i += 256) {
+        for (int i = tid; i < N; i += DCH_T) {
             const double d = dres[i];
             if (d > bv) {   // ascending i per thread: the first maximum stays
                 bv = d;
@@ -307,7 +353,7 @@ __global__ __launch_bounds__(256) void k_density_cholesky(int N, int O,
         sv[tid] = bv;
         si[tid] = bi;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = DCH_T / 2; w > 0; w >>= 1) {
             if (tid < w) {
                 const double ov = sv[tid + w];
                 const int oi = si[tid + w];
@@ -318,27 +364,52 @@ __global__ __launch_bounds__(256) void k_density_cholesky(int N, int O,
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            s_piv = si[0];
-            s_d = sv[0];
-        }
-        __syncthreads();
-        const int p = s_piv;
-        const double dp = s_d;
+        const int p = si[0];
+        const double dp = sv[0];
         if (!(dp > 0.0) || p >= N) {
             if (tid == 0) status[0] = 4;
-            for (int e = tid; e < N * (O - k); e += 256) C[(int64_t)(e / (O - k)) * O + k + e % (O - k)] = 0.0;
-            return;
+            kdone = k;
+            break;
         }
         const double inv = 1.0 / sqrt(dp);
-        for (int i = tid; i < N; i += 256) {
-            double v = D[(int64_t)i * N + p];
-            for (int j = 0; j < k; ++j) v -= C[(int64_t)i * O + j] * C[(int64_t)p * O + j];
-            v *= inv;
-            C[(int64_t)i * O + k] = v;
-            dres[i] = (i == p) ? -INFINITY : dres[i] - v * v;
+        double v[4];
+        for (int i0 = 0; i0 < N; i0 += 4 * DCH_T) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + tid + u * DCH_T;
+                v[u] = (i < N) ? D[(int64_t)i * N + p] : 0.0;
+            }
+            for (int j0 = 0; j0 < k; j0 += 1024) {
+                const int nj = min(1024, k - j0);
+                __syncthreads();
+                if (tid < nj) sp[tid] = Ct[(int64_t)(j0 + tid) * N + p];
+                __syncthreads();
+                for (int j = 0; j < nj; ++j) {
+                    const double c = sp[j];
+                    const double *row = Ct + (int64_t)(j0 + j) * N;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + tid + u * DCH_T;
+                        if (i < N) v[u] = fma(-row[i], c, v[u]);
+                    }
+                }
+            }
+            __syncthreads();   // every read of column p's earlier entries is done
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + tid + u * DCH_T;
+                if (i < N) {
+                    const double l = v[u] * inv;
+                    Ct[(int64_t)k * N + i] = l;
+                    dres[i] = (i == p) ? -INFINITY : dres[i] - l * l;
+                }
+            }
         }
         __syncthreads();
+    }
+    for (int64_t e = tid; e < (int64_t)N * O; e += DCH_T) {
+        const int i = (int)(e / O), j = (int)(e % O);
+        C[e] = (j < kdone) ? Ct[(int64_t)j * N + i] : 0.0;
     }
 }
 
