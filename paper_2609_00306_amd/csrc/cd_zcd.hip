@@ -48,32 +48,47 @@ __device__ __forceinline__ void zcd_better(double &bd, int &bi, double d, int i)
     }
 }
 
+// Butterfly max of (d, idx) over the 64 lanes of a wave, lowest idx on ties
+// (a total order, so every lane ends with the same pair).
+__device__ __forceinline__ void zcd_wave_max(double &d, int &i)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double od = __shfl_xor(d, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        zcd_better(d, i, od, oi);
+    }
+}
+
+// Largest of one (d, idx) per thread over the 256-thread workgroup: a wave
+// butterfly, then the four wave results in order; every thread gets it.
+__device__ __forceinline__ void zcd_block_max(double &d, int &i, double *sv, int *si)
+{
+    zcd_wave_max(d, i);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();   // earlier readers of sv/si are done
+    if ((threadIdx.x & 63) == 0) {
+        sv[w] = d;
+        si[w] = i;
+    }
+    __syncthreads();
+    d = sv[0];
+    i = si[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) zcd_better(d, i, sv[k], si[k]);
+}
+
 // Largest entry of n_slots (d, idx) pairs, lowest idx on ties; every thread
 // of the workgroup gets the result.
 __device__ __forceinline__ void zcd_reduce(const Nom *slots, int n_slots, double &bd, int &bi,
                                            double *sv, int *si)
 {
-    const int tid = threadIdx.x;
     double d = -INFINITY;
     int i = 0x7fffffff;
-    for (int s = tid; s < n_slots; s += 256) zcd_better(d, i, slots[s].d, slots[s].idx);
-    __syncthreads();
-    sv[tid] = d;
-    si[tid] = i;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) {
-            double od = sv[tid + w];
-            int oi = si[tid + w];
-            if (nom_before(od, oi, sv[tid], si[tid])) {
-                sv[tid] = od;
-                si[tid] = oi;
-            }
-        }
-        __syncthreads();
-    }
-    bd = sv[0];
-    bi = si[0];
+    for (int s = threadIdx.x; s < n_slots; s += 256) zcd_better(d, i, slots[s].d, slots[s].idx);
+    zcd_block_max(d, i, sv, si);
+    bd = d;
+    bi = i;
 }
 
 __global__ __launch_bounds__(256) void k_zcd(const ZcdParams Z)
@@ -97,19 +112,12 @@ __global__ __launch_bounds__(256) void k_zcd(const ZcdParams Z)
         Z.D[r] = dmine;
     }
     {
-        sv[tid] = (kl == 0) ? dmine : -INFINITY;
-        si[tid] = (own && kl == 0) ? (int)r : 0x7fffffff;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w && nom_before(sv[tid + w], si[tid + w], sv[tid], si[tid])) {
-                sv[tid] = sv[tid + w];
-                si[tid] = si[tid + w];
-            }
-            __syncthreads();
-        }
+        double bd = (kl == 0) ? dmine : -INFINITY;
+        int bi = (own && kl == 0) ? (int)r : 0x7fffffff;
+        zcd_block_max(bd, bi, sv, si);
         if (tid == 0) {
-            Z.part[g].d = sv[0];
-            Z.part[g].idx = si[0];
+            Z.part[g].d = bd;
+            Z.part[g].idx = bi;
         }
     }
     if (!grid_barrier(Z.gs, Z.G, g, gen, Z.spin_limit)) {
@@ -180,20 +188,13 @@ __global__ __launch_bounds__(256) void k_zcd(const ZcdParams Z)
             dnew = dr;
         }
         // largest updated residual of this workgroup's rows
-        sv[tid] = dnew;
-        si[tid] = (own && kl == 0) ? (int)r : 0x7fffffff;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w && nom_before(sv[tid + w], si[tid + w], sv[tid], si[tid])) {
-                sv[tid] = sv[tid + w];
-                si[tid] = si[tid + w];
-            }
-            __syncthreads();
-        }
+        double bd = dnew;
+        int bi = (own && kl == 0) ? (int)r : 0x7fffffff;
+        zcd_block_max(bd, bi, sv, si);
         Nom *slots = Z.part + ((K + 1) & 1) * Z.G;
         if (tid == 0) {
-            slots[g].d = sv[0];
-            slots[g].idx = si[0];
+            slots[g].d = bd;
+            slots[g].idx = bi;
         }
         if (!grid_barrier(Z.gs, Z.G, g, gen, Z.spin_limit)) {
             if (g == 0 && tid == 0) {
