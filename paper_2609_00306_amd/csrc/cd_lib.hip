@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -124,17 +125,31 @@ struct DevInfo {
     int coop_blocks_per_cu = 0;
 };
 
+// Compute units and pivot-selection occupancy of the current device, queried
+// once per device and kept (every entry point asks for them).
 cd_status dev_info(DevInfo &di)
 {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static DevInfo cache[kMaxDev];
     if (hipGetDevice(&di.dev) != hipSuccess) return fail(CD_ERR_DEVICE, "no HIP device");
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, di.dev) != hipSuccess)
-        return fail(CD_ERR_DEVICE, "hipGetDeviceProperties failed");
-    di.n_cu = prop.multiProcessorCount;
+    if (di.dev >= 0 && di.dev < kMaxDev) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (cache[di.dev].dev == di.dev) {
+            di = cache[di.dev];
+            return CD_OK;
+        }
+    }
+    if (hipDeviceGetAttribute(&di.n_cu, hipDeviceAttributeMultiprocessorCount, di.dev) != hipSuccess)
+        return fail(CD_ERR_DEVICE, "compute-unit count query failed");
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step1, 256, 0) != hipSuccess)
         return fail(CD_ERR_DEVICE, "occupancy query failed");
     di.coop_blocks_per_cu = nb;
+    if (di.dev >= 0 && di.dev < kMaxDev) {
+        std::lock_guard<std::mutex> lock(mu);
+        cache[di.dev] = di;
+    }
     return CD_OK;
 }
 
