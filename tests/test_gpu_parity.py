@@ -648,3 +648,38 @@ def test_zdecompose_large_properties():
     for K in rng.integers(1, M, 40):
         assert np.abs(L[K, piv[:K]]).max() <= 1e-9
 
+
+
+def test_scf_energy_from_span_factor_vectors():
+    """The span-factor decomposition (eta = 0.1) is a different but valid
+    Cholesky basis: the SCF on its J/K lands within the decomposition error
+    (order tau) of the SCF on the exact-pivoting vectors."""
+    from paper_2609_00306_amd.inputs import scf_charges
+    m = config_molecule("C2")
+    tau = 1e-6
+    cx, Z = scf_charges(m)
+    S, H = cdlib.one_electron(m.xyz, m.alpha, cx, Z)
+    e_ch = oracle.charge_repulsion(cx, Z)
+    E = []
+    for eta in (1.0, 0.1):
+        d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=1e-12, eta=eta)
+        r = cdlib.scf(d, S, H, m.n_occ, e_ch)
+        assert r.converged
+        E.append(float(r.energies[-1]))
+    assert abs(E[0] - E[1]) <= 50 * tau
+
+
+def test_mp2_on_restricted_candidate_vectors():
+    """The energy kernels take any vectors: on a restricted-candidate
+    decomposition of C1 the GPU chain (transform, energy) equals the oracle's
+    chain on the oracle's restricted decomposition."""
+    from paper_2609_00306_amd.inputs import exponent_block, mp2_orbitals
+    m = config_molecule("C1")
+    fn = exponent_block(m, (0, 1))
+    d = cdlib.decompose(m.xyz, m.alpha, 1e-6, schwarz=0.0, pivot_fn=fn)
+    M = d.M()
+    rp, ref = check_against_oracle(m, 1e-6, 0.0, d, M, pivot_fn=fn)
+    Co, Cv, eo, ev = mp2_orbitals(m)
+    E = float(cdlib.mp2_energy(cdlib.transform(d, Co, Cv), d.n_vectors, eo, ev).item())
+    Er, _ = oracle.mp2(oracle.transform(m.n_basis, rp, ref.L, Co, Cv), eo, ev)
+    assert abs(E - Er) <= 1e-7 * abs(Er)
