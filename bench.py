@@ -287,6 +287,9 @@ def main():
     ap.add_argument("--hermitian", type=int, default=0, metavar="N",
                     help="only time the Hermitian (finite-field) decomposition of the N-row "
                          "stand-in matrix (one JSON line)")
+    ap.add_argument("--tuning", default="builtin", choices=["auto", "builtin"],
+                    help="launch shapes of the decomposition: measured by cd_autotune before "
+                         "the warm-up (auto) or the built-in choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
@@ -341,8 +344,11 @@ def main():
     jk = cdlib.prepare_jk(d, m.C, args.precision, lmo=fused)
     stream = torch.cuda.current_stream()
 
+    # launch shapes: measured once on this workload (untimed), or the built-in ones
+    tuning = cdlib.autotune([d], tau, schwarz) if args.tuning == "auto" else None
+
     def step(phase_ev, jk_ev):
-        cdlib.run_decompose([d], tau, schwarz, events=phase_ev, eta=args.eta)
+        cdlib.run_decompose([d], tau, schwarz, events=phase_ev, eta=args.eta, tuning=tuning)
         jk_ev[0].record(stream)
         cdlib.run_jk(jk, args.precision)
         jk_ev[1].record(stream)
@@ -358,7 +364,7 @@ def main():
     # per-batch device-clock stamps of the pivot selection (one untimed step)
     cap = 4096
     timeline = torch.zeros(1 + 16 * cap, dtype=torch.int64, device=dev)
-    cdlib.run_decompose([d], tau, schwarz, timeline=timeline, eta=args.eta)
+    cdlib.run_decompose([d], tau, schwarz, timeline=timeline, eta=args.eta, tuning=tuning)
     torch.cuda.synchronize()
     tl = timeline.cpu().numpy()
     nbatch = int(tl[0])
@@ -497,7 +503,10 @@ def main():
                                f"tau={tau:g}, Schwarz {schwarz:g}, O={O}",
                    "n_basis": N, "n_rows": n, "n_active": d.n_active, "n_vectors": M,
                    "tau": tau, "n_occ": O, "jk_precision": args.precision, "eta": args.eta,
-                   "pivot_block": args.pivot_block},
+                   "pivot_block": args.pivot_block,
+                   "tuning": None if tuning is None else
+                   {"step2_row_tiles": tuning.step2_row_tiles,
+                    "step1_min_rows": tuning.step1_min_rows}},
         "cd_ms": t_cd,
         "cd_vectors_per_s": M / (t_cd * 1e-3),
         "jk_ms": t_jk,
