@@ -10,8 +10,9 @@
 //   density      : the projector on the O lowest solutions of F C = S C e,
 //                  by trace-correcting purification of X F X (Niklasson,
 //                  Phys. Rev. B 66, 155115 (2002)): P <- P^2 when tr P > O,
-//                  else 2 P - P^2, from P0 = (l_max - X F X) / (l_max - l_min)
-//                  with Gershgorin bounds; D = X P X;
+//                  else 2 P - P^2 (the branch taken on the device), from
+//                  P0 = (l_max - X F X) / (l_max - l_min) with Gershgorin
+//                  bounds; D = X P X;
 //   orbitals     : D = C C^T with C [N][O] from a pivoted Cholesky
 //                  decomposition of the rank-O density (any such C gives the
 //                  same J and K, which depend on D only);
@@ -116,6 +117,17 @@ __global__ __launch_bounds__(256) void k_lincomb(int N, double *out, double a, c
     if (Y) v += b * Y[e];
     if (e / N == e % N) v += c;
     out[e] = v;
+}
+
+// One trace-correcting purification step, the branch taken from tr P
+// (tr[0], written by k_traces): P <- P^2 when tr P > O, else 2 P - P^2.
+__global__ __launch_bounds__(256) void k_tc2_step(int N, double *P, const double *P2,
+                                                  const double *tr, double occ)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const double q = P2[e];
+    P[e] = (tr[0] > occ) ? q : 2.0 * P[e] - q;
 }
 
 // Fixed-order sum and max of one value per thread of a 256-thread workgroup
