@@ -843,7 +843,7 @@ cd_status cd_one_electron(const cd_one_electron_problem *p, uint32_t flags, void
 // Device workspace of cd_scf: eight N x N matrices, the Cholesky scratch, the
 // reduction results, and the J/K workspace.
 struct ScfWs {
-    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red, *Fh, *Eh, *part;
+    double *X, *A, *B, *T, *W1, *W2, *J, *K, *dres, *red, *Fh, *Eh, *part, *gpart;
     void *jk;
     size_t jk_bytes;
 };
@@ -881,6 +881,7 @@ static cd_status scf_carve(const cd_scf_problem &p, cd_precision prec, void *bas
     w.dres = c.take<double>(std::max(1, p.n_basis));
     w.red = c.take<double>(8);
     w.part = c.take<double>(SCF_DIIS * 256);
+    w.gpart = c.take<double>(n2 * SCF_KSPLIT_MAX);
     w.Fh = c.take<double>(n2 * std::max(1, p.diis));
     w.Eh = c.take<double>(n2 * std::max(1, p.diis));
     // the J/K workspace depends on the sizes only; the size query is given
@@ -945,8 +946,19 @@ cd_status cd_scf(cd_scf_problem *p, cd_precision prec, void *ws, size_t ws_bytes
     p->n_iter = 0;
     p->converged = 0;
 
+    // k-splits of the N x N products: enough workgroups for the compute units
+    const int tiles = (int)(blocks_of(N, 64) * blocks_of(N, 64));
+    int ks = 1;
+    while (ks < SCF_KSPLIT_MAX && tiles * (ks + 1) <= 256 && N / (ks + 1) >= 64) ++ks;
+    const int kchunk = (int)(blocks_of(blocks_of(N, ks), SCF_TKC) * SCF_TKC);
+    const dim3 gk(gg.x, gg.y, (unsigned)blocks_of(N, kchunk));
     auto gemm = [&](const double *A, const double *B, double *C) {
-        k_gemm_nn<<<gg, 256, 0, st>>>(N, A, B, C);
+        if (gk.z == 1) {
+            k_gemm_nn<<<gg, 256, 0, st>>>(N, A, B, C, N);
+        } else {
+            k_gemm_nn<<<gk, 256, 0, st>>>(N, A, B, w.gpart, kchunk);
+            k_sum_split<<<eb, 256, 0, st>>>(n2, (int)gk.z, w.gpart, C);
+        }
     };
     auto lincomb = [&](double *out, double a, const double *X, double b, const double *Y,
                        double c) { k_lincomb<<<eb, 256, 0, st>>>(N, out, a, X, b, Y, c); };

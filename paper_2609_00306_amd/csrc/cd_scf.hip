@@ -72,11 +72,15 @@ __global__ __launch_bounds__(256) void k_one_electron(int N, const double *__res
 }
 
 // ---------------------------------------------------------------- dense GEMM
-// C = A B for row-major N x N matrices: one 64 x 64 tile per workgroup.
+// C = A B for row-major N x N matrices: one 64 x 64 tile per workgroup; with
+// gridDim.z > 1 workgroup z takes the k-range [z kchunk, (z + 1) kchunk) and
+// writes its partial product to C + z N^2 (added by k_sum_split), so a small
+// N still fills the compute units.
 constexpr int SCF_TKC = 32;
+constexpr int SCF_KSPLIT_MAX = 8;
 __global__ __launch_bounds__(256) void k_gemm_nn(int N, const double *__restrict__ A,
                                                  const double *__restrict__ B,
-                                                 double *__restrict__ C)
+                                                 double *__restrict__ C, int kchunk)
 {
     using SA = OperandStage<64, SCF_TKC, false>;
     using SB = OperandStage<64, SCF_TKC, true>;
@@ -84,10 +88,12 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int N, const double *__restrict
     __shared__ double sB[SB::kSize];
     const int r0 = 64 * blockIdx.y, c0 = 64 * blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kb = blockIdx.z * kchunk, ke = min(N, kb + kchunk);
+    C += (int64_t)blockIdx.z * N * N;
     f64x4 acc[4];
     zero_acc(acc);
     gemm_tile<4, SCF_TKC, false, true>(
-        0, N,
+        kb, ke,
         [&](int64_t k, int m) -> double {
             const int r = r0 + m;
             return (r < N) ? A[(int64_t)r * N + k] : 0.0;
@@ -104,6 +110,17 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int N, const double *__restrict
             const int row = r0 + 16 * r + mfma_row(lane, v), col = c0 + 16 * w + (lane & 15);
             if (row < N && col < N) C[(int64_t)row * N + col] = acc[r][v];
         }
+}
+
+// C[e] = sum_z part[z n2 + e], z ascending
+__global__ __launch_bounds__(256) void k_sum_split(int64_t n2, int ks, const double *__restrict__ part,
+                                                   double *__restrict__ C)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n2) return;
+    double v = part[e];
+    for (int z = 1; z < ks; ++z) v += part[(int64_t)z * n2 + e];
+    C[e] = v;
 }
 
 // out = a X + b Y + c I (Y may be null when b == 0)
