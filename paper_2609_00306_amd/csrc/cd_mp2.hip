@@ -11,9 +11,9 @@
 // One workgroup per (pair i <= j, virtual tile pair TA <= TB of 64 x 64):
 // W1 = B_i(:, TA)^T B_j(:, TB) and, off the tile diagonal, W2 =
 // B_i(:, TB)^T B_j(:, TA), both FP64 MFMA products over P (k-major operands,
-// the shared gemm_tile engine).  When the last tile TB holds at most 32
-// virtuals, both products take it as their row side with 2 row tiles, which
-// halves the matrix work spent on its zero padding.  The epilogue adds the terms of every ordered
+// the shared gemm_tile engine).  When the last tile TB holds at most 48
+// virtuals, both products take it as their row side with only as many 16-row
+// tiles as it needs, which trims the matrix work spent on its zero padding.  The epilogue adds the terms of every ordered
 // (a, b) with a in TA, b in TB and, off the diagonal, (b, a); a fixed-order
 // reduction leaves one partial per workgroup.  Then one workgroup per pair
 // adds its tile pairs, and one workgroup adds the pairs (i == j once, i < j
@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "cd_mfma.hpp"
 
@@ -122,20 +124,12 @@ __global__ __launch_bounds__(256) void k_mp2_tiles(const Mp2Params Q)
                 else dst[m * ld + n] = acc[r][v];
             }
     };
-    // A last virtual tile with at most 32 columns in use is taken as the row
-    // side of both products (2 row tiles instead of 4): W1 is then formed as
-    // W1^T = B_j(:, TB)^T B_i(:, TA) and stored transposed.
-    const bool short_tb = (TB == Q.T - 1) && (V - 64 * TB <= 32);
-    if (!short_tb) {
-        f64x4 acc[4];
-        product(i, TA, j, TB, acc);
-        store(acc, &sW1[0][0], 65, false);
-        if (TA != TB) {
-            product(i, TB, j, TA, acc);   // ends with a barrier: the staging is free
-            store(acc, sW2, 64, false);
-        }
-    } else {
-        f64x4 acc[2];
+    // A last virtual tile with at most 48 virtuals in use is taken as the row
+    // side of both products with ceil(used / 16) row tiles instead of 4: W1 is
+    // then formed as W1^T = B_j(:, TB)^T B_i(:, TA) and stored transposed.
+    auto short_pair = [&](auto rt_tag) {
+        constexpr int RT = decltype(rt_tag)::value;
+        f64x4 acc[RT];
         if (TA != TB) {
             product(j, TB, i, TA, acc);   // W1^T
             store(acc, &sW1[0][0], 65, true);
@@ -144,6 +138,22 @@ __global__ __launch_bounds__(256) void k_mp2_tiles(const Mp2Params Q)
         } else {
             product(i, TA, j, TB, acc);   // rows and columns both in the short tile
             store(acc, &sW1[0][0], 65, false);
+        }
+    };
+    const int rt_tb = (TB == Q.T - 1) ? (V - 64 * TB + 15) / 16 : 4;
+    if (rt_tb == 1) {
+        short_pair(std::integral_constant<int, 1>{});
+    } else if (rt_tb == 2) {
+        short_pair(std::integral_constant<int, 2>{});
+    } else if (rt_tb == 3) {
+        short_pair(std::integral_constant<int, 3>{});
+    } else {
+        f64x4 acc[4];
+        product(i, TA, j, TB, acc);
+        store(acc, &sW1[0][0], 65, false);
+        if (TA != TB) {
+            product(i, TB, j, TA, acc);   // ends with a barrier: the staging is free
+            store(acc, sW2, 64, false);
         }
     }
     __syncthreads();

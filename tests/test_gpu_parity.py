@@ -378,9 +378,11 @@ def _mp2_gpu(B, M, eo, ev, dev, pad_rows=0):
 
 
 @pytest.mark.parametrize("M,O,V", [(37, 5, 50), (70, 9, 130), (64, 1, 64), (200, 12, 200),
+                                   (50, 4, 100), (33, 3, 40), (90, 6, 180),
                                    (5, 3, 1), (0, 4, 70), (16, 0, 40), (16, 3, 0)])
 def test_mp2_parity(gpu, M, O, V):
-    """Several virtual tiles with a ragged tail, one exact tile, a single
+    """Several virtual tiles with a ragged tail (last tile with 2, 8, 36, 40,
+    50 and 52 virtuals: 1, 3 and 4 row tiles), one exact tile, a single
     virtual, and the empty cases (no vectors: E = 0; no occupied or no
     virtual orbitals: E = 0)."""
     from paper_2609_00306_amd.inputs import random_mo_vectors
