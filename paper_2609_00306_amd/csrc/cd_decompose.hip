@@ -713,21 +713,23 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
 // ---------------------------------------------------------------- pivot block
 // Lp[K][J] = L^J at pivot row P_K (J < K), copied from the active-row
 // vectors; prow[K] = pair data of pivot row K.  One workgroup per K.
-__global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict__ LT,
-                                                       int64_t ldT,
-                                                       const int32_t *__restrict__ piv_slot,
-                                                       const int64_t *__restrict__ pivots,
-                                                       const RowRec *__restrict__ rows,
-                                                       const int64_t *__restrict__ n_vectors,
-                                                       double *__restrict__ Lp, int64_t ldp,
-                                                       RowRec *__restrict__ prow)
+__device__ __forceinline__ int pivot_mol(const int32_t *begin, int count)
 {
-    const int64_t M = *n_vectors;
-    const int64_t Kc = blockIdx.x;
+    int mol = 0;
+    while (mol + 1 < count && (int)blockIdx.x >= begin[mol + 1]) ++mol;
+    return mol;
+}
+
+__global__ __launch_bounds__(256) void k_gather_pivots(const PivotBatch B)
+{
+    const int mol = pivot_mol(B.gather_begin, B.count);
+    const PivotMol &Q = B.m[mol];
+    const int64_t M = *Q.n_vectors;
+    const int64_t Kc = (int64_t)blockIdx.x - B.gather_begin[mol];
     if (Kc >= M) return;
-    const double *src = LT + (int64_t)piv_slot[Kc] * ldT;
-    for (int64_t J = threadIdx.x; J < Kc; J += 256) Lp[Kc * ldp + J] = src[J];
-    if (threadIdx.x == 0) prow[Kc] = rows[pivots[Kc]];
+    const double *src = Q.LT + (int64_t)Q.piv_slot[Kc] * Q.ldT;
+    for (int64_t J = threadIdx.x; J < Kc; J += 256) Q.Lp[Kc * Q.ldp + J] = src[J];
+    if (threadIdx.x == 0) Q.prow[Kc] = Q.rows[Q.pivots[Kc]];
 }
 
 // Inverse-transposed pivot blocks.  For the 64 vectors K = b0 + j of one
@@ -737,28 +739,34 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const double *__restrict_
 // T being the right-hand side (r|P_K) - sum over earlier blocks, so
 // L_blk = T G with G = S^{-T} (upper triangular).  Lane c solves S x = e_c by
 // forward substitution with x in registers (both loops unrolled, four partial
-// sums per row); x is row c of G.  In a ragged last block the unused part of
-// S is the identity.
-__global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__ Lp, int64_t ldp,
-                                                      const double *__restrict__ dpiv,
-                                                      const int64_t *__restrict__ n_vectors,
-                                                      double *__restrict__ G)
+// sums per row, the diagonal applied as a precomputed reciprocal); x is row c
+// of G.  In a ragged last block the unused part of S is the identity.  One
+// launch covers the blocks of every problem of a pivot-selection launch.
+__global__ __launch_bounds__(64) void k_block_inverse(const PivotBatch B)
 {
-    const int64_t b0 = (int64_t)blockIdx.x * 64;
-    const int64_t M = *n_vectors;
+    const int mol = pivot_mol(B.inverse_begin, B.count);
+    const PivotMol &Q = B.m[mol];
+    const int64_t blk = (int64_t)blockIdx.x - B.inverse_begin[mol];
+    const double *__restrict__ Lp = Q.Lp;
+    const int64_t ldp = Q.ldp;
+    const int64_t b0 = blk * 64;
+    const int64_t M = *Q.n_vectors;
     if (b0 >= M) return;
     const int nb = (int)min((int64_t)64, M - b0);
     __shared__ double sS[64][66];
+    __shared__ double sR[64];   // 1 / S[j][j], so the substitution chain holds no division
     const int c = threadIdx.x;
     for (int j = 0; j < 64; ++j) {
         double v = 0.0;
         if (c < j) {
             if (j < nb) v = Lp[(b0 + j) * ldp + b0 + c];
         } else if (c == j) {
-            v = (j < nb) ? sqrt(dpiv[b0 + j]) : 1.0;
+            v = (j < nb) ? sqrt(Q.dpiv[b0 + j]) : 1.0;
         }
         sS[j][c] = v;
     }
+    __syncthreads();
+    sR[c] = 1.0 / sS[c][c];
     __syncthreads();
     double x[64];
 #pragma unroll
@@ -766,13 +774,13 @@ __global__ __launch_bounds__(64) void k_block_inverse(const double *__restrict__
         double a[4] = {(j == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < j; ++i) a[i & 3] = fma(-sS[j][i], x[i], a[i & 3]);
-        x[j] = ((a[0] + a[1]) + (a[2] + a[3])) / sS[j][j];
+        x[j] = ((a[0] + a[1]) + (a[2] + a[3])) * sR[j];
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 64; ++j) sS[c][j] = x[j];
     __syncthreads();
-    double *g = G + (int64_t)blockIdx.x * 4096;
+    double *g = Q.G + blk * 4096;
     for (int r = 0; r < 64; ++r) g[r * 64 + c] = sS[r][c];
 }
 

@@ -47,6 +47,29 @@ struct Step1Batch {
     Step1Params p[kStep1Batch];
 };
 
+// Pivot-row gather and pivot-block inverses of the problems of one
+// pivot-selection launch, in one launch each.
+struct PivotMol {
+    const double *LT;          // active-row vectors, row-major
+    int64_t ldT;
+    const int32_t *piv_slot;
+    const int64_t *pivots;
+    const RowRec *rows;
+    const int64_t *n_vectors;
+    double *Lp;                // [max_vectors][max_vectors] pivot rows
+    int64_t ldp;
+    RowRec *prow;
+    const double *dpiv;
+    double *G;                 // inverse-transposed 64 x 64 pivot blocks
+};
+
+struct PivotBatch {
+    int32_t count;
+    int32_t gather_begin[kStep1Batch + 1];    // workgroups of the gather, per problem
+    int32_t inverse_begin[kStep1Batch + 1];   // workgroups of the block inverses
+    PivotMol m[kStep1Batch];
+};
+
 // All-row solve of up to kStep2Batch problems in one launch.
 constexpr int kStep2Batch = 16;
 struct Step2Mol {

@@ -452,14 +452,31 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         if (e != hipSuccess)
             return fail(CD_ERR_DEVICE, "pivot-selection launch (%d workgroups): %s", nblk,
                         hipGetErrorString(e));
-        for (int i : grp) {
+        // pivot rows and pivot-block inverses of the whole group, one launch each
+        PivotBatch PB{};
+        PB.count = (int32_t)grp.size();
+        PB.gather_begin[0] = 0;
+        PB.inverse_begin[0] = 0;
+        for (size_t j = 0; j < grp.size(); ++j) {
+            const int i = grp[j];
             const cd_problem &p = probs[i];
-            k_gather_pivots<<<(unsigned)p.max_vectors, 256, 0, st>>>(
-                W[i].LT_act, ld_act(p.max_vectors), W[i].piv_slot, p.pivots, W[i].rows, p.n_vectors,
-                W[i].Lp, p.max_vectors, W[i].prow);
-            k_block_inverse<<<(unsigned)blocks_of(p.max_vectors, 64), 64, 0, st>>>(
-                W[i].Lp, p.max_vectors, W[i].dpiv, p.n_vectors, W[i].Ginv);
+            PivotMol &q = PB.m[j];
+            q.LT = W[i].LT_act;
+            q.ldT = ld_act(p.max_vectors);
+            q.piv_slot = W[i].piv_slot;
+            q.pivots = p.pivots;
+            q.rows = W[i].rows;
+            q.n_vectors = p.n_vectors;
+            q.Lp = W[i].Lp;
+            q.ldp = p.max_vectors;
+            q.prow = W[i].prow;
+            q.dpiv = W[i].dpiv;
+            q.G = W[i].Ginv;
+            PB.gather_begin[j + 1] = PB.gather_begin[j] + (int32_t)p.max_vectors;
+            PB.inverse_begin[j + 1] = PB.inverse_begin[j] + (int32_t)blocks_of(p.max_vectors, 64);
         }
+        k_gather_pivots<<<(unsigned)PB.gather_begin[PB.count], 256, 0, st>>>(PB);
+        k_block_inverse<<<(unsigned)PB.inverse_begin[PB.count], 64, 0, st>>>(PB);
         if ((s = check_launch("pivot gather"))) return s;
     }
     if ((s = record(2))) return s;
