@@ -701,6 +701,47 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     return CD_OK;
 }
 
+// Independent problems of one J/K call run on kJkSide internal streams
+// (default priority), forked from and joined back to the caller's stream with
+// events, so the short kernels of small problems overlap.  A hipGraph capture
+// of the caller's stream takes the side streams in as branches.  Created once
+// per device; one call at a time enqueues on them (the mutex).  Two side
+// streams measured best: with the runtime's four hardware queues per process,
+// three or four made the 64-molecule batch slower than none.
+constexpr int kJkSide = 2;
+struct SideStreams {
+    hipStream_t s[kJkSide];
+    hipEvent_t fork;
+    hipEvent_t join[kJkSide];
+    bool ok = false;
+};
+
+static std::mutex &side_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
+// Called with side_mutex() held.
+static cd_status side_streams(int dev, SideStreams *&out)
+{
+    constexpr int kMaxDev = 64;
+    static SideStreams cache[kMaxDev];
+    if (dev < 0 || dev >= kMaxDev) return fail(CD_ERR_UNSUPPORTED, "device index %d", dev);
+    SideStreams &c = cache[dev];
+    if (!c.ok) {
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipStreamCreateWithFlags(&c.s[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c.join[k], hipEventDisableTiming) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "side stream creation failed");
+        if (hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "side event creation failed");
+        c.ok = true;
+    }
+    out = &c;
+    return CD_OK;
+}
+
 cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
                       uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
@@ -716,8 +757,19 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     if ((s = dev_info(di))) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *wbase = static_cast<char *>(ws);
+    std::unique_lock<std::mutex> side_lock(side_mutex(), std::defer_lock);
+    SideStreams *side = nullptr;
+    if (count > 1) {
+        side_lock.lock();
+        if ((s = side_streams(di.dev, side))) return s;
+        if (hipEventRecord(side->fork, st) != hipSuccess) return fail(CD_ERR_DEVICE, "fork record failed");
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipStreamWaitEvent(side->s[k], side->fork, 0) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "fork wait failed");
+    }
     for (int32_t i = 0; i < count; ++i) {
         const cd_jk_problem &p = probs[i];
+        const hipStream_t sp = side ? side->s[i % kJkSide] : st;
         const int nsplit = jk_nsplit(p.n_basis, di.n_cu);
         JkWs w = carve_jk(wbase, p, nsplit);
         wbase += w.bytes;
@@ -725,16 +777,16 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const int O = p.n_occ;
         if (N == 0) continue;
         const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
-        k_fill_f64<<<fb, 256, 0, st>>>(p.J, NN, 0.0);
-        k_fill_f64<<<fb, 256, 0, st>>>(p.K, NN, 0.0);
+        k_fill_f64<<<fb, 256, 0, sp>>>(p.J, NN, 0.0);
+        k_fill_f64<<<fb, 256, 0, sp>>>(p.K, NN, 0.0);
         if (p.Lmo && n == 0 && O > 0 && mv > 0)
-            k_fill_f64<<<256, 256, 0, st>>>(p.Lmo, mv * O * O, 0.0);
+            k_fill_f64<<<256, 256, 0, sp>>>(p.Lmo, mv * O * O, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
-        launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
-        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>((int)N, O, p.C, w.Dm);
-        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, st>>>(n, p.row_pair, (int)N, w.Dm, w.w);
-        k_jV<<<(unsigned)mv, 256, 0, st>>>(p.L, n, w.w, p.n_vectors, w.V);
-        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, st>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
+        launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, sp);
+        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>((int)N, O, p.C, w.Dm);
+        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sp>>>(n, p.row_pair, (int)N, w.Dm, w.w);
+        k_jV<<<(unsigned)mv, 256, 0, sp>>>(p.L, n, w.w, p.n_vectors, w.V);
+        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sp>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
                                                          (int)N, p.J);
         const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
         const int T = (int)blocks_of(N, 64);
@@ -743,29 +795,36 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
         if (prec == CD_FP64) {
-            k_half_sparse<false><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<false><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                         p.n_vectors, w.X, ldx, 0);
-            k_syrk_rows<<<sgrid, 256, 0, st>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
+            k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
             if (p.Lmo)   // the second half of the transform on the same X
                 k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv),
-                        256, 0, st>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
+                        256, 0, sp>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
         } else if (prec == CD_FP32) {
-            k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
+            k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
                                                             O, p.n_vectors, X32, ldx);
-            k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, st>>>(X32, ldx, (int)N, p.n_vectors, O,
+            k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, sp>>>(X32, ldx, (int)N, p.n_vectors, O,
                                                           nsplit, w.Kp);
         } else {
             // X in FP64 (matrix cores), written split into three BF16 planes; the
             // exchange product then runs on BF16 matrix cores from the planes
             const int64_t ldb = bf16_ld(ldx), plane = N * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
-            k_half_sparse<true><<<hgrid, 256, 0, st>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<true><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                        p.n_vectors, Xp, ldb, plane);
-            k_syrk_rows_bf16p<<<sgrid, 256, 0, st>>>(Xp, ldb, plane, (int)N, p.n_vectors, O,
+            k_syrk_rows_bf16p<<<sgrid, 256, 0, sp>>>(Xp, ldb, plane, (int)N, p.n_vectors, O,
                                                      nsplit, w.Kp);
         }
-        k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, st>>>(w.Kp, (int)N, nsplit, 0, p.K);
+        k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
+    }
+    if (side) {
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipEventRecord(side->join[k], side->s[k]) != hipSuccess ||
+                hipStreamWaitEvent(st, side->join[k], 0) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "join failed");
+        side_lock.unlock();
     }
     if (flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)
