@@ -153,6 +153,49 @@ cd_status dev_info(DevInfo &di)
     return CD_OK;
 }
 
+// Independent problems of one call (the J/K builds, the decomposition setup)
+// run on kJkSide internal streams (default priority), forked from and joined
+// back to the caller's stream with events, so the short kernels of small
+// problems overlap.  A hipGraph capture
+// of the caller's stream takes the side streams in as branches.  Created once
+// per device; one call at a time enqueues on them (the mutex).  Two side
+// streams measured best: with the runtime's four hardware queues per process,
+// three or four made the 64-molecule batch slower than none.
+constexpr int kJkSide = 2;
+struct SideStreams {
+    hipStream_t s[kJkSide];
+    hipEvent_t fork;
+    hipEvent_t join[kJkSide];
+    bool ok = false;
+};
+
+static std::mutex &side_mutex()
+{
+    static std::mutex mu;
+    return mu;
+}
+
+// Called with side_mutex() held.
+static cd_status side_streams(int dev, SideStreams *&out)
+{
+    constexpr int kMaxDev = 64;
+    static SideStreams cache[kMaxDev];
+    if (dev < 0 || dev >= kMaxDev) return fail(CD_ERR_UNSUPPORTED, "device index %d", dev);
+    SideStreams &c = cache[dev];
+    if (!c.ok) {
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipStreamCreateWithFlags(&c.s[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c.join[k], hipEventDisableTiming) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "side stream creation failed");
+        if (hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "side event creation failed");
+        c.ok = true;
+    }
+    out = &c;
+    return CD_OK;
+}
+
+
 cd_status check_mol(const cd_molecule &m)
 {
     if (m.n_basis < 0) return fail(CD_ERR_INVALID_ARG, "n_basis < 0");
@@ -380,11 +423,32 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     }
     // ---- pair table, diagonal, screening
     if ((s = record(0))) return s;
-    for (int32_t i = 0; i < count; ++i) {
-        const cd_problem &p = probs[i];
-        k_init_decompose<<<1, 256, 0, st>>>(W[i].gs, p.status, p.n_vectors, W[i].d1max);
-        if ((s = launch_setup(p.mol, opts, W[i], p.row_pair, p.n_rows, p.n_active, st, true)))
-            return s;
+    {
+        // independent problems on the side streams, joined before the selection
+        std::unique_lock<std::mutex> side_lock(side_mutex(), std::defer_lock);
+        SideStreams *side = nullptr;
+        if (count > 1) {
+            side_lock.lock();
+            if ((s = side_streams(di.dev, side))) return s;
+            if (hipEventRecord(side->fork, st) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "fork record failed");
+            for (int k = 0; k < kJkSide; ++k)
+                if (hipStreamWaitEvent(side->s[k], side->fork, 0) != hipSuccess)
+                    return fail(CD_ERR_DEVICE, "fork wait failed");
+        }
+        for (int32_t i = 0; i < count; ++i) {
+            const cd_problem &p = probs[i];
+            const hipStream_t sp = side ? side->s[i % kJkSide] : st;
+            k_init_decompose<<<1, 256, 0, sp>>>(W[i].gs, p.status, p.n_vectors, W[i].d1max);
+            if ((s = launch_setup(p.mol, opts, W[i], p.row_pair, p.n_rows, p.n_active, sp, true)))
+                return s;
+        }
+        if (side) {
+            for (int k = 0; k < kJkSide; ++k)
+                if (hipEventRecord(side->join[k], side->s[k]) != hipSuccess ||
+                    hipStreamWaitEvent(st, side->join[k], 0) != hipSuccess)
+                    return fail(CD_ERR_DEVICE, "join failed");
+        }
     }
     if ((s = record(1))) return s;
 
@@ -698,47 +762,6 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         tot += carve_jk(nullptr, probs[i], jk_nsplit(probs[i].n_basis, di.n_cu)).bytes;
     }
     *ws_bytes = tot;
-    return CD_OK;
-}
-
-// Independent problems of one J/K call run on kJkSide internal streams
-// (default priority), forked from and joined back to the caller's stream with
-// events, so the short kernels of small problems overlap.  A hipGraph capture
-// of the caller's stream takes the side streams in as branches.  Created once
-// per device; one call at a time enqueues on them (the mutex).  Two side
-// streams measured best: with the runtime's four hardware queues per process,
-// three or four made the 64-molecule batch slower than none.
-constexpr int kJkSide = 2;
-struct SideStreams {
-    hipStream_t s[kJkSide];
-    hipEvent_t fork;
-    hipEvent_t join[kJkSide];
-    bool ok = false;
-};
-
-static std::mutex &side_mutex()
-{
-    static std::mutex mu;
-    return mu;
-}
-
-// Called with side_mutex() held.
-static cd_status side_streams(int dev, SideStreams *&out)
-{
-    constexpr int kMaxDev = 64;
-    static SideStreams cache[kMaxDev];
-    if (dev < 0 || dev >= kMaxDev) return fail(CD_ERR_UNSUPPORTED, "device index %d", dev);
-    SideStreams &c = cache[dev];
-    if (!c.ok) {
-        for (int k = 0; k < kJkSide; ++k)
-            if (hipStreamCreateWithFlags(&c.s[k], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&c.join[k], hipEventDisableTiming) != hipSuccess)
-                return fail(CD_ERR_DEVICE, "side stream creation failed");
-        if (hipEventCreateWithFlags(&c.fork, hipEventDisableTiming) != hipSuccess)
-            return fail(CD_ERR_DEVICE, "side event creation failed");
-        c.ok = true;
-    }
-    out = &c;
     return CD_OK;
 }
 
