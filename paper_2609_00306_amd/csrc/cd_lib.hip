@@ -782,7 +782,9 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     char *wbase = static_cast<char *>(ws);
     std::unique_lock<std::mutex> side_lock(side_mutex(), std::defer_lock);
     SideStreams *side = nullptr;
-    if (count > 1) {
+    // several problems: problem i on side stream i mod kJkSide; one problem:
+    // its J chain on side stream 0, beside the K chain on the caller's stream
+    if (count > 0) {
         side_lock.lock();
         if ((s = side_streams(di.dev, side))) return s;
         if (hipEventRecord(side->fork, st) != hipSuccess) return fail(CD_ERR_DEVICE, "fork record failed");
@@ -792,7 +794,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     }
     for (int32_t i = 0; i < count; ++i) {
         const cd_jk_problem &p = probs[i];
-        const hipStream_t sp = side ? side->s[i % kJkSide] : st;
+        const hipStream_t sp = (count > 1) ? side->s[i % kJkSide] : st;
+        const hipStream_t sj = (count > 1) ? sp : side->s[0];   // the J chain
         const int nsplit = jk_nsplit(p.n_basis, di.n_cu);
         JkWs w = carve_jk(wbase, p, nsplit);
         wbase += w.bytes;
@@ -800,16 +803,16 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const int O = p.n_occ;
         if (N == 0) continue;
         const unsigned fb = (unsigned)std::min<int64_t>(4096, blocks_of(NN, 256));
-        k_fill_f64<<<fb, 256, 0, sp>>>(p.J, NN, 0.0);
+        k_fill_f64<<<fb, 256, 0, sj>>>(p.J, NN, 0.0);
         k_fill_f64<<<fb, 256, 0, sp>>>(p.K, NN, 0.0);
         if (p.Lmo && n == 0 && O > 0 && mv > 0)
             k_fill_f64<<<256, 256, 0, sp>>>(p.Lmo, mv * O * O, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
         launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, sp);
-        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>((int)N, O, p.C, w.Dm);
-        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sp>>>(n, p.row_pair, (int)N, w.Dm, w.w);
-        k_jV<<<(unsigned)mv, 256, 0, sp>>>(p.L, n, w.w, p.n_vectors, w.V);
-        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sp>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
+        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sj>>>((int)N, O, p.C, w.Dm);
+        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sj>>>(n, p.row_pair, (int)N, w.Dm, w.w);
+        k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
+        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
                                                          (int)N, p.J);
         const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
         const int T = (int)blocks_of(N, 64);
