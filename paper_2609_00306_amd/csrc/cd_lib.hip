@@ -823,10 +823,19 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         if (prec == CD_FP64) {
             k_half_sparse<false><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                         p.n_vectors, w.X, ldx, 0);
-            k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
-            if (p.Lmo)   // the second half of the transform on the same X
+            // the second half of the transform on the same X: for one problem
+            // on side stream 1, beside the exchange product
+            hipStream_t st2 = sp;
+            if (p.Lmo && count == 1) {
+                st2 = side->s[1 % kJkSide];
+                if (hipEventRecord(side->fork, sp) != hipSuccess ||
+                    hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
+                    return fail(CD_ERR_DEVICE, "fork failed");
+            }
+            if (p.Lmo)
                 k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv),
-                        256, 0, sp>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
+                        256, 0, st2>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
+            k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
                                                             O, p.n_vectors, X32, ldx);
