@@ -214,6 +214,12 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
  * cd_build_jk: J_{mu nu} = sum_P L^P_{mu nu} V^P, V^P = sum_{rho sigma} L^P_{rho sigma} D_{rho sigma};
  * K_{mu nu} = sum_P sum_i X^P_{i mu} X^P_{i nu}, X^P_{i mu} = sum_sigma L^P_{mu sigma} C_{sigma i}.
  * Screened pairs contribute nothing; J and K are symmetric and written in full.
+ * Stream use: the work is ordered after what is already on 'stream', and
+ * everything after the call on 'stream' is ordered after it.  In between, the
+ * library runs parts of it (independent problems; for one problem the J chain
+ * and the second half of Lmo) on two streams of its own, forked from and
+ * joined back to 'stream' with events, so the call can be captured in a
+ * graph.  Calls from several host threads enqueue one at a time.
  */
 cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
                       uint32_t flags, void *ws, size_t ws_bytes, void *stream);
