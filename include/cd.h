@@ -169,6 +169,9 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
  * pivot's own residual is set to zero, and the loop ends when max D < tau.
  * Rows whose D1 < tau can never be pivots and are only solved for at the
  * end (the two-step organisation of Sec. 3, with exact pivoting).
+ * With count > 1 the per-problem setup runs on two library streams forked
+ * from and joined back to 'stream' (ordering on 'stream' is kept; graph
+ * capture works).
  */
 cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                        void *ws, size_t ws_bytes, void *stream);
