@@ -685,3 +685,48 @@ def test_mp2_on_restricted_candidate_vectors():
     E = float(cdlib.mp2_energy(cdlib.transform(d, Co, Cv), d.n_vectors, eo, ev).item())
     Er, _ = oracle.mp2(oracle.transform(m.n_basis, rp, ref.L, Co, Cv), eo, ev)
     assert abs(E - Er) <= 1e-7 * abs(Er)
+
+
+def test_graph_replay_of_batched_step_matches_eager():
+    """The batched step (decomposition of six molecules + FP64 J/K of all of
+    them, with the library's side streams) captured in a graph: every replay,
+    with eager work and synchronisation in between and the outputs poisoned
+    before it, reproduces the eager results bit for bit."""
+    from paper_2609_00306_amd.inputs import BATCH_C4, batch_c4
+    mols = batch_c4(count=6)
+    tau, schwarz = BATCH_C4["tau"], BATCH_C4["schwarz"]
+    pairs = [(m.xyz, m.alpha) for m in mols]
+    decs, ws = cdlib.allocate_many(pairs, tau, schwarz, device="cuda")
+    jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], "fp64")
+
+    def step():
+        cdlib.run_decompose(decs, tau, schwarz, workspace=ws)
+        cdlib.run_jk_many(jks, jws, "fp64")
+
+    step()
+    torch.cuda.synchronize()
+    ref = [(d.M(), d.pivots[:d.M()].clone(), d.L[:d.M()].clone(), j.J.clone(), j.K.clone())
+           for d, j in zip(decs, jks)]
+    assert all(int(d.status.item()) == 0 for d in decs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        for d, j in zip(decs, jks):            # eager work between replays
+            d.L.fill_(float("nan"))
+            d.pivots.fill_(-1)
+            j.J.fill_(float("nan"))
+            j.K.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (M, piv, L, J, K), d, j in zip(ref, decs, jks):
+            assert d.M() == M and int(d.status.item()) == 0
+            assert torch.equal(d.pivots[:M], piv)
+            assert torch.equal(d.L[:M], L)
+            assert torch.equal(j.J, J) and torch.equal(j.K, K)
