@@ -338,9 +338,10 @@ def main():
     torch.cuda.empty_cache()
     d = cdlib.allocate(m.xyz, m.alpha, tau, schwarz, max(1, M), device=dev, pivot_fn=fn)
     n = d.n_rows
-    # in FP64 the J/K build also writes the transformed vectors C^T L C from the
-    # half transform it already forms; otherwise the transform is its own call
-    fused = args.precision == "fp64"
+    # in FP64 and 3 x BF16 the J/K build also writes the transformed vectors
+    # C^T L C from the FP64 half transform it already forms; in FP32 the
+    # transform is its own call
+    fused = args.precision in ("fp64", "bf16x3")
     jk = cdlib.prepare_jk(d, m.C, args.precision, lmo=fused)
     stream = torch.cuda.current_stream()
 

@@ -341,7 +341,7 @@ class JK:
 
 def prepare_jk(d: Decomposition, C, prec: str = "fp64", lmo: bool = False) -> JK:
     """Outputs and workspace of one J/K build; with ``lmo`` the build also
-    writes C^T L^P C from its half transform (FP64 only)."""
+    writes C^T L^P C from its FP64 half transform (fp64 and bf16x3)."""
     dev = d.L.device
     C = _dev_f64(C, dev)
     N = d.n_basis

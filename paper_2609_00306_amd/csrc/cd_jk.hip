@@ -217,7 +217,8 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
 // With PLANES the FP64 result x is written split as x = b0 + b1 + b2 into three
 // BF16 planes (b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane
 // p at Yp + p * plane, row mu at mu * ldy: the operand of the 3 x BF16 exchange
-// product, split once here instead of in every tile that reads it.
+// product, split once here instead of in every tile that reads it.  With a
+// non-null Y64 the FP64 value is also written there (row mu at mu * ldy64).
 __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, __bf16 &b2)
 {
     b0 = (__bf16)(float)x;
@@ -234,7 +235,8 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
                                                      const double *__restrict__ C, int ncol,
                                                      const int64_t *__restrict__ n_vectors,
                                                      void *__restrict__ Yv, int64_t ldy,
-                                                     int64_t plane)
+                                                     int64_t plane, double *__restrict__ Y64,
+                                                     int64_t ldy64)
 {
     __shared__ double sU[2 * JKS::kSize];
     double *sA = sU, *sB = sU + JKS::kSize;
@@ -274,6 +276,7 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
         });
     } else {
         __bf16 *out = static_cast<__bf16 *>(Yv) + (int64_t)mu * ldy;
+        double *out64 = Y64 ? Y64 + (int64_t)mu * ldy64 : nullptr;
         for_each_acc(acc, 4, [&](int m, int n, double v) {
             if (p0 + m < M && n0 + n < ncol) {
                 __bf16 b0, b1, b2;
@@ -282,6 +285,7 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
                 out[e] = b0;
                 out[plane + e] = b1;
                 out[2 * plane + e] = b2;
+                if (out64) out64[e] = v;   // the FP64 value as well (for C^T L C)
             }
         });
     }

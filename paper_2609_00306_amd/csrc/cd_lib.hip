@@ -704,6 +704,7 @@ void launch_sparse_prep(const SparseWs &w, int64_t N, int64_t n, int64_t mv,
 
 struct JkWs {
     double *Dm, *w, *V, *X, *Kp;
+    double *X64;   // FP64 copy of X beside the BF16 planes (3 x BF16 with Lmo)
     SparseWs sp;
     size_t bytes;
 };
@@ -712,7 +713,7 @@ struct JkWs {
 // row starts 16-byte aligned.
 int64_t bf16_ld(int64_t n) { return (n + 7) / 8 * 8; }
 
-JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
+JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
 {
     JkWs w{};
     Carver c(ws);
@@ -727,6 +728,7 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit)
     const int64_t xb = (3 * N * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
     w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
+    w.X64 = (p.Lmo && prec == CD_BF16X3) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
     w.bytes = c.off;
     return w;
 }
@@ -759,7 +761,7 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     size_t tot = 0;
     for (int32_t i = 0; i < count; ++i) {
         if ((s = check_jk(probs[i]))) return s;
-        tot += carve_jk(nullptr, probs[i], jk_nsplit(probs[i].n_basis, di.n_cu)).bytes;
+        tot += carve_jk(nullptr, probs[i], jk_nsplit(probs[i].n_basis, di.n_cu), prec).bytes;
     }
     *ws_bytes = tot;
     return CD_OK;
@@ -769,8 +771,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                       uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     for (int32_t i = 0; i < count && probs; ++i)
-        if (probs[i].Lmo && prec != CD_FP64)
-            return fail(CD_ERR_INVALID_ARG, "problem %d: Lmo needs FP64 precision", i);
+        if (probs[i].Lmo && prec == CD_FP32)
+            return fail(CD_ERR_INVALID_ARG, "problem %d: Lmo needs FP64 or 3 x BF16", i);
     size_t need = 0;
     cd_status s = cd_query_jk(probs, count, prec, &need);
     if (s) return s;
@@ -797,7 +799,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const hipStream_t sp = (count > 1) ? side->s[i % kJkSide] : st;
         const hipStream_t sj = (count > 1) ? sp : side->s[0];   // the J chain
         const int nsplit = jk_nsplit(p.n_basis, di.n_cu);
-        JkWs w = carve_jk(wbase, p, nsplit);
+        JkWs w = carve_jk(wbase, p, nsplit, prec);
         wbase += w.bytes;
         const int64_t N = p.n_basis, NN = N * N, n = p.n_rows, mv = p.max_vectors;
         const int O = p.n_occ;
@@ -820,21 +822,24 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const int64_t ldx = mv * O;
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
-        if (prec == CD_FP64) {
-            k_half_sparse<false><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
-                                                        p.n_vectors, w.X, ldx, 0);
-            // the second half of the transform on the same X: for one problem
-            // on side stream 1, beside the exchange product
+        // the second half of the transform on the FP64 X: for one problem on
+        // side stream 1, beside the exchange product
+        auto second_half = [&](const double *X64) -> cd_status {
             hipStream_t st2 = sp;
-            if (p.Lmo && count == 1) {
+            if (count == 1) {
                 st2 = side->s[1 % kJkSide];
                 if (hipEventRecord(side->fork, sp) != hipSuccess ||
                     hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
                     return fail(CD_ERR_DEVICE, "fork failed");
             }
-            if (p.Lmo)
-                k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv),
-                        256, 0, st2>>>(w.X, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
+            k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv), 256,
+                    0, st2>>>(X64, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
+            return CD_OK;
+        };
+        if (prec == CD_FP64) {
+            k_half_sparse<false><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+                                                        p.n_vectors, w.X, ldx, 0, nullptr, 0);
+            if (p.Lmo && (s = second_half(w.X))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
@@ -847,7 +852,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             const int64_t ldb = bf16_ld(ldx), plane = N * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
             k_half_sparse<true><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
-                                                       p.n_vectors, Xp, ldb, plane);
+                                                       p.n_vectors, Xp, ldb, plane, w.X64, ldx);
+            if (p.Lmo && (s = second_half(w.X64))) return s;
             k_syrk_rows_bf16p<<<sgrid, 256, 0, sp>>>(Xp, ldb, plane, (int)N, p.n_vectors, O,
                                                      nsplit, w.Kp);
         }
@@ -914,7 +920,7 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
             k_half_sparse<false><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
                                         (unsigned)N),
                                    256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
-                                                 p.n_vectors, Y, ldy, 0);
+                                                 p.n_vectors, Y, ldy, 0, nullptr, 0);
         } else {
             k_fill_f64<<<256, 256, 0, st>>>(Y, mv * N * p.q, 0.0);
         }

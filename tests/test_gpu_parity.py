@@ -146,16 +146,18 @@ def test_jk_fp64_parity(name, schwarz):
     assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
 
 
-def test_jk_with_fused_transform():
-    """The FP64 J/K build with the optional MO-basis output: J and K as
-    without it, and C^T L^P C equal to the stand-alone transform with
-    C1 = C2 = C and to the oracle's."""
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_jk_with_fused_transform(prec):
+    """The J/K build with the optional MO-basis output (FP64, and 3 x BF16,
+    whose half transform is FP64 before the split): J and K as without it, and
+    C^T L^P C equal to the stand-alone transform with C1 = C2 = C and to the
+    oracle's."""
     m = config_molecule("C2")
     d, M = run_gpu(m, 1e-6, 1e-12)
     rp, ref = check_against_oracle(m, 1e-6, 1e-12, d, M)
-    jk = cdlib.prepare_jk(d, m.C, "fp64", lmo=True)
-    cdlib.run_jk(jk, "fp64", sync=True)
-    J0, K0 = cdlib.build_jk(d, m.C, "fp64")
+    jk = cdlib.prepare_jk(d, m.C, prec, lmo=True)
+    cdlib.run_jk(jk, prec, sync=True)
+    J0, K0 = cdlib.build_jk(d, m.C, prec)
     assert torch.equal(jk.J, J0) and torch.equal(jk.K, K0)
     T = cdlib.transform(d, m.C, m.C)
     assert torch.equal(jk.Lmo[:M], T[:M])
