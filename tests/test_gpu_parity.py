@@ -147,12 +147,13 @@ def test_jk_fp64_parity(name, schwarz):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-def test_jk_with_fused_transform(prec):
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_jk_with_fused_transform(name, prec):
     """The J/K build with the optional MO-basis output (FP64, and 3 x BF16,
     whose half transform is FP64 before the split): J and K as without it, and
     C^T L^P C equal to the stand-alone transform with C1 = C2 = C and to the
     oracle's."""
-    m = config_molecule("C2")
+    m = config_molecule(name)
     d, M = run_gpu(m, 1e-6, 1e-12)
     rp, ref = check_against_oracle(m, 1e-6, 1e-12, d, M)
     jk = cdlib.prepare_jk(d, m.C, prec, lmo=True)
