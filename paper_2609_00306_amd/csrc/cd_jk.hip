@@ -134,13 +134,22 @@ __global__ __launch_bounds__(256) void k_transpose(const double *__restrict__ L,
     const int64_t r0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * 64;
     const int64_t M = *n_vectors;
     if (p0 >= M) return;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int pp = e >> 6, rr = e & 63;
-        t[pp][rr] = (p0 + pp < M && r0 + rr < n_rows) ? L[(p0 + pp) * n_rows + r0 + rr] : 0.0;
+    // all 16 loads of a thread in flight before the first LDS write
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, pp = e >> 6, rr = e & 63;
+        v[j] = (p0 + pp < M && r0 + rr < n_rows) ? L[(p0 + pp) * n_rows + r0 + rr] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        t[e >> 6][e & 63] = v[j];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int rr = e >> 6, pp = e & 63;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, rr = e >> 6, pp = e & 63;
         if (r0 + rr < n_rows && p0 + pp < M) LT[(r0 + rr) * ldt + p0 + pp] = t[pp][rr];
     }
 }
