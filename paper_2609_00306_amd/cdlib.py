@@ -358,9 +358,10 @@ def prepare_jk(d: Decomposition, C, prec: str = "fp64", lmo: bool = False) -> JK
     return JK(J, K, st, w, p, C, Lmo)
 
 
-def prepare_jk_many(decs: Sequence[Decomposition], Cs, prec: str = "fp64"):
-    """J/K outputs for several decompositions plus one shared workspace."""
-    jks = [prepare_jk(d, C, prec) for d, C in zip(decs, Cs)]
+def prepare_jk_many(decs: Sequence[Decomposition], Cs, prec: str = "fp64", lmo: bool = False):
+    """J/K outputs for several decompositions plus one shared workspace (with
+    ``lmo`` each problem also gets its C^T L^P C output)."""
+    jks = [prepare_jk(d, C, prec, lmo=lmo) for d, C in zip(decs, Cs)]
     total = sum(int(j.workspace.numel()) for j in jks)
     dev = decs[0].L.device
     for j in jks:

@@ -306,16 +306,22 @@ def test_autotune_shapes_give_the_same_decomposition():
             assert (d.L[:d.M()] - r.L[:r.M()]).abs().max().item() <= 1e-12
 
 
-def test_batched_jk_matches_single():
+@pytest.mark.parametrize("prec,lmo", [("fp64", False), ("fp64", True), ("bf16x3", True)])
+def test_batched_jk_matches_single(prec, lmo):
+    """Several problems in one call (on the library's two streams) give the
+    single-problem results bit for bit, with and without the MO output."""
     mols = [make_molecule(4 + i, 4.0, (0.3, 1.1, 4.0), 3, seed=700 + i) for i in range(5)]
     decs, ws = cdlib.allocate_many([(m.xyz, m.alpha) for m in mols], 1e-6, 1e-12)
     cdlib.run_decompose(decs, 1e-6, 1e-12, workspace=ws)
-    jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], "fp64")
-    cdlib.run_jk_many(jks, jws, "fp64")
+    jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], prec, lmo=lmo)
+    cdlib.run_jk_many(jks, jws, prec)
     torch.cuda.synchronize()
     for m, d, jk in zip(mols, decs, jks):
-        J, K = cdlib.build_jk(d, m.C, "fp64")
+        J, K = cdlib.build_jk(d, m.C, prec)
         assert torch.equal(J, jk.J) and torch.equal(K, jk.K)
+        if lmo:
+            M = d.M()
+            assert torch.equal(jk.Lmo[:M], cdlib.transform(d, m.C, m.C)[:M])
 
 
 @pytest.mark.parametrize("name", ["C5"])
