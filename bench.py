@@ -1,16 +1,20 @@
 """Benchmark of the full hot path on one MI355X.
 
 One step = cd_decompose (pairs, diagonal, screening, pivot selection,
-all-row solve) + cd_build_jk (J and K) + cd_transform (AO->MO transform of
-every vector with the occupied coefficients on both sides), on the
-400-function workload (100 centres in a 16 angstrom box, exponents 0.1 ..
-10 bohr^-2, 50 occupied orbitals, Schwarz screening 1e-12) at tau = 1e-6.
-Inputs are resident in device memory before the timed region.
+all-row solve) + cd_build_jk (J and K, with the AO->MO transform of every
+vector by the occupied coefficients on both sides fused into it, or as a
+separate cd_transform call where the precision does not fuse it).  The default
+workload is the 1200-function one (300 centres in a 24 angstrom box,
+exponents 0.1 .. 10 bohr^-2, 150 occupied orbitals, Schwarz screening 1e-12)
+at tau = 1e-6, the largest single-GPU configuration.  Inputs are resident in
+device memory before the timed region.
 
-Prints one JSON line.  value = Cholesky vectors per second of the whole step
-(M / step time).  Extra fields give the decomposition alone, J/K TFLOP/s,
-per-phase device times from HIP events recorded on the library's stream, the
-roofline of the dominant kernel and the CPU oracle's rate.
+Prints one JSON line.  value = Cholesky vectors per second of the whole FP64
+step (M / step time).  The same line carries the step and the J/K build with
+FP32 and with 3 x BF16 exchange products against FP64 (times and errors), the
+64-molecule batched workload against the same molecules one by one at equal
+precision, per-phase device times from HIP events recorded on the library's
+stream, the roofline of the dominant kernel and the CPU oracle's rate.
 """
 from __future__ import annotations
 
@@ -26,26 +30,24 @@ if ROOT not in sys.path:
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X
 HBM_TBPS = 8.0
+METRIC = "Cholesky vectors/s + J/K build TFLOP/s at tau=1e-6; mixed/batched vs plain FP64"
+PRECISIONS = ("fp64", "fp32", "bf16x3")
+#: precisions whose J/K build also writes C^T L C (the transform fused into it)
+FUSED = ("fp64", "bf16x3")
 
-# HBM bytes per launch of the two decomposition kernels on the default workload
-# (400 functions, tau = 1e-6), from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0` (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch), each scaled by what the same counter reads for a plain 1 GiB
-# device copy (`bench.py --copy-probe 1024`): FETCH_SIZE reads 524 302 KiB
-# there (factor 2.0), WRITE_SIZE 1 048 576 KiB (factor 1.0).  The figures
-# belong to the kernel sources they were taken on; once those change the
-# traffic is reported as null until the counters are taken again.
+# HBM bytes per launch of the decomposition kernels on a workload, from two
+# rocprofv3 --pmc runs of the default bench command (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
+# a plain 1 GiB device copy (`bench.py --copy-probe 1024`): FETCH_SIZE reads
+# 524 302 KiB there (factor 2.0), WRITE_SIZE 1 048 576 KiB (factor 1.0).  The
+# figures belong to the kernel sources they were taken on; once those change
+# the traffic is reported as null until the counters are taken again.
 KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_mfma.hpp",
                   "paper_2609_00306_amd/csrc/cd_device.hpp",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.2, 1048576.0 / 1048576.0
-COUNTERS = {
-    "sources_sha256": "759c7b00a436e790c22cb8ab041cca7fbabadcfe2e0e7788284f191b6d398992",
-    "workload": ("C2", 1e-6),
-    "fetch_kib": {"k_step2": 2348599.5, "k_step1": 73105.5},
-    "write_kib": {"k_step2": 259291.5, "k_step1": 30159.5},
-}
+COUNTERS = {}   # (config, tau) -> {"sources_sha256", "fetch_kib": {kernel: KiB}, "write_kib": ..}
 
 
 def kernel_sources_sha256():
@@ -59,27 +61,34 @@ def kernel_sources_sha256():
 
 def counter_traffic(kernel, config, tau):
     """HBM bytes per launch of 'kernel' from the recorded counters, or None."""
-    if (config, tau) != COUNTERS["workload"]:
+    c = COUNTERS.get((config, tau))
+    if c is None or kernel not in c["fetch_kib"]:
         return None
-    if kernel_sources_sha256() != COUNTERS["sources_sha256"]:
+    if kernel_sources_sha256() != c["sources_sha256"]:
         return None
-    return 1024.0 * (COUNTERS["fetch_kib"][kernel] * FETCH_SCALE
-                     + COUNTERS["write_kib"][kernel] * WRITE_SCALE)
+    return 1024.0 * (c["fetch_kib"][kernel] * FETCH_SCALE + c["write_kib"][kernel] * WRITE_SCALE)
 
 
-def cpu_baseline(m, tau, schwarz):
-    """The CPU oracle timed on the host cores: one full decomposition + FP64 J/K."""
+def cpu_baseline(m, tau, schwarz, M_full, prefix):
+    """The CPU oracle timed on the host cores: the first 'prefix' vectors of the
+    same decomposition (the oracle's cost per vector grows with the vector
+    index, about n K operations for vector K, so the full run is estimated
+    from the prefix by that model)."""
     import oracle
     rp, _ = oracle.rows(m.xyz, m.alpha, schwarz)
+    P = int(min(prefix, M_full))
     t0 = time.perf_counter()
-    ref = oracle.decompose(m.xyz, m.alpha, rp, tau)
+    ref = oracle.decompose(m.xyz, m.alpha, rp, tau, max_vectors=P)
     t1 = time.perf_counter()
-    oracle.jk_cd(m.n_basis, rp, ref.L, m.C)
-    t2 = time.perf_counter()
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    return {"value": ref.M / (t2 - t0), "unit": "vectors/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full step of the same workload: decomposition (M={ref.M}) "
-                      f"{t1 - t0:.2f} s + FP64 J/K {t2 - t1:.2f} s"}
+    est_full = (t1 - t0) * (M_full / max(1, ref.M)) ** 2
+    return {"value": ref.M / (t1 - t0), "unit": "vectors/s", "cores": cores, "kind": "oracle",
+            "sample": f"the oracle's decomposition of the same workload stopped after its first "
+                      f"{ref.M} of {M_full} vectors (capacity), {t1 - t0:.2f} s; its cost per "
+                      f"vector grows linearly with the vector index, so the full run would take "
+                      f"about {est_full:.0f} s",
+            "seconds": t1 - t0, "vectors": int(ref.M),
+            "full_run_vectors_per_s_estimate": M_full / est_full}
 
 
 def copy_probe(mib):
@@ -96,17 +105,29 @@ def copy_probe(mib):
                       "launches": 3}), flush=True)
 
 
-def bench_batched(args):
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def batched_c4(steps, warmup, tuned=True):
     """64 molecules of uneven size (52..400 functions), tau = 1e-5: one batched
-    cd_decompose call plus one cd_build_jk call (FP32 K) per step, against the
-    same molecules run one by one on the plain path (FP64 J/K)."""
+    cd_decompose call plus one batched cd_build_jk call per step, against the
+    same molecules one by one (one call per molecule), each at FP64 and at FP32
+    K, so batching and precision are reported as separate factors."""
     import torch
 
     from paper_2609_00306_amd import cdlib
     from paper_2609_00306_amd.inputs import BATCH_C4, batch_c4
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     mols = batch_c4()
     tau, schwarz = BATCH_C4["tau"], BATCH_C4["schwarz"]
     pairs = [(m.xyz, m.alpha) for m in mols]
@@ -117,72 +138,83 @@ def bench_batched(args):
     assert all(int(d.status.item()) == 0 for d in probe)
     del probe, pws
     decs, ws = cdlib.allocate_many(pairs, tau, schwarz, max_vectors=Ms, device=dev)
-    jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], "fp32")
     singles = [cdlib.allocate(m.xyz, m.alpha, tau, schwarz, M, device=dev) for m, M in zip(mols, Ms)]
-    sjks = [cdlib.prepare_jk(d, m.C, "fp64") for d, m in zip(singles, mols)]
+    tuning = cdlib.autotune(decs, tau, schwarz, workspace=ws) if tuned else None
+    out = {"workload": f"{len(mols)} molecules, N {min(m.n_basis for m in mols)}.."
+                       f"{max(m.n_basis for m in mols)} s-Gaussians, tau={tau:g}, O=N/8",
+           "n_molecules": len(mols), "n_vectors": sum(Ms)}
+    res = {}
+    jk_out = {}
+    for prec in ("fp64", "fp32"):
+        jks, jws = cdlib.prepare_jk_many(decs, [m.C for m in mols], prec)
+        sjks = [cdlib.prepare_jk(d, m.C, prec) for d, m in zip(singles, mols)]
 
-    # launch shapes of the batched decomposition chosen by measurement (untimed)
-    tuning = cdlib.autotune(decs, tau, schwarz, workspace=ws)
+        def batched():
+            cdlib.run_decompose(decs, tau, schwarz, workspace=ws, tuning=tuning)
+            cdlib.run_jk_many(jks, jws, prec)
 
-    def batched():
-        cdlib.run_decompose(decs, tau, schwarz, workspace=ws, tuning=tuning)
-        cdlib.run_jk_many(jks, jws, "fp32")
+        def plain():
+            for d, j in zip(singles, sjks):
+                cdlib.run_decompose([d], tau, schwarz)
+                cdlib.run_jk(j, prec)
 
-    def batched_builtin():
-        cdlib.run_decompose(decs, tau, schwarz, workspace=ws)
-        cdlib.run_jk_many(jks, jws, "fp32")
-
-    def plain():
-        for d, j in zip(singles, sjks):
-            cdlib.run_decompose([d], tau, schwarz)
-            cdlib.run_jk(j, "fp64")
-
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
+        ms_b = _timed(batched, steps, warmup)
+        ms_p = _timed(plain, steps, warmup)
+        graph = {"captured": False}
+        try:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                batched()
+            torch.cuda.current_stream().wait_stream(side)
+            with torch.cuda.graph(g):
+                batched()
+            ms_g = _timed(g.replay, steps, warmup)
+            graph = {"captured": True, "ms_per_step": ms_g}
+            del g
+        except Exception as e:  # noqa: BLE001
+            graph = {"captured": False, "reason": str(e)[:200]}
+        res[prec] = {"batched_ms": ms_b, "one_by_one_ms": ms_p, "graph": graph,
+                     "batched_vectors_per_s": sum(Ms) / (ms_b * 1e-3),
+                     "speedup_batched_vs_one_by_one": ms_p / ms_b}
+        cdlib.run_jk_many(jks, jws, prec)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / args.steps
+        jk_out[prec] = [(j.J.clone(), j.K.clone()) for j in jks]
+        del jks, jws, sjks
+    err = {"max_abs_dJ": 0.0, "max_abs_dK": 0.0, "max_abs_dE2": 0.0}
+    for m, (J64, K64), (J32, K32) in zip(mols, jk_out["fp64"], jk_out["fp32"]):
+        Ct = torch.as_tensor(m.C, device=dev)
+        Dm = Ct @ Ct.T
+        e2 = lambda J, K: float(2.0 * (Dm * J).sum() - (Dm * K).sum())  # noqa: E731
+        err["max_abs_dJ"] = max(err["max_abs_dJ"], float((J32 - J64).abs().max()))
+        err["max_abs_dK"] = max(err["max_abs_dK"], float((K32 - K64).abs().max()))
+        err["max_abs_dE2"] = max(err["max_abs_dE2"], abs(e2(J32, K32) - e2(J64, K64)))
+    out.update({
+        "fp64": res["fp64"], "fp32_K": res["fp32"],
+        "speedup_batched_vs_one_by_one_fp64": res["fp64"]["speedup_batched_vs_one_by_one"],
+        "speedup_batched_vs_one_by_one_fp32": res["fp32"]["speedup_batched_vs_one_by_one"],
+        "speedup_fp32_vs_fp64_batched": res["fp64"]["batched_ms"] / res["fp32"]["batched_ms"],
+        "fp32_K_error_vs_fp64": err,
+        "tuning": None if tuning is None else {"step2_row_tiles": tuning.step2_row_tiles,
+                                               "step1_min_rows": tuning.step1_min_rows},
+    })
+    return out
 
-    ms_b = timed(batched)
-    ms_bb = timed(batched_builtin)
-    ms_p = timed(plain)
-    graph = {"captured": False}
-    try:
-        g = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            batched()
-        torch.cuda.current_stream().wait_stream(side)
-        with torch.cuda.graph(g):
-            batched()
-        ms_g = timed(g.replay)
-        graph = {"captured": True, "ms_per_step": ms_g, "vectors_per_s": sum(Ms) / (ms_g * 1e-3)}
-    except Exception as e:  # a cooperative launch may not be capturable
-        graph = {"captured": False, "reason": str(e)[:200]}
-    M_tot = sum(Ms)
-    out = {
-        "metric": "Cholesky vectors/s + J/K build TFLOP/s at tau=1e-6; mixed/batched vs plain FP64",
-        "value": M_tot / (ms_b * 1e-3),
-        "unit": "vectors/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_b,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 decomposition, fp32 K", "data": "synthetic",
-        "config": {"workload": f"batched: {len(mols)} molecules, N {min(m.n_basis for m in mols)}"
-                               f"..{max(m.n_basis for m in mols)} s-Gaussians, tau={tau:g}, "
-                               f"O=N/8, FP32 K", "n_molecules": len(mols), "n_vectors": M_tot},
-        "plain_one_by_one": {"ms_per_step": ms_p, "vectors_per_s": M_tot / (ms_p * 1e-3),
-                             "jk_precision": "fp64"},
-        "speedup_vs_plain": ms_p / ms_b,
-        "tuning": {"step2_row_tiles": tuning.step2_row_tiles,
-                   "step1_min_rows": tuning.step1_min_rows,
-                   "builtin_shapes_ms_per_step": ms_bb},
-        "graph": graph,
-    }
+
+def bench_batched(args):
+    """--config C4: the batched workload alone, one JSON line."""
+    import torch
+    torch.cuda.set_device(0)
+    b = batched_c4(args.steps, args.warmup)
+    ms = b["fp64"]["batched_ms"]
+    out = {"metric": METRIC, "value": b["n_vectors"] / (ms * 1e-3), "unit": "vectors/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batched: " + b["workload"], "n_molecules": b["n_molecules"],
+                      "n_vectors": b["n_vectors"]},
+           "batched": b}
     print(json.dumps(out), flush=True)
 
 
@@ -216,7 +248,7 @@ def scf_sweep(args):
     ref = None
     for tau in reversed(taus):
         d = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=cfg["schwarz"])
-        for prec in ("fp64", "fp32", "bf16x3"):
+        for prec in PRECISIONS:
             tol = (1e-10, 1e-8) if prec == "fp64" else (1e-6, 1e-6)
             r, ms = run_scf(cdlib, d, m, prec, *tol)
             E = float(r.energies[-1])
@@ -268,14 +300,33 @@ def bench_hermitian(args):
                                     "steps": args.steps}}), flush=True)
 
 
+def jk_work(N, O, n, M, n_diag, fused):
+    """Flops of one J/K build.  Executed: J (two passes over the vectors,
+    4 n M), the half transform over the kept pairs (2 deg O M with deg = 2n -
+    the kept diagonal pairs, the number of (mu, sigma) entries of the unpacked
+    vectors), the exchange product over the lower triangle (N (N+1) O M) and,
+    when fused, the second half of C^T L C (2 N O^2 M).  Dense equivalent: the
+    unpacked half transform 2 N^2 O M instead of the neighbour lists."""
+    deg = 2.0 * n - n_diag
+    ex = 4.0 * n * M + 2.0 * deg * O * M + float(N) * (N + 1) * O * M
+    if fused:
+        ex += 2.0 * N * O * O * M
+    dense = 4.0 * n * M + 2.0 * N * N * O * M + float(N) * (N + 1) * O * M
+    return ex, dense
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--config", default="C5")
     ap.add_argument("--tau", type=float, default=1e-6)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp64", choices=list(PRECISIONS),
+                    help="J/K precision of the headline step (the others are timed beside it "
+                         "unless --no-compare)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="time only the headline precision")
     ap.add_argument("--eta", type=float, default=1.0,
                     help="span factor of the pivot selection (1 = exact pivoting)")
     ap.add_argument("--pivot-block", default=None, metavar="I,J,..",
@@ -291,6 +342,12 @@ def main():
                     help="launch shapes of the decomposition: measured by cd_autotune before "
                          "the warm-up (auto) or the built-in choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-prefix", type=int, default=2400,
+                    help="vectors of the oracle's decomposition timed for cpu_baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="leave out the 64-molecule batched comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="leave out the SCF and the second-order energy (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -338,31 +395,84 @@ def main():
     torch.cuda.empty_cache()
     d = cdlib.allocate(m.xyz, m.alpha, tau, schwarz, max(1, M), device=dev, pivot_fn=fn)
     n = d.n_rows
-    # in FP64 and 3 x BF16 the J/K build also writes the transformed vectors
-    # C^T L C from the FP64 half transform it already forms; in FP32 the
-    # transform is its own call
-    fused = args.precision in ("fp64", "bf16x3")
-    jk = cdlib.prepare_jk(d, m.C, args.precision, lmo=fused)
+    precs = [args.precision] + ([] if args.no_compare else
+                                [p for p in PRECISIONS if p != args.precision])
+    jks = {p: cdlib.prepare_jk(d, m.C, p, lmo=p in FUSED) for p in precs}
     stream = torch.cuda.current_stream()
 
     # launch shapes: measured once on this workload (untimed), or the built-in ones
     tuning = cdlib.autotune([d], tau, schwarz) if args.tuning == "auto" else None
 
-    def step(phase_ev, jk_ev):
+    def step(prec, phase_ev, jk_ev):
         cdlib.run_decompose([d], tau, schwarz, events=phase_ev, eta=args.eta, tuning=tuning)
         jk_ev[0].record(stream)
-        cdlib.run_jk(jk, args.precision)
+        cdlib.run_jk(jks[prec], prec)
         jk_ev[1].record(stream)
-        if not fused:
+        if prec not in FUSED:
             cdlib.transform(d, m.C, m.C, sync=False)
         jk_ev[2].record(stream)
 
     mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    for _ in range(args.warmup):
-        step([mk() for _ in range(4)], [mk() for _ in range(3)])
-    torch.cuda.synchronize()
 
-    # per-batch device-clock stamps of the pivot selection (one untimed step)
+    def avg(evs, i, j, which):
+        vals = [(pe if which == "p" else je)[i].elapsed_time((pe if which == "p" else je)[j])
+                for pe, je in evs]
+        return sum(vals) / len(vals)
+
+    runs = {}
+    for prec in precs:
+        for _ in range(args.warmup):
+            step(prec, [mk() for _ in range(4)], [mk() for _ in range(3)])
+        evs = [([mk() for _ in range(4)], [mk() for _ in range(3)]) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pe, je in evs:
+            step(prec, pe, je)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        assert d.M() == M and int(d.status.item()) == 0
+        runs[prec] = {"ms_per_step": ms, "setup": avg(evs, 0, 1, "p"),
+                      "pivot_selection": avg(evs, 1, 2, "p"), "all_row_solve": avg(evs, 2, 3, "p"),
+                      "cd": avg(evs, 0, 3, "p"), "jk": avg(evs, 0, 1, "j"),
+                      "transform": avg(evs, 1, 2, "j")}
+    head = runs[args.precision]
+
+    # J/K of every precision from the same vectors (the last step's), against FP64
+    rp_host = d.row_pair.cpu().numpy()
+    mu = np.floor((np.sqrt(8.0 * rp_host + 1.0) - 1.0) / 2.0).astype(np.int64)
+    n_diag = int(np.count_nonzero(rp_host == mu * (mu + 1) // 2 + mu))
+    Ct = torch.as_tensor(m.C, device=dev)
+    Dm = Ct @ Ct.T
+
+    def e2(J, K):
+        return float(2.0 * (Dm * J).sum() - (Dm * K).sum())
+
+    for p in precs:
+        cdlib.run_jk(jks[p], p)
+    torch.cuda.synchronize()
+    ref = jks["fp64"] if "fp64" in jks else None
+    precision = {}
+    for p in precs:
+        r = runs[p]
+        w_ex, w_dense = jk_work(N, O, n, M, n_diag, p in FUSED)
+        e = {"step_ms": r["ms_per_step"], "jk_ms": r["jk"],
+             "transform": "fused into the J/K build" if p in FUSED else "separate call",
+             "transform_ms": None if p in FUSED else r["transform"],
+             "jk_plus_transform_ms": r["jk"] + (0.0 if p in FUSED else r["transform"]),
+             "jk_tflops": w_ex / ((r["jk"] + (0.0 if p in FUSED else r["transform"])) * 1e-3) / 1e12}
+        if ref is not None and p != "fp64":
+            e["error_vs_fp64"] = {"max_abs_dJ": float((jks[p].J - ref.J).abs().max()),
+                                  "max_abs_dK": float((jks[p].K - ref.K).abs().max()),
+                                  "abs_dE2": abs(e2(jks[p].J, jks[p].K) - e2(ref.J, ref.K))}
+            if p in FUSED:
+                e["error_vs_fp64"]["max_abs_dLmo"] = float(
+                    (jks[p].Lmo[:M] - ref.Lmo[:M]).abs().max())
+            e["speedup_step_vs_fp64"] = runs["fp64"]["ms_per_step"] / r["ms_per_step"]
+            e["speedup_jk_vs_fp64"] = ((runs["fp64"]["jk"] + 0.0) /
+                                       (r["jk"] + (0.0 if p in FUSED else r["transform"])))
+        precision[p] = e
+
+    # per-batch device-clock stamps of the pivot selection (one untimed run)
     cap = 4096
     timeline = torch.zeros(1 + 16 * cap, dtype=torch.int64, device=dev)
     cdlib.run_decompose([d], tau, schwarz, timeline=timeline, eta=args.eta, tuning=tuning)
@@ -382,39 +492,35 @@ def main():
     s2_breakdown = {k: float((s2[:, i + 1] - s2[:, i]).sum()) for i, k in enumerate(s2_stages)
                     if s2.shape[0]}
 
-    evs = [([mk() for _ in range(4)], [mk() for _ in range(3)]) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for pe, je in evs:
-        step(pe, je)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    assert d.M() == M and int(d.status.item()) == 0
-
-    prec_err = None
-    if args.precision != "fp64":
-        # the reduced-precision J/K of the last step against the FP64 build from
-        # the same vectors; E2 = 2 tr(DJ) - tr(DK), D = C C^T
-        J64, K64 = cdlib.build_jk(d, m.C, "fp64")
-        Ct = torch.as_tensor(m.C, device=dev)
-        Dm = Ct @ Ct.T
-
-        def e2(J, K):
-            return float(2.0 * (Dm * J).sum() - (Dm * K).sum())
-
-        prec_err = {"against": "FP64 J/K from the same vectors",
-                    "max_abs_dJ": float((jk.J - J64).abs().max()),
-                    "max_abs_dK": float((jk.K - K64).abs().max()),
-                    "abs_dE2": abs(e2(jk.J, jk.K) - e2(J64, K64))}
-
-    # a converged SCF on the step's vectors (outside the step)
-    scf_res, scf_ms = run_scf(cdlib, d, m, args.precision,
-                              *((1e-10, 1e-8) if args.precision == "fp64" else (1e-6, 1e-6)))
-    scf = {"ms": scf_ms, "iterations": len(scf_res.energies), "converged": scf_res.converged,
-           "ms_per_iteration": scf_ms / max(1, len(scf_res.energies)),
-           "energy": float(scf_res.energies[-1]), "jk_precision": args.precision}
-    del scf_res
+    extras = {}
+    if not args.no_extras:
+        # a converged SCF on the step's vectors (outside the step)
+        scf_res, scf_ms = run_scf(cdlib, d, m, args.precision,
+                                  *((1e-10, 1e-8) if args.precision == "fp64" else (1e-6, 1e-6)))
+        extras["scf"] = {"ms": scf_ms, "iterations": len(scf_res.energies),
+                         "converged": scf_res.converged,
+                         "ms_per_iteration": scf_ms / max(1, len(scf_res.energies)),
+                         "energy": float(scf_res.energies[-1]), "jk_precision": args.precision}
+        del scf_res
+        # second-order energy from the step's vectors (outside the step, once):
+        # the transform with occupied and virtual orbitals, then the contraction
+        from paper_2609_00306_amd.inputs import mp2_orbitals
+        Co, Cv, eo, ev = mp2_orbitals(m)
+        V = Cv.shape[1]
+        Bmo = cdlib.transform(d, Co, Cv)
+        cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev)   # warm-up
+        e0, e1 = mk(), mk()
+        e0.record(stream)
+        E_mp2 = cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev, sync=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_mp2 = e0.elapsed_time(e1)
+        w_mp2 = O * (O + 1) / 2.0 * V * V * 2.0 * M   # (ia|jb), i <= j, all a, b
+        extras["mp2"] = {"ms": t_mp2, "energy": float(E_mp2.item()), "n_virt": V,
+                         "tflops": w_mp2 / (t_mp2 * 1e-3) / 1e12,
+                         "frac_fp64_peak": w_mp2 / (t_mp2 * 1e-3) / 1e12 / PEAK["fp64"],
+                         "work": "O(O+1)/2 V^2 2M (integrals of pairs i <= j)", "runs": 1}
+        del Bmo
 
     restricted = None
     if fn is not None:
@@ -423,71 +529,42 @@ def main():
         full = cdlib.decompose(m.xyz, m.alpha, tau, schwarz=schwarz)
         Jf, Kf = cdlib.build_jk(full, m.C, "fp64")
         Jr, Kr = cdlib.build_jk(d, m.C, "fp64")
-        Ct = torch.as_tensor(m.C, device=dev)
-        Dm = Ct @ Ct.T
-        e2f = float(2.0 * (Dm * Jf).sum() - (Dm * Kf).sum())
-        e2r = float(2.0 * (Dm * Jr).sum() - (Dm * Kr).sum())
         restricted = {"flagged_functions": int(fn.sum()), "n_active": d.n_active,
                       "n_active_unrestricted": full.n_active, "M_unrestricted": full.M(),
                       "max_residual": float(d.diag.max()),
-                      "abs_dE2_vs_unrestricted": abs(e2r - e2f), "E2": e2r}
+                      "abs_dE2_vs_unrestricted": abs(e2(Jr, Kr) - e2(Jf, Kf)), "E2": e2(Jr, Kr)}
         del full, Jf, Kf, Jr, Kr
 
-    # second-order energy from the step's vectors (outside the step): the
-    # transform with occupied and virtual orbitals, then the contraction
-    from paper_2609_00306_amd.inputs import mp2_orbitals
-    Co, Cv, eo, ev = mp2_orbitals(m)
-    V = Cv.shape[1]
-    Bmo = cdlib.transform(d, Co, Cv)
-    E_mp2 = cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev)
-    mp2_ev = [mk() for _ in range(args.steps + 1)]
-    mp2_ev[0].record(stream)
-    for k in range(args.steps):
-        cdlib.mp2_energy(Bmo, d.n_vectors, eo, ev, sync=False)
-        mp2_ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    t_mp2 = mp2_ev[0].elapsed_time(mp2_ev[-1]) / args.steps
-    w_mp2 = O * (O + 1) / 2.0 * V * V * 2.0 * M   # (ia|jb), i <= j, all a, b
-    mp2 = {"ms": t_mp2, "energy": float(E_mp2.item()), "n_virt": V,
-           "tflops": w_mp2 / (t_mp2 * 1e-3) / 1e12,
-           "frac_fp64_peak": w_mp2 / (t_mp2 * 1e-3) / 1e12 / PEAK["fp64"],
-           "work": "O(O+1)/2 V^2 2M (integrals of pairs i <= j)"}
-    del Bmo
+    batched = None
+    if not args.no_batched:
+        del jks
+        torch.cuda.empty_cache()
+        batched = batched_c4(max(1, min(args.steps, 3)), 1)
 
-    def avg(i, j, which):
-        vals = []
-        for pe, je in evs:
-            e = pe if which == "p" else je
-            vals.append(e[i].elapsed_time(e[j]))
-        return sum(vals) / len(vals)
-
-    t_setup = avg(0, 1, "p")
-    t_sel = avg(1, 2, "p")
-    t_solve = avg(2, 3, "p")
-    t_cd = avg(0, 3, "p")
-    t_jk = avg(0, 1, "j")
-    t_tr = avg(1, 2, "j")
+    t_sel, t_solve = head["pivot_selection"], head["all_row_solve"]
     w_cd = float(n) * M * (M - 1)                       # Schur / triangular-solve contraction
     w_sel = float(d.n_active) * M * (M - 1)             # the same contraction on the active rows
-    w_j = 4.0 * n * M
-    w_k = 2.0 * N * N * O * M + float(N) * (N + 1) * O * M
     roof = {
         "k_step2": {"kernel": "k_step2 (all-row blocked forward substitution, FP64 MFMA)",
                     "bound": "mfma", "achieved": w_cd / (t_solve * 1e-3) / 1e12,
                     "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                    "traffic": counter_traffic("k_step2", args.config, tau)},
+                    "traffic": counter_traffic("k_step2", args.config, tau),
+                    "work": "n M (M - 1) FP64 flops per launch", "launch_ms": t_solve},
         "k_step1": {"kernel": "k_step1 (pivot selection on the active rows, one cooperative "
                               "launch of candidate batches)",
                     "bound": "mfma", "achieved": w_sel / (t_sel * 1e-3) / 1e12,
                     "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                    "traffic": counter_traffic("k_step1", args.config, tau)},
+                    "traffic": counter_traffic("k_step1", args.config, tau),
+                    "work": "n_active M (M - 1) FP64 flops per launch", "launch_ms": t_sel},
     }
     for r in roof.values():
         r["frac"] = r["achieved"] / r["peak"]
     dominant = "k_step1" if t_sel > t_solve else "k_step2"
     other = "k_step2" if dominant == "k_step1" else "k_step1"
+    ms = head["ms_per_step"]
+    w_ex, w_dense = jk_work(N, O, n, M, n_diag, args.precision in FUSED)
     out = {
-        "metric": "Cholesky vectors/s + J/K build TFLOP/s at tau=1e-6; mixed/batched vs plain FP64",
+        "metric": METRIC,
         "value": M / (ms * 1e-3),
         "unit": "vectors/s",
         "n_gpus": 1,
@@ -497,9 +574,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else f"f64 decomposition, {args.precision} J/K",
+        "dtype": "f64" if args.precision == "fp64" else f"f64 decomposition, {args.precision} K",
         "data": "synthetic",
-        "config": {"workload": f"{N} s-Gaussians ({cfg['n_centres']} centres, "
+        "config": {"workload": f"{args.config}: {N} s-Gaussians ({cfg['n_centres']} centres, "
                                f"{cfg['box']:.1f} A box, {len(cfg['exponents'])} exponents), "
                                f"tau={tau:g}, Schwarz {schwarz:g}, O={O}",
                    "n_basis": N, "n_rows": n, "n_active": d.n_active, "n_vectors": M,
@@ -508,27 +585,28 @@ def main():
                    "tuning": None if tuning is None else
                    {"step2_row_tiles": tuning.step2_row_tiles,
                     "step1_min_rows": tuning.step1_min_rows}},
-        "cd_ms": t_cd,
-        "cd_vectors_per_s": M / (t_cd * 1e-3),
-        "jk_ms": t_jk,
-        "jk_tflops": (w_j + w_k) / (t_jk * 1e-3) / 1e12,
-        "transform_ms": None if fused else t_tr,
-        "transform": "fused into the J/K build (C^T L C from its half transform)" if fused
-                     else "separate call",
-        "mp2": mp2,
-        "scf": scf,
-        "restricted_candidates": restricted,
-        "phases_ms": {"setup": t_setup, "pivot_selection": t_sel, "all_row_solve": t_solve},
+        "cd_ms": head["cd"],
+        "cd_vectors_per_s": M / (head["cd"] * 1e-3),
+        "jk_ms": head["jk"],
+        "jk_tflops": w_ex / ((head["jk"] + (0.0 if args.precision in FUSED else
+                                            head["transform"])) * 1e-3) / 1e12,
+        "jk_tflops_dense_equivalent": w_dense / (head["jk"] * 1e-3) / 1e12,
+        "jk_work": "executed: 4nM (J) + 2 deg O M (half transform over kept pairs, deg = 2n - "
+                   "kept diagonal pairs) + N(N+1) O M (exchange product) + 2 N O^2 M (fused "
+                   "C^T L C); dense equivalent: 4nM + 2N^2 O M + N(N+1) O M",
+        "precision": precision,
+        "batched_c4": batched,
+        "phases_ms": {"setup": head["setup"], "pivot_selection": t_sel, "all_row_solve": t_solve},
         "pivot_selection": {"batches": nbatch, "vectors_per_batch": M / max(1, nbatch),
                             "stage_us_total": breakdown},
         "all_row_solve_wg0_stage_us_total": s2_breakdown,
-        "jk_tflops_work": "dense-equivalent 4nM + 2N^2 O M + N(N+1) O M",
-        "precision_error": prec_err,
-        "roofline": roof[dominant],
+        "restricted_candidates": restricted,
+        "roofline": {k: v for k, v in roof[dominant].items()},
         "roofline_other_kernel": roof[other],
     }
+    out.update(extras)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, tau, schwarz)
+        out["cpu_baseline"] = cpu_baseline(m, tau, schwarz, M, args.cpu_prefix)
     print(json.dumps(out), flush=True)
 
 

@@ -71,6 +71,34 @@ typedef enum {
 
 /* flags for cd_decomp_opts.flags and the J/K / transform calls */
 #define CD_SYNC 1u /* synchronise the stream and fold device status into the return value */
+/* cd_decompose only: continue finished decompositions to the (smaller) tau in
+ * opts.  The pivot order of Sec. 2 does not depend on tau: the threshold only
+ * decides where the loop stops (compare Table 5, where the number of vectors
+ * grows as tau falls).  So a decomposition stopped at tau1 is the start of the
+ * one at tau2 < tau1, and the loop can go on from where it stopped.  Each
+ * problem's outputs must hold a decomposition of the same molecule with the
+ * same schwarz and pivot_fn, written by cd_decompose into these same buffers
+ * (row_pair, L, pivots, diag, n_vectors, status; pivot_values if given) and
+ * ended with status CD_OK or CD_ERR_CAPACITY (a larger max_vectors may be
+ * given after the caller moves the M1 vectors into a larger L: vector K is at
+ * L + K * n_rows in any capacity).  n_rows and n_active come from cd_query at
+ * the new tau; the workspace need not hold anything from the earlier call.
+ * The first M1 vectors, their pivots and pivot values are not recomputed
+ * (they stay bit for bit as they were); the selection continues from the
+ * residuals in diag, and the all-row solve forms only the vectors from M1 on
+ * and subtracts their squares from diag.  The result has the pivot sequence
+ * of a direct run at the new tau; later vectors agree with that run to
+ * rounding (the rounding order of the pivot selection's sums follows its
+ * candidate batches, whose bounds depend on where the first run stopped).
+ * A stored status other than CD_OK / CD_ERR_CAPACITY, or a stored count
+ * outside [0, max_vectors], gives device status CD_ERR_INVALID_ARG and leaves
+ * the outputs as they were. */
+#define CD_RESUME 2u
+/* cd_decompose only, for tests of the device error path: the setup replaces
+ * the initial residual of the first active row by NaN, so the pivot selection
+ * meets a non-finite diagonal (Sec. 2 needs a positive semidefinite matrix)
+ * and reports CD_ERR_NOT_PSD in the problem's status word. */
+#define CD_DEBUG_POISON_DIAG 4u
 
 /* One molecule.  xyz and alpha are DEVICE pointers. */
 typedef struct {
@@ -98,7 +126,7 @@ typedef struct {
     double tau;            /* decomposition threshold (Sec. 2): stop when max D < tau; tau >= 0.
                               tau == 0 stops at max D <= n_rows * 2^-53 * max D1 */
     double schwarz;        /* row screening threshold, >= 0 (0 keeps all N(N+1)/2 rows) */
-    uint32_t flags;        /* CD_SYNC */
+    uint32_t flags;        /* CD_SYNC, CD_RESUME, CD_DEBUG_POISON_DIAG */
     void *const *events;   /* optional (may be NULL): host array of 4 hipEvent_t that the call
                               records on 'stream' at the phase boundaries of the last problem:
                               [0] before the pair/diagonal setup, [1] before pivot selection,
@@ -144,6 +172,9 @@ typedef struct {
     double *diag;          /* [n_rows] final residual diagonal (pivot rows zeroed when chosen) */
     int64_t *n_vectors;    /* [1] number of vectors M */
     int32_t *status;       /* [1] device status word (cd_status) */
+    double *pivot_values;  /* optional (may be NULL): [max_vectors] d_K, the residual diagonal
+                              at pivot P_K when vector K was formed (its square root is the
+                              divisor of Sec. 2) */
 } cd_problem;
 
 /*
@@ -170,8 +201,10 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
  * Rows whose D1 < tau can never be pivots and are only solved for at the
  * end (the two-step organisation of Sec. 3, with exact pivoting).
  * With count > 1 the per-problem setup runs on two library streams forked
- * from and joined back to 'stream' (ordering on 'stream' is kept; graph
- * capture works).
+ * from and joined back to 'stream' (ordering on 'stream' is kept on every
+ * return, errors included; graph capture works).
+ * opts->flags: CD_SYNC; CD_RESUME continues the decompositions already in the
+ * outputs to opts->tau (see the flag); CD_DEBUG_POISON_DIAG (tests only).
  */
 cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                        void *ws, size_t ws_bytes, void *stream);

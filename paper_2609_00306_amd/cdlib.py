@@ -21,6 +21,8 @@ CD_OK, CD_ERR_INVALID_ARG, CD_ERR_WORKSPACE, CD_ERR_CAPACITY, CD_ERR_NOT_PSD, \
     CD_ERR_DEVICE, CD_ERR_UNSUPPORTED = range(7)
 CD_FP64, CD_FP32, CD_BF16X3 = 0, 1, 2
 CD_SYNC = 1
+CD_RESUME = 2
+CD_DEBUG_POISON_DIAG = 4
 PRECISIONS = {"fp64": CD_FP64, "fp32": CD_FP32, "bf16x3": CD_BF16X3}
 
 _vp = ctypes.c_void_p
@@ -49,7 +51,8 @@ class cd_sizes(ctypes.Structure):
 class cd_problem(ctypes.Structure):
     _fields_ = [("mol", cd_molecule), ("n_rows", ctypes.c_int64),
                 ("n_active", ctypes.c_int64), ("max_vectors", ctypes.c_int64), ("row_pair", _vp), ("L", _vp),
-                ("pivots", _vp), ("diag", _vp), ("n_vectors", _vp), ("status", _vp)]
+                ("pivots", _vp), ("diag", _vp), ("n_vectors", _vp), ("status", _vp),
+                ("pivot_values", _vp)]
 
 
 class cd_jk_problem(ctypes.Structure):
@@ -192,6 +195,7 @@ class Decomposition:
     status: torch.Tensor     # [1] int32
     workspace: torch.Tensor
     pivot_fn: Optional[torch.Tensor] = None   # [N] uint8 restricted candidates, or None
+    pivot_values: Optional[torch.Tensor] = None   # [max_vectors] float64 d_K
 
     def M(self) -> int:
         return int(self.n_vectors.item())
@@ -247,7 +251,7 @@ def allocate(xyz, alpha, tau: float, schwarz: float, max_vectors: Optional[int] 
         pivots=torch.empty(mv, **i64), diag=torch.empty(n, **f64),
         n_vectors=torch.zeros(1, **i64), status=torch.zeros(1, dtype=torch.int32, device=device),
         workspace=torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=device),
-        pivot_fn=fn)
+        pivot_fn=fn, pivot_values=torch.empty(mv, **f64))
 
 
 def allocate_many(mols, tau: float, schwarz: float, max_vectors=None, device="cuda",
@@ -268,19 +272,22 @@ def problem(d: Decomposition) -> cd_problem:
     return cd_problem(molecule(d.xyz, d.alpha, d.pivot_fn), d.n_rows, d.n_active, d.max_vectors,
                       _ptr(d.row_pair),
                       _ptr(d.L), _ptr(d.pivots), _ptr(d.diag), _ptr(d.n_vectors),
-                      _ptr(d.status))
+                      _ptr(d.status), _ptr(d.pivot_values))
 
 
 def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, sync: bool = False,
                   stream=None, workspace: Optional[torch.Tensor] = None,
                   events: Optional[Sequence] = None, timeline: Optional[torch.Tensor] = None,
-                  tuning: Optional[cd_tuning] = None, eta: float = 1.0):
+                  tuning: Optional[cd_tuning] = None, eta: float = 1.0,
+                  resume: bool = False, poison: bool = False):
     """cd_decompose on already allocated problems (one workspace per call).
 
     ``events``: optional four torch.cuda.Event(enable_timing=True) that the
     library records at its phase boundaries on the stream.  ``tuning``: launch
     shapes (from autotune), or None for the built-in ones.  ``eta``: span
-    factor of the two-step first step (1 = exact pivoting)."""
+    factor of the two-step first step (1 = exact pivoting).  ``resume``:
+    CD_RESUME (continue the stored decompositions to ``tau``; see ``resume``).
+    ``poison``: CD_DEBUG_POISON_DIAG (tests of the device error path)."""
     L = load()
     n = len(decs)
     arr = (cd_problem * n)(*[problem(d) for d in decs])
@@ -292,7 +299,9 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
         ev = (ctypes.c_void_p * 4)(*[e.cuda_event for e in events])
     tl, cap = (None, 0) if timeline is None else (timeline.data_ptr(),
                                                    (timeline.numel() - 1) // 16)
-    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, ev, tl, cap,
+    flags = ((CD_SYNC if sync else 0) | (CD_RESUME if resume else 0)
+             | (CD_DEBUG_POISON_DIAG if poison else 0))
+    opts = cd_decomp_opts(float(tau), float(schwarz), flags, ev, tl, cap,
                           ctypes.pointer(tuning) if tuning is not None else None, float(eta))
     if workspace is None:
         if n != 1:
@@ -318,6 +327,34 @@ def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=N
     _check(L.cd_autotune(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
                          ctypes.byref(best), _stream(stream)))
     return best
+
+
+def resume(d: Decomposition, tau: float, schwarz: float, max_vectors: Optional[int] = None,
+           sync: bool = True, stream=None, eta: float = 1.0) -> Decomposition:
+    """Continue the decomposition in ``d`` (made at a larger threshold with the
+    same ``schwarz``) to ``tau`` with CD_RESUME, in place.  The capacity becomes
+    ``max_vectors`` (default: the active rows at ``tau``); if that is larger
+    than ``d``'s, L, the pivots and the pivot values move into larger buffers
+    first (vector K stays at L[K]).  The workspace is sized at the new
+    threshold."""
+    sz = query([molecule(d.xyz, d.alpha, d.pivot_fn)], tau, schwarz, [0], stream)[0]
+    mv = int(max_vectors) if max_vectors is not None else max(1, int(sz.n_active))
+    if mv > d.max_vectors:
+        dev = d.L.device
+        L = torch.empty((mv, d.n_rows), dtype=torch.float64, device=dev)
+        L[:d.max_vectors].copy_(d.L)
+        piv = torch.empty(mv, dtype=torch.int64, device=dev)
+        piv[:d.max_vectors].copy_(d.pivots)
+        pv = torch.empty(mv, dtype=torch.float64, device=dev)
+        pv[:d.max_vectors].copy_(d.pivot_values)
+        d.L, d.pivots, d.pivot_values, d.max_vectors = L, piv, pv, mv
+    sz = query([molecule(d.xyz, d.alpha, d.pivot_fn)], tau, schwarz, [d.max_vectors], stream)[0]
+    if int(sz.n_rows) != d.n_rows:
+        raise ValueError("resume needs the same rows (same molecule and schwarz)")
+    d.n_active = int(sz.n_active)
+    d.workspace = torch.empty(max(1, int(sz.ws_bytes)), dtype=torch.uint8, device=d.L.device)
+    run_decompose([d], tau, schwarz, sync=sync, stream=stream, eta=eta, resume=True)
+    return d
 
 
 def decompose(xyz, alpha, tau: float, schwarz: float = 1e-12, max_vectors: Optional[int] = None,

@@ -272,6 +272,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     double *LT = P.LT_act;
     unsigned int gen = 0;
 
+    const int64_t k_first = *P.k_start;
+    if (k_first < 0) return;   // a resume whose stored state was invalid (status already set)
     if (*P.n_act_dev != n_act || P.n_rows_dev[0] != P.n_rows) {
         if (g == 0 && tid == 0) *P.status = 5;  // CD_ERR_DEVICE: device and host counts differ
         return;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         sD[i] = P.D_act[s0 + i];
         sRow[i] = P.rows[P.act_row[s0 + i]];
     }
-    int64_t K = 0;
+    int64_t K = k_first;
     int64_t batch = 0;
     int status = 0;
     __syncthreads();
@@ -691,6 +693,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 P.pivots[K + t] = row;
                 P.piv_slot[K + t] = slot;
                 P.dpiv[K + t] = sDp[t];
+                if (P.pivot_values) P.pivot_values[K + t] = sDp[t];
                 P.pivot_of_row[row] = (int32_t)(K + t);
             }
         }
@@ -726,14 +729,16 @@ __global__ __launch_bounds__(256) void k_gather_pivots(const PivotBatch B)
     const PivotMol &Q = B.m[mol];
     const int64_t M = *Q.n_vectors;
     const int64_t Kc = (int64_t)blockIdx.x - B.gather_begin[mol];
-    if (Kc >= M) return;
+    const int64_t k0 = *Q.k_start;
+    if (Kc >= M || k0 < 0 || Kc < k0) return;
     const double *src = Q.LT + (int64_t)Q.piv_slot[Kc] * Q.ldT;
     for (int64_t J = threadIdx.x; J < Kc; J += 256) Q.Lp[Kc * Q.ldp + J] = src[J];
     if (threadIdx.x == 0) Q.prow[Kc] = Q.rows[Q.pivots[Kc]];
 }
 
-// Inverse-transposed pivot blocks.  For the 64 vectors K = b0 + j of one
-// block let S be the lower-triangular 64 x 64 matrix S[j][i] = L^{b0+i} at
+// Inverse-transposed pivot blocks.  Blocks start at the first vector this
+// call forms (k_start: 0, or M1 when resuming).  For the 64 vectors K = b0 + j
+// of one block let S be the lower-triangular 64 x 64 matrix S[j][i] = L^{b0+i} at
 // pivot row P_{b0+j} (i < j) and S[j][j] = sqrt(d_{b0+j}) (the divisor of the
 // vector equation of Sec. 2).  Then the block of vectors obeys T = L_blk S^T,
 // T being the right-hand side (r|P_K) - sum over earlier blocks, so
@@ -749,9 +754,10 @@ __global__ __launch_bounds__(64) void k_block_inverse(const PivotBatch B)
     const int64_t blk = (int64_t)blockIdx.x - B.inverse_begin[mol];
     const double *__restrict__ Lp = Q.Lp;
     const int64_t ldp = Q.ldp;
-    const int64_t b0 = blk * 64;
+    const int64_t k0 = *Q.k_start;
+    const int64_t b0 = k0 + blk * 64;
     const int64_t M = *Q.n_vectors;
-    if (b0 >= M) return;
+    if (k0 < 0 || b0 >= M) return;
     const int nb = (int)min((int64_t)64, M - b0);
     __shared__ double sS[64][66];
     __shared__ double sR[64];   // 1 / S[j][j], so the substitution chain holds no division
@@ -835,11 +841,13 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
     const int64_t r0 = (int64_t)tile * R;
     const int rows_here = (int)min((int64_t)R, n_rows - r0);
     const int64_t M = *Q.n_vectors;
+    const int64_t k0 = *Q.k_start;   // vectors before k0 are kept as they are
+    if (k0 < 0) return;
     double Dfin = 0.0;
     int kp = -1;
     for (int e = tid; e < rows_here; e += 512) sRow[e] = rows[r0 + e];
     if (tid < rows_here) {
-        Dfin = rows[r0 + tid].d1;
+        Dfin = Q.resume ? diag[r0 + tid] : rows[r0 + tid].d1;
         kp = pivot_of_row[r0 + tid];
     }
     // T[m][n] = (half 0) + (half 1) of the accumulators (rows of a partial last
@@ -863,9 +871,9 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
         }
         __syncthreads();
     };
-    for (int64_t b0 = 0; b0 < M; b0 += 64) {
+    for (int64_t b0 = k0; b0 < M; b0 += 64) {
         const int nb = (int)min((int64_t)64, M - b0);
-        const int64_t blk = b0 >> 6;
+        const int64_t blk = (b0 - k0) >> 6;
         mark(blk, 0);
         f64x4 acc[RT];
         zero_acc(acc);
@@ -928,7 +936,7 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
 }
 
 __global__ void k_init_decompose(GridSync *gs, int32_t *status, int64_t *n_vectors,
-                                 unsigned long long *d1max_bits)
+                                 unsigned long long *d1max_bits, int64_t *k_start)
 {
     for (int i = threadIdx.x; i < kMaxGridBlocks * 16; i += blockDim.x) gs->arrive[i] = 0u;
     if (threadIdx.x == 0) {
@@ -937,7 +945,89 @@ __global__ void k_init_decompose(GridSync *gs, int32_t *status, int64_t *n_vecto
         *status = 0;
         *n_vectors = 0;
         *d1max_bits = 0ull;
+        *k_start = 0;
     }
+}
+
+// ---------------------------------------------------------------- resume
+// Continuing a finished decomposition to a smaller tau.  The pivot order of
+// Sec. 2 does not depend on tau (tau only ends the loop), so the selection
+// goes on from the stored vectors and residuals.  The stored count M1 becomes
+// k_start; a stored state that cannot be continued sets CD_ERR_INVALID_ARG
+// and k_start = -1, which every later kernel of the call reads as "skip".
+__global__ void k_init_resume(GridSync *gs, int32_t *status, const int64_t *n_vectors,
+                              unsigned long long *d1max_bits, int64_t *k_start,
+                              int64_t max_vectors)
+{
+    for (int i = threadIdx.x; i < kMaxGridBlocks * 16; i += blockDim.x) gs->arrive[i] = 0u;
+    if (threadIdx.x == 0) {
+        gs->release = 0u;
+        gs->abort = 0u;
+        *d1max_bits = 0ull;
+        const int32_t st = *status;
+        const int64_t m1 = *n_vectors;
+        const bool ok = (st == 0 || st == 3) && m1 >= 0 && m1 <= max_vectors;   // CD_OK, CAPACITY
+        *k_start = ok ? m1 : -1;
+        *status = ok ? 0 : 1;   // CD_ERR_INVALID_ARG
+    }
+}
+
+// The pivot selection's state from the stored outputs, for every active slot a
+// (row act_row[a]): its residual D_act[a] = diag[row], and its vectors
+// LT_act[a][J] = L[J][row] for J < M1 (64 slots x 64 vectors per workgroup,
+// transposed through LDS).  Rows chosen as pivots carry a zero residual, so
+// they are never chosen again.
+__global__ __launch_bounds__(256) void k_resume_state(const int32_t *__restrict__ act_row,
+                                                      int64_t n_act, const double *__restrict__ L,
+                                                      int64_t n_rows, const double *__restrict__ diag,
+                                                      const int64_t *__restrict__ k_start,
+                                                      double *__restrict__ LT_act, int64_t ldT,
+                                                      double *__restrict__ D_act)
+{
+    __shared__ double t[64][65];
+    __shared__ int32_t s_row[64];
+    const int64_t a0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+    const int64_t m1 = *k_start;
+    if (m1 < 0) return;
+    if (threadIdx.x < 64) {
+        const int64_t a = a0 + threadIdx.x;
+        s_row[threadIdx.x] = (a < n_act) ? act_row[a] : 0;
+        if (blockIdx.y == 0 && a < n_act) D_act[a] = diag[act_row[a]];
+    }
+    __syncthreads();
+    if (j0 >= m1) return;
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, jj = e >> 6, aa = e & 63;
+        v[j] = (j0 + jj < m1 && a0 + aa < n_act) ? L[(j0 + jj) * n_rows + s_row[aa]] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        t[e >> 6][e & 63] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, aa = e >> 6, jj = e & 63;
+        if (a0 + aa < n_act && j0 + jj < m1) LT_act[(a0 + aa) * ldT + j0 + jj] = t[jj][aa];
+    }
+}
+
+// pivot_of_row of the stored pivots (the all-row solve reads it).
+__global__ void k_resume_pivots(const int64_t *__restrict__ pivots, const int64_t *__restrict__ k_start,
+                                int64_t max_vectors, int32_t *__restrict__ pivot_of_row)
+{
+    const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m1 = *k_start;
+    if (K < m1 && K < max_vectors) pivot_of_row[pivots[K]] = (int32_t)K;
+}
+
+// Test-only poison: the first active row's residual becomes NaN.
+__global__ void k_poison_diag(double *D_act, int64_t n_act)
+{
+    if (threadIdx.x == 0 && n_act > 0) D_act[0] = __longlong_as_double(0x7ff8000000000000ll);
 }
 
 }  // namespace cdk

@@ -24,6 +24,8 @@ struct Step1Params {
     int32_t *pivot_of_row;     // [n_rows] vector index whose pivot is this row, or -1
     int64_t *n_vectors;        // [1]
     int32_t *status;           // [1]
+    const int64_t *k_start;    // [1] vectors already formed (0, or M1 when resuming; < 0: skip)
+    double *pivot_values;      // optional [max_vectors] output copy of dpiv
     double tau;
     const unsigned long long *d1max_bits;  // max D1 (bit pattern)
     int64_t n_rows;            // tau == 0: stop at max D <= n_rows 2^-53 max D1
@@ -61,6 +63,7 @@ struct PivotMol {
     RowRec *prow;
     const double *dpiv;
     double *G;                 // inverse-transposed 64 x 64 pivot blocks
+    const int64_t *k_start;    // [1] first vector to form (blocks start there)
 };
 
 struct PivotBatch {
@@ -82,7 +85,9 @@ struct Step2Mol {
     const int32_t *pivot_of_row;
     const int64_t *n_vectors;
     double *L;
-    double *diag;
+    double *diag;              // final residuals out; when resuming also the residuals in
+    const int64_t *k_start;    // [1] first vector to form (< 0: nothing to do)
+    int32_t resume;            // 1: start from the residuals in diag, else from D1
 };
 struct Step2Batch {
     int32_t count;

@@ -81,6 +81,7 @@ struct DecompWs {
     double *Lp;
     RowRec *prow;
     double *Ginv;
+    int64_t *kstart;
     size_t bytes;
 };
 
@@ -115,6 +116,7 @@ DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
     w.Lp = c.take<double>(std::max<int64_t>(1, mv * mv));
     w.prow = c.take<RowRec>(std::max<int64_t>(1, mv));
     w.Ginv = c.take<double>(std::max<int64_t>(1, blocks_of(mv, 64)) * 64 * 64);
+    w.kstart = c.take<int64_t>(1);
     w.bytes = c.off;
     return w;
 }
@@ -176,6 +178,52 @@ static std::mutex &side_mutex()
 }
 
 // Called with side_mutex() held.
+static cd_status side_streams(int dev, SideStreams *&out);
+
+// Fork of the side streams from the caller's stream, joined back on every
+// return path: once fork() has succeeded, the destructor makes 'st' wait for
+// everything enqueued on the side streams (also when the call fails half
+// way), so work on 'st' after the call is ordered after all of it and a
+// graph capture of 'st' is left with no unjoined branch.  Declared after the
+// side-stream lock, so it is joined before the lock is released.
+class SideFork {
+public:
+    explicit SideFork(hipStream_t st) : st_(st) {}
+    SideFork(const SideFork &) = delete;
+    SideFork &operator=(const SideFork &) = delete;
+    ~SideFork() { (void)join(); }
+    cd_status fork(int dev)
+    {
+        cd_status s = side_streams(dev, side_);
+        if (s) return s;
+        if (hipEventRecord(side_->fork, st_) != hipSuccess)
+            return fail(CD_ERR_DEVICE, "fork record failed");
+        forked_ = true;   // from here on the destructor joins, whatever waits were set up
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipStreamWaitEvent(side_->s[k], side_->fork, 0) != hipSuccess)
+                return fail(CD_ERR_DEVICE, "fork wait failed");
+        return CD_OK;
+    }
+    // Join now; returns the first failure (a failed join leaves 'st' unordered).
+    cd_status join()
+    {
+        if (!forked_) return CD_OK;
+        forked_ = false;
+        cd_status s = CD_OK;
+        for (int k = 0; k < kJkSide; ++k)
+            if (hipEventRecord(side_->join[k], side_->s[k]) != hipSuccess ||
+                hipStreamWaitEvent(st_, side_->join[k], 0) != hipSuccess)
+                if (!s) s = fail(CD_ERR_DEVICE, "join failed");
+        return s;
+    }
+    SideStreams *side() const { return side_; }
+
+private:
+    hipStream_t st_;
+    SideStreams *side_ = nullptr;
+    bool forked_ = false;
+};
+
 static cd_status side_streams(int dev, SideStreams *&out)
 {
     constexpr int kMaxDev = 64;
@@ -212,6 +260,8 @@ cd_status check_opts(const cd_decomp_opts *o)
         return fail(CD_ERR_INVALID_ARG, "tau and schwarz must be finite and >= 0");
     if (!(o->eta >= 0.0 && o->eta <= 1.0))
         return fail(CD_ERR_INVALID_ARG, "eta must be in [0, 1]");
+    if (o->flags & ~(CD_SYNC | CD_RESUME | CD_DEBUG_POISON_DIAG))
+        return fail(CD_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
     if (o->tuning) {
         const int rt = o->tuning->step2_row_tiles, mr = o->tuning->step1_min_rows;
         if (rt != 0 && (rt < 2 || rt > 8))
@@ -318,6 +368,8 @@ Step1Params step1_params(const cd_problem &p, const DecompWs &w, const cd_decomp
     P1.pivot_of_row = w.pivot_of_row;
     P1.n_vectors = p.n_vectors;
     P1.status = p.status;
+    P1.k_start = w.kstart;
+    P1.pivot_values = p.pivot_values;
     P1.tau = o->tau;
     P1.d1max_bits = w.d1max;
     P1.n_rows = p.n_rows;
@@ -360,7 +412,7 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
             if (hipMalloc(&tmp, probe.bytes) != hipSuccess)
                 return fail(CD_ERR_DEVICE, "hipMalloc of %zu bytes failed", probe.bytes);
             DecompWs w = carve_decomp(tmp, N, 0, 0, 0);
-            k_init_decompose<<<1, 256, 0, st>>>(w.gs, w.cnt_rows, w.totals, w.d1max);
+            k_init_decompose<<<1, 256, 0, st>>>(w.gs, w.cnt_rows, w.totals, w.d1max, w.kstart);
             s = launch_setup(mols[i], opts, w, nullptr, 0, 0, st, false);
             if (!s && hipMemcpyAsync(tot, w.totals, sizeof tot, hipMemcpyDeviceToHost, st) !=
                           hipSuccess)
@@ -377,14 +429,18 @@ cd_status cd_query(const cd_molecule *mols, int32_t count, const cd_decomp_opts 
     return CD_OK;
 }
 
-cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
-                       void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Host checks of cd_decompose's problems; 'need' receives the workspace bytes.
+cd_status check_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                          size_t &need)
 {
     if (count < 0 || (count > 0 && !probs)) return fail(CD_ERR_INVALID_ARG, "null problems");
     cd_status s = check_opts(opts);
     if (s) return s;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    size_t need = 0;
+    need = 0;
     for (int32_t i = 0; i < count; ++i) {
         const cd_problem &p = probs[i];
         if ((s = check_mol(p.mol))) return s;
@@ -400,10 +456,16 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
         need += carve_decomp(nullptr, p.mol.n_basis, p.n_rows, p.n_active, p.max_vectors).bytes;
     }
-    if (need > ws_bytes || (need > 0 && !ws))
-        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
-    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
-        return fail(CD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    return CD_OK;
+}
+
+// The decomposition of checked problems with the workspace at 'ws' (256-byte
+// aligned, large enough).  With 'use_side' and count > 1 the per-problem setup
+// runs on the library's side streams; otherwise everything is on 'st'.
+cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                         void *ws, hipStream_t st, bool use_side)
+{
+    cd_status s = CD_OK;
     DevInfo di;
     if ((s = dev_info(di))) return s;
 
@@ -423,32 +485,41 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     }
     // ---- pair table, diagonal, screening
     if ((s = record(0))) return s;
+    const bool resume = (opts->flags & CD_RESUME) != 0;
     {
         // independent problems on the side streams, joined before the selection
         std::unique_lock<std::mutex> side_lock(side_mutex(), std::defer_lock);
-        SideStreams *side = nullptr;
-        if (count > 1) {
+        SideFork side(st);
+        if (use_side && count > 1) {
             side_lock.lock();
-            if ((s = side_streams(di.dev, side))) return s;
-            if (hipEventRecord(side->fork, st) != hipSuccess)
-                return fail(CD_ERR_DEVICE, "fork record failed");
-            for (int k = 0; k < kJkSide; ++k)
-                if (hipStreamWaitEvent(side->s[k], side->fork, 0) != hipSuccess)
-                    return fail(CD_ERR_DEVICE, "fork wait failed");
+            if ((s = side.fork(di.dev))) return s;
         }
         for (int32_t i = 0; i < count; ++i) {
             const cd_problem &p = probs[i];
-            const hipStream_t sp = side ? side->s[i % kJkSide] : st;
-            k_init_decompose<<<1, 256, 0, sp>>>(W[i].gs, p.status, p.n_vectors, W[i].d1max);
-            if ((s = launch_setup(p.mol, opts, W[i], p.row_pair, p.n_rows, p.n_active, sp, true)))
+            const DecompWs &w = W[i];
+            const hipStream_t sp = side.side() ? side.side()->s[i % kJkSide] : st;
+            if (resume)
+                k_init_resume<<<1, 256, 0, sp>>>(w.gs, p.status, p.n_vectors, w.d1max, w.kstart,
+                                                 p.max_vectors);
+            else
+                k_init_decompose<<<1, 256, 0, sp>>>(w.gs, p.status, p.n_vectors, w.d1max,
+                                                    w.kstart);
+            if ((s = launch_setup(p.mol, opts, w, p.row_pair, p.n_rows, p.n_active, sp, true)))
                 return s;
+            if (resume && p.n_active > 0 && p.max_vectors > 0) {
+                // the selection's state from the stored vectors and residuals
+                k_resume_state<<<dim3((unsigned)blocks_of(p.n_active, 64),
+                                      (unsigned)blocks_of(p.max_vectors, 64)),
+                                 256, 0, sp>>>(w.act_row, p.n_active, p.L, p.n_rows, p.diag,
+                                               w.kstart, w.LT_act, ld_act(p.max_vectors), w.D_act);
+                k_resume_pivots<<<(unsigned)blocks_of(p.max_vectors, 256), 256, 0, sp>>>(
+                    p.pivots, w.kstart, p.max_vectors, w.pivot_of_row);
+            }
+            if (opts->flags & CD_DEBUG_POISON_DIAG)
+                k_poison_diag<<<1, 64, 0, sp>>>(w.D_act, p.n_active);
+            if ((s = check_launch("setup kernels"))) return s;
         }
-        if (side) {
-            for (int k = 0; k < kJkSide; ++k)
-                if (hipEventRecord(side->join[k], side->s[k]) != hipSuccess ||
-                    hipStreamWaitEvent(st, side->join[k], 0) != hipSuccess)
-                    return fail(CD_ERR_DEVICE, "join failed");
-        }
+        if ((s = side.join())) return s;
     }
     if ((s = record(1))) return s;
 
@@ -536,6 +607,7 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             q.prow = W[i].prow;
             q.dpiv = W[i].dpiv;
             q.G = W[i].Ginv;
+            q.k_start = W[i].kstart;
             PB.gather_begin[j + 1] = PB.gather_begin[j] + (int32_t)p.max_vectors;
             PB.inverse_begin[j + 1] = PB.inverse_begin[j] + (int32_t)blocks_of(p.max_vectors, 64);
         }
@@ -562,6 +634,8 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
             q.n_vectors = p.n_vectors;
             q.L = p.L;
             q.diag = p.diag;
+            q.k_start = W[i].kstart;
+            q.resume = resume ? 1 : 0;
         }
         const bool last = (i0 + kStep2Batch >= count);
         B.timeline = (last && opts->timeline) ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
@@ -582,6 +656,23 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
         }
     }
     return CD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    size_t need = 0;
+    cd_status s = check_decompose(probs, count, opts, need);
+    if (s) return s;
+    if (need > ws_bytes || (need > 0 && !ws))
+        return fail(CD_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(CD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    return decompose_impl(probs, count, opts, ws, static_cast<hipStream_t>(stream), true);
 }
 
 cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
@@ -783,16 +874,14 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *wbase = static_cast<char *>(ws);
     std::unique_lock<std::mutex> side_lock(side_mutex(), std::defer_lock);
+    SideFork guard(st);
     SideStreams *side = nullptr;
     // several problems: problem i on side stream i mod kJkSide; one problem:
     // its J chain on side stream 0, beside the K chain on the caller's stream
     if (count > 0) {
         side_lock.lock();
-        if ((s = side_streams(di.dev, side))) return s;
-        if (hipEventRecord(side->fork, st) != hipSuccess) return fail(CD_ERR_DEVICE, "fork record failed");
-        for (int k = 0; k < kJkSide; ++k)
-            if (hipStreamWaitEvent(side->s[k], side->fork, 0) != hipSuccess)
-                return fail(CD_ERR_DEVICE, "fork wait failed");
+        if ((s = guard.fork(di.dev))) return s;
+        side = guard.side();
     }
     for (int32_t i = 0; i < count; ++i) {
         const cd_jk_problem &p = probs[i];
@@ -860,13 +949,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
     }
-    if (side) {
-        for (int k = 0; k < kJkSide; ++k)
-            if (hipEventRecord(side->join[k], side->s[k]) != hipSuccess ||
-                hipStreamWaitEvent(st, side->join[k], 0) != hipSuccess)
-                return fail(CD_ERR_DEVICE, "join failed");
-        side_lock.unlock();
-    }
+    if ((s = guard.join())) return s;
+    if (side_lock.owns_lock()) side_lock.unlock();
     if (flags & CD_SYNC) {
         if (hipStreamSynchronize(st) != hipSuccess)
             return fail(CD_ERR_DEVICE, "stream synchronise failed");

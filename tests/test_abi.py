@@ -63,7 +63,7 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
          offsetof(cd_mp2_problem, status));
   printf("%zu %zu\n", sizeof(cd_zproblem), offsetof(cd_zproblem, status));
-  printf("%zu\n", offsetof(cd_jk_problem, Lmo));
+  printf("%zu %zu\n", offsetof(cd_jk_problem, Lmo), offsetof(cd_problem, pivot_values));
   printf("%zu %zu %zu %zu %zu\n", sizeof(cd_one_electron_problem),
          offsetof(cd_one_electron_problem, H), sizeof(cd_scf_problem),
          offsetof(cd_scf_problem, e_tol), offsetof(cd_scf_problem, converged));
@@ -92,7 +92,7 @@ def test_binding_structs_match_header():
             cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
             cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset,
             ctypes.sizeof(cdlib.cd_zproblem), cdlib.cd_zproblem.status.offset,
-            cdlib.cd_jk_problem.Lmo.offset,
+            cdlib.cd_jk_problem.Lmo.offset, cdlib.cd_problem.pivot_values.offset,
             ctypes.sizeof(cdlib.cd_one_electron_problem), cdlib.cd_one_electron_problem.H.offset,
             ctypes.sizeof(cdlib.cd_scf_problem), cdlib.cd_scf_problem.e_tol.offset,
             cdlib.cd_scf_problem.converged.offset]
@@ -139,6 +139,11 @@ def test_argument_validation_without_device(lib):
         assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
                                 None) == cdlib.CD_ERR_INVALID_ARG
         assert b"tuning" in lib.cd_last_error()
+    # flags other than CD_SYNC, CD_RESUME and CD_DEBUG_POISON_DIAG are rejected on the host
+    o = cdlib.cd_decomp_opts(1e-6, 1e-12, 8, None, None, 0, None)
+    assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
+                            None) == cdlib.CD_ERR_INVALID_ARG
+    assert b"flags" in lib.cd_last_error()
     # span factors outside [0, 1] (or NaN) are rejected on the host
     for eta in [-0.1, 1.5, float("nan")]:
         o = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None, None, 0, None, eta)

@@ -326,6 +326,54 @@ def test_jk_single_function(orc):
     assert K[0, 0] == pytest.approx(ref, rel=1e-14)
 
 
+def test_e2_single_function_closed_form(orc):
+    """E2 = 2 tr(DJ) - tr(DK) for one function: D = c^2 and J = K = c^2 (aa|aa),
+    so E2 = c^4 (aa|aa) = c^4 2 sqrt(a/pi); and for any 1 x 1 J, K it is
+    c^2 (2 J - K), which fixes the factor 2 and the sign."""
+    a, c = 1.3, 0.6
+    xyz = np.zeros((1, 3))
+    alpha = np.array([a])
+    C = np.array([[c]])
+    rp, _ = orc.rows(xyz, alpha, 0.0)
+    cd = orc.decompose(xyz, alpha, rp, 0.0)
+    J, K = orc.jk_cd(1, rp, cd.L, C)
+    assert orc.e2(C, J, K) == pytest.approx(c ** 4 * 2.0 * math.sqrt(a / math.pi), rel=1e-14)
+    assert orc.e2(C, np.array([[3.0]]), np.array([[5.0]])) == pytest.approx(c * c * (6.0 - 5.0),
+                                                                          rel=1e-15)
+    assert orc.e2(C, np.array([[0.0]]), np.array([[1.0]])) == pytest.approx(-c * c, rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_e2_matches_four_index_integrals(orc, seed):
+    """E2 from J and K against the closed-shell two-electron energy written on
+    the full four-index integral tensor, sum_{mu nu sg rh} D_{mu nu} D_{sg rh}
+    [2 (mu nu|sg rh) - (mu sg|nu rh)], contracted by einsum: once with the
+    exact J/K and once with the J/K of a tau = 0 decomposition."""
+    m = make_molecule(3, 3.0, (0.4, 1.6), 2, seed=seed)
+    N = m.n_basis
+    G = np.empty((N, N, N, N))
+    for i in range(N):
+        for j in range(N):
+            for k in range(N):
+                for l in range(N):
+                    G[i, j, k, l] = orc.eri(m.xyz, m.alpha, i, j, k, l)
+    Dm = m.C @ m.C.T
+    ref = (2.0 * np.einsum("ij,kl,ijkl->", Dm, Dm, G)
+           - np.einsum("ij,kl,ikjl->", Dm, Dm, G))
+    Je, Ke = orc.jk_exact(m.xyz, m.alpha, m.C)
+    assert orc.e2(m.C, Je, Ke) == pytest.approx(ref, rel=1e-13)
+    rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
+    cd = orc.decompose(m.xyz, m.alpha, rp, 0.0)
+    J, K = orc.jk_cd(N, rp, cd.L, m.C)
+    assert orc.e2(m.C, J, K) == pytest.approx(ref, rel=1e-12)
+    # Coulomb and exchange parts separately: E2 = 2 EJ - EK with EJ, EK > 0
+    ej = np.einsum("ij,kl,ijkl->", Dm, Dm, G)
+    ek = np.einsum("ij,kl,ikjl->", Dm, Dm, G)
+    assert ej > 0 and ek > 0
+    assert orc.e2(m.C, Je, np.zeros_like(Ke)) == pytest.approx(2.0 * ej, rel=1e-13)
+    assert orc.e2(m.C, np.zeros_like(Je), Ke) == pytest.approx(-ek, rel=1e-13)
+
+
 def test_jk_linear_in_density(orc):
     m = make_molecule(5, 4.0, (0.3, 1.2), 4, seed=31)
     rp, _ = orc.rows(m.xyz, m.alpha, 0.0)
