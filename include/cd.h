@@ -210,6 +210,27 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
                        void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * cd_decompose_noalloc: cd_decompose for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same problems, options, results and errors as
+ * cd_decompose, with no workspace argument: the kernels use a static device
+ * array of CD_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends, and the call allocates nothing (no
+ * hipMalloc or hipFree, no allocating library routine).  Problems whose
+ * workspace (the sum of cd_query's ws_bytes for them) exceeds that size are
+ * rejected with CD_ERR_WORKSPACE before any device work.  Every problem runs on
+ * 'stream' (no library side streams).  All calls on one GPU share that GPU's
+ * array, which keeps the last call's contents (the call initialises what it
+ * needs): calls that overlap on one GPU (on different streams, or from
+ * several threads without ordering) race and give wrong results; calls
+ * ordered on one stream are safe.  The first call on a device also looks up
+ * the array's device address there (once per device).
+ */
+#define CD_NOALLOC_SCRATCH_BYTES (128u << 20) /* 128 MiB */
+cd_status cd_decompose_noalloc(const cd_problem *probs, int32_t count,
+                               const cd_decomp_opts *opts, void *stream);
+
+/*
  * cd_autotune: choose the launch shapes of cd_decompose for these problems by
  * measurement.  Blocking (synchronises 'stream').  It runs the decomposition
  * once per candidate shape, timing the pivot selection and the all-row solve

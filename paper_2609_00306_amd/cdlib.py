@@ -99,7 +99,7 @@ class cd_zproblem(ctypes.Structure):
 
 
 #: every function include/cd.h declares
-EXPORTS = ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
+EXPORTS = ("cd_query", "cd_decompose", "cd_decompose_noalloc", "cd_autotune", "cd_query_jk", "cd_build_jk", "cd_query_transform",
            "cd_transform", "cd_query_mp2", "cd_mp2_energy", "cd_one_electron", "cd_query_scf",
            "cd_scf", "cd_query_zdecompose", "cd_zdecompose", "cd_last_error", "cd_version")
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
                            P(ctypes.c_int64), P(cd_sizes), _vp]
     L.cd_decompose.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp,
                                ctypes.c_size_t, _vp]
+    L.cd_decompose_noalloc.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp]
     L.cd_autotune.argtypes = [P(cd_problem), ctypes.c_int32, P(cd_decomp_opts), _vp,
                               ctypes.c_size_t, P(cd_tuning), _vp]
     L.cd_query_jk.argtypes = [P(cd_jk_problem), ctypes.c_int32, ctypes.c_int,
@@ -145,7 +146,7 @@ def load(path: str = LIB_PATH):
     L.cd_query_zdecompose.argtypes = [P(cd_zproblem), P(ctypes.c_size_t)]
     L.cd_zdecompose.argtypes = [P(cd_zproblem), ctypes.c_double, ctypes.c_uint32, _vp,
                                 ctypes.c_size_t, _vp]
-    for f in ("cd_query", "cd_decompose", "cd_autotune", "cd_query_jk", "cd_build_jk",
+    for f in ("cd_query", "cd_decompose", "cd_decompose_noalloc", "cd_autotune", "cd_query_jk", "cd_build_jk",
               "cd_query_transform", "cd_transform", "cd_query_mp2", "cd_mp2_energy",
               "cd_one_electron", "cd_query_scf", "cd_scf", "cd_query_zdecompose",
               "cd_zdecompose"):
@@ -309,6 +310,22 @@ def run_decompose(decs: Sequence[Decomposition], tau: float, schwarz: float, syn
         workspace = decs[0].workspace
     _check(L.cd_decompose(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
                           _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def run_decompose_noalloc(decs: Sequence[Decomposition], tau: float, schwarz: float,
+                          sync: bool = False, stream=None, eta: float = 1.0):
+    """cd_decompose_noalloc: the decomposition with the library's static device
+    scratch instead of a workspace (no device allocation in the call; calls
+    that overlap on one GPU race).  The problems' own workspaces are unused."""
+    L = load()
+    n = len(decs)
+    arr = (cd_problem * n)(*[problem(d) for d in decs])
+    opts = cd_decomp_opts(float(tau), float(schwarz), CD_SYNC if sync else 0, None, None, 0,
+                          None, float(eta))
+    _check(L.cd_decompose_noalloc(arr, n, ctypes.byref(opts), _stream(stream)))
 
 
 def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=None,

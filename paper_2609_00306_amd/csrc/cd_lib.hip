@@ -675,6 +675,58 @@ cd_status cd_decompose(const cd_problem *probs, int32_t count, const cd_decomp_o
     return decompose_impl(probs, count, opts, ws, static_cast<hipStream_t>(stream), true);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free form
+// The workspace of cd_decompose_noalloc: a static device array that every GPU
+// the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per
+// device, with that device current, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[CD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+cd_status scratch_address(int dev, void **out)
+{
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDev];
+    if (dev < 0 || dev >= kMaxDev) return fail(CD_ERR_UNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CD_ERR_DEVICE, "address of the static scratch: %s", hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return CD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cd_status cd_decompose_noalloc(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
+                               void *stream)
+{
+    size_t need = 0;
+    cd_status s = check_decompose(probs, count, opts, need);
+    if (s) return s;
+    if (need > (size_t)CD_NOALLOC_SCRATCH_BYTES)
+        return fail(CD_ERR_WORKSPACE,
+                    "the problems need %zu bytes of workspace; the static scratch holds %zu",
+                    need, (size_t)CD_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(CD_ERR_DEVICE, "no HIP device");
+    void *ws = nullptr;
+    if ((s = scratch_address(dev, &ws))) return s;
+    // every problem on the caller's stream (no side streams)
+    return decompose_impl(probs, count, opts, ws, static_cast<hipStream_t>(stream), false);
+}
+
 cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                       void *ws, size_t ws_bytes, cd_tuning *best, void *stream)
 {
