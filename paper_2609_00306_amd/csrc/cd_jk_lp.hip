@@ -1,18 +1,18 @@
-// Reduced-precision forms of the exchange build (K), with FP32 accumulation
-// inside k-slabs of 32 and FP64 accumulation across slabs; J is always built
-// in FP64 (it is bound by reading L).
+// Reduced-precision forms of the exchange build (K); J is always built in
+// FP64 (it is bound by reading L).
 //
 //   FP32  : the half transform X^P = Lt^P C and the product K = sum_P X^P^T X^P
-//           both on v_mfma_f32_16x16x4f32, operands rounded to FP32 on load.
+//           both on v_mfma_f32_16x16x4f32, operands rounded to FP32 on load,
+//           FP32 accumulation inside k-slabs of 32 and FP64 across slabs.
 //   BF16X3: the half transform runs in FP64 and writes X split into three BF16
 //           planes (k_half_sparse<true>); the product K reads the planes
-//           (k_syrk_rows_bf16p).  Every operand x is split as x = b0 + b1 + b2 (round-to-nearest
-//           BF16 each: b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)),
-//           and a product a*c keeps the six terms up to order 2^-16:
-//           a0c0 + a0c1 + a1c0 + a0c2 + a1c1 + a2c0  (Henry, Tang & Heinecke,
-//           "Leveraging the bfloat16 artificial intelligence datatype for
-//           higher-precision computations", ARITH 2019), on
-//           v_mfma_f32_16x16x32_bf16.
+//           (k_syrk_bf16x3).  Every operand x is split as x = b0 + b1 + b2
+//           (round-to-nearest BF16 each: b0 = bf16(x), b1 = bf16(x - b0),
+//           b2 = bf16(x - b0 - b1)), and a product a*c keeps the six terms up
+//           to order 2^-16: a0c0 + a0c1 + a1c0 + a0c2 + a1c1 + a2c0 (Henry, Tang
+//           & Heinecke, "Leveraging the bfloat16 artificial intelligence
+//           datatype for higher-precision computations", ARITH 2019), on
+//           v_mfma_f32_16x16x32_bf16, FP32 inside steps of 32 and FP64 across.
 //
 // Result lane layout of both FP32-accumulating instructions (read back on
 // gfx950): lane l, element v holds D[m = 4 (l / 16) + v][n = l % 16].
@@ -26,33 +26,22 @@ namespace cdk {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum LpMode { LP_F32 = 1, LP_BF16X3 = 2 };
+enum LpMode { LP_F32 = 1 };
 
 constexpr int LP_TKC = 32;     // k-chunk staged in LDS
 constexpr int LP_SLAB = 32;    // FP32 accumulation length before folding into FP64
 
 __device__ __forceinline__ int lp_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 
-__device__ __forceinline__ void split3(double x, __bf16 &b0, __bf16 &b1, __bf16 &b2)
-{
-    b0 = (__bf16)(float)x;
-    const double r1 = x - (double)(float)b0;
-    b1 = (__bf16)(float)r1;
-    const double r2 = r1 - (double)(float)b1;
-    b2 = (__bf16)(float)r2;
-}
-
-// LDS staging of one k-chunk for a 64 x 64 tile.
-//  F32 : k-major sources   sA32[k][m], sB32[k][n]
-//        k-contiguous (KC) sA32[m][k], sB32[n][k]  (rows padded to TKC + 1)
-//  BF16: sAp[p][m][k], sBp[p][n][k] p = 0..2    (k contiguous, 8 per lane load)
+// LDS staging of one k-chunk of FP32 operands for a 64 x 64 tile:
+//   k-major sources   sA32[k][m], sB32[k][n]
+//   k-contiguous (KC) sA32[m][k], sB32[n][k]  (rows padded to TKC + 1)
 // so that the LDS writes follow the contiguous index of the global loads.
 template <int MODE, bool KC = false>
 struct LpStage {
-    static constexpr int kBf16Ld = LP_TKC + 8;   // padded row (bf16 elements)
-    static constexpr int kF32Ld = LP_TKC + 1;    // padded row (KC, FP32)
-    static constexpr int kBytes = (MODE == LP_F32) ? 2 * 64 * (LP_TKC + 1) * 4
-                                                   : 2 * 3 * 64 * kBf16Ld * 2;
+    static_assert(MODE == LP_F32, "FP32 staging only");
+    static constexpr int kF32Ld = LP_TKC + 1;    // padded row (KC)
+    static constexpr int kBytes = 2 * 64 * (LP_TKC + 1) * 4;
     __device__ static __forceinline__ int f32_index(int k, int m)
     {
         return KC ? m * kF32Ld + k : k * 64 + m;
@@ -90,84 +79,30 @@ struct LpStage {
     __device__ static __forceinline__ void put(unsigned char *smem, const double (&ra)[kPer],
                                                const double (&rb)[kPer])
     {
-        if (MODE == LP_F32) {
-            float *sA = reinterpret_cast<float *>(smem);
-            float *sB = sA + 64 * kF32Ld;
+        float *sA = reinterpret_cast<float *>(smem);
+        float *sB = sA + 64 * kF32Ld;
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                int k, m;
-                coord(threadIdx.x + 256 * u, k, m);
-                sA[f32_index(k, m)] = (float)ra[u];
-                sB[f32_index(k, m)] = (float)rb[u];
-            }
-        } else {
-            __bf16 *sA = reinterpret_cast<__bf16 *>(smem);
-            __bf16 *sB = sA + 3 * 64 * kBf16Ld;
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                int k, m;
-                coord(threadIdx.x + 256 * u, k, m);
-                __bf16 a0, a1, a2, c0, c1, c2;
-                split3(ra[u], a0, a1, a2);
-                split3(rb[u], c0, c1, c2);
-                sA[(0 * 64 + m) * kBf16Ld + k] = a0;
-                sA[(1 * 64 + m) * kBf16Ld + k] = a1;
-                sA[(2 * 64 + m) * kBf16Ld + k] = a2;
-                sB[(0 * 64 + m) * kBf16Ld + k] = c0;
-                sB[(1 * 64 + m) * kBf16Ld + k] = c1;
-                sB[(2 * 64 + m) * kBf16Ld + k] = c2;
-            }
+        for (int u = 0; u < kPer; ++u) {
+            int k, m;
+            coord(threadIdx.x + 256 * u, k, m);
+            sA[f32_index(k, m)] = (float)ra[u];
+            sB[f32_index(k, m)] = (float)rb[u];
         }
     }
     // multiply the staged chunk into acc[r] (rows 16 r.., columns 16 w..)
     __device__ static __forceinline__ void mma(const unsigned char *smem, f32x4 (&acc)[4])
     {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        if (MODE == LP_F32) {
-            const float *sA = reinterpret_cast<const float *>(smem);
-            const float *sB = sA + 64 * kF32Ld;
+        const float *sA = reinterpret_cast<const float *>(smem);
+        const float *sB = sA + 64 * kF32Ld;
 #pragma unroll
-            for (int ks = 0; ks < LP_TKC; ks += 4) {
-                const int kk = ks + (lane >> 4);
-                const float b = sB[f32_index(kk, 16 * w + (lane & 15))];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float a = sA[f32_index(kk, 16 * r + (lane & 15))];
-                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r], 0, 0, 0);
-                }
-            }
-        } else {
-            mma_planes(reinterpret_cast<const __bf16 *>(smem),
-                       reinterpret_cast<const __bf16 *>(smem) + 3 * 64 * kBf16Ld, acc);
-        }
-    }
-    // BF16 planes sA[p][m][k], sB[p][n][k] (k contiguous, rows of kBf16Ld): the
-    // six products of the 3 x BF16 split into acc[r] (rows 16 r.., columns 16 w..)
-    __device__ static __forceinline__ void mma_planes(const __bf16 *sA, const __bf16 *sB,
-                                                      f32x4 (&acc)[4])
-    {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        {
-            const int kk = 8 * (lane >> 4);
-            bf16x8 b[3];
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-                b[p] = *reinterpret_cast<const bf16x8 *>(
-                    &sB[(p * 64 + 16 * w + (lane & 15)) * kBf16Ld + kk]);
+        for (int ks = 0; ks < LP_TKC; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            const float b = sB[f32_index(kk, 16 * w + (lane & 15))];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                bf16x8 a[3];
-#pragma unroll
-                for (int p = 0; p < 3; ++p)
-                    a[p] = *reinterpret_cast<const bf16x8 *>(
-                        &sA[(p * 64 + 16 * r + (lane & 15)) * kBf16Ld + kk]);
-                // smallest terms first
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc[r], 0, 0, 0);
+                const float a = sA[f32_index(kk, 16 * r + (lane & 15))];
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r], 0, 0, 0);
             }
         }
     }
@@ -293,83 +228,248 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
         }
 }
 
-// Partial K from X held as three BF16 planes (written by the FP64 half
-// transform): Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k] with the six
-// products of the 3 x BF16 split, FP32 inside each 32-k chunk, FP64 across.
-// Each thread loads one 16-byte piece (8 values) of one row per plane and
-// operand; ldx is a multiple of 8 so the pieces are aligned.
-__global__ __launch_bounds__(256) void k_syrk_rows_bf16p(const __bf16 *__restrict__ Xp,
-                                                         int64_t ldx, int64_t plane, int N,
-                                                         const int64_t *__restrict__ n_vectors,
-                                                         int ncol, int nsplit,
-                                                         double *__restrict__ Kp)
+// ---------------------------------------------------------------- 3 x BF16, large tiles
+// Partial K from the three BF16 planes of X with 128 x 128 output tiles:
+//   Kp[s][mu][nu] = sum_{k in split s} X[mu][k] X[nu][k]   (lower tile pairs)
+// with the six products of the 3 x BF16 split (see the top of this file).
+// Each wave owns a 64 x 64 quarter of the tile (4 x 4 accumulators of the
+// 16x16x32 BF16 instruction), so every operand fragment read from LDS feeds
+// four tiles.  A step stages 32 values of the 256 rows (the 128 rows of each
+// side, all three planes: 48 KB) in one of three LDS buffers.  The loads go
+// from memory straight into LDS (global_load_lds, 16 bytes per lane, a wave's
+// 64 pieces filling one contiguous KB) two steps ahead of the products, so no
+// registers hold them and 96 KB per compute unit are in flight; one barrier per
+// step.  LDS rows are 64 bytes with no padding; the 16-byte k-group g of row r
+// sits at group g ^ ((r / 4) % 4), so the 16 rows read by one quarter-wave at
+// one k-group fall on 16 different 16-byte bank groups.
+//
+// FP32 accumulation runs over one step (32 values; each step's products start
+// from a zero accumulator) and each row tile's step sums are added in FP64
+// while the next row tile's products run.  Longer FP32 slabs were measured:
+// with 512 values per slab the error of K grew about twentyfold (to 6e-7 Eh on
+// the 1200-function workload, and 5e-6 Eh in E2), roughly in proportion to the
+// slab length, so the matrix unit's FP32 accumulation rounds with a bias and
+// slabs stay at one step.
+//
+// X holds its three planes 'plane' values apart, each of ldx-value rows padded
+// to a whole number of 128-row tiles (the rows past N are never written and
+// only enter K entries past N, which are not stored).
+//
+// Grid (one workgroup per compute unit at 144 KB of LDS): workgroup g runs on
+// XCD g % 8; its j = g / 8 -th item is tile pair j % pairs of split
+// 8 (j / pairs) + g % 8, so each XCD works on its own k-ranges of X and the
+// tile pairs of one k-range, dispatched together, share it through that XCD's
+// L2.  'nsplit' / 8 k-ranges per XCD are chosen on the host so that the
+// workgroups fill an XCD's compute units in whole rounds.
+constexpr int BX_TILE = 128;
+constexpr int BX_TK = 32;                        // k per stage: one 16x16x32 step
+constexpr int BX_ROWS = 2 * BX_TILE;             // A rows, then B rows
+constexpr int BX_STAGE = 3 * BX_ROWS * BX_TK;    // bf16 elements per stage (48 KB)
+constexpr int BX_LOADS = BX_STAGE * 2 / 16 / 256;   // 16-byte pieces per thread per stage (12)
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// bf16 offset in a stage of k-group g (8 values) of row r of plane p
+__device__ __forceinline__ int bx_off(int p, int r, int g)
 {
-    using S = LpStage<LP_BF16X3, true>;
-    constexpr int LD = S::kBf16Ld;
-    __shared__ __align__(16) __bf16 sA[3 * 64 * LD];
-    __shared__ __align__(16) __bf16 sB[3 * 64 * LD];
-    int t, s;
-    syrk_tile_split(N, nsplit, t, s);
-    int tm = 0;
-    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
-    const int tn = t - tm * (tm + 1) / 2;
+    return 8 * ((p * BX_ROWS + r) * 4 + (g ^ ((r >> 2) & 3)));
+}
+
+__device__ __forceinline__ void bx_item(int pairs, int &tm, int &tn, int &split)
+{
+    const int g = blockIdx.x, xcd = g & 7, j = g >> 3;
+    const int t = j % pairs;
+    split = 8 * (j / pairs) + xcd;
+    int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (m * (m + 1) / 2 > t) --m;
+    while ((m + 1) * (m + 2) / 2 <= t) ++m;
+    tm = m;
+    tn = t - m * (m + 1) / 2;
+}
+
+// Workgroup barrier that orders LDS only: a fence restricted to LDS, so the
+// memory loads in flight (the next steps' pieces) need not complete first, as
+// they would at __syncthreads().  The pieces loaded straight into LDS are
+// waited for explicitly (wait_vmcnt) before the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One 16-byte piece per lane from global memory straight into LDS: lane l
+// writes bytes [16 l, 16 l + 16) of the wave's KB at 'lds' (wave-uniform, it
+// goes to M0).  Written as inline assembly (no output registers: the load
+// writes LDS only) so that the compiler, which drains every load of this kind
+// in flight before any LDS read, leaves the prefetch alone; the caller waits
+// for the pieces explicitly (wait_vmcnt: loads complete in issue order) before
+// the barrier that publishes them.
+__device__ __forceinline__ void lds_dma16(const void *g, lds_void *lds)
+{
+    const uint32_t m0 = (uint32_t)(uintptr_t)lds;
+    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(m0) : "memory");
+}
+
+// s_waitcnt with only vmcnt limited (expcnt and lgkmcnt at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 16, "vmcnt immediate");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
+}
+
+__global__ __launch_bounds__(256) void k_syrk_bf16x3(const __bf16 *__restrict__ Xp, int64_t ldx,
+                                                     int64_t plane, int N,
+                                                     const int64_t *__restrict__ n_vectors,
+                                                     int ncol, int pairs, int nsplit,
+                                                     double *__restrict__ Kp)
+{
+    __shared__ __align__(16) __bf16 sX0[BX_STAGE];
+    __shared__ __align__(16) __bf16 sX1[BX_STAGE];
+    __shared__ __align__(16) __bf16 sX2[BX_STAGE];
+    int tm, tn, s;
+    bx_item(pairs, tm, tn, s);
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
-    per = (per + LP_SLAB - 1) / LP_SLAB * LP_SLAB;
+    per = (per + BX_TK - 1) / BX_TK * BX_TK;
     const int64_t kb = s * per;
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
-    const int m0 = tm * 64, n0 = tn * 64;
-    const int tid = threadIdx.x, row = tid >> 2, kv = 8 * (tid & 3);
-    const __bf16 *pa = Xp + (int64_t)min(m0 + row, N - 1) * ldx + kv;
-    const __bf16 *pb = Xp + (int64_t)min(n0 + row, N - 1) * ldx + kv;
-    double acc64[4][4] = {};
-    f32x4 acc[4];
-    bf16x8 va[3], vb[3];
-    auto fetch = [&](int64_t k0) {
-        if (k0 + kv + 8 <= ke) {
+    const int m0 = tm * BX_TILE, n0 = tn * BX_TILE;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+
+    // Piece v of this lane is the LDS piece q = 64 (4 v + w) + lane of a stage:
+    // plane (4 v + w) / 16, row 16 ((4 v + w) % 16) + lane / 4, stored k-group
+    // lane % 4, which holds k-group g = (lane % 4) ^ ((lane / 16) % 4) of that
+    // row.  Rows 0..127 are the A side (rows m0..), 128..255 the B side (n0..);
+    // the planes hold whole 128-row tiles (rows past N are padding), so a
+    // piece's address is this lane's offset plus a wave-uniform one.
+    const int g = (lane & 3) ^ ((lane >> 4) & 3);
+    const __bf16 *lane_src = Xp + (int64_t)(lane >> 2) * ldx + 8 * g;
+    auto wave_off = [&](int v) __attribute__((always_inline)) -> int64_t {
+        const int b = 4 * v + w, rb = b & 15;
+        const int row0 = (rb < 8) ? m0 + 16 * rb : n0 + 16 * (rb - 8);
+        return (int64_t)(b >> 4) * plane + (int64_t)row0 * ldx;
+    };
+    // a full step straight into LDS (12 loads per lane); a partial last step
+    // through registers with the values past ke set to zero
+    auto load_step = [&](__bf16 *stage, int64_t k0) __attribute__((always_inline)) {
+        if (k0 + BX_TK <= ke) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                va[p] = *reinterpret_cast<const bf16x8 *>(pa + p * plane + k0);
-                vb[p] = *reinterpret_cast<const bf16x8 *>(pb + p * plane + k0);
-            }
+            for (int v = 0; v < BX_LOADS; ++v)
+                lds_dma16(lane_src + wave_off(v) + k0, (lds_void *)(stage + 512 * (4 * v + w)));
         } else {
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+            for (int v = 0; v < BX_LOADS; ++v) {
+                const __bf16 *src = lane_src + wave_off(v) + k0;
+                bf16x8 x;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool ok = k0 + kv + j < ke;
-                    va[p][j] = ok ? pa[p * plane + k0 + j] : (__bf16)0.0f;
-                    vb[p][j] = ok ? pb[p * plane + k0 + j] : (__bf16)0.0f;
-                }
+                for (int e = 0; e < 8; ++e) x[e] = (k0 + 8 * g + e < ke) ? src[e] : (__bf16)0.0f;
+                *reinterpret_cast<bf16x8 *>(stage + 512 * (4 * v + w) + 8 * lane) = x;
+            }
         }
     };
-    if (kb < ke) fetch(kb);
-    for (int64_t k0 = kb; k0 < ke; k0 += LP_TKC) {
+
+    double acc64[4][4][4];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            *reinterpret_cast<bf16x8 *>(&sA[(p * 64 + row) * LD + kv]) = va[p];
-            *reinterpret_cast<bf16x8 *>(&sB[(p * 64 + row) * LD + kv]) = vb[p];
-        }
-        __syncthreads();
-        if (k0 + LP_TKC < ke) fetch(k0 + LP_TKC);
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-        S::mma_planes(sA, sB, acc);
-        __syncthreads();
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
+    const int lr = lane & 15, kg = lane >> 4;
+
+    // One staged step: for each row tile i, the six products into four fresh
+    // FP32 accumulators (one per column tile), then their FP64 fold.  The rows
+    // are software-pipelined: the A fragments of row i + 1 are read before the
+    // products of row i + 1 are issued, and the fold of row i comes after
+    // them, so the vector unit adds while the matrix unit multiplies.
+    // Products go smallest first: a0b2, a1b1, a0b1, a2b0, a1b0, a0b0.
+    auto mma_step = [&](const __bf16 *S) __attribute__((always_inline)) {
+        bf16x8 b[3][4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[r][v] += (double)acc[r][v];
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[p][j] = *reinterpret_cast<const bf16x8 *>(
+                    S + bx_off(p, BX_TILE + 64 * wc + 16 * j + lr, kg));
+        auto read_a = [&](int i, bf16x8 (&a)[3]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+                a[p] = *reinterpret_cast<const bf16x8 *>(S + bx_off(p, 64 * wr + 16 * i + lr, kg));
+        };
+        auto products = [&](const bf16x8 (&a)[3], f32x4 (&t)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2][j],
+                                                               f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1][j], t[j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1][j], t[j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0][j], t[j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0][j], t[j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                t[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0][j], t[j], 0, 0, 0);
+        };
+        auto fold = [&](int i, const f32x4 (&t)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)t[j][e];
+        };
+        bf16x8 a0[3], a1[3];
+        f32x4 t0[4], t1[4];
+        read_a(0, a0);
+        read_a(1, a1);
+        products(a0, t0);
+        read_a(2, a0);
+        products(a1, t1);
+        fold(0, t0);
+        read_a(3, a1);
+        products(a0, t0);
+        fold(1, t1);
+        products(a1, t1);
+        fold(2, t0);
+        fold(3, t1);
+    };
+    // step c: wait for its own loads (the next step's may stay in flight), a
+    // barrier (every wave's pieces of step c have landed, and every wave is
+    // done with the buffer that step c + 2 refills), the loads of step c + 2,
+    // then the products of step c
+    const int64_t nch = (ke > kb) ? (ke - kb + BX_TK - 1) / BX_TK : 0;
+    auto step = [&](int64_t c, const __bf16 *cur, __bf16 *refill) __attribute__((always_inline)) {
+        if (c + 1 < nch) wait_vmcnt<BX_LOADS>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        if (c + 2 < nch) load_step(refill, kb + (c + 2) * BX_TK);
+        mma_step(cur);
+    };
+    if (nch > 0) load_step(sX0, kb);
+    if (nch > 1) load_step(sX1, kb + BX_TK);
+    for (int64_t c = 0; c < nch; c += 3) {
+        step(c, sX0, sX2);
+        if (c + 1 < nch) step(c + 1, sX1, sX0);
+        if (c + 2 < nch) step(c + 2, sX2, sX1);
     }
-    const int lane = tid & 63, w = tid >> 6;
     double *out = Kp + (int64_t)s * N * N;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int m = m0 + 16 * r + lp_row(lane, v), n = n0 + 16 * w + (lane & 15);
-            if (m < N && n < N) out[(int64_t)m * N + n] = acc64[r][v];
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 64 * wr + 16 * i + lp_row(lane, e);
+                const int n = n0 + 64 * wc + 16 * j + lr;
+                if (m < N && n < N) out[(int64_t)m * N + n] = acc64[i][j][e];
+            }
 }
 
 }  // namespace cdk

@@ -810,6 +810,40 @@ int jk_nsplit(int N, int n_cu)
     return std::max(8, std::min(ns, 64));
 }
 
+// Tile pairs (lower triangle) of the large-tile 3 x BF16 exchange product.
+int bx_pairs(int N)
+{
+    const int T = (N + BX_TILE - 1) / BX_TILE;
+    return T * (T + 1) / 2;
+}
+
+// k-ranges per XCD of the 3 x BF16 exchange product: the smallest count whose
+// pairs * ss workgroups (one per compute unit) fill the compute units of an
+// XCD in whole rounds to 95% or better, else the best fill up to 16.
+int bx_subsplits(int pairs, int n_cu)
+{
+    const double cu_xcd = std::max(1, n_cu / 8);
+    int best = 1;
+    double best_fill = 0.0;
+    for (int ss = 1; ss <= 16; ++ss) {
+        const double rounds = pairs * ss / cu_xcd;
+        const double fill = rounds / std::ceil(rounds);
+        if (fill >= 0.95) return ss;
+        if (fill > best_fill + 1e-12) {
+            best_fill = fill;
+            best = ss;
+        }
+    }
+    return best;
+}
+
+// Number of partial K matrices of the exchange product at a precision.
+int jk_splits(int N, int n_cu, cd_precision prec)
+{
+    if (prec == CD_BF16X3) return 8 * bx_subsplits(bx_pairs(N), n_cu);
+    return jk_nsplit(N, n_cu);
+}
+
 // Unpacking of the packed vectors for the J/K and transform products: a
 // dense row map, per-function neighbour lists and the row-major copy LT.
 struct SparseWs {
@@ -856,6 +890,10 @@ struct JkWs {
 // row starts 16-byte aligned.
 int64_t bf16_ld(int64_t n) { return (n + 7) / 8 * 8; }
 
+// Rows of one BF16 plane of X: N padded to whole 128-row tiles of the
+// exchange product.
+int64_t bx_rows(int64_t N) { return (N + BX_TILE - 1) / BX_TILE * BX_TILE; }
+
 JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
 {
     JkWs w{};
@@ -868,7 +906,7 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     // X: FP64 [N][M O], FP32 in the same space, or three BF16 planes of rows of
     // bf16_ld(M O) values
     const int64_t xf = p.max_vectors * (int64_t)p.n_occ * N;
-    const int64_t xb = (3 * N * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
+    const int64_t xb = (3 * bx_rows(N) * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
     w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.X64 = (p.Lmo && prec == CD_BF16X3) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
@@ -904,7 +942,7 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
     size_t tot = 0;
     for (int32_t i = 0; i < count; ++i) {
         if ((s = check_jk(probs[i]))) return s;
-        tot += carve_jk(nullptr, probs[i], jk_nsplit(probs[i].n_basis, di.n_cu), prec).bytes;
+        tot += carve_jk(nullptr, probs[i], jk_splits(probs[i].n_basis, di.n_cu, prec), prec).bytes;
     }
     *ws_bytes = tot;
     return CD_OK;
@@ -939,7 +977,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const cd_jk_problem &p = probs[i];
         const hipStream_t sp = (count > 1) ? side->s[i % kJkSide] : st;
         const hipStream_t sj = (count > 1) ? sp : side->s[0];   // the J chain
-        const int nsplit = jk_nsplit(p.n_basis, di.n_cu);
+        const int nsplit = jk_splits(p.n_basis, di.n_cu, prec);
         JkWs w = carve_jk(wbase, p, nsplit, prec);
         wbase += w.bytes;
         const int64_t N = p.n_basis, NN = N * N, n = p.n_rows, mv = p.max_vectors;
@@ -990,13 +1028,14 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         } else {
             // X in FP64 (matrix cores), written split into three BF16 planes; the
             // exchange product then runs on BF16 matrix cores from the planes
-            const int64_t ldb = bf16_ld(ldx), plane = N * ldb;
+            const int64_t ldb = bf16_ld(ldx), plane = bx_rows(N) * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
             k_half_sparse<true><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                        p.n_vectors, Xp, ldb, plane, w.X64, ldx);
             if (p.Lmo && (s = second_half(w.X64))) return s;
-            k_syrk_rows_bf16p<<<sgrid, 256, 0, sp>>>(Xp, ldb, plane, (int)N, p.n_vectors, O,
-                                                     nsplit, w.Kp);
+            const int pairs = bx_pairs((int)N);
+            k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
+                Xp, ldb, plane, (int)N, p.n_vectors, O, pairs, nsplit, w.Kp);
         }
         k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
