@@ -33,7 +33,7 @@ HBM_TBPS = 8.0
 METRIC = "Cholesky vectors/s + J/K build TFLOP/s at tau=1e-6; mixed/batched vs plain FP64"
 PRECISIONS = ("fp64", "fp32", "bf16x3")
 #: precisions whose J/K build also writes C^T L C (the transform fused into it)
-FUSED = ("fp64", "bf16x3")
+FUSED = ("fp64", "fp32", "bf16x3")
 
 # HBM bytes per launch of the decomposition kernels on a workload, from two
 # rocprofv3 --pmc runs of the default bench command (FETCH_SIZE, then

@@ -258,10 +258,10 @@ typedef struct {
     double *J;                 /* [N][N] out */
     double *K;                 /* [N][N] out */
     int32_t *status;           /* [1] */
-    double *Lmo;               /* optional (may be NULL), CD_FP64 or CD_BF16X3 (CD_ERR_INVALID_ARG
-                                  with CD_FP32): [max_vectors][O][O] out, Lmo^P = C^T L^P C for
-                                  P < M in FP64 (cd_transform with C1 = C2 = C), formed from the
-                                  FP64 half transform L^P C that K already needs */
+    double *Lmo;               /* optional (may be NULL): [max_vectors][O][O] out,
+                                  Lmo^P = C^T L^P C for P < M in FP64 (cd_transform with
+                                  C1 = C2 = C) at every precision, formed from the FP64 half
+                                  transform L^P C that K already needs */
 } cd_jk_problem;
 
 /* Workspace for cd_build_jk at the given precision (host-side, no device work). */

@@ -223,11 +223,13 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
 // Half transform over neighbour lists (FP64):
 //   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
 // tile: m = P (64), n = i (64), k = neighbour index.
-// With PLANES the FP64 result x is written split as x = b0 + b1 + b2 into three
-// BF16 planes (b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane
-// p at Yp + p * plane, row mu at mu * ldy: the operand of the 3 x BF16 exchange
-// product, split once here instead of in every tile that reads it.  With a
-// non-null Y64 the FP64 value is also written there (row mu at mu * ldy64).
+// OUT selects what is written: HALF_F64 the FP64 result; HALF_BF16X3 the FP64
+// result x split as x = b0 + b1 + b2 into three BF16 planes (b0 = bf16(x),
+// b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane p at Yp + p * plane, row mu
+// at mu * ldy: the operand of the 3 x BF16 exchange product, split once here
+// instead of in every tile that reads it; HALF_F32 the result rounded to FP32
+// (the operand of the FP32 exchange product).  In the last two forms a
+// non-null Y64 also receives the FP64 value (row mu at mu * ldy64).
 __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, __bf16 &b2)
 {
     b0 = (__bf16)(float)x;
@@ -236,7 +238,10 @@ __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, _
     b2 = (__bf16)(float)(r1 - (double)(float)b1);
 }
 
-template <bool PLANES>
+// Output forms of the half transform.
+enum HalfOut { HALF_F64 = 0, HALF_BF16X3 = 1, HALF_F32 = 2 };
+
+template <int OUT>
 __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
                                                      const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ nb_s,
@@ -278,10 +283,20 @@ __global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ 
             },
             acc, sA, sB);
     }
-    if (!PLANES) {
+    if (OUT == HALF_F64) {
         double *out = static_cast<double *>(Yv) + (int64_t)mu * ldy;
         for_each_acc(acc, 4, [&](int m, int n, double v) {
             if (p0 + m < M && n0 + n < ncol) out[(p0 + m) * ncol + n0 + n] = v;
+        });
+    } else if (OUT == HALF_F32) {
+        float *out = static_cast<float *>(Yv) + (int64_t)mu * ldy;
+        double *out64 = Y64 ? Y64 + (int64_t)mu * ldy64 : nullptr;
+        for_each_acc(acc, 4, [&](int m, int n, double v) {
+            if (p0 + m < M && n0 + n < ncol) {
+                const int64_t e = (p0 + m) * ncol + n0 + n;
+                out[e] = (float)v;
+                if (out64) out64[e] = v;   // the FP64 value as well (for C^T L C)
+            }
         });
     } else {
         __bf16 *out = static_cast<__bf16 *>(Yv) + (int64_t)mu * ldy;
@@ -361,30 +376,87 @@ __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int 
     K[e] = accumulate ? K[e] + s : s;
 }
 
-// Lmo[P][a][b] = sum_mu C1[mu][a] Y[mu][P q + b]   (Y from k_half_sparse with C2)
-__global__ __launch_bounds__(256) void k_tr2(const double *__restrict__ Y, int64_t ldy, int N,
-                                             const double *__restrict__ C1, int p, int q,
-                                             const int64_t *__restrict__ n_vectors,
-                                             int64_t p_base, double *__restrict__ Lmo)
+// Second half of the transform as one wide product over all vectors:
+//   O[a][c] = sum_mu C1[mu][a] Y[mu][c],   c = P q + b,   Lmo[P][a][b] = O[a][c]
+// (Y from k_half_sparse with C2, row mu holding the M q values of that
+// function).  Treating the vectors' columns as one long dimension pads only
+// the a side to the tile (O = 150 takes 160 rows) instead of both sides of
+// every vector's p x q block.  A 512-thread workgroup covers 32 RT rows a and
+// 64 columns c; wave w owns the 16 columns 16 (w % 4) and the RT row tiles of
+// half w / 4, so two waves share each SIMD and every wave runs the whole k
+// range (no partial sums to combine).  Operands go through LDS in k-chunks
+// of 32 with the next chunk loaded into registers meanwhile.
+constexpr int TR_TKC = 32;
+
+template <int RT>
+__global__ __launch_bounds__(512) void k_tr2w(const double *__restrict__ Y, int64_t ldy, int N,
+                                              const double *__restrict__ C1, int p, int q,
+                                              const int64_t *__restrict__ n_vectors,
+                                              double *__restrict__ Lmo)
 {
-    __shared__ double sU[2 * JKS::kSize];
-    double *sA = sU, *sB = sU + JKS::kSize;
-    const int64_t Pv = p_base + blockIdx.z;
-    if (Pv >= *n_vectors) return;
-    const int m0 = blockIdx.x * 64;   // a
-    const int n0 = blockIdx.y * 64;   // b
-    const double *Yp = Y + (Pv - p_base) * (int64_t)q;   // Y[mu][P q + b], row stride ldy
-    f64x4 acc[4];
+    constexpr int ROWS = 32 * RT;
+    constexpr int NA = ROWS * TR_TKC / 512, NB = 64 * TR_TKC / 512;   // loads per thread
+    __shared__ double sA[TR_TKC][ROWS];
+    __shared__ double sB[TR_TKC][64];
+    const int64_t ncol = *n_vectors * q;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    if (c0 >= ncol) return;
+    const int a0 = blockIdx.y * ROWS;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, cw = w & 3, rh = w >> 2;
+    // element u of this thread's chunk share: A (k, m) with m fastest, B (k, n) likewise
+    double ra[NA], rb[NB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 512 * u, k = e / ROWS, m = e % ROWS;
+            ra[u] = (k0 + k < N && a0 + m < p) ? C1[(int64_t)(k0 + k) * p + a0 + m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + 512 * u, k = e >> 6, n = e & 63;
+            rb[u] = (k0 + k < N && c0 + n < ncol) ? Y[(int64_t)(k0 + k) * ldy + c0 + n] : 0.0;
+        }
+    };
+    f64x4 acc[RT];
     zero_acc(acc);
-    gemm_tile<4, JK_TKC, true, true>(
-        0, N,
-        [&](int64_t k, int m) -> double { return C1[k * p + min(m0 + m, p - 1)]; },
-        [&](int64_t k, int n) -> double { return Yp[k * ldy + min(n0 + n, q - 1)]; },
-        acc, sA, sB);
-    double *out = Lmo + Pv * (int64_t)p * q;
-    for_each_acc(acc, 4, [&](int m, int n, double v) {
-        if (m0 + m < p && n0 + n < q) out[(int64_t)(m0 + m) * q + n0 + n] = v;
-    });
+    fetch(0);
+    for (int k0 = 0; k0 < N; k0 += TR_TKC) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 512 * u;
+            sA[e / ROWS][e % ROWS] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + 512 * u;
+            sB[e >> 6][e & 63] = rb[u];
+        }
+        __syncthreads();
+        if (k0 + TR_TKC < N) fetch(k0 + TR_TKC);
+#pragma unroll
+        for (int ks = 0; ks < TR_TKC; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            const double b = sB[kk][16 * cw + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const double a = sA[kk][16 * (RT * rh + r) + (lane & 15)];
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t c = c0 + 16 * cw + (lane & 15);
+    if (c < ncol) {
+        const int64_t P = c / q, b = c % q;
+        double *out = Lmo + P * (int64_t)p * q + b;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = a0 + 16 * (RT * rh + r) + mfma_row(lane, v);
+                if (a < p) out[(int64_t)a * q] = acc[r][v];
+            }
+    }
 }
 
 }  // namespace cdk

@@ -1,9 +1,10 @@
 // Reduced-precision forms of the exchange build (K); J is always built in
 // FP64 (it is bound by reading L).
 //
-//   FP32  : the half transform X^P = Lt^P C and the product K = sum_P X^P^T X^P
-//           both on v_mfma_f32_16x16x4f32, operands rounded to FP32 on load,
-//           FP32 accumulation inside k-slabs of 32 and FP64 across slabs.
+//   FP32  : the half transform X^P = Lt^P C runs in FP64 and writes X rounded
+//           to FP32 (k_half_sparse<HALF_F32>); the product K = sum_P X^P^T X^P
+//           runs on v_mfma_f32_16x16x4f32 (k_syrk_rows_lp), FP32 accumulation
+//           inside k-slabs of 32 and FP64 across slabs.
 //   BF16X3: the half transform runs in FP64 and writes X split into three BF16
 //           planes (k_half_sparse<true>); the product K reads the planes
 //           (k_syrk_bf16x3).  Every operand x is split as x = b0 + b1 + b2
@@ -139,56 +140,6 @@ __device__ __forceinline__ void lp_tile(int64_t kbeg, int64_t kend, LA la, LB lb
             in_slab = 0;
         }
     }
-}
-
-// Half transform over neighbour lists, reduced precision, FP32 out:
-//   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
-template <int MODE>
-__global__ __launch_bounds__(256) void k_half_sparse_lp(const double *__restrict__ LT, int64_t ldt,
-                                                        const int64_t *__restrict__ off,
-                                                        const int32_t *__restrict__ nb_s,
-                                                        const int32_t *__restrict__ nb_r,
-                                                        const double *__restrict__ C, int ncol,
-                                                        const int64_t *__restrict__ n_vectors,
-                                                        float *__restrict__ Y, int64_t ldy)
-{
-    __shared__ __align__(16) unsigned char smem[LpStage<MODE>::kBytes];
-    const int64_t M = *n_vectors;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
-    if (p0 >= M) return;
-    const int n0 = blockIdx.y * 64;
-    const int mu = blockIdx.z;
-    const int64_t j0 = off[mu], deg = off[mu + 1] - j0;
-    double acc[4][4] = {};
-    __shared__ int sNs[NB_SEG], sNr[NB_SEG];   // neighbour list, staged in segments
-    for (int64_t seg = 0; seg < deg; seg += NB_SEG) {
-        const int len = (int)min((int64_t)NB_SEG, deg - seg);
-        __syncthreads();
-        for (int e = threadIdx.x; e < len; e += 256) {
-            sNs[e] = nb_s[j0 + seg + e];
-            sNr[e] = nb_r[j0 + seg + e];
-        }
-        __syncthreads();
-        lp_tile<MODE, false>(
-            seg, seg + len,
-            [&](int64_t k, int m) -> double {
-                return LT[(int64_t)sNr[k - seg] * ldt + min(p0 + m, M - 1)];
-            },
-            [&](int64_t k, int n) -> double {
-                return C[(int64_t)sNs[k - seg] * ncol + min(n0 + n, ncol - 1)];
-            },
-            acc, smem);
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float *out = Y + (int64_t)mu * ldy;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t P = p0 + 16 * r + lp_row(lane, v);
-            const int i = n0 + 16 * w + (lane & 15);
-            if (P < M && i < ncol) out[P * ncol + i] = (float)acc[r][v];
-        }
 }
 
 // Partial K from row-major FP32 X, reduced precision:

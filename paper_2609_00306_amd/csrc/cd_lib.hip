@@ -837,6 +837,26 @@ int bx_subsplits(int pairs, int n_cu)
     return best;
 }
 
+// The second half of the transform (k_tr2w): row tiles per half-workgroup for
+// p rows, and the launch.
+int tr2_row_tiles(int p) { return std::max(1, std::min(5, (p + 31) / 32)); }
+
+cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int p, int q,
+                     const int64_t *n_vectors, int64_t max_vectors, double *Lmo, hipStream_t st)
+{
+    const int rt = tr2_row_tiles(p);
+    const dim3 grid((unsigned)blocks_of(max_vectors * (int64_t)q, 64),
+                    (unsigned)blocks_of(p, 32 * rt));
+    switch (rt) {
+    case 1: k_tr2w<1><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    case 2: k_tr2w<2><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    case 3: k_tr2w<3><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    case 4: k_tr2w<4><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    default: k_tr2w<5><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    }
+    return CD_OK;
+}
+
 // Number of partial K matrices of the exchange product at a precision.
 int jk_splits(int N, int n_cu, cd_precision prec)
 {
@@ -909,7 +929,7 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     const int64_t xb = (3 * bx_rows(N) * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
     w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
-    w.X64 = (p.Lmo && prec == CD_BF16X3) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
+    w.X64 = (p.Lmo && prec != CD_FP64) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
     w.bytes = c.off;
     return w;
 }
@@ -951,9 +971,6 @@ cd_status cd_query_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
 cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision prec,
                       uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
-    for (int32_t i = 0; i < count && probs; ++i)
-        if (probs[i].Lmo && prec == CD_FP32)
-            return fail(CD_ERR_INVALID_ARG, "problem %d: Lmo needs FP64 or 3 x BF16", i);
     size_t need = 0;
     cd_status s = cd_query_jk(probs, count, prec, &need);
     if (s) return s;
@@ -1011,18 +1028,19 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                     hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
                     return fail(CD_ERR_DEVICE, "fork failed");
             }
-            k_tr2<<<dim3((unsigned)blocks_of(O, 64), (unsigned)blocks_of(O, 64), (unsigned)mv), 256,
-                    0, st2>>>(X64, ldx, (int)N, p.C, O, O, p.n_vectors, 0, p.Lmo);
-            return CD_OK;
+            return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, p.Lmo, st2);
         };
         if (prec == CD_FP64) {
-            k_half_sparse<false><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<HALF_F64><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                         p.n_vectors, w.X, ldx, 0, nullptr, 0);
             if (p.Lmo && (s = second_half(w.X))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
-            k_half_sparse_lp<LP_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C,
-                                                            O, p.n_vectors, X32, ldx);
+            // X in FP64 (matrix cores), written rounded to FP32 (and in FP64 for
+            // C^T L C); the exchange product then runs on FP32 matrix cores
+            k_half_sparse<HALF_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+                                                           p.n_vectors, X32, ldx, 0, w.X64, ldx);
+            if (p.Lmo && (s = second_half(w.X64))) return s;
             k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, sp>>>(X32, ldx, (int)N, p.n_vectors, O,
                                                           nsplit, w.Kp);
         } else {
@@ -1030,7 +1048,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             // exchange product then runs on BF16 matrix cores from the planes
             const int64_t ldb = bf16_ld(ldx), plane = bx_rows(N) * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
-            k_half_sparse<true><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<HALF_BF16X3><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
                                                        p.n_vectors, Xp, ldb, plane, w.X64, ldx);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             const int pairs = bx_pairs((int)N);
@@ -1092,15 +1110,14 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
         const int64_t ldy = mv * p.q;
         if (n > 0) {
             launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
-            k_half_sparse<false><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
+            k_half_sparse<HALF_F64><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
                                         (unsigned)N),
                                    256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
                                                  p.n_vectors, Y, ldy, 0, nullptr, 0);
         } else {
             k_fill_f64<<<256, 256, 0, st>>>(Y, mv * N * p.q, 0.0);
         }
-        k_tr2<<<dim3((unsigned)blocks_of(p.p, 64), (unsigned)blocks_of(p.q, 64), (unsigned)mv),
-                256, 0, st>>>(Y, ldy, (int)N, p.C1, p.p, p.q, p.n_vectors, 0, p.Lmo);
+        launch_tr2(Y, ldy, (int)N, p.C1, p.p, p.q, p.n_vectors, mv, p.Lmo, st);
         if ((s = check_launch("transform kernels"))) return s;
     }
     if (flags & CD_SYNC) {

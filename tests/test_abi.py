@@ -175,15 +175,11 @@ def test_argument_validation_without_device(lib):
                              None) == cdlib.CD_ERR_INVALID_ARG
     assert lib.cd_zdecompose(ctypes.byref(zp), 1e-6, 0, ctypes.c_void_p(0x1000), ws.value,
                              None) == cdlib.CD_ERR_INVALID_ARG
-    # J/K: the optional MO-basis output is refused with FP32 K, and an unknown
-    # precision is refused, both before any device work
+    # J/K: an unknown precision is refused before any device work
     jp = cdlib.cd_jk_problem(4, 0, 0, None, None, ctypes.c_void_p(0x1000), 2,
                              ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000),
                              ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000),
                              ctypes.c_void_p(0x1000))
-    assert lib.cd_build_jk(ctypes.byref(jp), 1, cdlib.PRECISIONS["fp32"], 0, None, 0,
-                           None) == cdlib.CD_ERR_INVALID_ARG
-    assert b"Lmo" in lib.cd_last_error()
     assert lib.cd_query_jk(ctypes.byref(jp), 1, 7, ctypes.byref(ws)) == cdlib.CD_ERR_INVALID_ARG
     assert b"precision" in lib.cd_last_error()
     # SCF: sizes and pointers are checked on the host

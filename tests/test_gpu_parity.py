@@ -153,13 +153,13 @@ def test_jk_fp64_parity(name, schwarz):
     assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("name", ["C1", "C2"])
 def test_jk_with_fused_transform(name, prec):
-    """The J/K build with the optional MO-basis output (FP64, and 3 x BF16,
-    whose half transform is FP64 before the split): J and K as without it, and
-    C^T L^P C equal to the stand-alone transform with C1 = C2 = C and to the
-    oracle's."""
+    """The J/K build with the optional MO-basis output (FP64, and FP32 and
+    3 x BF16, whose half transform is FP64 before rounding or splitting): J and
+    K as without it, and C^T L^P C equal to the stand-alone transform with
+    C1 = C2 = C and to the oracle's."""
     m = config_molecule(name)
     d, M = run_gpu(m, 1e-6, 1e-12)
     rp, ref = check_against_oracle(m, 1e-6, 1e-12, d, M)
@@ -171,8 +171,11 @@ def test_jk_with_fused_transform(name, prec):
     assert torch.equal(jk.Lmo[:M], T[:M])
     exp = oracle.transform(m.n_basis, rp, ref.L, m.C, m.C)
     assert np.abs(jk.Lmo[:M].cpu().numpy() - exp).max() <= TOL_L
-    with pytest.raises(cdlib.CDError):
+    # the FP32 build with the MO output needs the FP64 copy of the half
+    # transform: a workspace sized for FP64 is refused
+    with pytest.raises(cdlib.CDError) as e:
         cdlib.run_jk(cdlib.prepare_jk(d, m.C, "fp64", lmo=True), "fp32", sync=True)
+    assert e.value.status == cdlib.CD_ERR_WORKSPACE
 
 
 def test_transform_parity():
@@ -292,7 +295,7 @@ def test_autotune_shapes_give_the_same_decomposition():
 
 
 @pytest.mark.parametrize("prec,lmo", [("fp64", False), ("fp64", True), ("fp32", False),
-                                      ("bf16x3", False), ("bf16x3", True)])
+                                      ("fp32", True), ("bf16x3", False), ("bf16x3", True)])
 def test_batched_jk_matches_single(prec, lmo):
     """Several problems in one call (on the library's two streams) give the
     single-problem results bit for bit, with and without the MO output, and
