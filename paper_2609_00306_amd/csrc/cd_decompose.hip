@@ -263,8 +263,13 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
     const int g = (int)blockIdx.x - B.block_begin[mol];
     const int64_t n_act = P.n_act;
     const int64_t ldT = P.ldT;
-    const int64_t s0 = (int64_t)g * P.slice;
-    const int ns = (int)max((int64_t)0, min((int64_t)P.slice, n_act - s0));
+    // This workgroup's active rows: slots g, g + G, g + 2G, .. (dealt round
+    // robin, so every workgroup holds rows from the whole molecule and about
+    // as many of them stay eligible as in any other workgroup: the candidate-
+    // column product, which all workgroups wait for, is balanced).  Local row
+    // i is slot g + i G; slots ascend with i.
+    const int ns = (n_act > g) ? (int)min((int64_t)P.slice, (n_act - g + G - 1) / G) : 0;
+    auto slot_of = [&](int i) -> int64_t { return (int64_t)g + (int64_t)i * G; };
     const double tau = P.tau;
     const double ftol = (tau <= 0.0)
         ? (double)P.n_rows * 0x1p-53 * __longlong_as_double((long long)*P.d1max_bits) : 0.0;
@@ -279,8 +284,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         return;
     }
     for (int i = tid; i < ns; i += 256) {
-        sD[i] = P.D_act[s0 + i];
-        sRow[i] = P.rows[P.act_row[s0 + i]];
+        sD[i] = P.D_act[slot_of(i)];
+        sRow[i] = P.rows[P.act_row[slot_of(i)]];
     }
     int64_t K = k_first;
     int64_t batch = 0;
@@ -317,10 +322,10 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                     const double d = sD[i];
                     if (d != d || d == INFINITY) {
                         v[j] = INFINITY;
-                        x[j] = (int)(s0 + i);
+                        x[j] = (int)slot_of(i);
                     } else if (eligible(d, tau, ftol)) {
                         v[j] = d;
-                        x[j] = (int)(s0 + i);
+                        x[j] = (int)slot_of(i);
                     }
                 }
             }
@@ -459,8 +464,8 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
         for (int i = tid; i < ns; i += 256) sCand[i] = -1;
         __syncthreads();
         if (tid < nq) {
-            const int64_t sl = (int64_t)sQ[tid] - s0;
-            if (sl >= 0 && sl < ns) sCand[sl] = tid;
+            const int64_t dq = (int64_t)sQ[tid] - g;
+            if (dq >= 0 && dq % G == 0 && dq / G < ns) sCand[dq / G] = tid;
         }
         __syncthreads();
         stamp(P, g, batch, 2);
@@ -480,7 +485,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
 #pragma unroll
             for (int u = 0; u < S1K::kNA; ++u) {
                 const int m = S1K::row_of(u);
-                aoff[u] = (m < rows_m) ? (s0 + sList[pb + m]) * ldT : -1;
+                aoff[u] = (m < rows_m) ? slot_of(sList[pb + m]) * ldT : -1;
             }
 #pragma unroll
             for (int u = 0; u < S1K::kNB; ++u) {
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
                 const int m = e >> 6, n = e & 63;
                 if (n < nq) {
                     const int li = pb + m;
-                    const int64_t slot = s0 + sList[li];
+                    const int64_t slot = slot_of(sList[li]);
                     const int o = m * 65 + n;
                     const double sum =
                         (rt <= 2) ? ((sU[o] + sU[o + PR]) + sU[o + 2 * PR]) + sU[o + 3 * PR] : sU[o];
@@ -632,7 +637,7 @@ __global__ __launch_bounds__(256) void k_step1(const Step1Batch B)
             // ---- apply the accepted pivots to own eligible rows as they appear
             for (int li = tid - 64; li < cnt; li += 192) {
                 const int sl = sList[li];
-                const int64_t slot = s0 + sl;
+                const int64_t slot = slot_of(sl);
                 double d = sD[sl];
                 double l[QMAX];
                 bool fin = false;

@@ -32,7 +32,7 @@ struct Step1Params {
     int64_t max_vectors;
     double eta;                // span factor: 1 = exact pivoting, < 1 = qualified-set acceptance
     int32_t q;                 // candidate batch size (<= QMAX)
-    int32_t slice;             // active rows per workgroup
+    int32_t slice;             // at most this many active rows per workgroup (dealt round robin)
     uint32_t spin_limit;
     int64_t *timeline;         // optional: [timeline_cap][8] device clock stamps per batch
     int64_t *timeline_count;   // optional: number of batches
