@@ -35,25 +35,39 @@ PRECISIONS = ("fp64", "fp32", "bf16x3")
 #: precisions whose J/K build also writes C^T L C (the transform fused into it)
 FUSED = ("fp64", "fp32", "bf16x3")
 
-# HBM bytes per launch of the decomposition kernels on a workload, from two
-# rocprofv3 --pmc runs of the default bench command (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
-# a plain 1 GiB device copy (`bench.py --copy-probe 1024`): FETCH_SIZE reads
-# 524 302 KiB there (factor 2.0), WRITE_SIZE 1 048 576 KiB (factor 1.0).  The
-# figures belong to the kernel sources they were taken on; once those change
-# the traffic is reported as null until the counters are taken again.
-KERNEL_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
+# HBM bytes per launch of a kernel on a workload, from two rocprofv3 --pmc runs
+# of the bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch; commands in
+# profiles/hbm_bytes_1200fn_tau1e-6.md), each scaled by what the same counter
+# reads for a plain 1 GiB device copy (`bench.py --copy-probe 1024`): FETCH_SIZE
+# reads 524 302 KiB there (factor 2.0), WRITE_SIZE 1 048 576 KiB (factor 1.0).
+# The figures belong to the kernel sources they were taken on; once those
+# change the traffic is reported as null until the counters are taken again.
+DECOMP_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_mfma.hpp",
                   "paper_2609_00306_amd/csrc/cd_device.hpp",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.2, 1048576.0 / 1048576.0
-COUNTERS = {}   # (config, tau) -> {"sources_sha256", "fetch_kib": {kernel: KiB}, "write_kib": ..}
+BF16_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
+                "paper_2609_00306_amd/csrc/cd_device.hpp",
+                "paper_2609_00306_amd/csrc/cd_mfma.hpp"]
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.25, 1048576.0 / 1048576.0
+_DECOMP_SHA = "bf68eecef8680557d5f29517f9b55c2681fdc919d5c3a0cd6f50b173fe0ff9d7"
+COUNTERS = {
+    ("C5", 1e-6): {
+        "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
+                    "fetch_kib": 68393270.9, "write_kib": 2676555.9},
+        "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
+                    "fetch_kib": 3722680.5, "write_kib": 355594.6},
+        "k_syrk_bf16x3": {"sources": BF16_SOURCES,
+                          "sha256": "204409b35944e4b93070dd9c462a9bcd086808ae8eb2c4ab79610cdb16f6d335",
+                          "fetch_kib": 19512166.2, "write_kib": 198720.0},
+    },
+}
 
 
-def kernel_sources_sha256():
+def sources_sha256(files):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -61,12 +75,10 @@ def kernel_sources_sha256():
 
 def counter_traffic(kernel, config, tau):
     """HBM bytes per launch of 'kernel' from the recorded counters, or None."""
-    c = COUNTERS.get((config, tau))
-    if c is None or kernel not in c["fetch_kib"]:
+    c = COUNTERS.get((config, tau), {}).get(kernel)
+    if c is None or sources_sha256(c["sources"]) != c["sha256"]:
         return None
-    if kernel_sources_sha256() != c["sources_sha256"]:
-        return None
-    return 1024.0 * (c["fetch_kib"][kernel] * FETCH_SCALE + c["write_kib"][kernel] * WRITE_SCALE)
+    return 1024.0 * (c["fetch_kib"] * FETCH_SCALE + c["write_kib"] * WRITE_SCALE)
 
 
 def cpu_baseline(m, tau, schwarz, M_full, prefix):
@@ -467,6 +479,10 @@ def main():
             if p in FUSED:
                 e["error_vs_fp64"]["max_abs_dLmo"] = float(
                     (jks[p].Lmo[:M] - ref.Lmo[:M]).abs().max())
+        if p == "bf16x3":
+            t = counter_traffic("k_syrk_bf16x3", args.config, tau)
+            e["exchange_product_hbm_bytes"] = t
+            e["exchange_product_planes_bytes"] = 6.0 * (-(-N // 128) * 128) * M * O
             e["speedup_step_vs_fp64"] = runs["fp64"]["ms_per_step"] / r["ms_per_step"]
             e["speedup_jk_vs_fp64"] = ((runs["fp64"]["jk"] + 0.0) /
                                        (r["jk"] + (0.0 if p in FUSED else r["transform"])))
