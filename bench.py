@@ -479,13 +479,12 @@ def main():
             if p in FUSED:
                 e["error_vs_fp64"]["max_abs_dLmo"] = float(
                     (jks[p].Lmo[:M] - ref.Lmo[:M]).abs().max())
-        if p == "bf16x3":
-            t = counter_traffic("k_syrk_bf16x3", args.config, tau)
-            e["exchange_product_hbm_bytes"] = t
-            e["exchange_product_planes_bytes"] = 6.0 * (-(-N // 128) * 128) * M * O
             e["speedup_step_vs_fp64"] = runs["fp64"]["ms_per_step"] / r["ms_per_step"]
             e["speedup_jk_vs_fp64"] = ((runs["fp64"]["jk"] + 0.0) /
                                        (r["jk"] + (0.0 if p in FUSED else r["transform"])))
+        if p == "bf16x3":
+            e["exchange_product_hbm_bytes"] = counter_traffic("k_syrk_bf16x3", args.config, tau)
+            e["exchange_product_planes_bytes"] = 6.0 * (-(-N // 128) * 128) * M * O
         precision[p] = e
 
     # per-batch device-clock stamps of the pivot selection (one untimed run)

@@ -468,6 +468,16 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
     cd_status s = CD_OK;
     DevInfo di;
     if ((s = dev_info(di))) return s;
+    // the pivot selection holds at most SMAX active rows per workgroup and one
+    // workgroup per compute unit (at most S1_MAXG): refused before any device work
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t g_need = blocks_of(probs[i].n_active, SMAX);
+        if (probs[i].max_vectors > 0 && g_need > std::min(di.n_cu, S1_MAXG))
+            return fail(CD_ERR_UNSUPPORTED,
+                        "problem %d: %lld active rows exceed the pivot-selection capacity "
+                        "(%d rows per workgroup, %d workgroups)",
+                        i, (long long)probs[i].n_active, SMAX, std::min(di.n_cu, S1_MAXG));
+    }
 
     auto record = [&](int k) -> cd_status {
         if (opts->events && hipEventRecord(static_cast<hipEvent_t>(opts->events[k]), st) != hipSuccess)
@@ -539,10 +549,6 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
                                        std::max<int64_t>(1, blocks_of(probs[i].n_active, min_rows)));
         return std::max(g, gmin(i));
     };
-    for (int i : order)
-        if (gmin(i) > gcap)
-            return fail(CD_ERR_UNSUPPORTED, "problem %d: %lld active rows exceed the step-1 capacity",
-                        i, (long long)probs[i].n_active);
     size_t pos = 0;
     while (pos < order.size()) {
         std::vector<int> grp;

@@ -124,6 +124,9 @@ CONFIGS: Dict[str, dict] = {
                n_occ=120, seed=3, taus=(1e-6,), schwarz=1e-12),
     "C5": dict(n_centres=300, box=24.0, exponents=GEOMETRIC4, n_occ=150, seed=5,
                taus=(1e-6,), schwarz=1e-12),
+    # the same molecule with every one of the N(N+1)/2 = 720 600 pairs kept
+    "C5u": dict(n_centres=300, box=24.0, exponents=GEOMETRIC4, n_occ=150, seed=5,
+                taus=(1e-6,), schwarz=0.0),
 }
 
 #: batched workload: 64 molecules, seeds 4000+i, c ~ U{13..100} centres,

@@ -469,6 +469,73 @@ def test_large_workload_properties(name):
     assert np.abs(X - L[:, sel]).max() <= 1e-9
 
 
+def test_unscreened_large_workload():
+    """The 1200-function molecule with no screening: all 720 600 pairs are rows
+    and L holds 32 GB.  The rows screened out at 1e-12 have D1 far below tau,
+    so the active rows, the pivots and every kept row's arithmetic are those of
+    the screened run: pivots, pivot values and the vectors of the rows both runs
+    share agree bit for bit.  The extra rows obey what holds at any size
+    (Sec. 2): final residual < tau, |A - L L^T| <= tau on sampled entries, and
+    the row-sampled replay of Eq. CVsLT with the oracle's integrals."""
+    from scipy.linalg import solve_triangular
+    m = config_molecule("C5")
+    tau = 1e-6
+    ref, Mr = run_gpu(m, tau, 1e-12)
+    d = cdlib.allocate(m.xyz, m.alpha, tau, 0.0, max_vectors=Mr + 8)
+    assert d.n_rows == 720600 and d.n_active == ref.n_active
+    cdlib.run_decompose([d], tau, 0.0)
+    torch.cuda.synchronize()
+    M = d.M()
+    assert int(d.status.item()) == 0 and M == Mr
+    rp_s = ref.row_pair
+    pos = torch.searchsorted(d.row_pair, rp_s)
+    assert torch.equal(d.row_pair[pos], rp_s)
+    piv_u = d.row_pair[d.pivots[:M]]
+    assert torch.equal(piv_u, rp_s[ref.pivots[:M]])
+    assert torch.equal(d.pivot_values[:M], ref.pivot_values[:M])
+    for k0 in range(0, M, 512):   # vectors of the shared rows, in slabs (bit for bit)
+        k1 = min(M, k0 + 512)
+        assert torch.equal(d.L[k0:k1].index_select(1, pos), ref.L[k0:k1])
+    assert torch.equal(d.diag[pos], ref.diag)
+    assert float(d.diag.max()) < tau and float(d.diag.min()) >= -1e-12
+    # the rows only the unscreened run has
+    extra = torch.ones(d.n_rows, dtype=torch.bool, device=d.L.device)
+    extra[pos] = False
+    ex = torch.nonzero(extra).flatten()
+    assert ex.numel() == 720600 - ref.n_rows
+    rng = np.random.default_rng(31)
+    sel = torch.as_tensor(np.sort(rng.choice(ex.numel(), 12, replace=False)), device=ex.device)
+    rows = ex[sel]
+    rp = d.row_pair.cpu().numpy()
+    piv = d.pivots[:M].cpu().numpy()
+    Lsel = d.L[:M].index_select(1, rows).cpu().numpy()
+    LB = d.L[:M].index_select(1, d.pivots[:M]).cpu().numpy().T.copy()
+    r_np = rows.cpu().numpy()
+    A = oracle.eri_matrix(m.xyz, m.alpha, np.concatenate([rp[piv], rp[r_np]]))
+    X = solve_triangular(LB, A[:M, M:], lower=True)
+    assert np.abs(X - Lsel).max() <= 1e-9
+    Aext = A[M:, M:]
+    assert np.abs(Aext - Lsel.T @ Lsel).max() <= tau
+    assert np.abs(np.diag(Aext) - (Lsel ** 2).sum(0) - d.diag[rows].cpu().numpy()).max() <= 1e-12
+
+
+def test_active_rows_beyond_the_selection_capacity_are_refused():
+    """The pivot selection holds at most 256 active rows per workgroup and 256
+    workgroups (65 536 rows); beyond that cd_decompose refuses on the host with
+    CD_ERR_UNSUPPORTED before any device work: the 400-function molecule with
+    no screening at tau = 0 has all 80 200 rows active."""
+    m = config_molecule("C2")
+    d = cdlib.allocate(m.xyz, m.alpha, 0.0, 0.0, max_vectors=16)
+    assert d.n_active == 80200
+    st0 = d.status.clone()
+    with pytest.raises(cdlib.CDError) as e:
+        cdlib.run_decompose([d], 0.0, 0.0)
+    assert e.value.status == cdlib.CD_ERR_UNSUPPORTED
+    assert b"capacity" in cdlib.load().cd_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(d.status, st0)
+
+
 # Second-order energy from transformed vectors (CD-based MP2, Secs. 5 and 7).
 # Both sides add the same terms in different orders (FP64 matrix-core
 # products over P, tile-wise sums over a, b): with |terms| summed in S, the
