@@ -500,9 +500,9 @@ def main():
     st = st[np.all(st > 0, axis=1)]          # batches that ran every stage
     breakdown = {k: float((st[:, i + 1] - st[:, i]).sum()) for i, k in enumerate(stages)
                  if st.shape[0]}
-    nblk = (M + 63) // 64
+    nblk = (M + 127) // 128
     s2 = tl[1 + 8 * cap:1 + 8 * cap + 8 * min(nblk, cap)].reshape(-1, 8)[:, :6].astype(float) / 100.0
-    s2_stages = ["off_block_product", "stage", "integrals", "substitution", "store"]
+    s2_stages = ["off_block_product", "integrals", "substitution", "residuals", "store"]
     s2 = s2[np.all(s2 > 0, axis=1)]
     s2_breakdown = {k: float((s2[:, i + 1] - s2[:, i]).sum()) for i, k in enumerate(s2_stages)
                     if s2.shape[0]}

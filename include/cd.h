@@ -117,7 +117,7 @@ typedef struct {
  * choice).  cd_autotune measures and returns one; cd_decompose takes one
  * through cd_decomp_opts.tuning. */
 typedef struct {
-    int32_t step2_row_tiles;   /* all-row solve: rows per workgroup in units of 16, 2..8 */
+    int32_t step2_row_tiles;   /* all-row solve: rows per workgroup in units of 16, 2..7 */
     int32_t step1_min_rows;    /* pivot selection: at least this many active rows per
                                   workgroup (fewer, fuller workgroups), 16..256 */
 } cd_tuning;

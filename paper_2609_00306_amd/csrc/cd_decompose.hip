@@ -191,6 +191,12 @@ constexpr int SMAX = 256;      // active rows per workgroup
 constexpr int NOMSORT = 1024;  // union capacity (workgroups * CNOM)
 constexpr int S1_MAXG = NOMSORT / CNOM;
 using S1K = SplitK<3>;         // candidate-column product: 48 rows per pass, k-chunks of 16
+// all-row solve
+constexpr int S2_NB = 128;    // vectors per block
+constexpr int S2_TK = 16;     // k per chunk of the off-block product
+constexpr int S2_NST = 3;     // chunk buffers (loads run two chunks ahead)
+constexpr int S2_TLD = 130;   // row stride (doubles) of the right-hand side in LDS
+
 constexpr int S1_LROWS = 64;      // eligible rows whose candidate columns stay in LDS
 constexpr int S1_HLD = QMAX + 2;   // row length of the in-batch history (16-byte aligned rows)
 constexpr int S1_BLOCK = QMAX * (QMAX + 1) + QMAX * S1_HLD;
@@ -795,54 +801,148 @@ __global__ __launch_bounds__(64) void k_block_inverse(const PivotBatch B)
     for (int r = 0; r < 64; ++r) g[r * 64 + c] = sS[r][c];
 }
 
+// Inverse-transposed 128 x 128 pivot blocks of the all-row solve, composed from
+// the two 64-blocks it holds.  With the pivot block of vectors [b0, b0 + 128)
+// split as S = [[S1, 0], [C, S2]] (S1, S2 the 64-blocks of k_block_inverse,
+// C[i][j] = L^{b0+j} at pivot row P_{b0+64+i}),
+//     S^{-T} = [[G1, X], [0, G2]],  G1 = S1^{-T}, G2 = S2^{-T}, X = -G1 C^T G2.
+// The result is written in the operand order of the solve's FP64 MFMA so that
+// each lane reads its values as consecutive 16-byte pieces:
+//     Gf[blk][cg][s2][lane][e] = G[4 s + lane / 16][16 cg + lane % 16],  s = 2 s2 + e,
+// for the 8 column groups cg of 16 columns and the 32 k-steps s of 4.  In a
+// ragged last block the unused part of G is the identity (S2 of a ragged block
+// is, and C is zero on the missing rows), which the solve never reads into
+// a stored vector.
+__global__ __launch_bounds__(256) void k_block_g128(const PivotBatch B)
+{
+    const int mol = pivot_mol(B.g128_begin, B.count);
+    const PivotMol &Q = B.m[mol];
+    const int64_t blk = (int64_t)blockIdx.x - B.g128_begin[mol];
+    const int64_t k0 = *Q.k_start;
+    const int64_t b0 = k0 + blk * S2_NB;
+    const int64_t M = *Q.n_vectors;
+    if (k0 < 0 || b0 >= M) return;
+    const int nb2 = (int)min((int64_t)S2_NB, M - b0) - 64;   // vectors of the second half
+    __shared__ double sG1[64][65], sG2[64][65], sW[64][65];
+    const int tid = threadIdx.x;
+    const double *g1 = Q.G + (2 * blk) * 4096, *g2 = g1 + 4096;
+    for (int e = tid; e < 4096; e += 256) {
+        const int i = e >> 6, j = e & 63;
+        sG1[i][j] = g1[e];
+        sG2[i][j] = (nb2 > 0) ? g2[e] : 0.0;
+        sW[i][j] = (i < nb2) ? Q.Lp[(b0 + 64 + i) * Q.ldp + b0 + j] : 0.0;   // C
+    }
+    __syncthreads();
+    // thread: row i = tid / 4 of a 64 x 64 product, columns 16 (tid % 4) ..
+    const int i = tid >> 2, c0 = 16 * (tid & 3);
+    double y[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) y[c] = 0.0;
+    for (int k = 0; k < 64; ++k) {   // Y = C^T G2
+        const double a = sW[k][i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) y[c] = fma(a, sG2[k][c0 + c], y[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sW[i][c0 + c] = y[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) y[c] = 0.0;
+    for (int k = 0; k < 64; ++k) {   // X = -G1 Y
+        const double a = sG1[i][k];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) y[c] = fma(a, sW[k][c0 + c], y[c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sW[i][c0 + c] = -y[c];
+    __syncthreads();
+    double *out = Q.Gf + blk * (S2_NB * S2_NB);
+    for (int e = tid; e < S2_NB * S2_NB; e += 256) {
+        const int lane = (e >> 1) & 63, s = 2 * ((e >> 7) & 15) + (e & 1), cg = e >> 11;
+        const int k = 4 * s + (lane >> 4), n = 16 * cg + (lane & 15);
+        double v;
+        if (k < 64) v = (n < 64) ? sG1[k][n] : sW[k][n - 64];
+        else v = (n < 64) ? 0.0 : sG2[k - 64][n - 64];
+        out[e] = v;
+    }
+}
+
 // ---------------------------------------------------------------- step 2
-// Every row r: L[K][r] = [ (r|P_K) - sum_{J<K} L[J][r] Lp[K][J] ] / sqrt(d_K),
-// blocked over 64 vectors.  The off-block sum is an FP64 MFMA product over a
-// (16 RT)-row tile; the ERIs (r|P_K) are generated into the right-hand side,
-// and the in-block triangular part is a second MFMA product with the block's
-// inverse-transposed pivot block G.  Also the final residual diagonal (R4: a
-// row is zeroed when it is chosen as pivot).
-// k-chunk of the all-row solve: 64 where the prefetch registers still fit
-// without spilling (checked with the compiler's resource report), else 32.
-__host__ __device__ constexpr int s2_tkc(int rt) { return (rt <= 3) ? 64 : 32; }
+// Every row r: L[K][r] = [ (r|P_K) - sum_{J<K} L[J][r] Lp[K][J] ] / sqrt(d_K)
+// (Sec. 3, Eq. CVsLT), blocked over 128 vectors.  A 512-thread workgroup owns
+// 16 RT rows; for each block it forms
+//   off-block product  P = A B^T,  A[m][k] = L[k][r0 + m], B[n][k] = Lp[b0 + n][k], k < b0
+//   right-hand side    T = (r|P_K) - P
+//   in-block solve     L_blk = T G       (G: inverse-transposed 128 x 128 pivot block)
+// and the final residual diagonal (a row is zeroed when it is chosen as pivot).
+//
+// Wave w owns 16 of the block's 128 columns (group cg: w for w < 4, 11 - w
+// otherwise, so the two waves of a SIMD share the triangular in-block work
+// equally) and all RT row tiles, one v_mfma_f64_16x16x4f64 accumulator per
+// tile.  The off-block product streams 16-wide k-chunks through three LDS
+// buffers, loaded straight from memory into LDS two chunks ahead of the
+// products (global_load_lds; one barrier per chunk):
+//   A part: [k][m], rows of 16 RT doubles, 4-byte pieces (L's rows have any
+//           parity, so 16-byte pieces could be misaligned); lane l of piece
+//           v of wave w writes half l % 2 of double 32 (8 v + w) + l / 2;
+//   B part: [n][16 k] in 16-byte pieces, the piece of k-pair g of row n stored
+//           at g ^ ((n / 2) % 8), so the 16 rows one half-wave reads fall on
+//           16 different bank groups.
+// Rows past the matrix are read as the tile's last row and columns past the
+// block as its last pivot row: finite values in accumulator rows and columns
+// that are never stored.  The right-hand side and the block result go through
+// one LDS array T of rows of S2_TLD doubles, which reuses the chunk buffers.
+// (r|P) - t, kept out of line: inlined, the ERI's registers and constants
+// crowd the off-block product's loop, whose LDS reads then no longer run ahead
+// of the matrix instructions.
+__device__ __attribute__((noinline)) double s2_rhs(const RowRec &r, const RowRec &p, double t)
+{
+    return eri(r, p) - t;
+}
+
+template <int RT>
+struct S2Lds {
+    static constexpr int R = 16 * RT;
+    static constexpr int kA = R * S2_TK;                 // A part of a chunk (doubles)
+    static constexpr int kB = S2_NB * S2_TK;             // B part of a chunk
+    static constexpr int kChunk = kA + kB;
+    static constexpr int kT = R * S2_TLD;
+    static constexpr int kU = (S2_NST * kChunk > kT) ? S2_NST * kChunk : kT;
+    static constexpr int kALoads = kA / 32 / 8;          // 4-byte-piece loads per wave (RT)
+    static constexpr int kBLoads = kB / 128 / 8;         // 16-byte-piece loads per wave (2)
+    static_assert(kALoads * 32 * 8 == kA && kBLoads * 128 * 8 == kB, "whole loads per wave");
+    static_assert(S2_NST == 3 || S2_NST == 4, "the chunk loop's waits cover 3 or 4 buffers");
+};
 
 template <int RT>
 __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
 {
+    using S = S2Lds<RT>;
+    constexpr int R = S::R;
     int mol = 0;
     while (mol + 1 < B.count && (int)blockIdx.x >= B.tile_begin[mol + 1]) ++mol;
     const Step2Mol &Q = B.m[mol];
-    const RowRec *__restrict__ rows = Q.rows;
     const int64_t n_rows = Q.n_rows;
     const RowRec *__restrict__ prow = Q.prow;
     const double *__restrict__ Lp = Q.Lp;
     const int64_t ldp = Q.ldp;
-    const double *__restrict__ Ginv = Q.Ginv;
-    const int32_t *__restrict__ pivot_of_row = Q.pivot_of_row;
     double *__restrict__ L = Q.L;
-    double *__restrict__ diag = Q.diag;
     const int tile = (int)blockIdx.x - B.tile_begin[mol];
-    // optional device-clock stamps of the last problem's first tile, per 64-vector block
+    // optional device-clock stamps of the last problem's first tile, per block
     const bool stamping = B.timeline && mol == B.count - 1 && tile == 0 && threadIdx.x == 0;
     auto mark = [&](int64_t blk, int what) {
         if (stamping && blk < B.tl_cap) B.timeline[blk * 8 + what] = (int64_t)wall_clock64();
     };
-    constexpr int R = 16 * RT;
-    constexpr int TKC = s2_tkc(RT);
-    using SA = OperandStage<R, TKC, true, 512>;
-    using SB = OperandStage<64, TKC, false, 512>;
-    constexpr int kUnion = (SA::kSize + SB::kSize > R * 65) ? SA::kSize + SB::kSize : R * 65;
-    __shared__ double sU[kUnion];
-    __shared__ double sG[64 * 64];
-    __shared__ RowRec sPr[64];
+    __shared__ __align__(16) double sU[S::kU];
+    __shared__ RowRec sPr[S2_NB];
     __shared__ RowRec sRow[R];
-    double *sA = sU;
-    double *sB = sU + SA::kSize;
-    double (*sT)[65] = reinterpret_cast<double (*)[65]>(sU);
+    double *sT = sU;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const int cw = w & 3, h = w >> 2;   // column group, k half (waves w and w + 4 share a SIMD)
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cg = (w < 4) ? w : 11 - w;
     const int64_t r0 = (int64_t)tile * R;
     const int rows_here = (int)min((int64_t)R, n_rows - r0);
     const int64_t M = *Q.n_vectors;
@@ -850,81 +950,164 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
     if (k0 < 0) return;
     double Dfin = 0.0;
     int kp = -1;
-    for (int e = tid; e < rows_here; e += 512) sRow[e] = rows[r0 + e];
+    for (int e = tid; e < R; e += 512) sRow[e] = Q.rows[r0 + min(e, rows_here - 1)];
     if (tid < rows_here) {
-        Dfin = Q.resume ? diag[r0 + tid] : rows[r0 + tid].d1;
-        kp = pivot_of_row[r0 + tid];
+        Dfin = Q.resume ? Q.diag[r0 + tid] : Q.rows[r0 + tid].d1;
+        kp = Q.pivot_of_row[r0 + tid];
     }
-    // T[m][n] = (half 0) + (half 1) of the accumulators (rows of a partial last
-    // tile past rows_here hold values that are never stored)
-    auto halves_to_T = [&](const f64x4 (&acc)[RT]) {
-        if (h == 1) {
+    __syncthreads();
+    // byte offsets of this lane's A pieces from L + kc n_rows + r0 (fixed per tile)
+    int64_t aoff[RT];
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
+    for (int v = 0; v < RT; ++v) {
+        const int f = 32 * (8 * v + w) + (lane >> 1);
+        const int k = f / R, m = min(f % R, rows_here - 1);
+        aoff[v] = ((int64_t)k * n_rows + m) * 8 + 4 * (lane & 1);
+    }
+    // B pieces: row n and stored k-pair of this lane's piece v
+    int bn[2], bk[2];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sT[16 * r + mfma_row(lane, v)][16 * cw + (lane & 15)] = acc[r][v];
-        }
-        __syncthreads();
-        if (h == 0) {
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double &o = sT[16 * r + mfma_row(lane, v)][16 * cw + (lane & 15)];
-                    o = acc[r][v] + o;
-                }
-        }
-        __syncthreads();
+    for (int v = 0; v < 2; ++v) {
+        const int n = 8 * (8 * v + w) + (lane >> 3);
+        bn[v] = n;
+        bk[v] = 2 * ((lane & 7) ^ ((n >> 1) & 7));
+    }
+    // LDS index of this lane's B operand at k-step s: column 16 cg + lane % 16,
+    // k = 4 s + lane / 16, i.e. k-pair 2 s + lane / 32, element (lane / 16) % 2
+    const int nB = 16 * cg + (lane & 15), swB = (nB >> 1) & 7;
+    auto b_index = [&](int s) -> int {
+        return nB * S2_TK + 2 * ((2 * s + (lane >> 5)) ^ swB) + ((lane >> 4) & 1);
     };
-    for (int64_t b0 = k0; b0 < M; b0 += 64) {
-        const int nb = (int)min((int64_t)64, M - b0);
-        const int64_t blk = (b0 - k0) >> 6;
+
+    for (int64_t b0 = k0; b0 < M; b0 += S2_NB) {
+        const int nb = (int)min((int64_t)S2_NB, M - b0);
+        const int64_t blk = (b0 - k0) / S2_NB;
         mark(blk, 0);
+        for (int e = tid; e < S2_NB; e += 512) sPr[e] = prow[b0 + min(e, nb - 1)];
+        int64_t boff[2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) boff[v] = ((int64_t)min(bn[v], nb - 1) * ldp + bk[v]) * 8;
+        const char *Abase = reinterpret_cast<const char *>(L + r0);
+        const char *Bbase = reinterpret_cast<const char *>(Lp + b0 * ldp);
+
+        // chunk c of the off-block product (k in [16 c, 16 c + 16), k < b0) into buffer 'buf'
+        auto load_chunk = [&](int64_t c, int buf) __attribute__((always_inline)) {
+            double *st = sU + buf * S::kChunk;
+            const int64_t kc = c * S2_TK;
+            if (kc + S2_TK <= b0) {
+                const char *a = Abase + kc * n_rows * 8;
+#pragma unroll
+                for (int v = 0; v < RT; ++v)
+                    lds_dma4(a + aoff[v], (lds_void *)(st + 32 * (8 * v + w)));
+                const char *b = Bbase + kc * 8;
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    lds_dma16(b + boff[v], (lds_void *)(st + S::kA + 128 * (8 * v + w)));
+            } else {
+                // ragged last chunk (only when k_start is not a multiple of 16):
+                // through registers, zeros past b0
+                for (int e = tid; e < S::kA; e += 512) {
+                    const int k = e / R, m = min(e % R, rows_here - 1);
+                    st[e] = (kc + k < b0) ? L[(kc + k) * n_rows + r0 + m] : 0.0;
+                }
+                for (int e = tid; e < S::kB; e += 512) {
+                    const int n = e / S2_TK, k = e % S2_TK;
+                    const int at = n * S2_TK + 2 * ((k >> 1) ^ ((n >> 1) & 7)) + (k & 1);
+                    st[S::kA + at] =
+                        (kc + k < b0) ? Lp[(b0 + min(n, nb - 1)) * ldp + kc + k] : 0.0;
+                }
+            }
+        };
         f64x4 acc[RT];
         zero_acc(acc);
-        gemm_tile_2w<RT, TKC, true, false>(
-            0, b0,
-            [&](int64_t k, int m) -> double {
-                return (m < rows_here) ? L[k * n_rows + r0 + m] : 0.0;
-            },
-            [&](int64_t k, int n) -> double {
-                return (n < nb) ? Lp[(b0 + n) * ldp + k] : 0.0;
-            },
-            acc, sA, sB);
-        for (int e = tid; e < 64; e += 512)
-            if (e < nb) sPr[e] = prow[b0 + e];
-        {
-            const double *g = Ginv + blk * 4096;
-            for (int e = tid; e < 64 * 64; e += 512) sG[e] = g[e];
-        }
-        mark(blk, 1);
-        halves_to_T(acc);
-        mark(blk, 2);
-        // right-hand side: (r|P_K) - off-block sum
-        for (int e = tid; e < R * 64; e += 512) {
-            const int m = e >> 6, j = e & 63;
-            if (m < rows_here && j < nb) sT[m][j] = eri(sRow[m], sPr[j]) - sT[m][j];
-        }
-        __syncthreads();
-        mark(blk, 3);
-        // in-block part: L_blk = T G (G upper triangular, 64 x 64), the k-steps
-        // split between the two halves like the off-block product
-        zero_acc(acc);
-#pragma unroll 4
-        for (int ks = 0; ks < 64; ks += 8) {
-            const int kk = ks + 4 * h + (lane >> 4);
-            const double b = sG[kk * 64 + 16 * cw + (lane & 15)];
+        const int64_t nch = (b0 + S2_TK - 1) / S2_TK;
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const double a = sT[16 * r + (lane & 15)][kk];
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+        for (int c = 0; c < S2_NST - 1; ++c)
+            if (c < nch) load_chunk(c, c);
+        int buf = 0;   // buffer of chunk c (c % S2_NST)
+        for (int64_t c = 0; c < nch; ++c) {
+            // own pieces of chunk c landed (those of the next S2_NST - 2 chunks
+            // may stay in flight), then a barrier: every wave's pieces of chunk c
+            // are in, and every wave is done with the buffer that chunk
+            // c + S2_NST - 1 refills
+            constexpr int L1 = S::kALoads + S::kBLoads;   // this wave's loads per chunk
+            if (c + S2_NST - 2 < nch) wait_vmcnt<(S2_NST - 2) * L1>();
+            else if (S2_NST > 3 && c + 1 < nch) wait_vmcnt<L1>();
+            else wait_vmcnt<0>();
+            lds_barrier();
+            if (c + S2_NST - 1 < nch) load_chunk(c + S2_NST - 1, (buf == 0) ? S2_NST - 1 : buf - 1);
+            const double *st = sU + buf * S::kChunk;
+            buf = (buf == S2_NST - 1) ? 0 : buf + 1;
+            const double *sA = st, *sB = st + S::kA;
+#pragma unroll
+            for (int s = 0; s < S2_TK / 4; ++s) {
+                const double b = sB[b_index(s)];
+                const int kk = 4 * s + (lane >> 4);
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    const double a = sA[kk * R + 16 * r + (lane & 15)];
+                    acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+                }
             }
         }
+        // this wave's G operands (k-steps s < 4 (cg + 1): G is upper triangular),
+        // in flight while the right-hand side is formed
+        double2 gr[16];
+        {
+            const double2 *gs = reinterpret_cast<const double2 *>(Q.Gf + blk * (S2_NB * S2_NB)) +
+                                cg * 1024 + lane;
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2)
+                gr[s2] = (s2 < 2 * (cg + 1)) ? gs[64 * s2] : double2{0.0, 0.0};
+        }
+        __syncthreads();   // the chunk buffers become T
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                sT[(16 * r + mfma_row(lane, v)) * S2_TLD + 16 * cg + (lane & 15)] = acc[r][v];
         __syncthreads();
-        halves_to_T(acc);
+        mark(blk, 1);
+        // right-hand side T = (r|P_K) - P, zero outside the tile's rows and the block's vectors
+        for (int e = tid; e < R * S2_NB; e += 512) {
+            const int m = e >> 7, n = e & (S2_NB - 1);
+            double &t = sT[m * S2_TLD + n];
+            t = (m < rows_here && n < nb) ? s2_rhs(sRow[m], sPr[n], t) : 0.0;
+        }
+        __syncthreads();
+        mark(blk, 2);
+        // in-block solve L_blk = T G over the k-steps where this wave's G columns are nonzero
+        zero_acc(acc);
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            if (s2 < 2 * (cg + 1)) {   // wave-uniform
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int kk = 4 * (2 * s2 + e) + (lane >> 4);
+                    const double b = e ? gr[s2].y : gr[s2].x;
+#pragma unroll
+                    for (int r = 0; r < RT; ++r) {
+                        const double a = sT[(16 * r + (lane & 15)) * S2_TLD + kk];
+                        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // every G load has landed (waves with few columns leave some unread):
+        // otherwise the compiler guards the registers they target with a full
+        // wait inside the next block's chunk loop, which drains its prefetch
+        wait_vmcnt<0>();
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                sT[(16 * r + mfma_row(lane, v)) * S2_TLD + 16 * cg + (lane & 15)] = acc[r][v];
+        __syncthreads();
+        mark(blk, 3);
         if (tid < rows_here) {
             for (int j = 0; j < nb; ++j) {
-                const double l = sT[tid][j];
+                const double l = sT[tid * S2_TLD + j];
                 Dfin = fma(-l, l, Dfin);
                 if (b0 + j == kp) Dfin = 0.0;
             }
@@ -932,12 +1115,12 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
         mark(blk, 4);
         for (int e = tid; e < nb * R; e += 512) {
             const int j = e / R, m = e % R;
-            if (m < rows_here) L[(b0 + j) * n_rows + r0 + m] = sT[m][j];
+            if (m < rows_here) L[(b0 + j) * n_rows + r0 + m] = sT[m * S2_TLD + j];
         }
         __syncthreads();
         mark(blk, 5);
     }
-    if (tid < rows_here) diag[r0 + tid] = Dfin;
+    if (tid < rows_here) Q.diag[r0 + tid] = Dfin;
 }
 
 __global__ void k_init_decompose(GridSync *gs, int32_t *status, int64_t *n_vectors,

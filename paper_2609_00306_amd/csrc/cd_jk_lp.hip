@@ -218,8 +218,6 @@ constexpr int BX_ROWS = 2 * BX_TILE;             // A rows, then B rows
 constexpr int BX_STAGE = 3 * BX_ROWS * BX_TK;    // bf16 elements per stage (48 KB)
 constexpr int BX_LOADS = BX_STAGE * 2 / 16 / 256;   // 16-byte pieces per thread per stage (12)
 
-typedef __attribute__((address_space(3))) void lds_void;
-
 // bf16 offset in a stage of k-group g (8 values) of row r of plane p
 __device__ __forceinline__ int bx_off(int p, int r, int g)
 {
@@ -236,38 +234,6 @@ __device__ __forceinline__ void bx_item(int pairs, int &tm, int &tn, int &split)
     while ((m + 1) * (m + 2) / 2 <= t) ++m;
     tm = m;
     tn = t - m * (m + 1) / 2;
-}
-
-// Workgroup barrier that orders LDS only: a fence restricted to LDS, so the
-// memory loads in flight (the next steps' pieces) need not complete first, as
-// they would at __syncthreads().  The pieces loaded straight into LDS are
-// waited for explicitly (wait_vmcnt) before the barrier.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// One 16-byte piece per lane from global memory straight into LDS: lane l
-// writes bytes [16 l, 16 l + 16) of the wave's KB at 'lds' (wave-uniform, it
-// goes to M0).  Written as inline assembly (no output registers: the load
-// writes LDS only) so that the compiler, which drains every load of this kind
-// in flight before any LDS read, leaves the prefetch alone; the caller waits
-// for the pieces explicitly (wait_vmcnt: loads complete in issue order) before
-// the barrier that publishes them.
-__device__ __forceinline__ void lds_dma16(const void *g, lds_void *lds)
-{
-    const uint32_t m0 = (uint32_t)(uintptr_t)lds;
-    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(m0) : "memory");
-}
-
-// s_waitcnt with only vmcnt limited (expcnt and lgkmcnt at their maxima)
-template <int N>
-__device__ __forceinline__ void wait_vmcnt()
-{
-    static_assert(N >= 0 && N < 16, "vmcnt immediate");
-    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
 }
 
 __global__ __launch_bounds__(256) void k_syrk_bf16x3(const __bf16 *__restrict__ Xp, int64_t ldx,

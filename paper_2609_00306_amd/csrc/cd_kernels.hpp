@@ -58,11 +58,12 @@ struct PivotMol {
     const int64_t *pivots;
     const RowRec *rows;
     const int64_t *n_vectors;
-    double *Lp;                // [max_vectors][max_vectors] pivot rows
-    int64_t ldp;
+    double *Lp;                // [max_vectors][ldp] pivot rows
+    int64_t ldp;               // multiple of 16
     RowRec *prow;
     const double *dpiv;
     double *G;                 // inverse-transposed 64 x 64 pivot blocks
+    double *Gf;                // inverse-transposed 128 x 128 pivot blocks, solve operand order
     const int64_t *k_start;    // [1] first vector to form (blocks start there)
 };
 
@@ -70,6 +71,7 @@ struct PivotBatch {
     int32_t count;
     int32_t gather_begin[kStep1Batch + 1];    // workgroups of the gather, per problem
     int32_t inverse_begin[kStep1Batch + 1];   // workgroups of the block inverses
+    int32_t g128_begin[kStep1Batch + 1];      // workgroups of the 128-block composition
     PivotMol m[kStep1Batch];
 };
 
@@ -81,7 +83,7 @@ struct Step2Mol {
     const RowRec *prow;
     const double *Lp;
     int64_t ldp;
-    const double *Ginv;   // [blocks][64][64] inverse-transposed pivot blocks
+    const double *Gf;     // [blocks][128 x 128] inverse-transposed pivot blocks (k_block_g128)
     const int32_t *pivot_of_row;
     const int64_t *n_vectors;
     double *L;

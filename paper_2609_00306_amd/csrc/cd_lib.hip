@@ -81,6 +81,7 @@ struct DecompWs {
     double *Lp;
     RowRec *prow;
     double *Ginv;
+    double *Gf;
     int64_t *kstart;
     size_t bytes;
 };
@@ -113,9 +114,10 @@ DecompWs carve_decomp(void *ws, int64_t N, int64_t n, int64_t na, int64_t mv)
     w.piv_slot = c.take<int32_t>(std::max<int64_t>(1, mv));
     w.dpiv = c.take<double>(std::max<int64_t>(1, mv));
     w.pivot_of_row = c.take<int32_t>(std::max<int64_t>(1, n));
-    w.Lp = c.take<double>(std::max<int64_t>(1, mv * mv));
+    w.Lp = c.take<double>(std::max<int64_t>(1, mv * ld_act(mv)));
     w.prow = c.take<RowRec>(std::max<int64_t>(1, mv));
     w.Ginv = c.take<double>(std::max<int64_t>(1, blocks_of(mv, 64)) * 64 * 64);
+    w.Gf = c.take<double>(std::max<int64_t>(1, blocks_of(mv, S2_NB)) * S2_NB * S2_NB);
     w.kstart = c.take<int64_t>(1);
     w.bytes = c.off;
     return w;
@@ -264,8 +266,8 @@ cd_status check_opts(const cd_decomp_opts *o)
         return fail(CD_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
     if (o->tuning) {
         const int rt = o->tuning->step2_row_tiles, mr = o->tuning->step1_min_rows;
-        if (rt != 0 && (rt < 2 || rt > 8))
-            return fail(CD_ERR_INVALID_ARG, "tuning.step2_row_tiles must be 0 or 2..8");
+        if (rt != 0 && (rt < 2 || rt > 7))
+            return fail(CD_ERR_INVALID_ARG, "tuning.step2_row_tiles must be 0 or 2..7");
         if (mr != 0 && (mr < 16 || mr > SMAX))
             return fail(CD_ERR_INVALID_ARG, "tuning.step1_min_rows must be 0 or 16..%d", SMAX);
     }
@@ -295,25 +297,23 @@ cd_status launch_setup(const cd_molecule &m, const cd_decomp_opts *o, const Deco
     return check_launch("setup kernels");
 }
 
-// Row tile of the all-row solve: 'rt_req' 16-row tiles if given (2..8), else
-// the smallest 16-row multiple (2..8) that gives at most one tile per compute
-// unit, else 8 (128 rows).
-// Built-in tile height of the all-row solve.  One workgroup runs per compute
-// unit, so the solve takes ceil(tiles / n_cu) rounds of one tile each; a tile
-// of 16 RT rows costs about RT * cost[RT] units (taller tiles reuse each
-// pivot-row operand over more rows until the 8-tile kernel runs out of
-// registers; the factors are fitted to measured 400-, 1000- and 1200-function
-// solves).  The cheapest RT wins, the taller on ties.
+// Built-in tile height of the all-row solve (16 RT rows, RT in 2..7).  One
+// workgroup runs per compute unit, so the solve takes ceil(tiles / n_cu) rounds
+// of one tile each; a tile of 16 RT rows costs about RT * cost[RT] units
+// (taller tiles reuse each pivot-row operand over more rows).  The cheapest RT
+// wins, the taller on ties.
 int step2_rows_default(const Step2Batch &B, int n_cu)
 {
-    static const double cost[9] = {0.0, 0.0, 1.28, 1.16, 1.05, 1.0, 1.0, 0.98, 1.09};
-    int best = 8;
+    // per-row cost of one round relative to 64-row tiles, measured on the
+    // 1200-function solve (M = 5612)
+    static const double cost[8] = {0.0, 0.0, 1.2, 1.04, 1.0, 0.95, 0.92, 0.92};
+    int best = 7;
     double best_cost = 0.0;
-    for (int rt = 8; rt >= 2; --rt) {
+    for (int rt = 7; rt >= 2; --rt) {
         int64_t tiles = 0;
         for (int i = 0; i < B.count; ++i) tiles += blocks_of(B.m[i].n_rows, 16 * rt);
         const double c = (double)blocks_of(tiles, std::max(1, n_cu)) * rt * cost[rt];
-        if (rt == 8 || c < best_cost) {
+        if (rt == 7 || c < best_cost) {
             best = rt;
             best_cost = c;
         }
@@ -340,7 +340,6 @@ cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st
         CD_STEP2(5)
         CD_STEP2(6)
         CD_STEP2(7)
-        CD_STEP2(8)
     }
 #undef CD_STEP2
     return check_launch("all-row solve");
@@ -598,6 +597,7 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
         PB.count = (int32_t)grp.size();
         PB.gather_begin[0] = 0;
         PB.inverse_begin[0] = 0;
+        PB.g128_begin[0] = 0;
         for (size_t j = 0; j < grp.size(); ++j) {
             const int i = grp[j];
             const cd_problem &p = probs[i];
@@ -609,16 +609,19 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
             q.rows = W[i].rows;
             q.n_vectors = p.n_vectors;
             q.Lp = W[i].Lp;
-            q.ldp = p.max_vectors;
+            q.ldp = ld_act(p.max_vectors);
             q.prow = W[i].prow;
             q.dpiv = W[i].dpiv;
             q.G = W[i].Ginv;
+            q.Gf = W[i].Gf;
             q.k_start = W[i].kstart;
             PB.gather_begin[j + 1] = PB.gather_begin[j] + (int32_t)p.max_vectors;
             PB.inverse_begin[j + 1] = PB.inverse_begin[j] + (int32_t)blocks_of(p.max_vectors, 64);
+            PB.g128_begin[j + 1] = PB.g128_begin[j] + (int32_t)blocks_of(p.max_vectors, S2_NB);
         }
         k_gather_pivots<<<(unsigned)PB.gather_begin[PB.count], 256, 0, st>>>(PB);
         k_block_inverse<<<(unsigned)PB.inverse_begin[PB.count], 64, 0, st>>>(PB);
+        k_block_g128<<<(unsigned)PB.g128_begin[PB.count], 256, 0, st>>>(PB);
         if ((s = check_launch("pivot gather"))) return s;
     }
     if ((s = record(2))) return s;
@@ -634,8 +637,8 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
             q.n_rows = p.n_rows;
             q.prow = W[i].prow;
             q.Lp = W[i].Lp;
-            q.Ginv = W[i].Ginv;
-            q.ldp = p.max_vectors;
+            q.Gf = W[i].Gf;
+            q.ldp = ld_act(p.max_vectors);
             q.pivot_of_row = W[i].pivot_of_row;
             q.n_vectors = p.n_vectors;
             q.L = p.L;
@@ -776,7 +779,7 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
     cd_tuning pick{0, 0};
     s = run();   // warm-up with the built-in shapes
     float best_ms = 0.f;
-    for (int rt = 2; !s && rt <= 8; ++rt) {
+    for (int rt = 2; !s && rt <= 7; ++rt) {
         t = cd_tuning{rt, 0};
         if ((s = run())) break;
         if (rt == 2 || solve < best_ms) {

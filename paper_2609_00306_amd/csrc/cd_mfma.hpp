@@ -308,6 +308,51 @@ struct SplitK {
     }
 };
 
+// ---------------------------------------------------------------- LDS staging
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Workgroup barrier that orders LDS only: a fence restricted to LDS, so the
+// memory loads in flight (the next steps' pieces) need not complete first, as
+// they would at __syncthreads().  The pieces loaded straight into LDS are
+// waited for explicitly (wait_vmcnt) before the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One 16-byte piece per lane from global memory straight into LDS: lane l
+// writes bytes [16 l, 16 l + 16) of the wave's KB at 'lds' (wave-uniform, it
+// goes to M0).  Written as inline assembly (no output registers: the load
+// writes LDS only) so that the compiler, which drains every load of this kind
+// in flight before any LDS read, leaves the prefetch alone; the caller waits
+// for the pieces explicitly (wait_vmcnt: loads complete in issue order) before
+// the barrier that publishes them.
+__device__ __forceinline__ void lds_dma16(const void *g, lds_void *lds)
+{
+    const uint32_t m0 = (uint32_t)(uintptr_t)lds;
+    asm volatile("global_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(m0) : "memory");
+}
+
+// One 4-byte piece per lane straight into LDS: lane l writes bytes [4 l, 4 l + 4)
+// of the wave's 256 bytes at 'lds' (wave-uniform, it goes to M0); otherwise as
+// lds_dma16.  Needs only 4-byte alignment of 'g'.
+__device__ __forceinline__ void lds_dma4(const void *g, lds_void *lds)
+{
+    const uint32_t m0 = (uint32_t)(uintptr_t)lds;
+    asm volatile("global_load_lds_dword %0, off" : : "v"(g), "{m0}"(m0) : "memory");
+}
+
+// s_waitcnt with only vmcnt limited (expcnt and lgkmcnt at their maxima); the
+// 6-bit count is split over bits 3:0 and 15:14 of the immediate
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt immediate");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 template <int RT>
 __device__ __forceinline__ void zero_acc(f64x4 (&acc)[RT])
 {
