@@ -381,79 +381,126 @@ __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int 
 // (Y from k_half_sparse with C2, row mu holding the M q values of that
 // function).  Treating the vectors' columns as one long dimension pads only
 // the a side to the tile (O = 150 takes 160 rows) instead of both sides of
-// every vector's p x q block.  A 512-thread workgroup covers 32 RT rows a and
-// 64 columns c; wave w owns the 16 columns 16 (w % 4) and the RT row tiles of
-// half w / 4, so two waves share each SIMD and every wave runs the whole k
-// range (no partial sums to combine).  Operands go through LDS in k-chunks
-// of 32 with the next chunk loaded into registers meanwhile.
-constexpr int TR_TKC = 32;
+// every vector's p x q block.
+//
+// A 512-thread workgroup covers 16 RA rows a (all of them for p <= 160) and
+// 128 columns c; wave w owns the 16 columns 16 w and all RA row tiles, so Y,
+// the large operand, is read exactly once over the grid.  k-chunks of 16
+// functions go straight from memory into three LDS buffers two chunks ahead of
+// the products (global_load_lds, 16-byte pieces, one barrier per chunk):
+//   A part: [k][16 RA] from C1p, C1 copied with its rows padded to whole
+//           workgroup row ranges and to a whole number of chunks (zeros);
+//   B part: [k][128] from Y, whose rows are padded to whole 128-column tiles.
+// In both, the 16-byte piece j of an odd row k is stored at j ^ 8 (RA even),
+// so the two rows a half-wave reads lie on different bank halves.  Rows of Y
+// past N are read as row N - 1 against zero rows of C1p; columns past M q are
+// never stored.
+constexpr int TR_TK = 16;
 
-template <int RT>
+// C1p[mu][a] = C1[mu][a] for mu < N, a < p, else 0   (rows of ld doubles)
+__global__ void k_pack_c1(const double *__restrict__ C1, int N, int p, int rows, int ld,
+                          double *__restrict__ C1p)
+{
+    const int64_t total = (int64_t)rows * ld;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int mu = (int)(e / ld), a = (int)(e % ld);
+        C1p[e] = (mu < N && a < p) ? C1[(int64_t)mu * p + a] : 0.0;
+    }
+}
+
+template <int RA>
 __global__ __launch_bounds__(512) void k_tr2w(const double *__restrict__ Y, int64_t ldy, int N,
-                                              const double *__restrict__ C1, int p, int q,
+                                              const double *__restrict__ C1p, int ldc, int p, int q,
                                               const int64_t *__restrict__ n_vectors,
                                               double *__restrict__ Lmo)
 {
-    constexpr int ROWS = 32 * RT;
-    constexpr int NA = ROWS * TR_TKC / 512, NB = 64 * TR_TKC / 512;   // loads per thread
-    __shared__ double sA[TR_TKC][ROWS];
-    __shared__ double sB[TR_TKC][64];
+    static_assert(RA % 2 == 0 && RA <= 10, "row tiles: even, at most 10");
+    constexpr int AL = 16 * RA;                 // A row length (doubles)
+    constexpr int kA = TR_TK * AL, kB = TR_TK * 128, kChunk = kA + kB;
+    constexpr int kAP = kA / 128;               // 16-byte-piece loads of A per chunk (RA + RA/4..)
+    constexpr int kAL = kAP / 8, kAX = kAP % 8; // per wave, one more for waves < kAX
+    __shared__ __align__(16) double sU[3 * kChunk];
     const int64_t ncol = *n_vectors * q;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t c0 = (int64_t)blockIdx.x * 128;
     if (c0 >= ncol) return;
-    const int a0 = blockIdx.y * ROWS;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, cw = w & 3, rh = w >> 2;
-    // element u of this thread's chunk share: A (k, m) with m fastest, B (k, n) likewise
-    double ra[NA], rb[NB];
-    auto fetch = [&](int k0) {
+    const int a0 = blockIdx.y * AL;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nch = (N + TR_TK - 1) / TR_TK;
+
+    // B pieces: instruction v of this wave fills row k = 8 v + w of the chunk;
+    // lane l's stored piece l holds column pair l ^ (8 (k % 2))
+    const double *ysrc[2];
+    int yrow[2];
 #pragma unroll
-        for (int u = 0; u < NA; ++u) {
-            const int e = tid + 512 * u, k = e / ROWS, m = e % ROWS;
-            ra[u] = (k0 + k < N && a0 + m < p) ? C1[(int64_t)(k0 + k) * p + a0 + m] : 0.0;
+    for (int v = 0; v < 2; ++v) {
+        const int k = 8 * v + w;
+        yrow[v] = k;
+        ysrc[v] = Y + c0 + 2 * (lane ^ (8 * (k & 1)));
+    }
+    // A pieces: instruction i = 8 v + w covers pieces [64 i, 64 i + 64) of the
+    // chunk's [16][AL / 2] piece array
+    int aoff[kAL + 1];
+#pragma unroll
+    for (int v = 0; v <= kAL; ++v) {
+        const int pc = 64 * (8 * v + w) + lane, k = pc / (AL / 2), j = pc % (AL / 2);
+        aoff[v] = k * ldc + a0 + 2 * (j ^ (8 * (k & 1)));
+    }
+    auto load_chunk = [&](int c, int buf) __attribute__((always_inline)) {
+        double *st = sU + buf * kChunk;
+        const int kc = c * TR_TK;
+        const double *a = C1p + (int64_t)kc * ldc;
+#pragma unroll
+        for (int v = 0; v <= kAL; ++v) {
+            const int i = 8 * v + w;
+            if (v < kAL || w < kAX) lds_dma16(a + aoff[v], (lds_void *)(st + 128 * i));
         }
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int e = tid + 512 * u, k = e >> 6, n = e & 63;
-            rb[u] = (k0 + k < N && c0 + n < ncol) ? Y[(int64_t)(k0 + k) * ldy + c0 + n] : 0.0;
+        for (int v = 0; v < 2; ++v) {
+            const int64_t row = min(kc + yrow[v], N - 1);
+            lds_dma16(ysrc[v] + row * ldy, (lds_void *)(st + kA + 128 * (8 * v + w)));
         }
     };
-    f64x4 acc[RT];
+    f64x4 acc[RA];
     zero_acc(acc);
-    fetch(0);
-    for (int k0 = 0; k0 < N; k0 += TR_TKC) {
-#pragma unroll
-        for (int u = 0; u < NA; ++u) {
-            const int e = tid + 512 * u;
-            sA[e / ROWS][e % ROWS] = ra[u];
+    // operand LDS indices: A[m][k] at k AL + swz(16 r + m), B[k][n] at k 128 + swz(16 w + n)
+    const int m = lane & 15, kq = lane >> 4;
+    auto swz = [&](int k, int col) -> int { return 2 * ((col >> 1) ^ (8 * (k & 1))) + (col & 1); };
+    if (nch > 0) load_chunk(0, 0);
+    if (nch > 1) load_chunk(1, 1);
+    int buf = 0;
+    for (int c = 0; c < nch; ++c) {
+        if (w < kAX) {
+            if (c + 1 < nch) wait_vmcnt<kAL + 1 + 2>();
+            else wait_vmcnt<0>();
+        } else {
+            if (c + 1 < nch) wait_vmcnt<kAL + 2>();
+            else wait_vmcnt<0>();
         }
+        lds_barrier();
+        if (c + 2 < nch) load_chunk(c + 2, (buf == 0) ? 2 : buf - 1);
+        const double *sA = sU + buf * kChunk, *sB = sA + kA;
+        buf = (buf == 2) ? 0 : buf + 1;
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int e = tid + 512 * u;
-            sB[e >> 6][e & 63] = rb[u];
-        }
-        __syncthreads();
-        if (k0 + TR_TKC < N) fetch(k0 + TR_TKC);
+        for (int s = 0; s < TR_TK / 4; ++s) {
+            const int k = 4 * s + kq;
+            const double b = sB[k * 128 + swz(k, 16 * w + m)];
 #pragma unroll
-        for (int ks = 0; ks < TR_TKC; ks += 4) {
-            const int kk = ks + (lane >> 4);
-            const double b = sB[kk][16 * cw + (lane & 15)];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const double a = sA[kk][16 * (RT * rh + r) + (lane & 15)];
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+            for (int r = 0; r < RA; ++r) {
+                const double av = sA[k * AL + swz(k, 16 * r + m)];
+                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[r], 0, 0, 0);
             }
         }
-        __syncthreads();
     }
-    const int64_t c = c0 + 16 * cw + (lane & 15);
+    const int64_t c = c0 + 16 * w + m;
     if (c < ncol) {
         const int64_t P = c / q, b = c % q;
         double *out = Lmo + P * (int64_t)p * q + b;
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+        for (int r = 0; r < RA; ++r)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int a = a0 + 16 * (RT * rh + r) + mfma_row(lane, v);
+                const int a = a0 + 16 * r + mfma_row(lane, v);
                 if (a < p) out[(int64_t)a * q] = acc[r][v];
             }
     }

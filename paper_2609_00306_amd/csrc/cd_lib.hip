@@ -846,22 +846,31 @@ int bx_subsplits(int pairs, int n_cu)
     return best;
 }
 
-// The second half of the transform (k_tr2w): row tiles per half-workgroup for
-// p rows, and the launch.
-int tr2_row_tiles(int p) { return std::max(1, std::min(5, (p + 31) / 32)); }
+// The second half of the transform (k_tr2w): 16-row tiles of a per workgroup
+// (even, at most 10: 160 rows), the padded copy of C1 it reads, and the row
+// stride of Y / X (whole 128-column tiles).
+int tr2_row_tiles(int p) { return std::max(2, std::min(10, 2 * ((p + 31) / 32))); }
+int64_t tr2_c1p_ld(int p) { return (int64_t)blocks_of(p, 16 * tr2_row_tiles(p)) * 16 * tr2_row_tiles(p); }
+int64_t tr2_c1p_doubles(int64_t N, int p) { return blocks_of(N, TR_TK) * TR_TK * tr2_c1p_ld(p); }
+int64_t x_ld(int64_t mv, int64_t q) { return blocks_of(mv * q, 128) * 128; }
 
 cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int p, int q,
-                     const int64_t *n_vectors, int64_t max_vectors, double *Lmo, hipStream_t st)
+                     const int64_t *n_vectors, int64_t max_vectors, double *C1p, double *Lmo,
+                     hipStream_t st)
 {
-    const int rt = tr2_row_tiles(p);
-    const dim3 grid((unsigned)blocks_of(max_vectors * (int64_t)q, 64),
-                    (unsigned)blocks_of(p, 32 * rt));
-    switch (rt) {
-    case 1: k_tr2w<1><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
-    case 2: k_tr2w<2><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
-    case 3: k_tr2w<3><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
-    case 4: k_tr2w<4><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
-    default: k_tr2w<5><<<grid, 512, 0, st>>>(Y, ldy, N, C1, p, q, n_vectors, Lmo); break;
+    const int ra = tr2_row_tiles(p);
+    const int ldc = (int)tr2_c1p_ld(p);
+    const int rows = (int)(blocks_of(N, TR_TK) * TR_TK);
+    k_pack_c1<<<(unsigned)std::min<int64_t>(1024, blocks_of((int64_t)rows * ldc, 256)), 256, 0, st>>>(
+        C1, N, p, rows, ldc, C1p);
+    const dim3 grid((unsigned)blocks_of(max_vectors * (int64_t)q, 128),
+                    (unsigned)blocks_of(p, 16 * ra));
+    switch (ra) {
+    case 2: k_tr2w<2><<<grid, 512, 0, st>>>(Y, ldy, N, C1p, ldc, p, q, n_vectors, Lmo); break;
+    case 4: k_tr2w<4><<<grid, 512, 0, st>>>(Y, ldy, N, C1p, ldc, p, q, n_vectors, Lmo); break;
+    case 6: k_tr2w<6><<<grid, 512, 0, st>>>(Y, ldy, N, C1p, ldc, p, q, n_vectors, Lmo); break;
+    case 8: k_tr2w<8><<<grid, 512, 0, st>>>(Y, ldy, N, C1p, ldc, p, q, n_vectors, Lmo); break;
+    default: k_tr2w<10><<<grid, 512, 0, st>>>(Y, ldy, N, C1p, ldc, p, q, n_vectors, Lmo); break;
     }
     return CD_OK;
 }
@@ -911,6 +920,7 @@ void launch_sparse_prep(const SparseWs &w, int64_t N, int64_t n, int64_t mv,
 struct JkWs {
     double *Dm, *w, *V, *X, *Kp;
     double *X64;   // FP64 copy of X beside the BF16 planes (3 x BF16 with Lmo)
+    double *C1p;   // padded copy of C for the second half of the transform (with Lmo)
     SparseWs sp;
     size_t bytes;
 };
@@ -932,13 +942,15 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
     w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
     w.sp = carve_sparse(c, N, p.n_rows, p.max_vectors);
-    // X: FP64 [N][M O], FP32 in the same space, or three BF16 planes of rows of
-    // bf16_ld(M O) values
-    const int64_t xf = p.max_vectors * (int64_t)p.n_occ * N;
-    const int64_t xb = (3 * bx_rows(N) * bf16_ld(p.max_vectors * (int64_t)p.n_occ) + 3) / 4;
+    // X: FP64 [N][x_ld(M, O)], FP32 in the same space, or three BF16 planes of
+    // rows of the same number of values
+    const int64_t ldx = x_ld(p.max_vectors, p.n_occ);
+    const int64_t xf = ldx * N;
+    const int64_t xb = (3 * bx_rows(N) * bf16_ld(ldx) + 3) / 4;
     w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.X64 = (p.Lmo && prec != CD_FP64) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
+    w.C1p = p.Lmo ? c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(N, p.n_occ))) : nullptr;
     w.bytes = c.off;
     return w;
 }
@@ -1024,7 +1036,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
         const int T = (int)blocks_of(N, 64);
         const unsigned sgrid = (unsigned)(T * (T + 1) / 2 * nsplit);   // see syrk_tile_split
-        const int64_t ldx = mv * O;
+        const int64_t ldx = x_ld(mv, O);
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
         // the second half of the transform on the FP64 X: for one problem on
@@ -1037,7 +1049,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                     hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
                     return fail(CD_ERR_DEVICE, "fork failed");
             }
-            return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, p.Lmo, st2);
+            return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, st2);
         };
         if (prec == CD_FP64) {
             k_half_sparse<HALF_F64><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
@@ -1089,7 +1101,8 @@ cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, s
         if (p.max_vectors > 65535) return fail(CD_ERR_UNSUPPORTED, "max_vectors > 65535");
         Carver c(nullptr);
         carve_sparse(c, p.n_basis, p.n_rows, p.max_vectors);
-        c.take<double>(std::max<int64_t>(1, p.max_vectors * (int64_t)p.n_basis * p.q));
+        c.take<double>(std::max<int64_t>(1, x_ld(p.max_vectors, p.q) * p.n_basis));
+        c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(p.n_basis, p.p)));
         tot += c.off;
     }
     *ws_bytes = tot;
@@ -1111,12 +1124,13 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
         const int64_t N = p.n_basis, n = p.n_rows, mv = p.max_vectors;
         Carver c(wbase);
         SparseWs sp = carve_sparse(c, N, n, mv);
-        double *Y = c.take<double>(std::max<int64_t>(1, mv * N * p.q));
+        double *Y = c.take<double>(std::max<int64_t>(1, x_ld(mv, p.q) * N));
+        double *C1p = c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(N, p.p)));
         wbase += c.off;
         if (N == 0 || mv == 0 || p.p == 0 || p.q == 0) continue;
         if (!p.Lmo || !p.C1 || !p.C2 || !p.n_vectors || (n > 0 && (!p.L || !p.row_pair)))
             return fail(CD_ERR_INVALID_ARG, "null pointer in transform problem %d", i);
-        const int64_t ldy = mv * p.q;
+        const int64_t ldy = x_ld(mv, p.q);
         if (n > 0) {
             launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
             k_half_sparse<HALF_F64><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
@@ -1124,9 +1138,9 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
                                    256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
                                                  p.n_vectors, Y, ldy, 0, nullptr, 0);
         } else {
-            k_fill_f64<<<256, 256, 0, st>>>(Y, mv * N * p.q, 0.0);
+            k_fill_f64<<<256, 256, 0, st>>>(Y, ldy * N, 0.0);
         }
-        launch_tr2(Y, ldy, (int)N, p.C1, p.p, p.q, p.n_vectors, mv, p.Lmo, st);
+        launch_tr2(Y, ldy, (int)N, p.C1, p.p, p.q, p.n_vectors, mv, C1p, p.Lmo, st);
         if ((s = check_launch("transform kernels"))) return s;
     }
     if (flags & CD_SYNC) {
