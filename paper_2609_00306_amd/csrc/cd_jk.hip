@@ -114,8 +114,6 @@ __global__ __launch_bounds__(256) void k_jJ(const double *__restrict__ L, int64_
 }
 
 constexpr int JK_TKC = 32;
-constexpr int NB_SEG = 512;   // neighbour-list entries staged in LDS at a time
-using JKS = OperandStage<64, JK_TKC, true>;
 using JKR = OperandStage<64, JK_TKC, false>;
 
 // ---------------------------------------------------------------- sparse unpacking
@@ -220,9 +218,8 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
     }
 }
 
-// Half transform over neighbour lists (FP64):
+// Half transform over neighbour lists (FP64 matrix cores):
 //   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
-// tile: m = P (64), n = i (64), k = neighbour index.
 // OUT selects what is written: HALF_F64 the FP64 result; HALF_BF16X3 the FP64
 // result x split as x = b0 + b1 + b2 into three BF16 planes (b0 = bf16(x),
 // b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane p at Yp + p * plane, row mu
@@ -241,79 +238,140 @@ __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, _
 // Output forms of the half transform.
 enum HalfOut { HALF_F64 = 0, HALF_BF16X3 = 1, HALF_F32 = 2 };
 
+// A 512-thread workgroup covers 128 vectors P and 160 columns i of one
+// function mu (all of them for ncol <= 160), so each neighbour's LT row segment
+// is read once per column range; wave w owns the 16 vectors 16 w and all ten
+// column tiles.  Chunks of 16 neighbours go straight from memory into three
+// LDS buffers two chunks ahead of the products (global_load_lds, 16-byte
+// pieces gathered through the neighbour list staged in LDS; one barrier per
+// chunk).  A part [k][128] from LT (rows padded to whole 128-vector tiles),
+// B part [k][160] from Cp, C copied with rows padded to whole 160-column tiles
+// and one extra zero row that the ragged last chunk reads past the list.  The
+// 16-byte piece j of an odd row k is stored at j ^ 8.
+constexpr int HS_P = 128;     // vectors per workgroup
+constexpr int HS_C = 160;     // columns per workgroup (ten 16-column tiles)
+constexpr int HS_TK = 16;     // neighbours per chunk
+constexpr int HS_SEG = 512;   // neighbour-list entries staged in LDS at a time
+
 template <int OUT>
-__global__ __launch_bounds__(256) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
+__global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
                                                      const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ nb_s,
                                                      const int32_t *__restrict__ nb_r,
-                                                     const double *__restrict__ C, int ncol,
+                                                     const double *__restrict__ Cp, int ldc,
+                                                     int zero_row, int ncol,
                                                      const int64_t *__restrict__ n_vectors,
                                                      void *__restrict__ Yv, int64_t ldy,
                                                      int64_t plane, double *__restrict__ Y64,
                                                      int64_t ldy64)
 {
-    __shared__ double sU[2 * JKS::kSize];
-    double *sA = sU, *sB = sU + JKS::kSize;
+    constexpr int kA = HS_TK * HS_P, kB = HS_TK * HS_C, kChunk = kA + kB;
+    constexpr int CT = HS_C / 16;
+    __shared__ __align__(16) double sU[3 * kChunk];
+    __shared__ int sNs[HS_SEG], sNr[HS_SEG];
     const int64_t M = *n_vectors;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.x * HS_P;
     if (p0 >= M) return;
-    const int n0 = blockIdx.y * 64;
+    const int n0 = blockIdx.y * HS_C;
     const int mu = blockIdx.z;
     const int64_t j0 = off[mu], deg = off[mu + 1] - j0;
-    f64x4 acc[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    f64x4 acc[CT];
     zero_acc(acc);
-    // the neighbour list goes through LDS in segments, so no operand load waits
-    // on a global index load
-    __shared__ int sNs[NB_SEG], sNr[NB_SEG];
-    for (int64_t seg = 0; seg < deg; seg += NB_SEG) {
-        const int len = (int)min((int64_t)NB_SEG, deg - seg);
+    auto swz = [&](int k, int col) -> int { return 2 * ((col >> 1) ^ (8 * (k & 1))) + (col & 1); };
+    // B pieces of this lane: instruction v covers pieces [64 (8 v + w), +64) of
+    // the chunk's [16][80] piece array (waves 0..3 issue three, the others two)
+    int bk[3], bj[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int pc = 64 * (8 * v + w) + lane;
+        bk[v] = pc / (HS_C / 2);
+        bj[v] = 2 * ((pc % (HS_C / 2)) ^ (8 * (bk[v] & 1)));
+    }
+    for (int64_t seg = 0; seg < deg; seg += HS_SEG) {
+        const int len = (int)min((int64_t)HS_SEG, deg - seg);
         __syncthreads();
-        for (int e = threadIdx.x; e < len; e += 256) {
-            sNs[e] = nb_s[j0 + seg + e];
-            sNr[e] = nb_r[j0 + seg + e];
+        // past the list: the zero row of Cp against a valid LT row
+        for (int e = tid; e < HS_SEG; e += 512) {
+            sNs[e] = (e < len) ? nb_s[j0 + seg + e] : zero_row;
+            sNr[e] = nb_r[j0 + seg + min(e, len - 1)];
         }
         __syncthreads();
-        gemm_tile<4, JK_TKC, true, true>(
-            seg, seg + len,
-            [&](int64_t k, int m) -> double {
-                return LT[(int64_t)sNr[k - seg] * ldt + min(p0 + m, M - 1)];
-            },
-            [&](int64_t k, int n) -> double {
-                return C[(int64_t)sNs[k - seg] * ncol + min(n0 + n, ncol - 1)];
-            },
-            acc, sA, sB);
-    }
-    if (OUT == HALF_F64) {
-        double *out = static_cast<double *>(Yv) + (int64_t)mu * ldy;
-        for_each_acc(acc, 4, [&](int m, int n, double v) {
-            if (p0 + m < M && n0 + n < ncol) out[(p0 + m) * ncol + n0 + n] = v;
-        });
-    } else if (OUT == HALF_F32) {
-        float *out = static_cast<float *>(Yv) + (int64_t)mu * ldy;
-        double *out64 = Y64 ? Y64 + (int64_t)mu * ldy64 : nullptr;
-        for_each_acc(acc, 4, [&](int m, int n, double v) {
-            if (p0 + m < M && n0 + n < ncol) {
-                const int64_t e = (p0 + m) * ncol + n0 + n;
-                out[e] = (float)v;
-                if (out64) out64[e] = v;   // the FP64 value as well (for C^T L C)
+        const int nch = (len + HS_TK - 1) / HS_TK;
+        auto load_chunk = [&](int c, int buf) __attribute__((always_inline)) {
+            double *st = sU + buf * kChunk;
+            const int kc = c * HS_TK;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int k = 8 * v + w;   // A row k is this instruction's KB
+                const double *src = LT + (int64_t)sNr[kc + k] * ldt + p0 + 2 * (lane ^ (8 * (k & 1)));
+                lds_dma16(src, (lds_void *)(st + 128 * k));
             }
-        });
-    } else {
-        __bf16 *out = static_cast<__bf16 *>(Yv) + (int64_t)mu * ldy;
-        double *out64 = Y64 ? Y64 + (int64_t)mu * ldy64 : nullptr;
-        for_each_acc(acc, 4, [&](int m, int n, double v) {
-            if (p0 + m < M && n0 + n < ncol) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                if (v < 2 || w < 4) {
+                    const double *src = Cp + (int64_t)sNs[kc + bk[v]] * ldc + n0 + bj[v];
+                    lds_dma16(src, (lds_void *)(st + kA + 128 * (8 * v + w)));
+                }
+            }
+        };
+        if (nch > 0) load_chunk(0, 0);
+        if (nch > 1) load_chunk(1, 1);
+        int buf = 0;
+        for (int c = 0; c < nch; ++c) {
+            // own pieces of chunk c landed (chunk c + 1's may stay in flight),
+            // then a barrier: every wave's pieces of chunk c are in, and every
+            // wave is done with the buffer that chunk c + 2 refills
+            if (w < 4) {
+                if (c + 1 < nch) wait_vmcnt<5>();
+                else wait_vmcnt<0>();
+            } else {
+                if (c + 1 < nch) wait_vmcnt<4>();
+                else wait_vmcnt<0>();
+            }
+            lds_barrier();
+            if (c + 2 < nch) load_chunk(c + 2, (buf == 0) ? 2 : buf - 1);
+            const double *sA = sU + buf * kChunk, *sB = sA + kA;
+            buf = (buf == 2) ? 0 : buf + 1;
+#pragma unroll
+            for (int s = 0; s < HS_TK / 4; ++s) {
+                const int k = 4 * s + (lane >> 4);
+                const double a = sA[k * HS_P + swz(k, 16 * w + (lane & 15))];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const double bv = sB[k * HS_C + swz(k, 16 * ct + (lane & 15))];
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[ct], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // acc[ct][v]: vector p0 + 16 w + mfma_row(lane, v), column n0 + 16 ct + lane % 16
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t P = p0 + 16 * w + mfma_row(lane, v);
+            const int n = n0 + 16 * ct + (lane & 15);
+            if (P >= M || n >= ncol) continue;
+            const double x = acc[ct][v];
+            const int64_t e = P * ncol + n;
+            if (OUT == HALF_F64) {
+                static_cast<double *>(Yv)[(int64_t)mu * ldy + e] = x;
+            } else if (OUT == HALF_F32) {
+                static_cast<float *>(Yv)[(int64_t)mu * ldy + e] = (float)x;
+                if (Y64) Y64[(int64_t)mu * ldy64 + e] = x;   // the FP64 value as well (C^T L C)
+            } else {
                 __bf16 b0, b1, b2;
-                split_bf16x3(v, b0, b1, b2);
-                const int64_t e = (p0 + m) * ncol + n0 + n;
-                out[e] = b0;
-                out[plane + e] = b1;
-                out[2 * plane + e] = b2;
-                if (out64) out64[e] = v;   // the FP64 value as well (for C^T L C)
+                split_bf16x3(x, b0, b1, b2);
+                __bf16 *out = static_cast<__bf16 *>(Yv) + (int64_t)mu * ldy + e;
+                out[0] = b0;
+                out[plane] = b1;
+                out[2 * plane] = b2;
+                if (Y64) Y64[(int64_t)mu * ldy64 + e] = x;   // the FP64 value as well (C^T L C)
             }
-        });
-    }
+        }
 }
+
 
 // Work item of a split-k exchange product launched as a 1-D grid of
 // pairs x nsplit workgroups (nsplit a multiple of 8).  Workgroups are dealt to

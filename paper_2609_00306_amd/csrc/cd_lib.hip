@@ -854,6 +854,13 @@ int64_t tr2_c1p_ld(int p) { return (int64_t)blocks_of(p, 16 * tr2_row_tiles(p)) 
 int64_t tr2_c1p_doubles(int64_t N, int p) { return blocks_of(N, TR_TK) * TR_TK * tr2_c1p_ld(p); }
 int64_t x_ld(int64_t mv, int64_t q) { return blocks_of(mv * q, 128) * 128; }
 
+// Cp[mu][a] = C[mu][a] (mu < N, a < ncol), zero elsewhere: rows x ld doubles
+void launch_pack_c(const double *C, int N, int ncol, int rows, int ld, double *Cp, hipStream_t st)
+{
+    k_pack_c1<<<(unsigned)std::min<int64_t>(1024, blocks_of((int64_t)rows * ld, 256)), 256, 0, st>>>(
+        C, N, ncol, rows, ld, Cp);
+}
+
 cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int p, int q,
                      const int64_t *n_vectors, int64_t max_vectors, double *C1p, double *Lmo,
                      hipStream_t st)
@@ -861,8 +868,7 @@ cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int 
     const int ra = tr2_row_tiles(p);
     const int ldc = (int)tr2_c1p_ld(p);
     const int rows = (int)(blocks_of(N, TR_TK) * TR_TK);
-    k_pack_c1<<<(unsigned)std::min<int64_t>(1024, blocks_of((int64_t)rows * ldc, 256)), 256, 0, st>>>(
-        C1, N, p, rows, ldc, C1p);
+    launch_pack_c(C1, N, p, rows, ldc, C1p, st);
     const dim3 grid((unsigned)blocks_of(max_vectors * (int64_t)q, 128),
                     (unsigned)blocks_of(p, 16 * ra));
     switch (ra) {
@@ -890,6 +896,15 @@ struct SparseWs {
     double *LT;
 };
 
+// Row stride of the row-major copy of the vectors: whole 128-vector tiles of
+// the half transform, whose 16-byte pieces stay aligned and inside the row.
+int64_t lt_ld(int64_t mv) { return blocks_of(mv, HS_P) * HS_P; }
+
+// The padded copy of the coefficients the half transform reads: rows of whole
+// 160-column tiles, and one zero row (index N) past the functions.
+int64_t hs_cp_ld(int64_t ncol) { return blocks_of(ncol, HS_C) * HS_C; }
+int64_t hs_cp_doubles(int64_t N, int64_t ncol) { return (N + 1) * hs_cp_ld(ncol); }
+
 SparseWs carve_sparse(Carver &c, int64_t N, int64_t n, int64_t mv)
 {
     SparseWs w{};
@@ -898,7 +913,7 @@ SparseWs carve_sparse(Carver &c, int64_t N, int64_t n, int64_t mv)
     w.off = c.take<int64_t>(N + 1);
     w.nb_s = c.take<int32_t>(std::max<int64_t>(1, 2 * n));
     w.nb_r = c.take<int32_t>(std::max<int64_t>(1, 2 * n));
-    w.LT = c.take<double>(std::max<int64_t>(1, n * mv));
+    w.LT = c.take<double>(std::max<int64_t>(1, n * lt_ld(mv)));
     return w;
 }
 
@@ -914,13 +929,14 @@ void launch_sparse_prep(const SparseWs &w, int64_t N, int64_t n, int64_t mv,
     k_scan_deg<<<1, 256, 0, st>>>(w.deg, (int)N, w.off);
     k_nbr_fill<<<(unsigned)blocks_of(N, 4), 256, 0, st>>>(w.rowof, (int)N, w.off, w.nb_s, w.nb_r);
     k_transpose<<<dim3((unsigned)blocks_of(n, 64), (unsigned)blocks_of(mv, 64)), 256, 0, st>>>(
-        L, n, n_vectors, w.LT, mv);
+        L, n, n_vectors, w.LT, lt_ld(mv));
 }
 
 struct JkWs {
     double *Dm, *w, *V, *X, *Kp;
     double *X64;   // FP64 copy of X beside the BF16 planes (3 x BF16 with Lmo)
     double *C1p;   // padded copy of C for the second half of the transform (with Lmo)
+    double *Cp;    // padded copy of C for the half transform
     SparseWs sp;
     size_t bytes;
 };
@@ -951,6 +967,7 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.X64 = (p.Lmo && prec != CD_FP64) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
     w.C1p = p.Lmo ? c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(N, p.n_occ))) : nullptr;
+    w.Cp = c.take<double>(std::max<int64_t>(1, hs_cp_doubles(N, p.n_occ)));
     w.bytes = c.off;
     return w;
 }
@@ -1033,7 +1050,9 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
         k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
                                                          (int)N, p.J);
-        const dim3 hgrid((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(O, 64), (unsigned)N);
+        const dim3 hgrid((unsigned)blocks_of(mv, HS_P), (unsigned)blocks_of(O, HS_C), (unsigned)N);
+        const int ldcp = (int)hs_cp_ld(O);
+        launch_pack_c(p.C, (int)N, O, (int)N + 1, ldcp, w.Cp, sp);
         const int T = (int)blocks_of(N, 64);
         const unsigned sgrid = (unsigned)(T * (T + 1) / 2 * nsplit);   // see syrk_tile_split
         const int64_t ldx = x_ld(mv, O);
@@ -1052,14 +1071,14 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, st2);
         };
         if (prec == CD_FP64) {
-            k_half_sparse<HALF_F64><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<HALF_F64><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
                                                         p.n_vectors, w.X, ldx, 0, nullptr, 0);
             if (p.Lmo && (s = second_half(w.X))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             // X in FP64 (matrix cores), written rounded to FP32 (and in FP64 for
             // C^T L C); the exchange product then runs on FP32 matrix cores
-            k_half_sparse<HALF_F32><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<HALF_F32><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
                                                            p.n_vectors, X32, ldx, 0, w.X64, ldx);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, sp>>>(X32, ldx, (int)N, p.n_vectors, O,
@@ -1069,7 +1088,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             // exchange product then runs on BF16 matrix cores from the planes
             const int64_t ldb = bf16_ld(ldx), plane = bx_rows(N) * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
-            k_half_sparse<HALF_BF16X3><<<hgrid, 256, 0, sp>>>(q.LT, mv, q.off, q.nb_s, q.nb_r, p.C, O,
+            k_half_sparse<HALF_BF16X3><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
                                                        p.n_vectors, Xp, ldb, plane, w.X64, ldx);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             const int pairs = bx_pairs((int)N);
@@ -1103,6 +1122,7 @@ cd_status cd_query_transform(const cd_transform_problem *probs, int32_t count, s
         carve_sparse(c, p.n_basis, p.n_rows, p.max_vectors);
         c.take<double>(std::max<int64_t>(1, x_ld(p.max_vectors, p.q) * p.n_basis));
         c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(p.n_basis, p.p)));
+        c.take<double>(std::max<int64_t>(1, hs_cp_doubles(p.n_basis, p.q)));
         tot += c.off;
     }
     *ws_bytes = tot;
@@ -1126,6 +1146,7 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
         SparseWs sp = carve_sparse(c, N, n, mv);
         double *Y = c.take<double>(std::max<int64_t>(1, x_ld(mv, p.q) * N));
         double *C1p = c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(N, p.p)));
+        double *C2p = c.take<double>(std::max<int64_t>(1, hs_cp_doubles(N, p.q)));
         wbase += c.off;
         if (N == 0 || mv == 0 || p.p == 0 || p.q == 0) continue;
         if (!p.Lmo || !p.C1 || !p.C2 || !p.n_vectors || (n > 0 && (!p.L || !p.row_pair)))
@@ -1133,10 +1154,12 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
         const int64_t ldy = x_ld(mv, p.q);
         if (n > 0) {
             launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
-            k_half_sparse<HALF_F64><<<dim3((unsigned)blocks_of(mv, 64), (unsigned)blocks_of(p.q, 64),
+            const int ldcp = (int)hs_cp_ld(p.q);
+            launch_pack_c(p.C2, (int)N, p.q, (int)N + 1, ldcp, C2p, st);
+            k_half_sparse<HALF_F64><<<dim3((unsigned)blocks_of(mv, HS_P), (unsigned)blocks_of(p.q, HS_C),
                                         (unsigned)N),
-                                   256, 0, st>>>(sp.LT, mv, sp.off, sp.nb_s, sp.nb_r, p.C2, p.q,
-                                                 p.n_vectors, Y, ldy, 0, nullptr, 0);
+                                   512, 0, st>>>(sp.LT, lt_ld(mv), sp.off, sp.nb_s, sp.nb_r, C2p, ldcp,
+                                                 (int)N, p.q, p.n_vectors, Y, ldy, 0, nullptr, 0);
         } else {
             k_fill_f64<<<256, 256, 0, st>>>(Y, ldy * N, 0.0);
         }
