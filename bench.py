@@ -209,7 +209,8 @@ def batched_c4(steps, warmup, tuned=True):
         "speedup_fp32_vs_fp64_batched": res["fp64"]["batched_ms"] / res["fp32"]["batched_ms"],
         "fp32_K_error_vs_fp64": err,
         "tuning": None if tuning is None else {"step2_row_tiles": tuning.step2_row_tiles,
-                                               "step1_min_rows": tuning.step1_min_rows},
+                                               "step1_min_rows": tuning.step1_min_rows,
+                                               "step1_q": tuning.step1_q},
     })
     return out
 
@@ -599,7 +600,7 @@ def main():
                    "pivot_block": args.pivot_block,
                    "tuning": None if tuning is None else
                    {"step2_row_tiles": tuning.step2_row_tiles,
-                    "step1_min_rows": tuning.step1_min_rows}},
+                    "step1_min_rows": tuning.step1_min_rows, "step1_q": tuning.step1_q}},
         "cd_ms": head["cd"],
         "cd_vectors_per_s": M / (head["cd"] * 1e-3),
         "jk_ms": head["jk"],

@@ -120,6 +120,8 @@ typedef struct {
     int32_t step2_row_tiles;   /* all-row solve: rows per workgroup in units of 16, 2..7 */
     int32_t step1_min_rows;    /* pivot selection: at least this many active rows per
                                   workgroup (fewer, fuller workgroups), 16..256 */
+    int32_t step1_q;           /* pivot selection: candidates per batch, 8..64 (the pivot
+                                  sequence is the same for every value) */
 } cd_tuning;
 
 typedef struct {
@@ -234,13 +236,17 @@ cd_status cd_decompose_noalloc(const cd_problem *probs, int32_t count,
  * cd_autotune: choose the launch shapes of cd_decompose for these problems by
  * measurement.  Blocking (synchronises 'stream').  It runs the decomposition
  * once per candidate shape, timing the pivot selection and the all-row solve
- * with HIP events: first every all-row-solve tile height (2..8 row tiles of
+ * with HIP events: first every all-row-solve tile height (2..7 row tiles of
  * 16) with the built-in pivot-selection shape, then pivot-selection workgroups
- * of at least 16, 32, 48 or 64 active rows with the best tile height.  The
- * fastest shape is written to *best (host) and a last run with it leaves the
- * problems' outputs as cd_decompose would.  opts->tuning and opts->events are
- * ignored.  Errors as cd_decompose; a device status other than CD_OK in any
- * run is returned as the result.
+ * of at least 16, 32, 48 or 64 active rows with the best tile height, then
+ * batches of 32, 48 or 64 candidates with the best of those.  The fastest
+ * shape is written to *best (host) and a last run with it leaves the
+ * problems' outputs as cd_decompose would.  The library keeps the result for
+ * the rest of the process, keyed by the device and the problems' shapes
+ * (sizes, tau, screening, span factor, flags): a call with a shape seen before
+ * runs the decomposition once with the kept result instead of measuring.
+ * opts->tuning and opts->events are ignored.  Errors as cd_decompose; a device
+ * status other than CD_OK in any run is returned as the result.
  */
 cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                       void *ws, size_t ws_bytes, cd_tuning *best, void *stream);

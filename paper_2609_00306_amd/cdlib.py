@@ -33,7 +33,8 @@ class cd_molecule(ctypes.Structure):
 
 
 class cd_tuning(ctypes.Structure):
-    _fields_ = [("step2_row_tiles", ctypes.c_int32), ("step1_min_rows", ctypes.c_int32)]
+    _fields_ = [("step2_row_tiles", ctypes.c_int32), ("step1_min_rows", ctypes.c_int32),
+                ("step1_q", ctypes.c_int32)]
 
 
 class cd_decomp_opts(ctypes.Structure):
@@ -340,7 +341,7 @@ def autotune(decs: Sequence[Decomposition], tau: float, schwarz: float, stream=N
         if n != 1:
             raise ValueError("pass a shared workspace for more than one molecule")
         workspace = decs[0].workspace
-    best = cd_tuning(0, 0)
+    best = cd_tuning(0, 0, 0)
     _check(L.cd_autotune(arr, n, ctypes.byref(opts), _ptr(workspace), workspace.numel(),
                          ctypes.byref(best), _stream(stream)))
     return best

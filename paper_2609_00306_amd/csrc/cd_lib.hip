@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -266,6 +267,9 @@ cd_status check_opts(const cd_decomp_opts *o)
         return fail(CD_ERR_INVALID_ARG, "unknown flags 0x%x", o->flags);
     if (o->tuning) {
         const int rt = o->tuning->step2_row_tiles, mr = o->tuning->step1_min_rows;
+        const int q = o->tuning->step1_q;
+        if (q != 0 && (q < 8 || q > QMAX))
+            return fail(CD_ERR_INVALID_ARG, "tuning.step1_q must be 0 or 8..%d", QMAX);
         if (rt != 0 && (rt < 2 || rt > 7))
             return fail(CD_ERR_INVALID_ARG, "tuning.step2_row_tiles must be 0 or 2..7");
         if (mr != 0 && (mr < 16 || mr > SMAX))
@@ -373,7 +377,7 @@ Step1Params step1_params(const cd_problem &p, const DecompWs &w, const cd_decomp
     P1.d1max_bits = w.d1max;
     P1.n_rows = p.n_rows;
     P1.max_vectors = p.max_vectors;
-    P1.q = QMAX;
+    P1.q = (o->tuning && o->tuning->step1_q) ? o->tuning->step1_q : QMAX;
     P1.eta = (o->eta > 0.0 && o->eta < 1.0) ? o->eta : 1.0;
     P1.slice = slice;
     P1.spin_limit = 1u << 22;
@@ -736,6 +740,31 @@ cd_status cd_decompose_noalloc(const cd_problem *probs, int32_t count, const cd_
     return decompose_impl(probs, count, opts, ws, static_cast<hipStream_t>(stream), false);
 }
 
+namespace {
+// Shapes measured by cd_autotune in this process, keyed by device and problem shape.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, cd_tuning> g_tune_cache;
+
+std::vector<int64_t> tune_key(const cd_problem *probs, int32_t count, const cd_decomp_opts *o)
+{
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    auto bits = [](double x) {
+        int64_t b;
+        std::memcpy(&b, &x, sizeof b);
+        return b;
+    };
+    std::vector<int64_t> k = {dev, count, (int64_t)(o->flags & ~CD_SYNC), bits(o->tau),
+                              bits(o->schwarz), bits(o->eta)};
+    for (int32_t i = 0; i < count; ++i) {
+        const cd_problem &p = probs[i];
+        k.insert(k.end(), {p.mol.n_basis, p.n_rows, p.n_active, p.max_vectors,
+                           p.mol.pivot_fn ? 1 : 0});
+    }
+    return k;
+}
+}  // namespace
+
 cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                       void *ws, size_t ws_bytes, cd_tuning *best, void *stream)
 {
@@ -751,7 +780,7 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
             return fail(CD_ERR_DEVICE, "hipEventCreate failed");
         }
     void *evp[4] = {ev[0], ev[1], ev[2], ev[3]};
-    cd_tuning t{0, 0};
+    cd_tuning t{0, 0, 0};
     cd_decomp_opts o = *opts;
     o.flags = 0;
     o.events = evp;
@@ -776,11 +805,24 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
             return fail(CD_ERR_DEVICE, "event timing failed");
         return CD_OK;
     };
-    cd_tuning pick{0, 0};
+    // a shape measured before in this process: one run with the kept result
+    const std::vector<int64_t> key = tune_key(probs, count, opts);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            t = it->second;
+            s = run();
+            for (auto &e : ev) (void)hipEventDestroy(e);
+            if (!s) *best = t;
+            return s;
+        }
+    }
+    cd_tuning pick{0, 0, 0};
     s = run();   // warm-up with the built-in shapes
     float best_ms = 0.f;
     for (int rt = 2; !s && rt <= 7; ++rt) {
-        t = cd_tuning{rt, 0};
+        t = cd_tuning{rt, 0, 0};
         if ((s = run())) break;
         if (rt == 2 || solve < best_ms) {
             best_ms = solve;
@@ -789,11 +831,20 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
     }
     const int rows_opts[] = {16, 32, 48, 64};
     for (int k = 0; !s && k < 4; ++k) {
-        t = cd_tuning{pick.step2_row_tiles, rows_opts[k]};
+        t = cd_tuning{pick.step2_row_tiles, rows_opts[k], 0};
         if ((s = run())) break;
         if (k == 0 || sel < best_ms) {
             best_ms = sel;
             pick.step1_min_rows = rows_opts[k];
+        }
+    }
+    const int q_opts[] = {32, 48, QMAX};
+    for (int k = 0; !s && k < 3; ++k) {
+        t = cd_tuning{pick.step2_row_tiles, pick.step1_min_rows, q_opts[k]};
+        if ((s = run())) break;
+        if (k == 0 || sel < best_ms) {
+            best_ms = sel;
+            pick.step1_q = q_opts[k];
         }
     }
     if (!s) {
@@ -801,7 +852,11 @@ cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_op
         s = run();   // leaves the outputs of the chosen shape
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    if (!s) *best = pick;
+    if (!s) {
+        *best = pick;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = pick;
+    }
     return s;
 }
 

@@ -58,8 +58,9 @@ int main(void) {
          sizeof(cd_transform_problem));
   printf("%zu %zu %zu %zu %zu\n", offsetof(cd_problem, status), offsetof(cd_jk_problem, status),
          offsetof(cd_transform_problem, status), offsetof(cd_decomp_opts, events), offsetof(cd_decomp_opts, timeline_cap));
-  printf("%zu %zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
-         offsetof(cd_decomp_opts, tuning), offsetof(cd_decomp_opts, eta));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(cd_tuning), offsetof(cd_tuning, step1_min_rows),
+         offsetof(cd_tuning, step1_q), offsetof(cd_decomp_opts, tuning),
+         offsetof(cd_decomp_opts, eta));
   printf("%zu %zu %zu\n", sizeof(cd_mp2_problem), offsetof(cd_mp2_problem, n_vectors),
          offsetof(cd_mp2_problem, status));
   printf("%zu %zu\n", sizeof(cd_zproblem), offsetof(cd_zproblem, status));
@@ -88,7 +89,8 @@ def test_binding_structs_match_header():
             cdlib.cd_problem.status.offset, cdlib.cd_jk_problem.status.offset,
             cdlib.cd_transform_problem.status.offset, cdlib.cd_decomp_opts.events.offset,
             cdlib.cd_decomp_opts.timeline_cap.offset, ctypes.sizeof(cdlib.cd_tuning),
-            cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_decomp_opts.tuning.offset,
+            cdlib.cd_tuning.step1_min_rows.offset, cdlib.cd_tuning.step1_q.offset,
+            cdlib.cd_decomp_opts.tuning.offset,
             cdlib.cd_decomp_opts.eta.offset, ctypes.sizeof(cdlib.cd_mp2_problem),
             cdlib.cd_mp2_problem.n_vectors.offset, cdlib.cd_mp2_problem.status.offset,
             ctypes.sizeof(cdlib.cd_zproblem), cdlib.cd_zproblem.status.offset,
@@ -133,8 +135,8 @@ def test_argument_validation_without_device(lib):
                             1 << 30, None) == cdlib.CD_ERR_INVALID_ARG
     assert b"aligned" in lib.cd_last_error()
     # launch shapes outside their ranges are rejected on the host
-    for rt, mr in [(1, 0), (9, 0), (0, 8), (0, 1024)]:
-        t = cdlib.cd_tuning(rt, mr)
+    for rt, mr, q in [(1, 0, 0), (8, 0, 0), (0, 8, 0), (0, 1024, 0), (0, 0, 4), (0, 0, 65)]:
+        t = cdlib.cd_tuning(rt, mr, q)
         o = cdlib.cd_decomp_opts(1e-6, 1e-12, 0, None, None, 0, ctypes.pointer(t))
         assert lib.cd_decompose(ctypes.byref(p), 1, ctypes.byref(o), None, 0,
                                 None) == cdlib.CD_ERR_INVALID_ARG

@@ -280,18 +280,26 @@ def test_autotune_shapes_give_the_same_decomposition():
     decs, ws = cdlib.allocate_many(pairs, tau, 1e-12)
     t = cdlib.autotune(decs, tau, 1e-12, workspace=ws)
     assert 2 <= t.step2_row_tiles <= 7 and t.step1_min_rows in (16, 32, 48, 64)
+    assert t.step1_q in (32, 48, 64)
     torch.cuda.synchronize()
     for d, r in zip(decs, ref):
         assert d.M() == r.M() and int(d.status.item()) == 0
         assert torch.equal(d.pivots[:d.M()], r.pivots[:r.M()])
         assert (d.L[:d.M()] - r.L[:r.M()]).abs().max().item() <= 1e-12
     # explicit shapes at the ends of both ranges
-    for shape in [cdlib.cd_tuning(2, 16), cdlib.cd_tuning(7, 64)]:
+    for shape in [cdlib.cd_tuning(2, 16, 8), cdlib.cd_tuning(7, 64, 64)]:
         cdlib.run_decompose(decs, tau, 1e-12, workspace=ws, tuning=shape)
         torch.cuda.synchronize()
         for d, r in zip(decs, ref):
             assert torch.equal(d.pivots[:d.M()], r.pivots[:r.M()])
             assert (d.L[:d.M()] - r.L[:r.M()]).abs().max().item() <= 1e-12
+    # the same shapes again: the kept result, no new measurement
+    t2 = cdlib.autotune(decs, tau, 1e-12, workspace=ws)
+    assert (t2.step2_row_tiles, t2.step1_min_rows, t2.step1_q) == (
+        t.step2_row_tiles, t.step1_min_rows, t.step1_q)
+    torch.cuda.synchronize()
+    for d, r in zip(decs, ref):
+        assert torch.equal(d.pivots[:d.M()], r.pivots[:r.M()])
 
 
 @pytest.mark.parametrize("prec,lmo", [("fp64", False), ("fp64", True), ("fp32", False),
