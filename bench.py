@@ -50,16 +50,16 @@ BF16_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
                 "paper_2609_00306_amd/csrc/cd_device.hpp",
                 "paper_2609_00306_amd/csrc/cd_mfma.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.25, 1048576.0 / 1048576.0
-_DECOMP_SHA = "bf68eecef8680557d5f29517f9b55c2681fdc919d5c3a0cd6f50b173fe0ff9d7"
+_DECOMP_SHA = "2c7d41ec0628b9004d46af95b6dc8258ed8d5b62438267c4e61fd61c495fc694"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 68393270.9, "write_kib": 2676555.9},
+                    "fetch_kib": 34617693.9, "write_kib": 2680245.8},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3722680.5, "write_kib": 355594.6},
+                    "fetch_kib": 3717570.1, "write_kib": 355838.4},
         "k_syrk_bf16x3": {"sources": BF16_SOURCES,
-                          "sha256": "204409b35944e4b93070dd9c462a9bcd086808ae8eb2c4ab79610cdb16f6d335",
-                          "fetch_kib": 19512166.2, "write_kib": 198720.0},
+                          "sha256": "3c4ee224f0d8c5b7ee9f6b5a8b6289a26e045bd5faf2e74b909728a987389877",
+                          "fetch_kib": 23245332.6, "write_kib": 198720.0},
     },
 }
 
