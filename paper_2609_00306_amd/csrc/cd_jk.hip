@@ -238,22 +238,25 @@ __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, _
 // Output forms of the half transform.
 enum HalfOut { HALF_F64 = 0, HALF_BF16X3 = 1, HALF_F32 = 2 };
 
-// A 512-thread workgroup covers 128 vectors P and 160 columns i of one
-// function mu (all of them for ncol <= 160), so each neighbour's LT row segment
-// is read once per column range; wave w owns the 16 vectors 16 w and all ten
-// column tiles.  Chunks of 16 neighbours go straight from memory into three
-// LDS buffers two chunks ahead of the products (global_load_lds, 16-byte
-// pieces gathered through the neighbour list staged in LDS; one barrier per
-// chunk).  A part [k][128] from LT (rows padded to whole 128-vector tiles),
-// B part [k][160] from Cp, C copied with rows padded to whole 160-column tiles
-// and one extra zero row that the ragged last chunk reads past the list.  The
-// 16-byte piece j of an odd row k is stored at j ^ 8.
+// A 512-thread workgroup covers 128 vectors P and 16 CT columns i of one
+// function mu (CT = 10: all of them for ncol <= 160; CT = 4 for ncol <= 64),
+// so each neighbour's LT row segment is read once per column range; wave w
+// owns the 16 vectors 16 w and all CT column tiles.  Chunks of 16 neighbours
+// go straight from memory into three LDS buffers two chunks ahead of the
+// products (global_load_lds, 16-byte pieces gathered through the neighbour
+// list staged in LDS; one barrier per chunk).  A part [k][128] from LT (rows
+// padded to whole 128-vector tiles), B part [k][16 CT] from Cp, C copied with
+// rows padded to whole column ranges and one extra zero row that the ragged
+// last chunk reads past the list.  The 16-byte piece j of an odd row k is
+// stored at j ^ 8.
 constexpr int HS_P = 128;     // vectors per workgroup
-constexpr int HS_C = 160;     // columns per workgroup (ten 16-column tiles)
 constexpr int HS_TK = 16;     // neighbours per chunk
 constexpr int HS_SEG = 512;   // neighbour-list entries staged in LDS at a time
 
-template <int OUT>
+// column tiles of the half transform for ncol columns
+__host__ __device__ constexpr int hs_col_tiles(int ncol) { return (ncol <= 64) ? 4 : 10; }
+
+template <int OUT, int CT>
 __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
                                                      const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ nb_s,
@@ -265,8 +268,11 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
                                                      int64_t plane, double *__restrict__ Y64,
                                                      int64_t ldy64)
 {
+    constexpr int HS_C = 16 * CT;                 // columns per workgroup
     constexpr int kA = HS_TK * HS_P, kB = HS_TK * HS_C, kChunk = kA + kB;
-    constexpr int CT = HS_C / 16;
+    constexpr int kBL = kB / 128;                  // 16-byte-piece loads of B per chunk
+    constexpr int kBW = (kBL + 7) / 8;             // per wave, waves < kBL % 8 one more
+    static_assert(CT % 2 == 0, "whole 16-byte pieces per row pair");
     __shared__ __align__(16) double sU[3 * kChunk];
     __shared__ int sNs[HS_SEG], sNr[HS_SEG];
     const int64_t M = *n_vectors;
@@ -280,10 +286,10 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
     zero_acc(acc);
     auto swz = [&](int k, int col) -> int { return 2 * ((col >> 1) ^ (8 * (k & 1))) + (col & 1); };
     // B pieces of this lane: instruction v covers pieces [64 (8 v + w), +64) of
-    // the chunk's [16][80] piece array (waves 0..3 issue three, the others two)
-    int bk[3], bj[3];
+    // the chunk's [16][8 CT] piece array
+    int bk[kBW], bj[kBW];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < kBW; ++v) {
         const int pc = 64 * (8 * v + w) + lane;
         bk[v] = pc / (HS_C / 2);
         bj[v] = 2 * ((pc % (HS_C / 2)) ^ (8 * (bk[v] & 1)));
@@ -308,8 +314,8 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
                 lds_dma16(src, (lds_void *)(st + 128 * k));
             }
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                if (v < 2 || w < 4) {
+            for (int v = 0; v < kBW; ++v) {
+                if (8 * v + w < kBL) {
                     const double *src = Cp + (int64_t)sNs[kc + bk[v]] * ldc + n0 + bj[v];
                     lds_dma16(src, (lds_void *)(st + kA + 128 * (8 * v + w)));
                 }
@@ -322,11 +328,12 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
             // own pieces of chunk c landed (chunk c + 1's may stay in flight),
             // then a barrier: every wave's pieces of chunk c are in, and every
             // wave is done with the buffer that chunk c + 2 refills
-            if (w < 4) {
-                if (c + 1 < nch) wait_vmcnt<5>();
+            // this wave's loads per chunk: 2 of A, kBL / 8 of B and one more for waves < kBL % 8
+            if (w < kBL % 8) {
+                if (c + 1 < nch) wait_vmcnt<2 + kBL / 8 + 1>();
                 else wait_vmcnt<0>();
             } else {
-                if (c + 1 < nch) wait_vmcnt<4>();
+                if (c + 1 < nch) wait_vmcnt<2 + kBL / 8>();
                 else wait_vmcnt<0>();
             }
             lds_barrier();

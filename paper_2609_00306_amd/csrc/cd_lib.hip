@@ -956,8 +956,25 @@ struct SparseWs {
 int64_t lt_ld(int64_t mv) { return blocks_of(mv, HS_P) * HS_P; }
 
 // The padded copy of the coefficients the half transform reads: rows of whole
-// 160-column tiles, and one zero row (index N) past the functions.
-int64_t hs_cp_ld(int64_t ncol) { return blocks_of(ncol, HS_C) * HS_C; }
+// column ranges of a workgroup, and one zero row (index N) past the functions.
+int64_t hs_cols(int64_t ncol) { return 16 * hs_col_tiles((int)ncol); }
+int64_t hs_cp_ld(int64_t ncol) { return blocks_of(ncol, hs_cols(ncol)) * hs_cols(ncol); }
+
+// X^P = Lt^P C over the neighbour lists (k_half_sparse), output form OUT
+extern "C++" template <int OUT>
+void launch_half(const SparseWs &q, int64_t mv, const double *Cp, int ldcp, int N, int ncol,
+                 const int64_t *n_vectors, void *Y, int64_t ldy, int64_t plane, double *Y64,
+                 int64_t ldy64, hipStream_t st)
+{
+    const dim3 grid((unsigned)blocks_of(mv, HS_P), (unsigned)blocks_of(ncol, hs_cols(ncol)),
+                    (unsigned)N);
+    if (hs_col_tiles(ncol) == 4)
+        k_half_sparse<OUT, 4><<<grid, 512, 0, st>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, Cp, ldcp,
+                                                   N, ncol, n_vectors, Y, ldy, plane, Y64, ldy64);
+    else
+        k_half_sparse<OUT, 10><<<grid, 512, 0, st>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, Cp, ldcp,
+                                                    N, ncol, n_vectors, Y, ldy, plane, Y64, ldy64);
+}
 int64_t hs_cp_doubles(int64_t N, int64_t ncol) { return (N + 1) * hs_cp_ld(ncol); }
 
 SparseWs carve_sparse(Carver &c, int64_t N, int64_t n, int64_t mv)
@@ -1105,7 +1122,6 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
         k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
                                                          (int)N, p.J);
-        const dim3 hgrid((unsigned)blocks_of(mv, HS_P), (unsigned)blocks_of(O, HS_C), (unsigned)N);
         const int ldcp = (int)hs_cp_ld(O);
         launch_pack_c(p.C, (int)N, O, (int)N + 1, ldcp, w.Cp, sp);
         const int T = (int)blocks_of(N, 64);
@@ -1126,15 +1142,15 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, st2);
         };
         if (prec == CD_FP64) {
-            k_half_sparse<HALF_F64><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
-                                                        p.n_vectors, w.X, ldx, 0, nullptr, 0);
+            launch_half<HALF_F64>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, w.X, ldx, 0, nullptr, 0,
+                                  sp);
             if (p.Lmo && (s = second_half(w.X))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             // X in FP64 (matrix cores), written rounded to FP32 (and in FP64 for
             // C^T L C); the exchange product then runs on FP32 matrix cores
-            k_half_sparse<HALF_F32><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
-                                                           p.n_vectors, X32, ldx, 0, w.X64, ldx);
+            launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, ldx, 0, w.X64, ldx,
+                                  sp);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, sp>>>(X32, ldx, (int)N, p.n_vectors, O,
                                                           nsplit, w.Kp);
@@ -1143,8 +1159,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             // exchange product then runs on BF16 matrix cores from the planes
             const int64_t ldb = bf16_ld(ldx), plane = bx_rows(N) * ldb;
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
-            k_half_sparse<HALF_BF16X3><<<hgrid, 512, 0, sp>>>(q.LT, lt_ld(mv), q.off, q.nb_s, q.nb_r, w.Cp, ldcp, (int)N, O,
-                                                       p.n_vectors, Xp, ldb, plane, w.X64, ldx);
+            launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, ldb, plane, w.X64,
+                                     ldx, sp);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
@@ -1211,10 +1227,8 @@ cd_status cd_transform(const cd_transform_problem *probs, int32_t count, uint32_
             launch_sparse_prep(sp, N, n, mv, p.row_pair, p.L, p.n_vectors, st);
             const int ldcp = (int)hs_cp_ld(p.q);
             launch_pack_c(p.C2, (int)N, p.q, (int)N + 1, ldcp, C2p, st);
-            k_half_sparse<HALF_F64><<<dim3((unsigned)blocks_of(mv, HS_P), (unsigned)blocks_of(p.q, HS_C),
-                                        (unsigned)N),
-                                   512, 0, st>>>(sp.LT, lt_ld(mv), sp.off, sp.nb_s, sp.nb_r, C2p, ldcp,
-                                                 (int)N, p.q, p.n_vectors, Y, ldy, 0, nullptr, 0);
+            launch_half<HALF_F64>(sp, mv, C2p, ldcp, (int)N, p.q, p.n_vectors, Y, ldy, 0, nullptr, 0,
+                                  st);
         } else {
             k_fill_f64<<<256, 256, 0, st>>>(Y, ldy * N, 0.0);
         }
