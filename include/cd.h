@@ -139,9 +139,10 @@ typedef struct {
                               [1 + 8 b + i]: batch b, stage i: 0 start, 1 nominations exchanged,
                               2 candidates chosen, 3 candidate columns formed, 4 columns
                               exchanged, 5 candidate block factored, 6 rows updated;
-                              [1 + 8 cap + 8 k + i]: workgroup 0 of the all-row solve, 64-vector
-                              block k, stage i: 0 start, 1 off-block product done, 2 staged,
-                              3 integrals subtracted, 4 substitution done, 5 stored */
+                              [1 + 8 cap + 8 k + i]: workgroup 0 of the all-row solve, 128-vector
+                              block k, stage i: 0 start, 1 off-block product done and staged,
+                              2 integrals subtracted, 3 substitution done, 4 residuals
+                              updated, 5 stored */
     int64_t timeline_cap;  /* batches / blocks the timeline can hold */
     const cd_tuning *tuning; /* optional (may be NULL): host pointer to launch shapes */
     double eta;            /* span factor of the two-step first step (Sec. 3, Table 1), in [0, 1].
