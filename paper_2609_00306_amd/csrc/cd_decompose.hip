@@ -874,7 +874,7 @@ __global__ __launch_bounds__(256) void k_block_g128(const PivotBatch B)
 // (Sec. 3, Eq. CVsLT), blocked over 128 vectors.  A 512-thread workgroup owns
 // 16 RT rows; for each block it forms
 //   off-block product  P = A B^T,  A[m][k] = L[k][r0 + m], B[n][k] = Lp[b0 + n][k], k < b0
-//   right-hand side    T = (r|P_K) - P
+//   right-hand side    T = (r|P_K) - P   (the ERIs read from L, where k_rhs_eri put them)
 //   in-block solve     L_blk = T G       (G: inverse-transposed 128 x 128 pivot block)
 // and the final residual diagonal (a row is zeroed when it is chosen as pivot).
 //
@@ -894,12 +894,23 @@ __global__ __launch_bounds__(256) void k_block_g128(const PivotBatch B)
 // block as its last pivot row: finite values in accumulator rows and columns
 // that are never stored.  The right-hand side and the block result go through
 // one LDS array T of rows of S2_TLD doubles, which reuses the chunk buffers.
-// (r|P) - t, kept out of line: inlined, the ERI's registers and constants
-// crowd the off-block product's loop, whose LDS reads then no longer run ahead
-// of the matrix instructions.
-__device__ __attribute__((noinline)) double s2_rhs(const RowRec &r, const RowRec &p, double t)
+// The ERIs of the right-hand side, (r|P_K) for every row r and every vector K
+// the solve forms, written into L itself (the solve then replaces each with the
+// vector element).  A separate pass: inside the solve the ERI's registers and
+// constants crowd the off-block product's loop (its LDS reads then stop running
+// ahead of the matrix instructions), and there they cost a phase of every block.
+// Grid: x over rows (256 per workgroup, the row record kept in registers),
+// y strided over the vectors, z the problem.
+__global__ __launch_bounds__(256) void k_rhs_eri(const Step2Batch B)
 {
-    return eri(r, p) - t;
+    if ((int)blockIdx.z >= B.count) return;
+    const Step2Mol &Q = B.m[blockIdx.z];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t k0 = *Q.k_start, M = *Q.n_vectors;
+    if (k0 < 0 || r >= Q.n_rows) return;
+    const RowRec row = Q.rows[r];
+    for (int64_t K = k0 + blockIdx.y; K < M; K += gridDim.y)
+        Q.L[K * Q.n_rows + r] = eri(row, Q.prow[K]);
 }
 
 template <int RT>
@@ -925,7 +936,6 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
     while (mol + 1 < B.count && (int)blockIdx.x >= B.tile_begin[mol + 1]) ++mol;
     const Step2Mol &Q = B.m[mol];
     const int64_t n_rows = Q.n_rows;
-    const RowRec *__restrict__ prow = Q.prow;
     const double *__restrict__ Lp = Q.Lp;
     const int64_t ldp = Q.ldp;
     double *__restrict__ L = Q.L;
@@ -936,8 +946,6 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
         if (stamping && blk < B.tl_cap) B.timeline[blk * 8 + what] = (int64_t)wall_clock64();
     };
     __shared__ __align__(16) double sU[S::kU];
-    __shared__ RowRec sPr[S2_NB];
-    __shared__ RowRec sRow[R];
     double *sT = sU;
 
     const int tid = threadIdx.x;
@@ -950,7 +958,6 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
     if (k0 < 0) return;
     double Dfin = 0.0;
     int kp = -1;
-    for (int e = tid; e < R; e += 512) sRow[e] = Q.rows[r0 + min(e, rows_here - 1)];
     if (tid < rows_here) {
         Dfin = Q.resume ? Q.diag[r0 + tid] : Q.rows[r0 + tid].d1;
         kp = Q.pivot_of_row[r0 + tid];
@@ -983,7 +990,6 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
         const int nb = (int)min((int64_t)S2_NB, M - b0);
         const int64_t blk = (b0 - k0) / S2_NB;
         mark(blk, 0);
-        for (int e = tid; e < S2_NB; e += 512) sPr[e] = prow[b0 + min(e, nb - 1)];
         int64_t boff[2];
 #pragma unroll
         for (int v = 0; v < 2; ++v) boff[v] = ((int64_t)min(bn[v], nb - 1) * ldp + bk[v]) * 8;
@@ -1068,11 +1074,12 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
                 sT[(16 * r + mfma_row(lane, v)) * S2_TLD + 16 * cg + (lane & 15)] = acc[r][v];
         __syncthreads();
         mark(blk, 1);
-        // right-hand side T = (r|P_K) - P, zero outside the tile's rows and the block's vectors
+        // right-hand side T = (r|P_K) - P, zero outside the tile's rows and the block's
+        // vectors (consecutive threads: consecutive rows of one vector)
         for (int e = tid; e < R * S2_NB; e += 512) {
-            const int m = e >> 7, n = e & (S2_NB - 1);
+            const int n = e / R, m = e % R;
             double &t = sT[m * S2_TLD + n];
-            t = (m < rows_here && n < nb) ? s2_rhs(sRow[m], sPr[n], t) : 0.0;
+            t = (m < rows_here && n < nb) ? L[(b0 + n) * n_rows + r0 + m] - t : 0.0;
         }
         __syncthreads();
         mark(blk, 2);

@@ -333,6 +333,9 @@ cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st
         B.tile_begin[i + 1] = B.tile_begin[i] + (int32_t)blocks_of(B.m[i].n_rows, 16 * rt);
     const unsigned grid = (unsigned)B.tile_begin[B.count];
     if (grid == 0) return CD_OK;
+    int64_t max_rows = 0;
+    for (int i = 0; i < B.count; ++i) max_rows = std::max(max_rows, B.m[i].n_rows);
+    k_rhs_eri<<<dim3((unsigned)blocks_of(max_rows, 256), 64, (unsigned)B.count), 256, 0, st>>>(B);
 #define CD_STEP2(RT)                                 \
     case RT:                                         \
         k_step2<RT><<<grid, 512, 0, st>>>(B);        \
