@@ -114,47 +114,6 @@ __device__ __forceinline__ void gemm_tile(int64_t kbeg, int64_t kend, LA la, LB 
     }
 }
 
-// Two waves per SIMD: a 512-thread workgroup in which waves w and w + 4 own
-// the same 16 columns [16 (w % 4), +16) and all RT row tiles, and split every
-// k-chunk between them (wave half h takes the 4-wide k-steps h, h + 2, ..).
-// Each half keeps its own accumulators (the caller adds the halves); the two
-// waves of a SIMD interleave their matrix instructions.
-template <int RT, int TKC, bool AK, bool BK, class LA, class LB>
-__device__ __forceinline__ void gemm_tile_2w(int64_t kbeg, int64_t kend, LA la, LB lb,
-                                             f64x4 (&acc)[RT], double *sA, double *sB)
-{
-    using SA = OperandStage<16 * RT, TKC, AK, 512>;
-    using SB = OperandStage<64, TKC, BK, 512>;
-    static_assert(TKC % 8 == 0, "k-chunk must split into an even number of 4-wide steps");
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int cw = w & 3, h = w >> 2;
-    if (kbeg >= kend) return;
-    double ra[SA::kPerThread], rb[SB::kPerThread];
-    SA::fetch(la, kbeg, kend, ra);
-    SB::fetch(lb, kbeg, kend, rb);
-    for (int64_t k0 = kbeg; k0 < kend; k0 += TKC) {
-        SA::put(sA, ra);
-        SB::put(sB, rb);
-        __syncthreads();
-        if (k0 + TKC < kend) {
-            SA::fetch(la, k0 + TKC, kend, ra);
-            SB::fetch(lb, k0 + TKC, kend, rb);
-        }
-#pragma unroll
-        for (int ks = 0; ks < TKC; ks += 8) {
-            const int kk = ks + 4 * h + (lane >> 4);
-            const double b = sB[SB::lds_index(kk, 16 * cw + (lane & 15))];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const double a = sA[SA::lds_index(kk, 16 * r + (lane & 15))];
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- split-k form
 // Wave-parallel product for short, tall operands: every wave owns whole
 // k-chunks of 16 (chunk c goes to wave c % 4), stages them in its own LDS
