@@ -3,10 +3,10 @@
 //
 //   FP32  : the half transform X^P = Lt^P C runs in FP64 and writes X rounded
 //           to FP32 (k_half_sparse<HALF_F32>); the product K = sum_P X^P^T X^P
-//           runs on v_mfma_f32_16x16x4f32 (k_syrk_rows_lp), FP32 accumulation
-//           inside k-slabs of 32 and FP64 across slabs.
+//           runs on v_mfma_f32_16x16x4f32 (k_syrk_f32), FP32 accumulation
+//           inside k-steps of 32 and FP64 across steps.
 //   BF16X3: the half transform runs in FP64 and writes X split into three BF16
-//           planes (k_half_sparse<true>); the product K reads the planes
+//           planes (k_half_sparse<HALF_BF16X3>); the product K reads the planes
 //           (k_syrk_bf16x3).  Every operand x is split as x = b0 + b1 + b2
 //           (round-to-nearest BF16 each: b0 = bf16(x), b1 = bf16(x - b0),
 //           b2 = bf16(x - b0 - b1)), and a product a*c keeps the six terms up
@@ -14,6 +14,9 @@
 //           & Heinecke, "Leveraging the bfloat16 artificial intelligence
 //           datatype for higher-precision computations", ARITH 2019), on
 //           v_mfma_f32_16x16x32_bf16, FP32 inside steps of 32 and FP64 across.
+//
+// Both read X in the k-blocked layout the half transform writes (xb_index):
+// one k-step of 32 values of 128 rows is one contiguous run of memory.
 //
 // Result lane layout of both FP32-accumulating instructions (read back on
 // gfx950): lane l, element v holds D[m = 4 (l / 16) + v][n = l % 16].
@@ -27,156 +30,167 @@ namespace cdk {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-enum LpMode { LP_F32 = 1 };
-
-constexpr int LP_TKC = 32;     // k-chunk staged in LDS
-constexpr int LP_SLAB = 32;    // FP32 accumulation length before folding into FP64
-
 __device__ __forceinline__ int lp_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 
-// LDS staging of one k-chunk of FP32 operands for a 64 x 64 tile:
-//   k-major sources   sA32[k][m], sB32[k][n]
-//   k-contiguous (KC) sA32[m][k], sB32[n][k]  (rows padded to TKC + 1)
-// so that the LDS writes follow the contiguous index of the global loads.
-template <int MODE, bool KC = false>
-struct LpStage {
-    static_assert(MODE == LP_F32, "FP32 staging only");
-    static constexpr int kF32Ld = LP_TKC + 1;    // padded row (KC)
-    static constexpr int kBytes = 2 * 64 * (LP_TKC + 1) * 4;
-    __device__ static __forceinline__ int f32_index(int k, int m)
-    {
-        return KC ? m * kF32Ld + k : k * 64 + m;
-    }
-    static constexpr int kPer = LP_TKC * 64 / 256;   // elements per thread per operand
-
-    // element e of a chunk -> (k, m), following the operand's contiguous index:
-    // m fastest for k-major sources, k fastest for k-contiguous ones (KC)
-    __device__ static __forceinline__ void coord(int e, int &k, int &m)
-    {
-        if (KC) {
-            m = e / LP_TKC;
-            k = e % LP_TKC;
-        } else {
-            k = e >> 6;
-            m = e & 63;
-        }
-    }
-    template <class LA, class LB>
-    __device__ static __forceinline__ void fetch(LA la, LB lb, int64_t k0, int64_t kend,
-                                                 double (&ra)[kPer], double (&rb)[kPer])
-    {
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = threadIdx.x + 256 * u;
-            int k, m;
-            coord(e, k, m);
-            const bool ok = k0 + k < kend;
-            const int64_t kk = ok ? k0 + k : kend - 1;   // always valid: load, then select
-            const double va = la(kk, m), vb = lb(kk, m);
-            ra[u] = ok ? va : 0.0;
-            rb[u] = ok ? vb : 0.0;
-        }
-    }
-    __device__ static __forceinline__ void put(unsigned char *smem, const double (&ra)[kPer],
-                                               const double (&rb)[kPer])
-    {
-        float *sA = reinterpret_cast<float *>(smem);
-        float *sB = sA + 64 * kF32Ld;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            int k, m;
-            coord(threadIdx.x + 256 * u, k, m);
-            sA[f32_index(k, m)] = (float)ra[u];
-            sB[f32_index(k, m)] = (float)rb[u];
-        }
-    }
-    // multiply the staged chunk into acc[r] (rows 16 r.., columns 16 w..)
-    __device__ static __forceinline__ void mma(const unsigned char *smem, f32x4 (&acc)[4])
-    {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const float *sA = reinterpret_cast<const float *>(smem);
-        const float *sB = sA + 64 * kF32Ld;
-#pragma unroll
-        for (int ks = 0; ks < LP_TKC; ks += 4) {
-            const int kk = ks + (lane >> 4);
-            const float b = sB[f32_index(kk, 16 * w + (lane & 15))];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float a = sA[f32_index(kk, 16 * r + (lane & 15))];
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[r], 0, 0, 0);
-            }
-        }
-    }
-};
-
-// acc64[r][v] += sum_k A(k, m) B(k, n) over [kbeg, kend), FP32 inside slabs.
-template <int MODE, bool KC, class LA, class LB>
-__device__ __forceinline__ void lp_tile(int64_t kbeg, int64_t kend, LA la, LB lb,
-                                        double (&acc64)[4][4], unsigned char *smem)
+// Work item of the large-tile exchange products (FP32 and 3 x BF16), launched
+// as pairs x nsplit workgroups with nsplit a multiple of 8: workgroup g runs
+// on XCD g % 8; its j = g / 8 -th item is tile pair j % pairs (lower
+// triangle, row-major) of split 8 (j / pairs) + g % 8.
+__device__ __forceinline__ void bx_item(int pairs, int &tm, int &tn, int &split)
 {
-    using S = LpStage<MODE, KC>;
-    f32x4 acc[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (kbeg >= kend) return;
-    double ra[S::kPer], rb[S::kPer];
-    S::fetch(la, lb, kbeg, kend, ra, rb);
-    int in_slab = 0;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += LP_TKC) {
-        S::put(smem, ra, rb);
-        __syncthreads();
-        if (k0 + LP_TKC < kend) S::fetch(la, lb, k0 + LP_TKC, kend, ra, rb);
-        S::mma(smem, acc);
-        __syncthreads();
-        in_slab += LP_TKC;
-        if (in_slab >= LP_SLAB || k0 + LP_TKC >= kend) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    acc64[r][v] += (double)acc[r][v];
-                    acc[r][v] = 0.f;
-                }
-            in_slab = 0;
-        }
-    }
+    const int g = blockIdx.x, xcd = g & 7, j = g >> 3;
+    const int t = j % pairs;
+    split = 8 * (j / pairs) + xcd;
+    int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (m * (m + 1) / 2 > t) --m;
+    while ((m + 1) * (m + 2) / 2 <= t) ++m;
+    tm = m;
+    tn = t - m * (m + 1) / 2;
 }
 
-// Partial K from row-major FP32 X, reduced precision:
-//   Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k]   (lower tile pairs)
-template <int MODE>
-__global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ X, int64_t ldx,
-                                                      int N, const int64_t *__restrict__ n_vectors,
-                                                      int ncol, int nsplit,
-                                                      double *__restrict__ Kp)
+// ---------------------------------------------------------------- FP32, large tiles
+// Partial K from the k-blocked FP32 X with 128 x 128 output tiles:
+//   Kp[s][mu][nu] = sum_{k in split s} X[mu][k] X[nu][k]   (lower tile pairs)
+// Grid and work items as the 3 x BF16 product below (bx_item: the tile pairs
+// of one k-range on one XCD).  Each wave owns a 64 x 64 quarter of the tile
+// (4 x 4 accumulators of the 16x16x4 FP32 instruction).  A step stages 32
+// values of the 256 rows (128 of each side: 32 KB) in one of three LDS
+// buffers, straight from memory (global_load_lds, 16 bytes per lane, 8 per
+// lane per step) two steps ahead of the products; one barrier per step.  LDS
+// rows are 128 bytes with no padding; the 16-byte group g of row r sits at
+// g ^ ((r / 2) % 8), so the 16 rows one quarter-wave reads at one k fall on
+// 16 different banks.
+//
+// FP32 accumulation runs over one step (32 values, from a zero accumulator)
+// and each row tile's step sums are added in FP64 while the next row tile's
+// products run, as in the 3 x BF16 product.
+constexpr int XF_STAGE = 256 * XB_K;                  // floats per stage (32 KB)
+constexpr int XF_LOADS = XF_STAGE * 4 / 16 / 256;     // 16-byte pieces per thread per stage (8)
+
+__global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ X, int64_t rows, int N,
+                                                  const int64_t *__restrict__ n_vectors, int ncol,
+                                                  int pairs, int nsplit, double *__restrict__ Kp)
 {
-    __shared__ __align__(16) unsigned char smem[LpStage<MODE, true>::kBytes];
-    int t, s;
-    syrk_tile_split(N, nsplit, t, s);
-    int tm = 0;
-    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
-    const int tn = t - tm * (tm + 1) / 2;
+    __shared__ __align__(16) float sX[3 * XF_STAGE];
+    int tm, tn, s;
+    bx_item(pairs, tm, tn, s);
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
-    per = (per + LP_SLAB - 1) / LP_SLAB * LP_SLAB;
+    per = (per + XB_K - 1) / XB_K * XB_K;
     const int64_t kb = s * per;
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
-    const int m0 = tm * 64, n0 = tn * 64;
-    double acc[4][4] = {};
-    lp_tile<MODE, true>(
-        kb, ke,
-        [&](int64_t k, int m) -> double { return (double)X[min(m0 + m, N - 1) * ldx + k]; },
-        [&](int64_t k, int n) -> double { return (double)X[min(n0 + n, N - 1) * ldx + k]; },
-        acc, smem);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = tm * 128, n0 = tn * 128;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..127 the
+    // A side m0.., 128..255 the B side n0..), slot lane % 8, which holds the
+    // 16-byte group (lane % 8) ^ ((r / 2) % 8) of that row
+    int goff[XF_LOADS];
+#pragma unroll
+    for (int v = 0; v < XF_LOADS; ++v) {
+        const int r = 8 * (4 * v + w) + (lane >> 3);
+        const int grow = (r < 128) ? m0 + r : n0 + r - 128;
+        goff[v] = grow * XB_K + 4 * ((lane & 7) ^ ((r >> 1) & 7));
+    }
+    // a full step straight into LDS; a partial last step through registers
+    // with the values past ke set to zero
+    auto load_step = [&](float *st, int64_t k0) __attribute__((always_inline)) {
+        if (k0 + XB_K <= ke) {
+            const float *base = X + (k0 / XB_K) * (rows * XB_K);
+#pragma unroll
+            for (int v = 0; v < XF_LOADS; ++v)
+                lds_dma16(base + goff[v], (lds_void *)(st + 256 * (4 * v + w)));
+        } else {
+            const float *base = X + (k0 / XB_K) * (rows * XB_K);
+            for (int e = tid; e < XF_STAGE; e += 256) {
+                const int r = e / XB_K, k = e % XB_K;
+                const int grow = (r < 128) ? m0 + r : n0 + r - 128;
+                st[r * XB_K + 4 * ((k >> 2) ^ ((r >> 1) & 7)) + (k & 3)] =
+                    (k0 + k < ke) ? base[grow * XB_K + k] : 0.f;
+            }
+        }
+    };
+    double acc64[4][4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
+    // operand of this lane at k-step q (k = 4 q + lane / 16) of a row r with
+    // r % 16 = lane % 16: group q of that row, swizzled
+    const int lr = lane & 15, sw = (lr >> 1) & 7, el = lane >> 4;
+    auto mma_step = [&](const float *S) __attribute__((always_inline)) {
+        float b[8][4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                b[q][j] = S[(128 + 64 * wc + 16 * j + lr) * XB_K + 4 * (q ^ sw) + el];
+        auto read_a = [&](int i, float (&a)[8]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = S[(64 * wr + 16 * i + lr) * XB_K + 4 * (q ^ sw) + el];
+        };
+        auto products = [&](const float (&a)[8], f32x4 (&t)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    t[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][j], t[j], 0, 0, 0);
+        };
+        auto fold = [&](int i, const f32x4 (&t)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)t[j][e];
+        };
+        float a0[8], a1[8];
+        f32x4 t0[4], t1[4];
+        read_a(0, a0);
+        read_a(1, a1);
+        products(a0, t0);
+        read_a(2, a0);
+        products(a1, t1);
+        fold(0, t0);
+        read_a(3, a1);
+        products(a0, t0);
+        fold(1, t1);
+        products(a1, t1);
+        fold(2, t0);
+        fold(3, t1);
+    };
+    // step c: its own loads landed (the next step's may stay in flight), a
+    // barrier (every wave's pieces of step c are in, and every wave is done
+    // with the buffer that step c + 2 refills), the loads of step c + 2, then
+    // the products of step c
+    const int64_t nch = (ke > kb) ? (ke - kb + XB_K - 1) / XB_K : 0;
+    auto step = [&](int64_t c, const float *cur, float *refill) __attribute__((always_inline)) {
+        if (c + 1 < nch) wait_vmcnt<XF_LOADS>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        if (c + 2 < nch) load_step(refill, kb + (c + 2) * XB_K);
+        mma_step(cur);
+    };
+    float *s0 = sX, *s1 = sX + XF_STAGE, *s2 = sX + 2 * XF_STAGE;
+    if (nch > 0) load_step(s0, kb);
+    if (nch > 1) load_step(s1, kb + XB_K);
+    for (int64_t c = 0; c < nch; c += 3) {
+        step(c, s0, s2);
+        if (c + 1 < nch) step(c + 1, s1, s0);
+        if (c + 2 < nch) step(c + 2, s2, s1);
+    }
     double *out = Kp + (int64_t)s * N * N;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int m = m0 + 16 * r + lp_row(lane, v), n = n0 + 16 * w + (lane & 15);
-            if (m < N && n < N) out[(int64_t)m * N + n] = acc[r][v];
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 64 * wr + 16 * i + lp_row(lane, e);
+                const int n = n0 + 64 * wc + 16 * j + lr;
+                if (m < N && n < N) out[(int64_t)m * N + n] = acc64[i][j][e];
+            }
 }
 
 // ---------------------------------------------------------------- 3 x BF16, large tiles
@@ -202,9 +216,9 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
 // slab length, so the matrix unit's FP32 accumulation rounds with a bias and
 // slabs stay at one step.
 //
-// X holds its three planes 'plane' values apart, each of ldx-value rows padded
-// to a whole number of 128-row tiles (the rows past N are never written and
-// only enter K entries past N, which are not stored).
+// X holds its three planes 'plane' values apart, each k-blocked (xb_index)
+// over 'rows' rows: N padded to a whole number of 128-row tiles (the rows past
+// N are never written and only enter K entries past N, which are not stored).
 //
 // Grid (one workgroup per compute unit at 144 KB of LDS): workgroup g runs on
 // XCD g % 8; its j = g / 8 -th item is tile pair j % pairs of split
@@ -213,7 +227,7 @@ __global__ __launch_bounds__(256) void k_syrk_rows_lp(const float *__restrict__ 
 // L2.  'nsplit' / 8 k-ranges per XCD are chosen on the host so that the
 // workgroups fill an XCD's compute units in whole rounds.
 constexpr int BX_TILE = 128;
-constexpr int BX_TK = 32;                        // k per stage: one 16x16x32 step
+constexpr int BX_TK = XB_K;                      // k per stage: one 16x16x32 step
 constexpr int BX_ROWS = 2 * BX_TILE;             // A rows, then B rows
 constexpr int BX_STAGE = 3 * BX_ROWS * BX_TK;    // bf16 elements per stage (48 KB)
 constexpr int BX_LOADS = BX_STAGE * 2 / 16 / 256;   // 16-byte pieces per thread per stage (12)
@@ -224,19 +238,8 @@ __device__ __forceinline__ int bx_off(int p, int r, int g)
     return 8 * ((p * BX_ROWS + r) * 4 + (g ^ ((r >> 2) & 3)));
 }
 
-__device__ __forceinline__ void bx_item(int pairs, int &tm, int &tn, int &split)
-{
-    const int g = blockIdx.x, xcd = g & 7, j = g >> 3;
-    const int t = j % pairs;
-    split = 8 * (j / pairs) + xcd;
-    int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while (m * (m + 1) / 2 > t) --m;
-    while ((m + 1) * (m + 2) / 2 <= t) ++m;
-    tm = m;
-    tn = t - m * (m + 1) / 2;
-}
 
-__global__ __launch_bounds__(256) void k_syrk_bf16x3(const __bf16 *__restrict__ Xp, int64_t ldx,
+__global__ __launch_bounds__(256) void k_syrk_bf16x3(const __bf16 *__restrict__ Xp, int64_t rows,
                                                      int64_t plane, int N,
                                                      const int64_t *__restrict__ n_vectors,
                                                      int ncol, int pairs, int nsplit,
@@ -260,25 +263,27 @@ __global__ __launch_bounds__(256) void k_syrk_bf16x3(const __bf16 *__restrict__ 
     // lane % 4, which holds k-group g = (lane % 4) ^ ((lane / 16) % 4) of that
     // row.  Rows 0..127 are the A side (rows m0..), 128..255 the B side (n0..);
     // the planes hold whole 128-row tiles (rows past N are padding), so a
-    // piece's address is this lane's offset plus a wave-uniform one.
+    // piece's address is this lane's offset plus a wave-uniform one plus the
+    // step's k-block.
     const int g = (lane & 3) ^ ((lane >> 4) & 3);
-    const __bf16 *lane_src = Xp + (int64_t)(lane >> 2) * ldx + 8 * g;
+    const __bf16 *lane_src = Xp + (lane >> 2) * XB_K + 8 * g;
     auto wave_off = [&](int v) __attribute__((always_inline)) -> int64_t {
         const int b = 4 * v + w, rb = b & 15;
         const int row0 = (rb < 8) ? m0 + 16 * rb : n0 + 16 * (rb - 8);
-        return (int64_t)(b >> 4) * plane + (int64_t)row0 * ldx;
+        return (int64_t)(b >> 4) * plane + row0 * XB_K;
     };
     // a full step straight into LDS (12 loads per lane); a partial last step
     // through registers with the values past ke set to zero
     auto load_step = [&](__bf16 *stage, int64_t k0) __attribute__((always_inline)) {
+        const int64_t kblk = (k0 / XB_K) * (rows * XB_K);
         if (k0 + BX_TK <= ke) {
 #pragma unroll
             for (int v = 0; v < BX_LOADS; ++v)
-                lds_dma16(lane_src + wave_off(v) + k0, (lds_void *)(stage + 512 * (4 * v + w)));
+                lds_dma16(lane_src + wave_off(v) + kblk, (lds_void *)(stage + 512 * (4 * v + w)));
         } else {
 #pragma unroll
             for (int v = 0; v < BX_LOADS; ++v) {
-                const __bf16 *src = lane_src + wave_off(v) + k0;
+                const __bf16 *src = lane_src + wave_off(v) + kblk;
                 bf16x8 x;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) x[e] = (k0 + 8 * g + e < ke) ? src[e] : (__bf16)0.0f;

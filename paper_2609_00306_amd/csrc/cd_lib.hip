@@ -743,6 +743,7 @@ cd_status cd_decompose_noalloc(const cd_problem *probs, int32_t count, const cd_
     return decompose_impl(probs, count, opts, ws, static_cast<hipStream_t>(stream), false);
 }
 
+extern "C++" {   // the cache below is C++ (its key is a std::vector)
 namespace {
 // Shapes measured by cd_autotune in this process, keyed by device and problem shape.
 std::mutex g_tune_mu;
@@ -767,6 +768,7 @@ std::vector<int64_t> tune_key(const cd_problem *probs, int32_t count, const cd_d
     return k;
 }
 }  // namespace
+}  // extern "C++"
 
 cd_status cd_autotune(const cd_problem *probs, int32_t count, const cd_decomp_opts *opts,
                       void *ws, size_t ws_bytes, cd_tuning *best, void *stream)
@@ -877,14 +879,14 @@ int jk_nsplit(int N, int n_cu)
     return std::max(8, std::min(ns, 64));
 }
 
-// Tile pairs (lower triangle) of the large-tile 3 x BF16 exchange product.
+// Tile pairs (lower triangle) of the large-tile (FP32 and 3 x BF16) exchange products.
 int bx_pairs(int N)
 {
     const int T = (N + BX_TILE - 1) / BX_TILE;
     return T * (T + 1) / 2;
 }
 
-// k-ranges per XCD of the 3 x BF16 exchange product: the smallest count whose
+// k-ranges per XCD of the large-tile exchange products: the smallest count whose
 // pairs * ss workgroups (one per compute unit) fill the compute units of an
 // XCD in whole rounds to 95% or better, else the best fill up to 16.
 int bx_subsplits(int pairs, int n_cu)
@@ -942,7 +944,7 @@ cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int 
 // Number of partial K matrices of the exchange product at a precision.
 int jk_splits(int N, int n_cu, cd_precision prec)
 {
-    if (prec == CD_BF16X3) return 8 * bx_subsplits(bx_pairs(N), n_cu);
+    if (prec != CD_FP64) return 8 * bx_subsplits(bx_pairs(N), n_cu);
     return jk_nsplit(N, n_cu);
 }
 
@@ -1016,12 +1018,12 @@ struct JkWs {
     size_t bytes;
 };
 
-// Row stride (in values) of the BF16 planes of X: a multiple of 8, so every
-// row starts 16-byte aligned.
+// Values per row of a BF16 plane of X (a plane holds bx_rows(N) rows of them,
+// k-blocked): a multiple of 8; x_ld's multiple of 128 is also one of XB_K.
 int64_t bf16_ld(int64_t n) { return (n + 7) / 8 * 8; }
 
-// Rows of one BF16 plane of X: N padded to whole 128-row tiles of the
-// exchange product.
+// Rows of the k-blocked FP32 X and of each BF16 plane: N padded to whole
+// 128-row tiles of the exchange product.
 int64_t bx_rows(int64_t N) { return (N + BX_TILE - 1) / BX_TILE * BX_TILE; }
 
 JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
@@ -1033,12 +1035,13 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
     w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
     w.sp = carve_sparse(c, N, p.n_rows, p.max_vectors);
-    // X: FP64 [N][x_ld(M, O)], FP32 in the same space, or three BF16 planes of
-    // rows of the same number of values
+    // X: FP64 [N][x_ld(M, O)], or in the same space the k-blocked FP32 X or
+    // three k-blocked BF16 planes, each over N rows padded to 128-row tiles
     const int64_t ldx = x_ld(p.max_vectors, p.n_occ);
     const int64_t xf = ldx * N;
+    const int64_t xs = (bx_rows(N) * ldx + 1) / 2;
     const int64_t xb = (3 * bx_rows(N) * bf16_ld(ldx) + 3) / 4;
-    w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, xb)));
+    w.X = c.take<double>(std::max<int64_t>(1, std::max(xf, std::max(xs, xb))));
     w.Kp = c.take<double>(std::max<int64_t>(1, (int64_t)nsplit * N * N));
     w.X64 = (p.Lmo && prec != CD_FP64) ? c.take<double>(std::max<int64_t>(1, xf)) : nullptr;
     w.C1p = p.Lmo ? c.take<double>(std::max<int64_t>(1, tr2_c1p_doubles(N, p.n_occ))) : nullptr;
@@ -1150,24 +1153,26 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             if (p.Lmo && (s = second_half(w.X))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
-            // X in FP64 (matrix cores), written rounded to FP32 (and in FP64 for
-            // C^T L C); the exchange product then runs on FP32 matrix cores
-            launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, ldx, 0, w.X64, ldx,
+            // X in FP64 (matrix cores), written rounded to FP32 (k-blocked; and in
+            // FP64 for C^T L C); the exchange product then runs on FP32 matrix cores
+            const int64_t R = bx_rows(N);
+            launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, R, 0, w.X64, ldx,
                                   sp);
             if (p.Lmo && (s = second_half(w.X64))) return s;
-            k_syrk_rows_lp<LP_F32><<<sgrid, 256, 0, sp>>>(X32, ldx, (int)N, p.n_vectors, O,
-                                                          nsplit, w.Kp);
+            const int pairs = bx_pairs((int)N);
+            k_syrk_f32<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O,
+                                                                  pairs, nsplit, w.Kp);
         } else {
-            // X in FP64 (matrix cores), written split into three BF16 planes; the
-            // exchange product then runs on BF16 matrix cores from the planes
-            const int64_t ldb = bf16_ld(ldx), plane = bx_rows(N) * ldb;
+            // X in FP64 (matrix cores), written split into three k-blocked BF16
+            // planes; the exchange product then runs on BF16 matrix cores from them
+            const int64_t R = bx_rows(N), plane = R * bf16_ld(ldx);
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
-            launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, ldb, plane, w.X64,
+            launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, R, plane, w.X64,
                                      ldx, sp);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
-                Xp, ldb, plane, (int)N, p.n_vectors, O, pairs, nsplit, w.Kp);
+                Xp, R, plane, (int)N, p.n_vectors, O, pairs, nsplit, w.Kp);
         }
         k_kreduce<<<(unsigned)blocks_of(NN, 256), 256, 0, sp>>>(w.Kp, (int)N, nsplit, 0, p.K);
         if ((s = check_launch("J/K kernels"))) return s;
