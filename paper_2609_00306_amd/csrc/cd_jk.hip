@@ -8,6 +8,8 @@
 //
 // L is packed over screened pairs (rows); a dense N x N row map unpacks it
 // on the fly into the MFMA operand tiles.
+#include <type_traits>
+
 #include "cd_device.hpp"
 #include "cd_mfma.hpp"
 
@@ -221,9 +223,8 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
 // Half transform over neighbour lists (FP64 matrix cores):
 //   Y[mu][P * ncol + i] = sum_{j in nbr(mu)} LT[r_j][P] C[sigma_j][i]
 // OUT selects what is written: HALF_F64 the FP64 result, row mu at mu * ldy;
-// HALF_BF16X3 the FP64 result x split as x = b0 + b1 + b2 into three BF16
-// planes (b0 = bf16(x), b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)), plane p at
-// Yp + p * plane: the operand of the 3 x BF16 exchange product, split once
+// HALF_BF16X3 the result split into three BF16 planes (split_bf16x3), plane p
+// at Yp + p * plane: the operand of the 3 x BF16 exchange product, split once
 // here instead of in every tile that reads it; HALF_F32 the result rounded to
 // FP32 (the operand of the FP32 exchange product).  The last two forms are
 // k-blocked (xb_index, ldy = the padded row count R), and a non-null Y64 also
@@ -233,20 +234,25 @@ __global__ __launch_bounds__(256) void k_nbr_fill(const int32_t *__restrict__ ro
 // cut into blocks of XB_K values, and block b holds the XB_K values of every
 // row mu contiguously at (b R + mu) XB_K.  A k-step of the exchange product
 // (one block, 128 rows) is then one contiguous run of memory instead of 128
-// rows far apart, which moves about half the HBM bytes the row-major form
-// did on the 1200-function workload.
+// rows far apart.
 constexpr int XB_K = 32;
 __host__ __device__ __forceinline__ int64_t xb_index(int64_t mu, int64_t e, int64_t rows)
 {
     return ((e / XB_K) * rows + mu) * XB_K + e % XB_K;
 }
 
+// x = b0 + b1 + b2 + O(2^-24 |x|): f = fp32(x), b0 = bf16(f), b1 = bf16(f - b0),
+// b2 = bf16(f - b0 - b1), every rounding to nearest; the differences are exact
+// in FP32 (each operand pair lies within a factor of two), so the split is
+// plain FP32 arithmetic.  |x - f| <= 2^-24 |x| and the part past b2 is below
+// 2^-27 |f|, both under the 2^-16 order the six products keep.
 __device__ __forceinline__ void split_bf16x3(double x, __bf16 &b0, __bf16 &b1, __bf16 &b2)
 {
-    b0 = (__bf16)(float)x;
-    const double r1 = x - (double)(float)b0;
-    b1 = (__bf16)(float)r1;
-    b2 = (__bf16)(float)(r1 - (double)(float)b1);
+    const float f = (float)x;
+    b0 = (__bf16)f;
+    const float r1 = f - (float)b0;
+    b1 = (__bf16)r1;
+    b2 = (__bf16)(r1 - (float)b1);
 }
 
 // Output forms of the half transform.
@@ -287,7 +293,10 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
     constexpr int kBL = kB / 128;                  // 16-byte-piece loads of B per chunk
     constexpr int kBW = (kBL + 7) / 8;             // per wave, waves < kBL % 8 one more
     static_assert(CT % 2 == 0, "whole 16-byte pieces per row pair");
-    __shared__ __align__(16) double sU[3 * kChunk];
+    // chunk buffers; after the products, the staged output planes (3 x BF16:
+    // three planes of 128 x 16 CT values, 120 KB at CT = 10)
+    constexpr int kStage = (OUT == HALF_BF16X3) ? 3 * HS_P * HS_C * 2 / 8 : 0;
+    __shared__ __align__(16) double sU[(3 * kChunk > kStage) ? 3 * kChunk : kStage];
     __shared__ int sNs[HS_SEG], sNr[HS_SEG];
     const int64_t M = *n_vectors;
     const int64_t p0 = (int64_t)blockIdx.x * HS_P;
@@ -367,6 +376,67 @@ __global__ __launch_bounds__(512) void k_half_sparse(const double *__restrict__ 
         }
     }
     // acc[ct][v]: vector p0 + 16 w + mfma_row(lane, v), column n0 + 16 ct + lane % 16
+    if constexpr (OUT != HALF_F64) if (gridDim.y == 1) {
+        // All columns in one workgroup: its outputs are the contiguous range
+        // e in [p0 ncol, (p0 + np) ncol), which starts on a k-block (p0 is a
+        // multiple of 128).  The planes go through LDS in e order (each value
+        // split once) and out as 16-byte runs, eight (FP32) or four (BF16) of
+        // which fill a block row, instead of 2- or 4-byte stores scattered
+        // over the blocks.
+        using OT = typename std::conditional<OUT == HALF_F32, float, __bf16>::type;
+        constexpr int G = 16 / (int)sizeof(OT);
+        constexpr int NPL = (OUT == HALF_F32) ? 1 : 3;
+        constexpr int PS = HS_P * HS_C;   // values per staged plane
+        static_assert(NPL * PS * sizeof(OT) <= sizeof(sU), "the planes fit in LDS");
+        const int np = (int)min((int64_t)HS_P, M - p0);
+        const int len = np * ncol;
+        const int64_t e0 = p0 * ncol;
+        OT *T = reinterpret_cast<OT *>(sU);
+        __syncthreads();   // every wave is done with the chunk buffers
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int P = 16 * w + mfma_row(lane, v);
+                const int n = 16 * ct + (lane & 15);
+                if (P < np && n < ncol) {
+                    if constexpr (OUT == HALF_F32) {
+                        T[P * ncol + n] = (float)acc[ct][v];
+                    } else {
+                        __bf16 b0, b1, b2;
+                        split_bf16x3(acc[ct][v], b0, b1, b2);
+                        T[P * ncol + n] = b0;
+                        T[PS + P * ncol + n] = b1;
+                        T[2 * PS + P * ncol + n] = b2;
+                    }
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+            OT *out = static_cast<OT *>(Yv) + pl * plane;
+            const OT *Tp = T + pl * PS;
+            for (int i = G * tid; i < len; i += G * 512) {
+                if (i + G <= len) {
+                    *reinterpret_cast<uint4 *>(out + xb_index(mu, e0 + i, ldy)) =
+                        *reinterpret_cast<const uint4 *>(Tp + i);
+                } else {
+                    for (int j = i; j < len; ++j) out[xb_index(mu, e0 + j, ldy)] = Tp[j];
+                }
+            }
+        }
+        if (Y64) {   // the FP64 value as well (C^T L C)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int P = 16 * w + mfma_row(lane, v);
+                    const int n = 16 * ct + (lane & 15);
+                    if (P < np && n < ncol) Y64[(int64_t)mu * ldy64 + e0 + P * ncol + n] = acc[ct][v];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll

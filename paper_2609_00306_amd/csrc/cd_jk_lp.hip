@@ -8,9 +8,8 @@
 //   BF16X3: the half transform runs in FP64 and writes X split into three BF16
 //           planes (k_half_sparse<HALF_BF16X3>); the product K reads the planes
 //           (k_syrk_bf16x3).  Every operand x is split as x = b0 + b1 + b2
-//           (round-to-nearest BF16 each: b0 = bf16(x), b1 = bf16(x - b0),
-//           b2 = bf16(x - b0 - b1)), and a product a*c keeps the six terms up
-//           to order 2^-16: a0c0 + a0c1 + a1c0 + a0c2 + a1c1 + a2c0 (Henry, Tang
+//           (round-to-nearest BF16 each, split_bf16x3), and a product a*c
+//           keeps the six terms up to order 2^-16: a0c0 + a0c1 + a1c0 + a0c2 + a1c1 + a2c0 (Henry, Tang
 //           & Heinecke, "Leveraging the bfloat16 artificial intelligence
 //           datatype for higher-precision computations", ARITH 2019), on
 //           v_mfma_f32_16x16x32_bf16, FP32 inside steps of 32 and FP64 across.
@@ -227,7 +226,7 @@ __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ X, i
 // L2.  'nsplit' / 8 k-ranges per XCD are chosen on the host so that the
 // workgroups fill an XCD's compute units in whole rounds.
 constexpr int BX_TILE = 128;
-constexpr int BX_TK = XB_K;                      // k per stage: one 16x16x32 step
+constexpr int BX_TK = XB_K;                   // k per stage: one 16x16x32 step, one block
 constexpr int BX_ROWS = 2 * BX_TILE;             // A rows, then B rows
 constexpr int BX_STAGE = 3 * BX_ROWS * BX_TK;    // bf16 elements per stage (48 KB)
 constexpr int BX_LOADS = BX_STAGE * 2 / 16 / 256;   // 16-byte pieces per thread per stage (12)

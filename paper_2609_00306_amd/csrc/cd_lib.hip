@@ -1136,10 +1136,15 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
         // the second half of the transform on the FP64 X: for one problem on
-        // side stream 1, beside the exchange product
-        auto second_half = [&](const double *X64) -> cd_status {
+        // side stream 1, beside the exchange product when 'beside', else before
+        // it on the same stream.  The 3 x BF16 product runs after it: beside it,
+        // the two took 1.5 ms longer on the 1200-function workload (the
+        // product's 144 KB workgroups and the transform's cannot share a compute
+        // unit, and the product's tile pairs of one k-range no longer run
+        // together); the FP64 and FP32 products gain 0.3-0.5 ms from the overlap.
+        auto second_half = [&](const double *X64, bool beside) -> cd_status {
             hipStream_t st2 = sp;
-            if (count == 1) {
+            if (count == 1 && beside) {
                 st2 = side->s[1 % kJkSide];
                 if (hipEventRecord(side->fork, sp) != hipSuccess ||
                     hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
@@ -1150,7 +1155,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         if (prec == CD_FP64) {
             launch_half<HALF_F64>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, w.X, ldx, 0, nullptr, 0,
                                   sp);
-            if (p.Lmo && (s = second_half(w.X))) return s;
+            if (p.Lmo && (s = second_half(w.X, true))) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             // X in FP64 (matrix cores), written rounded to FP32 (k-blocked; and in
@@ -1158,7 +1163,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             const int64_t R = bx_rows(N);
             launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, R, 0, w.X64, ldx,
                                   sp);
-            if (p.Lmo && (s = second_half(w.X64))) return s;
+            if (p.Lmo && (s = second_half(w.X64, true))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_f32<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O,
                                                                   pairs, nsplit, w.Kp);
@@ -1169,7 +1174,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
             launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, R, plane, w.X64,
                                      ldx, sp);
-            if (p.Lmo && (s = second_half(w.X64))) return s;
+            if (p.Lmo && (s = second_half(w.X64, false))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
                 Xp, R, plane, (int)N, p.n_vectors, O, pairs, nsplit, w.Kp);
