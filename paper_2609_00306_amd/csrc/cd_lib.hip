@@ -1123,11 +1123,25 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             k_fill_f64<<<256, 256, 0, sp>>>(p.Lmo, mv * O * O, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
         launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, sp);
-        k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sj>>>((int)N, O, p.C, w.Dm);
-        k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sj>>>(n, p.row_pair, (int)N, w.Dm, w.w);
-        k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
-        k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
-                                                         (int)N, p.J);
+        // the Coulomb build (density, then two passes over L): for one problem
+        // on side stream 0, enqueued where it slowed the rest least on the
+        // 1200-function workload: after the transpose (which it slowed from
+        // 1.1 to 3 ms, both reading L) beside the FP64 half transform (the
+        // FP64 product, which shares compute units with it, lost 2 ms); after
+        // the half transform beside the FP32 product (1.4 ms faster than beside
+        // the half transform); after the second half of the transform beside
+        // the 3 x BF16 product.
+        auto j_chain = [&]() -> cd_status {
+            if (sj != sp && (hipEventRecord(side->fork, sp) != hipSuccess ||
+                             hipStreamWaitEvent(sj, side->fork, 0) != hipSuccess))
+                return fail(CD_ERR_DEVICE, "fork failed");
+            k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sj>>>((int)N, O, p.C, w.Dm);
+            k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sj>>>(n, p.row_pair, (int)N, w.Dm, w.w);
+            k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
+            k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
+                                                             (int)N, p.J);
+            return CD_OK;
+        };
         const int ldcp = (int)hs_cp_ld(O);
         launch_pack_c(p.C, (int)N, O, (int)N + 1, ldcp, w.Cp, sp);
         const int T = (int)blocks_of(N, 64);
@@ -1153,6 +1167,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, st2);
         };
         if (prec == CD_FP64) {
+            if ((s = j_chain())) return s;
             launch_half<HALF_F64>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, w.X, ldx, 0, nullptr, 0,
                                   sp);
             if (p.Lmo && (s = second_half(w.X, true))) return s;
@@ -1163,6 +1178,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             const int64_t R = bx_rows(N);
             launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, R, 0, w.X64, ldx,
                                   sp);
+            if ((s = j_chain())) return s;
             if (p.Lmo && (s = second_half(w.X64, true))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_f32<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O,
@@ -1175,6 +1191,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, R, plane, w.X64,
                                      ldx, sp);
             if (p.Lmo && (s = second_half(w.X64, false))) return s;
+            if ((s = j_chain())) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
                 Xp, R, plane, (int)N, p.n_vectors, O, pairs, nsplit, w.Kp);
