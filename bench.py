@@ -46,20 +46,22 @@ DECOMP_SOURCES = ["paper_2609_00306_amd/csrc/cd_decompose.hip",
                   "paper_2609_00306_amd/csrc/cd_mfma.hpp",
                   "paper_2609_00306_amd/csrc/cd_device.hpp",
                   "paper_2609_00306_amd/csrc/cd_kernels.hpp"]
-BF16_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
+LP_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
                 "paper_2609_00306_amd/csrc/cd_device.hpp",
                 "paper_2609_00306_amd/csrc/cd_mfma.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.25, 1048576.0 / 1048576.0
-_DECOMP_SHA = "2c7d41ec0628b9004d46af95b6dc8258ed8d5b62438267c4e61fd61c495fc694"
+_DECOMP_SHA = "23db0db900845125edaca5dafd2fc8a37fad3054de9b28fe22e3ec0778528e5b"
+_LP_SHA = "e3aba4dc7ad6221c34752a91052e709f2b9dd518ba9fa26da6597ca967338915"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 34617693.9, "write_kib": 2680245.8},
+                    "fetch_kib": 36119483.0, "write_kib": 2680026.7},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3717570.1, "write_kib": 355838.4},
-        "k_syrk_bf16x3": {"sources": BF16_SOURCES,
-                          "sha256": "3c4ee224f0d8c5b7ee9f6b5a8b6289a26e045bd5faf2e74b909728a987389877",
-                          "fetch_kib": 23245332.6, "write_kib": 198720.0},
+                    "fetch_kib": 3717256.9, "write_kib": 355400.5},
+        "k_syrk_bf16x3": {"sources": LP_SOURCES, "sha256": _LP_SHA,
+                          "fetch_kib": 13052307.8, "write_kib": 198720.0},
+        "k_syrk_f32": {"sources": LP_SOURCES, "sha256": _LP_SHA,
+                       "fetch_kib": 4182614.9, "write_kib": 198720.0},
     },
 }
 
@@ -483,9 +485,13 @@ def main():
             e["speedup_step_vs_fp64"] = runs["fp64"]["ms_per_step"] / r["ms_per_step"]
             e["speedup_jk_vs_fp64"] = ((runs["fp64"]["jk"] + 0.0) /
                                        (r["jk"] + (0.0 if p in FUSED else r["transform"])))
-        if p == "bf16x3":
-            e["exchange_product_hbm_bytes"] = counter_traffic("k_syrk_bf16x3", args.config, tau)
-            e["exchange_product_planes_bytes"] = 6.0 * (-(-N // 128) * 128) * M * O
+        if p in ("bf16x3", "fp32"):
+            # HBM bytes of the exchange product against the bytes of its operand
+            # (the k-blocked X over N padded to 128-row tiles: 3 BF16 planes or FP32)
+            kern = "k_syrk_bf16x3" if p == "bf16x3" else "k_syrk_f32"
+            e["exchange_product_hbm_bytes"] = counter_traffic(kern, args.config, tau)
+            e["exchange_product_operand_bytes"] = ((6.0 if p == "bf16x3" else 4.0) *
+                                                   (-(-N // 128) * 128) * M * O)
         precision[p] = e
 
     # per-batch device-clock stamps of the pivot selection (one untimed run)
@@ -567,7 +573,8 @@ def main():
                     "traffic": counter_traffic("k_step2", args.config, tau),
                     "work": "n M (M - 1) FP64 flops per launch", "launch_ms": t_solve},
         "k_step1": {"kernel": "k_step1 (pivot selection on the active rows, one cooperative "
-                              "launch of candidate batches)",
+                              "launch of candidate batches; launch_ms is the phase, which also "
+                              "holds the pivot-block inverses and the solve's integral pass)",
                     "bound": "mfma", "achieved": w_sel / (t_sel * 1e-3) / 1e12,
                     "peak": PEAK["fp64"], "unit": "TFLOP/s",
                     "traffic": counter_traffic("k_step1", args.config, tau),

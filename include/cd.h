@@ -132,7 +132,8 @@ typedef struct {
     void *const *events;   /* optional (may be NULL): host array of 4 hipEvent_t that the call
                               records on 'stream' at the phase boundaries of the last problem:
                               [0] before the pair/diagonal setup, [1] before pivot selection,
-                              [2] before the all-row solve, [3] after it */
+                              [2] before the all-row substitution (k_step2; after the pivot
+                              blocks' inverses and the solve's integral pass), [3] after it */
     int64_t *timeline;     /* optional (may be NULL): DEVICE buffer of 1 + 16 * timeline_cap int64
                               of device-clock (100 MHz) stamps of the last problem, for profiling.
                               [0]: number of candidate batches of the pivot selection;

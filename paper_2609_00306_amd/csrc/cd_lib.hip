@@ -325,6 +325,18 @@ int step2_rows_default(const Step2Batch &B, int n_cu)
     return best;
 }
 
+// The all-row solve of a batch of problems: first the right-hand-side
+// integrals of every row against the new pivots (k_rhs_eri, written into L),
+// then the substitution (k_step2).
+cd_status launch_rhs_batch(const Step2Batch &B, hipStream_t st)
+{
+    int64_t max_rows = 0;
+    for (int i = 0; i < B.count; ++i) max_rows = std::max(max_rows, B.m[i].n_rows);
+    if (max_rows == 0) return CD_OK;
+    k_rhs_eri<<<dim3((unsigned)blocks_of(max_rows, 256), 64, (unsigned)B.count), 256, 0, st>>>(B);
+    return check_launch("all-row integrals");
+}
+
 cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st)
 {
     const int rt = rt_req ? rt_req : step2_rows_default(B, n_cu);
@@ -333,9 +345,6 @@ cd_status launch_step2_batch(Step2Batch &B, int n_cu, int rt_req, hipStream_t st
         B.tile_begin[i + 1] = B.tile_begin[i] + (int32_t)blocks_of(B.m[i].n_rows, 16 * rt);
     const unsigned grid = (unsigned)B.tile_begin[B.count];
     if (grid == 0) return CD_OK;
-    int64_t max_rows = 0;
-    for (int i = 0; i < B.count; ++i) max_rows = std::max(max_rows, B.m[i].n_rows);
-    k_rhs_eri<<<dim3((unsigned)blocks_of(max_rows, 256), 64, (unsigned)B.count), 256, 0, st>>>(B);
 #define CD_STEP2(RT)                                 \
     case RT:                                         \
         k_step2<RT><<<grid, 512, 0, st>>>(B);        \
@@ -631,9 +640,9 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
         k_block_g128<<<(unsigned)PB.g128_begin[PB.count], 256, 0, st>>>(PB);
         if ((s = check_launch("pivot gather"))) return s;
     }
-    if ((s = record(2))) return s;
-
-    // ---- all-row solve, up to kStep2Batch problems per launch
+    // ---- all-row solve, up to kStep2Batch problems per launch: the integral
+    //      passes, then (from event 2 on) the substitutions
+    std::vector<Step2Batch> S2;
     for (int32_t i0 = 0; i0 < count; i0 += kStep2Batch) {
         Step2Batch B{};
         for (int32_t i = i0; i < count && B.count < kStep2Batch; ++i) {
@@ -656,9 +665,14 @@ cd_status decompose_impl(const cd_problem *probs, int32_t count, const cd_decomp
         const bool last = (i0 + kStep2Batch >= count);
         B.timeline = (last && opts->timeline) ? opts->timeline + 1 + 8 * opts->timeline_cap : nullptr;
         B.tl_cap = opts->timeline ? opts->timeline_cap : 0;
-        const int rt_req = opts->tuning ? opts->tuning->step2_row_tiles : 0;
-        if (B.count > 0 && (s = launch_step2_batch(B, di.n_cu, rt_req, st))) return s;
+        if (B.count > 0) S2.push_back(B);
     }
+    for (const Step2Batch &B : S2)
+        if ((s = launch_rhs_batch(B, st))) return s;
+    if ((s = record(2))) return s;
+    const int rt_req = opts->tuning ? opts->tuning->step2_row_tiles : 0;
+    for (Step2Batch &B : S2)
+        if ((s = launch_step2_batch(B, di.n_cu, rt_req, st))) return s;
     if ((s = record(3))) return s;
 
     if (opts->flags & CD_SYNC) {
