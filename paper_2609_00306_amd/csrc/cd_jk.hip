@@ -115,8 +115,6 @@ __global__ __launch_bounds__(256) void k_jJ(const double *__restrict__ L, int64_
     }
 }
 
-constexpr int JK_TKC = 32;
-using JKR = OperandStage<64, JK_TKC, false>;
 
 // ---------------------------------------------------------------- sparse unpacking
 // The unpacked vector Lt^P[mu][sigma] is nonzero only on kept pairs, so the
@@ -481,12 +479,23 @@ __device__ __forceinline__ void syrk_tile_split(int N, int nsplit, int &t, int &
 
 // Partial K from row-major X (row mu holds the M * ncol values X^P_{i mu}):
 //   Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k]   (lower tile pairs)
+// A 256-thread workgroup owns a 64 x 64 tile pair; wave w the 32 x 32 quarter
+// (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 accumulators of the 16x16x4
+// FP64 instruction.  k-chunks of 16 values of the 128 rows (both sides: 16 KB)
+// go straight from memory into a three-buffer LDS ring two chunks ahead of the
+// products (global_load_lds, 16-byte pieces, 4 per lane per chunk; one
+// barrier per chunk); LDS rows are 128 bytes, unpadded, with the k-pair index
+// XORed with (row / 2) % 8.  Smaller tiles than the reduced-precision forms'
+// 128 x 128: N = 1200 pads to 1216 rows instead of 1280 and the diagonal tiles
+// compute less of the upper triangle (1.08x the lower-triangle flops instead
+// of 1.25x), and 48 KB of LDS leaves room for three workgroups per compute unit.
+constexpr int XR_TK = 16;
+constexpr int XR_STAGE = 128 * XR_TK;   // doubles per chunk (16 KB)
 __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X, int64_t ldx,
                                                    int N, const int64_t *__restrict__ n_vectors,
                                                    int ncol, int nsplit, double *__restrict__ Kp)
 {
-    __shared__ double sU[2 * JKR::kSize];
-    double *sA = sU, *sB = sU + JKR::kSize;
+    __shared__ __align__(16) double sX[3 * XR_STAGE];
     int t, s;
     syrk_tile_split(N, nsplit, t, s);
     int tm = 0;
@@ -494,21 +503,85 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
     const int tn = t - tm * (tm + 1) / 2;
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
-    per = (per + JK_TKC - 1) / JK_TKC * JK_TKC;
+    per = (per + XR_TK - 1) / XR_TK * XR_TK;
     const int64_t kb = s * per;
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
     const int m0 = tm * 64, n0 = tn * 64;
-    f64x4 acc[4];
-    zero_acc(acc);
-    gemm_tile<4, JK_TKC, false, false>(
-        kb, ke,
-        [&](int64_t k, int m) -> double { return X[min(m0 + m, N - 1) * ldx + k]; },
-        [&](int64_t k, int n) -> double { return X[min(n0 + n, N - 1) * ldx + k]; },
-        acc, sA, sB);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..63 the
+    // A side m0.., 64..127 the B side n0..; rows past N read row N - 1), slot
+    // lane % 8, which holds k-pair (lane % 8) ^ ((r / 2) % 8) of that row
+    int64_t goff[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 8 * (4 * v + w) + (lane >> 3);
+        const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
+        goff[v] = (int64_t)grow * ldx + 2 * ((lane & 7) ^ ((r >> 1) & 7));
+    }
+    // a full chunk straight into LDS; a partial last chunk through registers
+    // with the values past ke set to zero
+    auto load_chunk = [&](double *st, int64_t k0) __attribute__((always_inline)) {
+        if (k0 + XR_TK <= ke) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                lds_dma16(X + k0 + goff[v], (lds_void *)(st + 128 * (4 * v + w)));
+        } else {
+            for (int e = tid; e < XR_STAGE; e += 256) {
+                const int r = e / XR_TK, k = e % XR_TK;
+                const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
+                st[r * XR_TK + 2 * ((k >> 1) ^ ((r >> 1) & 7)) + (k & 1)] =
+                    (k0 + k < ke) ? X[(int64_t)grow * ldx + k0 + k] : 0.0;
+            }
+        }
+    };
+    // operands of this lane at k-step q: row r with r % 16 = lane % 16,
+    // k = 4 q + lane / 16, i.e. k-pair 2 q + lane / 32, element (lane / 16) % 2
+    const int lr = lane & 15, sw = (lr >> 1) & 7, hi = lane >> 5, el = (lane >> 4) & 1;
+    const int ar = 32 * (w >> 1) + lr, br = 64 + 32 * (w & 1) + lr;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    auto mma_chunk = [&](const double *S) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < XR_TK / 4; ++q) {
+            const int col = 2 * ((2 * q + hi) ^ sw) + el;
+            const double a0 = S[ar * XR_TK + col], a1 = S[(ar + 16) * XR_TK + col];
+            const double b0 = S[br * XR_TK + col], b1 = S[(br + 16) * XR_TK + col];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    };
+    // chunk c: its own loads landed (the next chunk's may stay in flight), a
+    // barrier (every wave's pieces of chunk c are in, and every wave is done
+    // with the buffer that chunk c + 2 refills), the loads of chunk c + 2, then
+    // the products of chunk c
+    const int64_t nch = (ke > kb) ? (ke - kb + XR_TK - 1) / XR_TK : 0;
+    if (nch > 0) load_chunk(sX, kb);
+    if (nch > 1) load_chunk(sX + XR_STAGE, kb + XR_TK);
+    int buf = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+        if (c + 1 < nch) wait_vmcnt<4>();
+        else wait_vmcnt<0>();
+        lds_barrier();
+        if (c + 2 < nch) load_chunk(sX + ((buf == 0) ? 2 : buf - 1) * XR_STAGE, kb + (c + 2) * XR_TK);
+        mma_chunk(sX + buf * XR_STAGE);
+        buf = (buf == 2) ? 0 : buf + 1;
+    }
     double *out = Kp + (int64_t)s * N * N;
-    for_each_acc(acc, 4, [&](int m, int n, double v) {
-        if (m0 + m < N && n0 + n < N) out[(int64_t)(m0 + m) * N + n0 + n] = v;
-    });
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 32 * (w >> 1) + 16 * i + mfma_row(lane, e);
+                const int n = n0 + 32 * (w & 1) + 16 * j + lr;
+                if (m < N && n < N) out[(int64_t)m * N + n] = acc[i][j][e];
+            }
 }
 
 

@@ -1137,14 +1137,17 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             k_fill_f64<<<256, 256, 0, sp>>>(p.Lmo, mv * O * O, 0.0);
         if (O == 0 || n == 0 || mv == 0) continue;
         launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, sp);
-        // the Coulomb build (density, then two passes over L): for one problem
-        // on side stream 0, enqueued where it slowed the rest least on the
-        // 1200-function workload: after the transpose (which it slowed from
-        // 1.1 to 3 ms, both reading L) beside the FP64 half transform (the
-        // FP64 product, which shares compute units with it, lost 2 ms); after
-        // the half transform beside the FP32 product (1.4 ms faster than beside
-        // the half transform); after the second half of the transform beside
-        // the 3 x BF16 product.
+        // The order on the problem's stream: the half transform, the second half
+        // of the transform (when asked for), the exchange product.  The Coulomb
+        // build (density, then two passes over L) runs, for one problem, on side
+        // stream 0 beside the exchange product, enqueued after the transform.
+        // Measured on the 1200-function workload: the transform beside the
+        // exchange product (both bound by the matrix units, and their
+        // workgroups mostly cannot share a compute unit) cost 2.7 ms more in FP64
+        // and 1.5 ms more in 3 x BF16 than one after the other (FP32: 0.3 ms
+        // less); the Coulomb build beside the transpose slowed it from 1.1 to
+        // 3 ms (both read L), and beside the half transform it slowed that from
+        // 5.7 to 7.4 ms.
         auto j_chain = [&]() -> cd_status {
             if (sj != sp && (hipEventRecord(side->fork, sp) != hipSuccess ||
                              hipStreamWaitEvent(sj, side->fork, 0) != hipSuccess))
@@ -1163,28 +1166,15 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         const int64_t ldx = x_ld(mv, O);
         float *X32 = reinterpret_cast<float *>(w.X);
         const SparseWs &q = w.sp;
-        // the second half of the transform on the FP64 X: for one problem on
-        // side stream 1, beside the exchange product when 'beside', else before
-        // it on the same stream.  The 3 x BF16 product runs after it: beside it,
-        // the two took 1.5 ms longer on the 1200-function workload (the
-        // product's 144 KB workgroups and the transform's cannot share a compute
-        // unit, and the product's tile pairs of one k-range no longer run
-        // together); the FP64 and FP32 products gain 0.3-0.5 ms from the overlap.
-        auto second_half = [&](const double *X64, bool beside) -> cd_status {
-            hipStream_t st2 = sp;
-            if (count == 1 && beside) {
-                st2 = side->s[1 % kJkSide];
-                if (hipEventRecord(side->fork, sp) != hipSuccess ||
-                    hipStreamWaitEvent(st2, side->fork, 0) != hipSuccess)
-                    return fail(CD_ERR_DEVICE, "fork failed");
-            }
-            return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, st2);
+        // the second half of the transform on the FP64 X
+        auto second_half = [&](const double *X64) -> cd_status {
+            return launch_tr2(X64, ldx, (int)N, p.C, O, O, p.n_vectors, mv, w.C1p, p.Lmo, sp);
         };
         if (prec == CD_FP64) {
-            if ((s = j_chain())) return s;
             launch_half<HALF_F64>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, w.X, ldx, 0, nullptr, 0,
                                   sp);
-            if (p.Lmo && (s = second_half(w.X, true))) return s;
+            if (p.Lmo && (s = second_half(w.X))) return s;
+            if ((s = j_chain())) return s;
             k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else if (prec == CD_FP32) {
             // X in FP64 (matrix cores), written rounded to FP32 (k-blocked; and in
@@ -1192,8 +1182,8 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             const int64_t R = bx_rows(N);
             launch_half<HALF_F32>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, X32, R, 0, w.X64, ldx,
                                   sp);
+            if (p.Lmo && (s = second_half(w.X64))) return s;
             if ((s = j_chain())) return s;
-            if (p.Lmo && (s = second_half(w.X64, true))) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_f32<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O,
                                                                   pairs, nsplit, w.Kp);
@@ -1204,7 +1194,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             __bf16 *Xp = reinterpret_cast<__bf16 *>(w.X);
             launch_half<HALF_BF16X3>(q, mv, w.Cp, ldcp, (int)N, O, p.n_vectors, Xp, R, plane, w.X64,
                                      ldx, sp);
-            if (p.Lmo && (s = second_half(w.X64, false))) return s;
+            if (p.Lmo && (s = second_half(w.X64))) return s;
             if ((s = j_chain())) return s;
             const int pairs = bx_pairs((int)N);
             k_syrk_bf16x3<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(
