@@ -55,13 +55,13 @@ _LP_SHA = "e3aba4dc7ad6221c34752a91052e709f2b9dd518ba9fa26da6597ca967338915"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 36119483.0, "write_kib": 2680026.7},
+                    "fetch_kib": 36123814.7, "write_kib": 2679828.0},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3717256.9, "write_kib": 355400.5},
+                    "fetch_kib": 3717333.2, "write_kib": 355230.7},
         "k_syrk_bf16x3": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                          "fetch_kib": 13052307.8, "write_kib": 198720.0},
+                          "fetch_kib": 13249173.9, "write_kib": 198720.0},
         "k_syrk_f32": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                       "fetch_kib": 4182614.9, "write_kib": 198720.0},
+                       "fetch_kib": 4182507.4, "write_kib": 198720.0},
     },
 }
 
