@@ -212,6 +212,32 @@ def test_jk_reduced_precision(name, schwarz, prec):
     assert abs(gpu_e2(m.C, J, K) - oracle.e2(m.C, Jr, Kr)) <= TOL_E2[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("n_occ", [100, 170])
+def test_jk_wide_occupied_sets(n_occ, prec):
+    """J/K with more occupied orbitals than the C1/C2 sets: 100 (one column range
+    of 160, whose reduced-precision planes are staged through LDS) and 170 (two
+    column ranges, whose planes are written value by value), 200 functions, against
+    the oracle's FP64 build from the oracle's vectors, and C^T L C against the
+    oracle's transform."""
+    m = make_molecule(50, 10.0, (0.3, 1.5, 7.0, 30.0), n_occ, seed=91)
+    d, M = run_gpu(m, 1e-6, 1e-12)
+    rp, ref = check_against_oracle(m, 1e-6, 1e-12, d, M)
+    Jr, Kr = oracle.jk_cd(m.n_basis, rp, ref.L, m.C)
+    J, K = cdlib.build_jk(d, m.C, prec)
+    J = J.cpu().numpy()
+    K = K.cpu().numpy()
+    assert np.abs(J - Jr).max() <= TOL_JK
+    assert np.abs(K - Kr).max() <= (TOL_JK if prec == "fp64" else TOL_K[prec])
+    assert np.array_equal(K, K.T)
+    # with the MO-basis output (a transform product of two row ranges at 170)
+    jk = cdlib.prepare_jk(d, m.C, prec, lmo=True)
+    cdlib.run_jk(jk, prec, sync=True)
+    assert np.array_equal(jk.K.cpu().numpy(), K)
+    exp = oracle.transform(m.n_basis, rp, ref.L, m.C, m.C)
+    assert np.abs(jk.Lmo[:M].cpu().numpy() - exp).max() <= TOL_L
+
+
 @pytest.mark.parametrize("name,eta", [("C1", 0.5), ("C1", 0.05), ("ragged", 0.1), ("C2", 0.1)])
 def test_span_factor_gives_a_valid_decomposition(name, eta):
     """Span factor eta < 1 (Sec. 3, Table 1): pivots are taken from the qualified
