@@ -41,27 +41,26 @@ __global__ void k_rowmap(int64_t n_rows, const int64_t *__restrict__ row_pair, i
     rowof[(int64_t)nu * N + mu] = (int32_t)r;
 }
 
-// D = C C^T  ([N][N], C [N][O])
-__global__ void k_density(int N, int O, const double *__restrict__ C, double *__restrict__ Dm)
+// w[r] = (2 - delta_{mu nu}) D_{mu nu} with D = C C^T (C [N][O]): the
+// packed-row weight of the density, each entry taken straight from C (only the
+// kept pairs' entries of D are needed).  16 lanes per row, lane j summing
+// i = j, j + 16, ..; the 16 partial sums are added across the lanes.
+__global__ __launch_bounds__(256) void k_drow(int64_t n_rows, const int64_t *__restrict__ row_pair,
+                                              int O, const double *__restrict__ C,
+                                              double *__restrict__ w)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)N * N) return;
-    int a = (int)(e / N), b = (int)(e % N);
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int j = threadIdx.x & 15;
+    int mu = 0, nu = 0;
     double s = 0.0;
-    for (int i = 0; i < O; ++i) s = fma(C[(int64_t)a * O + i], C[(int64_t)b * O + i], s);
-    Dm[e] = s;
-}
-
-// w[r] = (2 - delta_{mu nu}) D_{mu nu}: the packed-row weight of the density
-__global__ void k_drow(int64_t n_rows, const int64_t *__restrict__ row_pair, int N,
-                       const double *__restrict__ Dm, double *__restrict__ w)
-{
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rows) return;
-    int mu, nu;
-    unpack_pair(row_pair[r], mu, nu);
-    double d = Dm[(int64_t)mu * N + nu];
-    w[r] = (mu == nu) ? d : 2.0 * d;
+    if (r < n_rows) {
+        unpack_pair(row_pair[r], mu, nu);
+        const double *a = C + (int64_t)mu * O, *b = C + (int64_t)nu * O;
+        for (int i = j; i < O; i += 16) s = fma(a[i], b[i], s);
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (r < n_rows && j == 0) w[r] = (mu == nu) ? s : 2.0 * s;
 }
 
 // V[P] = sum_r L[P][r] w[r]  (one workgroup per vector)

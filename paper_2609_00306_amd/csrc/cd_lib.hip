@@ -1024,7 +1024,7 @@ void launch_sparse_prep(const SparseWs &w, int64_t N, int64_t n, int64_t mv,
 }
 
 struct JkWs {
-    double *Dm, *w, *V, *X, *Kp;
+    double *w, *V, *X, *Kp;
     double *X64;   // FP64 copy of X beside the BF16 planes (3 x BF16 with Lmo)
     double *C1p;   // padded copy of C for the second half of the transform (with Lmo)
     double *Cp;    // padded copy of C for the half transform
@@ -1045,7 +1045,6 @@ JkWs carve_jk(void *ws, const cd_jk_problem &p, int nsplit, cd_precision prec)
     JkWs w{};
     Carver c(ws);
     const int64_t N = p.n_basis;
-    w.Dm = c.take<double>(std::max<int64_t>(1, N * N));
     w.w = c.take<double>(std::max<int64_t>(1, p.n_rows));
     w.V = c.take<double>(std::max<int64_t>(1, p.max_vectors));
     w.sp = carve_sparse(c, N, p.n_rows, p.max_vectors);
@@ -1139,8 +1138,9 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
         launch_sparse_prep(w.sp, N, n, mv, p.row_pair, p.L, p.n_vectors, sp);
         // The order on the problem's stream: the half transform, the second half
         // of the transform (when asked for), the exchange product.  The Coulomb
-        // build (density, then two passes over L) runs, for one problem, on side
-        // stream 0 beside the exchange product, enqueued after the transform.
+        // build (the rows' density weights, then two passes over L) runs, for
+        // one problem, on side stream 0 beside the exchange product, enqueued
+        // after the transform.
         // Measured on the 1200-function workload: the transform beside the
         // exchange product (both bound by the matrix units, and their
         // workgroups mostly cannot share a compute unit) cost 2.7 ms more in FP64
@@ -1152,8 +1152,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
             if (sj != sp && (hipEventRecord(side->fork, sp) != hipSuccess ||
                              hipStreamWaitEvent(sj, side->fork, 0) != hipSuccess))
                 return fail(CD_ERR_DEVICE, "fork failed");
-            k_density<<<(unsigned)blocks_of(NN, 256), 256, 0, sj>>>((int)N, O, p.C, w.Dm);
-            k_drow<<<(unsigned)blocks_of(n, 256), 256, 0, sj>>>(n, p.row_pair, (int)N, w.Dm, w.w);
+            k_drow<<<(unsigned)blocks_of(n, 16), 256, 0, sj>>>(n, p.row_pair, O, p.C, w.w);
             k_jV<<<(unsigned)mv, 256, 0, sj>>>(p.L, n, w.w, p.n_vectors, w.V);
             k_jJ<<<(unsigned)blocks_of(n, 64), 256, 0, sj>>>(p.L, n, w.V, p.n_vectors, p.row_pair,
                                                              (int)N, p.J);
