@@ -31,7 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int lp_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 
-// Work item of the large-tile exchange products (FP32 and 3 x BF16), launched
+// Work item of the 3 x BF16 exchange product, launched
 // as pairs x nsplit workgroups with nsplit a multiple of 8: workgroup g runs
 // on XCD g % 8; its j = g / 8 -th item is tile pair j % pairs (lower
 // triangle, row-major) of split 8 (j / pairs) + g % 8.
@@ -47,147 +47,130 @@ __device__ __forceinline__ void bx_item(int pairs, int &tm, int &tn, int &split)
     tn = t - m * (m + 1) / 2;
 }
 
-// ---------------------------------------------------------------- FP32, large tiles
-// Partial K from the k-blocked FP32 X with 128 x 128 output tiles:
+// ---------------------------------------------------------------- FP32
+// Partial K from the k-blocked FP32 X with 64 x 64 output tiles:
 //   Kp[s][mu][nu] = sum_{k in split s} X[mu][k] X[nu][k]   (lower tile pairs)
-// Grid and work items as the 3 x BF16 product below (bx_item: the tile pairs
-// of one k-range on one XCD).  Each wave owns a 64 x 64 quarter of the tile
-// (4 x 4 accumulators of the 16x16x4 FP32 instruction).  A step stages 32
-// values of the 256 rows (128 of each side: 32 KB) in one of three LDS
-// buffers, straight from memory (global_load_lds, 16 bytes per lane, 8 per
-// lane per step) two steps ahead of the products; one barrier per step.  LDS
-// rows are 128 bytes with no padding; the 16-byte group g of row r sits at
+// Work items as the FP64 product (syrk_tile_split: the tile pairs of one
+// k-range on one XCD).  Wave w owns the 32 x 32 quarter (rows 32 (w / 2),
+// columns 32 (w % 2)) as 2 x 2 accumulators of the 16x16x4 FP32 instruction.
+// A step stages 32 values of the 128 rows (both sides: 16 KB) in one of three
+// LDS buffers, straight from memory (global_load_lds, 16 bytes per lane, 4
+// per lane per step) two steps ahead of the products; one barrier per step.
+// LDS rows are 128 bytes with no padding; the 16-byte group g of row r sits at
 // g ^ ((r / 2) % 8), so the 16 rows one quarter-wave reads at one k fall on
-// 16 different banks.
+// 16 different banks.  48 KB of LDS: three workgroups per compute unit.
+// 64 x 64 tiles pad N = 1200 to 1216 rows where 128 x 128 ones pad it to 1280
+// and compute more of the diagonal tiles' upper halves: 13.3 against 15.8 ms
+// on the 1200-function workload.
 //
-// FP32 accumulation runs over one step (32 values, from a zero accumulator)
-// and each row tile's step sums are added in FP64 while the next row tile's
-// products run, as in the 3 x BF16 product.
-constexpr int XF_STAGE = 256 * XB_K;                  // floats per stage (32 KB)
-constexpr int XF_LOADS = XF_STAGE * 4 / 16 / 256;     // 16-byte pieces per thread per stage (8)
+// FP32 accumulation runs over one step (32 values, from zero accumulators),
+// whose sums are then added in FP64.
+constexpr int XF_STAGE = 128 * XB_K;                  // floats per stage (16 KB)
+constexpr int XF_LOADS = XF_STAGE * 4 / 16 / 256;     // 16-byte pieces per thread per stage (4)
 
 __global__ __launch_bounds__(256) void k_syrk_f32(const float *__restrict__ X, int64_t rows, int N,
                                                   const int64_t *__restrict__ n_vectors, int ncol,
-                                                  int pairs, int nsplit, double *__restrict__ Kp)
+                                                  int nsplit, double *__restrict__ Kp)
 {
     __shared__ __align__(16) float sX[3 * XF_STAGE];
-    int tm, tn, s;
-    bx_item(pairs, tm, tn, s);
+    int t, s;
+    syrk_tile_split(N, nsplit, t, s);
+    int tm = 0;
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    const int tn = t - tm * (tm + 1) / 2;
     const int64_t nk = *n_vectors * ncol;
     int64_t per = (nk + nsplit - 1) / nsplit;
     per = (per + XB_K - 1) / XB_K * XB_K;
     const int64_t kb = s * per;
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
-    const int m0 = tm * 128, n0 = tn * 128;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..127 the
-    // A side m0.., 128..255 the B side n0..), slot lane % 8, which holds the
-    // 16-byte group (lane % 8) ^ ((r / 2) % 8) of that row
+    const int m0 = tm * 64, n0 = tn * 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..63 the
+    // A side m0.., 64..127 the B side n0..; rows past N read row N - 1), slot
+    // lane % 8, which holds the 16-byte group (lane % 8) ^ ((r / 2) % 8)
     int goff[XF_LOADS];
 #pragma unroll
     for (int v = 0; v < XF_LOADS; ++v) {
         const int r = 8 * (4 * v + w) + (lane >> 3);
-        const int grow = (r < 128) ? m0 + r : n0 + r - 128;
+        const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
         goff[v] = grow * XB_K + 4 * ((lane & 7) ^ ((r >> 1) & 7));
     }
     // a full step straight into LDS; a partial last step through registers
     // with the values past ke set to zero
     auto load_step = [&](float *st, int64_t k0) __attribute__((always_inline)) {
+        const float *base = X + (k0 / XB_K) * (rows * XB_K);
         if (k0 + XB_K <= ke) {
-            const float *base = X + (k0 / XB_K) * (rows * XB_K);
 #pragma unroll
             for (int v = 0; v < XF_LOADS; ++v)
                 lds_dma16(base + goff[v], (lds_void *)(st + 256 * (4 * v + w)));
         } else {
-            const float *base = X + (k0 / XB_K) * (rows * XB_K);
             for (int e = tid; e < XF_STAGE; e += 256) {
                 const int r = e / XB_K, k = e % XB_K;
-                const int grow = (r < 128) ? m0 + r : n0 + r - 128;
+                const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
                 st[r * XB_K + 4 * ((k >> 2) ^ ((r >> 1) & 7)) + (k & 3)] =
                     (k0 + k < ke) ? base[grow * XB_K + k] : 0.f;
             }
         }
     };
-    double acc64[4][4][4];
+    double acc64[2][2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc64[i][j][e] = 0.0;
     // operand of this lane at k-step q (k = 4 q + lane / 16) of a row r with
     // r % 16 = lane % 16: group q of that row, swizzled
     const int lr = lane & 15, sw = (lr >> 1) & 7, el = lane >> 4;
+    const int ar = 32 * (w >> 1) + lr, br = 64 + 32 * (w & 1) + lr;
     auto mma_step = [&](const float *S) __attribute__((always_inline)) {
-        float b[8][4];
+        f32x4 t4[2][2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                b[q][j] = S[(128 + 64 * wc + 16 * j + lr) * XB_K + 4 * (q ^ sw) + el];
-        auto read_a = [&](int i, float (&a)[8]) __attribute__((always_inline)) {
+            for (int j = 0; j < 2; ++j) t4[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] = S[(64 * wr + 16 * i + lr) * XB_K + 4 * (q ^ sw) + el];
-        };
-        auto products = [&](const float (&a)[8], f32x4 (&t)[4]) __attribute__((always_inline)) {
+        for (int q = 0; q < 8; ++q) {
+            const int g = 4 * (q ^ sw) + el;
+            const float a0 = S[ar * XB_K + g], a1 = S[(ar + 16) * XB_K + g];
+            const float b0 = S[br * XB_K + g], b1 = S[(br + 16) * XB_K + g];
+            t4[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, t4[0][0], 0, 0, 0);
+            t4[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, t4[0][1], 0, 0, 0);
+            t4[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, t4[1][0], 0, 0, 0);
+            t4[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, t4[1][1], 0, 0, 0);
+        }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) t[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    t[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][j], t[j], 0, 0, 0);
-        };
-        auto fold = [&](int i, const f32x4 (&t)[4]) __attribute__((always_inline)) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)t[j][e];
-        };
-        float a0[8], a1[8];
-        f32x4 t0[4], t1[4];
-        read_a(0, a0);
-        read_a(1, a1);
-        products(a0, t0);
-        read_a(2, a0);
-        products(a1, t1);
-        fold(0, t0);
-        read_a(3, a1);
-        products(a0, t0);
-        fold(1, t1);
-        products(a1, t1);
-        fold(2, t0);
-        fold(3, t1);
+                for (int e = 0; e < 4; ++e) acc64[i][j][e] += (double)t4[i][j][e];
     };
     // step c: its own loads landed (the next step's may stay in flight), a
     // barrier (every wave's pieces of step c are in, and every wave is done
     // with the buffer that step c + 2 refills), the loads of step c + 2, then
     // the products of step c
     const int64_t nch = (ke > kb) ? (ke - kb + XB_K - 1) / XB_K : 0;
-    auto step = [&](int64_t c, const float *cur, float *refill) __attribute__((always_inline)) {
+    if (nch > 0) load_step(sX, kb);
+    if (nch > 1) load_step(sX + XF_STAGE, kb + XB_K);
+    int buf = 0;
+    for (int64_t c = 0; c < nch; ++c) {
         if (c + 1 < nch) wait_vmcnt<XF_LOADS>();
         else wait_vmcnt<0>();
         lds_barrier();
-        if (c + 2 < nch) load_step(refill, kb + (c + 2) * XB_K);
-        mma_step(cur);
-    };
-    float *s0 = sX, *s1 = sX + XF_STAGE, *s2 = sX + 2 * XF_STAGE;
-    if (nch > 0) load_step(s0, kb);
-    if (nch > 1) load_step(s1, kb + XB_K);
-    for (int64_t c = 0; c < nch; c += 3) {
-        step(c, s0, s2);
-        if (c + 1 < nch) step(c + 1, s1, s0);
-        if (c + 2 < nch) step(c + 2, s2, s1);
+        if (c + 2 < nch) load_step(sX + ((buf == 0) ? 2 : buf - 1) * XF_STAGE, kb + (c + 2) * XB_K);
+        mma_step(sX + buf * XF_STAGE);
+        buf = (buf == 2) ? 0 : buf + 1;
     }
     double *out = Kp + (int64_t)s * N * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = m0 + 64 * wr + 16 * i + lp_row(lane, e);
-                const int n = n0 + 64 * wc + 16 * j + lr;
+                const int m = m0 + 32 * (w >> 1) + 16 * i + lp_row(lane, e);
+                const int n = n0 + 32 * (w & 1) + 16 * j + lr;
                 if (m < N && n < N) out[(int64_t)m * N + n] = acc64[i][j][e];
             }
 }

@@ -893,14 +893,14 @@ int jk_nsplit(int N, int n_cu)
     return std::max(8, std::min(ns, 64));
 }
 
-// Tile pairs (lower triangle) of the large-tile (FP32 and 3 x BF16) exchange products.
+// Tile pairs (lower triangle) of the large-tile 3 x BF16 exchange product.
 int bx_pairs(int N)
 {
     const int T = (N + BX_TILE - 1) / BX_TILE;
     return T * (T + 1) / 2;
 }
 
-// k-ranges per XCD of the large-tile exchange products: the smallest count whose
+// k-ranges per XCD of the large-tile 3 x BF16 exchange product: the smallest count whose
 // pairs * ss workgroups (one per compute unit) fill the compute units of an
 // XCD in whole rounds to 95% or better, else the best fill up to 16.
 int bx_subsplits(int pairs, int n_cu)
@@ -958,7 +958,15 @@ cd_status launch_tr2(const double *Y, int64_t ldy, int N, const double *C1, int 
 // Number of partial K matrices of the exchange product at a precision.
 int jk_splits(int N, int n_cu, cd_precision prec)
 {
-    if (prec != CD_FP64) return 8 * bx_subsplits(bx_pairs(N), n_cu);
+    if (prec == CD_BF16X3) return 8 * bx_subsplits(bx_pairs(N), n_cu);
+    if (prec == CD_FP32) {
+        // eight workgroups per compute unit in all (three run at a time): on the
+        // 1200-function workload 16 k-ranges took 13.3 ms, 8 took 13.8 ms
+        const int T = (N + 63) / 64, pairs = T * (T + 1) / 2;
+        int ns = (8 * n_cu + pairs - 1) / std::max(1, pairs);
+        ns = (ns + 7) / 8 * 8;
+        return std::max(8, std::min(ns, 64));
+    }
     return jk_nsplit(N, n_cu);
 }
 
@@ -1183,9 +1191,7 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                                   sp);
             if (p.Lmo && (s = second_half(w.X64))) return s;
             if ((s = j_chain())) return s;
-            const int pairs = bx_pairs((int)N);
-            k_syrk_f32<<<(unsigned)(pairs * nsplit), 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O,
-                                                                  pairs, nsplit, w.Kp);
+            k_syrk_f32<<<sgrid, 256, 0, sp>>>(X32, R, (int)N, p.n_vectors, O, nsplit, w.Kp);
         } else {
             // X in FP64 (matrix cores), written split into three k-blocked BF16
             // planes; the exchange product then runs on BF16 matrix cores from them
