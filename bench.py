@@ -51,17 +51,17 @@ LP_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
                 "paper_2609_00306_amd/csrc/cd_mfma.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.25, 1048576.0 / 1048576.0
 _DECOMP_SHA = "23db0db900845125edaca5dafd2fc8a37fad3054de9b28fe22e3ec0778528e5b"
-_LP_SHA = "e3aba4dc7ad6221c34752a91052e709f2b9dd518ba9fa26da6597ca967338915"
+_LP_SHA = "1f0a970e247f971c4ba77365c789fa8d62b7bb1ff504d2293d3acd5e2d2fa1fb"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 36123814.7, "write_kib": 2679828.0},
+                    "fetch_kib": 36151828.2, "write_kib": 2679561.1},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3717333.2, "write_kib": 355230.7},
+                    "fetch_kib": 3718633.7, "write_kib": 354674.9},
         "k_syrk_bf16x3": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                          "fetch_kib": 13249173.9, "write_kib": 198720.0},
+                          "fetch_kib": 13708449.6, "write_kib": 198720.0},
         "k_syrk_f32": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                       "fetch_kib": 4182507.4, "write_kib": 198720.0},
+                       "fetch_kib": 9469117.7, "write_kib": 94752.0},
     },
 }
 
