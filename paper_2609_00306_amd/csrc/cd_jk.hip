@@ -634,8 +634,11 @@ __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int 
 // A 512-thread workgroup covers 16 RA rows a (all of them for p <= 160) and
 // 128 columns c; wave w owns the 16 columns 16 w and all RA row tiles, so Y,
 // the large operand, is read exactly once over the grid.  k-chunks of 16
-// functions go straight from memory into three LDS buffers two chunks ahead of
-// the products (global_load_lds, 16-byte pieces, one barrier per chunk):
+// functions go straight from memory into two LDS buffers one chunk ahead of
+// the products (global_load_lds, 16-byte pieces, one barrier per chunk); at
+// 72 KB of LDS and at most 128 registers two workgroups share a compute unit
+// (5.35 -> 5.2 ms on the 1200-function workload against three buffers and one
+// workgroup per unit):
 //   A part: [k][16 RA] from C1p, C1 copied with its rows padded to whole
 //           workgroup row ranges and to a whole number of chunks (zeros);
 //   B part: [k][128] from Y, whose rows are padded to whole 128-column tiles.
@@ -658,7 +661,7 @@ __global__ void k_pack_c1(const double *__restrict__ C1, int N, int p, int rows,
 }
 
 template <int RA>
-__global__ __launch_bounds__(512) void k_tr2w(const double *__restrict__ Y, int64_t ldy, int N,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_tr2w(const double *__restrict__ Y, int64_t ldy, int N,
                                               const double *__restrict__ C1p, int ldc, int p, int q,
                                               const int64_t *__restrict__ n_vectors,
                                               double *__restrict__ Lmo)
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(512) void k_tr2w(const double *__restrict__ Y, int6
     constexpr int kA = TR_TK * AL, kB = TR_TK * 128, kChunk = kA + kB;
     constexpr int kAP = kA / 128;               // 16-byte-piece loads of A per chunk (RA + RA/4..)
     constexpr int kAL = kAP / 8, kAX = kAP % 8; // per wave, one more for waves < kAX
-    __shared__ __align__(16) double sU[3 * kChunk];
+    __shared__ __align__(16) double sU[2 * kChunk];
     const int64_t ncol = *n_vectors * q;
     const int64_t c0 = (int64_t)blockIdx.x * 128;
     if (c0 >= ncol) return;
@@ -715,20 +718,16 @@ __global__ __launch_bounds__(512) void k_tr2w(const double *__restrict__ Y, int6
     const int m = lane & 15, kq = lane >> 4;
     auto swz = [&](int k, int col) -> int { return 2 * ((col >> 1) ^ (8 * (k & 1))) + (col & 1); };
     if (nch > 0) load_chunk(0, 0);
-    if (nch > 1) load_chunk(1, 1);
     int buf = 0;
     for (int c = 0; c < nch; ++c) {
-        if (w < kAX) {
-            if (c + 1 < nch) wait_vmcnt<kAL + 1 + 2>();
-            else wait_vmcnt<0>();
-        } else {
-            if (c + 1 < nch) wait_vmcnt<kAL + 2>();
-            else wait_vmcnt<0>();
-        }
+        // own pieces of chunk c landed, then a barrier: every wave's pieces of
+        // chunk c are in, and every wave is done with the buffer that chunk
+        // c + 1 refills; chunk c + 1 loads while chunk c is multiplied
+        wait_vmcnt<0>();
         lds_barrier();
-        if (c + 2 < nch) load_chunk(c + 2, (buf == 0) ? 2 : buf - 1);
+        if (c + 1 < nch) load_chunk(c + 1, buf ^ 1);
         const double *sA = sU + buf * kChunk, *sB = sA + kA;
-        buf = (buf == 2) ? 0 : buf + 1;
+        buf ^= 1;
 #pragma unroll
         for (int s = 0; s < TR_TK / 4; ++s) {
             const int k = 4 * s + kq;
