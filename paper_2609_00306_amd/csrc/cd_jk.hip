@@ -259,15 +259,12 @@ enum HalfOut { HALF_F64 = 0, HALF_BF16X3 = 1, HALF_F32 = 2 };
 // function mu (CT = 10: all of them for ncol <= 160; CT = 4 for ncol <= 64),
 // so each neighbour's LT row segment is read once per column range; wave w
 // owns the 16 vectors 16 w and all CT column tiles.  Chunks of 16 neighbours
-// go straight from memory into LDS buffers ahead of the products
-// (global_load_lds, 16-byte pieces gathered through the neighbour list staged
-// in LDS; one barrier per chunk).  FP64 and FP32 forms: two buffers, one
-// chunk ahead; with 78 KB of LDS and at most 128 registers per lane two
-// workgroups share a compute unit, so one's loads and stores overlap the
-// other's products (three buffers and one workgroup per unit: 5.6 against
-// 4.9 ms for the FP64 form on the 1200-function workload).  3 x BF16 form:
-// three buffers, two chunks ahead, one workgroup per unit (capped at 128
-// registers its split spilled).  A part [k][128] from LT (rows
+// go straight from memory into two LDS buffers one chunk ahead of the
+// products (global_load_lds, 16-byte pieces gathered through the neighbour
+// list staged in LDS; one barrier per chunk).  With 78 KB of LDS and at most
+// 128 registers per lane two workgroups share a compute unit, so one's loads
+// and stores overlap the other's products (three buffers and one workgroup per
+// unit: 5.6 against 4.9 ms for the FP64 form on the 1200-function workload).  A part [k][128] from LT (rows
 // padded to whole 128-vector tiles), B part [k][16 CT] from Cp, C copied with
 // rows padded to whole column ranges and one extra zero row that the ragged
 // last chunk reads past the list.  The 16-byte piece j of an odd row k is
@@ -280,7 +277,7 @@ constexpr int HS_SEG = 512;   // neighbour-list entries staged in LDS at a time
 __host__ __device__ constexpr int hs_col_tiles(int ncol) { return (ncol <= 64) ? 4 : 10; }
 
 template <int OUT, int CT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OUT == HALF_BF16X3 ? 1 : 4))) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_half_sparse(const double *__restrict__ LT, int64_t ldt,
                                                      const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ nb_s,
                                                      const int32_t *__restrict__ nb_r,
@@ -296,10 +293,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OUT == HALF
     constexpr int kBL = kB / 128;                  // 16-byte-piece loads of B per chunk
     constexpr int kBW = (kBL + 7) / 8;             // per wave, waves < kBL % 8 one more
     static_assert(CT % 2 == 0, "whole 16-byte pieces per row pair");
-    // chunk buffers (three for the 3 x BF16 form: see above); after the
-    // products, the staged output planes
-    constexpr int NBUF = (OUT == HALF_BF16X3) ? 3 : 2;
-    __shared__ __align__(16) double sU[NBUF * kChunk];
+    // two chunk buffers; after the products, the staged output planes
+    __shared__ __align__(16) double sU[2 * kChunk];
     __shared__ int sNs[HS_SEG], sNr[HS_SEG];
     const int64_t M = *n_vectors;
     const int64_t p0 = (int64_t)blockIdx.x * HS_P;
@@ -348,35 +343,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OUT == HALF
             }
         };
         if (nch > 0) load_chunk(0, 0);
-        if (NBUF == 3 && nch > 1) load_chunk(1, 1);
         int buf = 0;
         for (int c = 0; c < nch; ++c) {
-            if constexpr (NBUF == 2) {
-                // own pieces of chunk c landed, then a barrier: every wave's
-                // pieces of chunk c are in, and every wave is done with the
-                // buffer that chunk c + 1 refills (chunk c - 1's); chunk c + 1
-                // loads while chunk c is multiplied
-                wait_vmcnt<0>();
-                lds_barrier();
-                if (c + 1 < nch) load_chunk(c + 1, buf ^ 1);
-            } else {
-                // own pieces of chunk c landed (chunk c + 1's may stay in
-                // flight), then a barrier: every wave's pieces of chunk c are
-                // in, and every wave is done with the buffer that chunk c + 2
-                // refills; this wave's loads per chunk: 2 of A, kBL / 8 of B
-                // and one more for waves < kBL % 8
-                if (w < kBL % 8) {
-                    if (c + 1 < nch) wait_vmcnt<2 + kBL / 8 + 1>();
-                    else wait_vmcnt<0>();
-                } else {
-                    if (c + 1 < nch) wait_vmcnt<2 + kBL / 8>();
-                    else wait_vmcnt<0>();
-                }
-                lds_barrier();
-                if (c + 2 < nch) load_chunk(c + 2, (buf == 0) ? 2 : buf - 1);
-            }
+            // own pieces of chunk c landed, then a barrier: every wave's pieces
+            // of chunk c are in, and every wave is done with the buffer that
+            // chunk c + 1 refills (chunk c - 1's); chunk c + 1 loads while
+            // chunk c is multiplied
+            wait_vmcnt<0>();
+            lds_barrier();
+            if (c + 1 < nch) load_chunk(c + 1, buf ^ 1);
             const double *sA = sU + buf * kChunk, *sB = sA + kA;
-            buf = (NBUF == 2) ? (buf ^ 1) : ((buf == 2) ? 0 : buf + 1);
+            buf ^= 1;
 #pragma unroll
             for (int s = 0; s < HS_TK / 4; ++s) {
                 const int k = 4 * s + (lane >> 4);
@@ -405,6 +382,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OUT == HALF
         static_assert(NPL * PS * sizeof(OT) <= sizeof(sU), "a half's planes fit in LDS");
         const int np = (int)min((int64_t)HS_P, M - p0);
         OT *T = reinterpret_cast<OT *>(sU);
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
             // the half's outputs: e in [(p0 + PH h) ncol, (p0 + min(np, PH (h + 1))) ncol),
             // again starting on a k-block (PH ncol is a multiple of XB_K)
