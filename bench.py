@@ -55,13 +55,13 @@ _LP_SHA = "1f0a970e247f971c4ba77365c789fa8d62b7bb1ff504d2293d3acd5e2d2fa1fb"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 36151828.2, "write_kib": 2679561.1},
+                    "fetch_kib": 36105870.1, "write_kib": 2679625.0},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3718633.7, "write_kib": 354674.9},
+                    "fetch_kib": 3719760.6, "write_kib": 355189.5},
         "k_syrk_bf16x3": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                          "fetch_kib": 13708449.6, "write_kib": 198720.0},
+                          "fetch_kib": 13626673.3, "write_kib": 198720.0},
         "k_syrk_f32": {"sources": LP_SOURCES, "sha256": _LP_SHA,
-                       "fetch_kib": 9469117.7, "write_kib": 94752.0},
+                       "fetch_kib": 9473423.2, "write_kib": 94752.0},
     },
 }
 
