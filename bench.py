@@ -50,14 +50,14 @@ LP_SOURCES = ["paper_2609_00306_amd/csrc/cd_jk_lp.hip",
                 "paper_2609_00306_amd/csrc/cd_device.hpp",
                 "paper_2609_00306_amd/csrc/cd_mfma.hpp"]
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524302.25, 1048576.0 / 1048576.0
-_DECOMP_SHA = "23db0db900845125edaca5dafd2fc8a37fad3054de9b28fe22e3ec0778528e5b"
+_DECOMP_SHA = "1446673a140d255bd8993e8e60526ad7b5f4bbc861702a2271d9d17a60e869d6"
 _LP_SHA = "1f0a970e247f971c4ba77365c789fa8d62b7bb1ff504d2293d3acd5e2d2fa1fb"
 COUNTERS = {
     ("C5", 1e-6): {
         "k_step2": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 36105870.1, "write_kib": 2679625.0},
+                    "fetch_kib": 36124221.8, "write_kib": 2679898.1},
         "k_step1": {"sources": DECOMP_SOURCES, "sha256": _DECOMP_SHA,
-                    "fetch_kib": 3719760.6, "write_kib": 355189.5},
+                    "fetch_kib": 3718871.4, "write_kib": 355229.4},
         "k_syrk_bf16x3": {"sources": LP_SOURCES, "sha256": _LP_SHA,
                           "fetch_kib": 13626673.3, "write_kib": 198720.0},
         "k_syrk_f32": {"sources": LP_SOURCES, "sha256": _LP_SHA,

@@ -193,8 +193,8 @@ constexpr int S1_MAXG = NOMSORT / CNOM;
 using S1K = SplitK<3>;         // candidate-column product: 48 rows per pass, k-chunks of 16
 // all-row solve
 constexpr int S2_NB = 128;    // vectors per block
-constexpr int S2_TK = 16;     // k per chunk of the off-block product
-constexpr int S2_NST = 3;     // chunk buffers (loads run two chunks ahead)
+constexpr int S2_TK = 32;     // k per chunk of the off-block product
+constexpr int S2_NST = 2;     // chunk buffers (loads run one chunk ahead)
 constexpr int S2_TLD = 130;   // row stride (doubles) of the right-hand side in LDS
 
 constexpr int S1_LROWS = 64;      // eligible rows whose candidate columns stay in LDS
@@ -881,15 +881,15 @@ __global__ __launch_bounds__(256) void k_block_g128(const PivotBatch B)
 // Wave w owns 16 of the block's 128 columns (group cg: w for w < 4, 11 - w
 // otherwise, so the two waves of a SIMD share the triangular in-block work
 // equally) and all RT row tiles, one v_mfma_f64_16x16x4f64 accumulator per
-// tile.  The off-block product streams 16-wide k-chunks through three LDS
-// buffers, loaded straight from memory into LDS two chunks ahead of the
-// products (global_load_lds; one barrier per chunk):
+// tile.  The off-block product streams S2_TK-wide k-chunks through S2_NST
+// LDS buffers, loaded straight from memory into LDS S2_NST - 1 chunks ahead of
+// the products (global_load_lds; one barrier per chunk):
 //   A part: [k][m], rows of 16 RT doubles, 4-byte pieces (L's rows have any
 //           parity, so 16-byte pieces could be misaligned); lane l of piece
 //           v of wave w writes half l % 2 of double 32 (8 v + w) + l / 2;
-//   B part: [n][16 k] in 16-byte pieces, the piece of k-pair g of row n stored
-//           at g ^ ((n / 2) % 8), so the 16 rows one half-wave reads fall on
-//           16 different bank groups.
+//   B part: [n][S2_TK k] in 16-byte pieces, the piece of k-pair g of row n
+//           stored at g ^ b_swz(n), so the 16 rows one half-wave reads fall
+//           on 16 different bank groups.
 // Rows past the matrix are read as the tile's last row and columns past the
 // block as its last pivot row: finite values in accumulator rows and columns
 // that are never stored.  The right-hand side and the block result go through
@@ -913,6 +913,17 @@ __global__ __launch_bounds__(256) void k_rhs_eri(const Step2Batch B)
         Q.L[K * Q.n_rows + r] = eri(row, Q.prow[K]);
 }
 
+// B rows of a chunk: S2_TK values, kBPairs 16-byte pairs; a wave's 64 pieces
+// cover kBRows rows.  The pair index of row n is XORed with b_swz(n), so the
+// 16 rows a quarter-wave reads at one k-pair fall on 16 different 16-byte
+// bank groups.
+constexpr int kBPairs = S2_TK / 2;
+constexpr int kBRows = 64 / kBPairs;
+__device__ __forceinline__ int b_swz(int n)
+{
+    return (S2_TK == 16) ? ((n >> 1) & 7) : (n & 15);
+}
+
 template <int RT>
 struct S2Lds {
     static constexpr int R = 16 * RT;
@@ -921,10 +932,10 @@ struct S2Lds {
     static constexpr int kChunk = kA + kB;
     static constexpr int kT = R * S2_TLD;
     static constexpr int kU = (S2_NST * kChunk > kT) ? S2_NST * kChunk : kT;
-    static constexpr int kALoads = kA / 32 / 8;          // 4-byte-piece loads per wave (RT)
-    static constexpr int kBLoads = kB / 128 / 8;         // 16-byte-piece loads per wave (2)
+    static constexpr int kALoads = kA / 32 / 8;          // 4-byte-piece loads per wave (RT S2_TK / 16)
+    static constexpr int kBLoads = kB / 128 / 8;         // 16-byte-piece loads per wave (S2_TK / 8)
     static_assert(kALoads * 32 * 8 == kA && kBLoads * 128 * 8 == kB, "whole loads per wave");
-    static_assert(S2_NST == 3 || S2_NST == 4, "the chunk loop's waits cover 3 or 4 buffers");
+    static_assert(S2_NST >= 2 && S2_NST <= 4, "the chunk loop's waits cover 2 to 4 buffers");
 };
 
 template <int RT>
@@ -964,24 +975,24 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
     }
     __syncthreads();
     // byte offsets of this lane's A pieces from L + kc n_rows + r0 (fixed per tile)
-    int64_t aoff[RT];
+    int64_t aoff[S::kALoads];
 #pragma unroll
-    for (int v = 0; v < RT; ++v) {
+    for (int v = 0; v < S::kALoads; ++v) {
         const int f = 32 * (8 * v + w) + (lane >> 1);
         const int k = f / R, m = min(f % R, rows_here - 1);
         aoff[v] = ((int64_t)k * n_rows + m) * 8 + 4 * (lane & 1);
     }
     // B pieces: row n and stored k-pair of this lane's piece v
-    int bn[2], bk[2];
+    int bn[S::kBLoads], bk[S::kBLoads];
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        const int n = 8 * (8 * v + w) + (lane >> 3);
+    for (int v = 0; v < S::kBLoads; ++v) {
+        const int n = kBRows * (8 * v + w) + lane / kBPairs;
         bn[v] = n;
-        bk[v] = 2 * ((lane & 7) ^ ((n >> 1) & 7));
+        bk[v] = 2 * ((lane % kBPairs) ^ b_swz(n));
     }
     // LDS index of this lane's B operand at k-step s: column 16 cg + lane % 16,
     // k = 4 s + lane / 16, i.e. k-pair 2 s + lane / 32, element (lane / 16) % 2
-    const int nB = 16 * cg + (lane & 15), swB = (nB >> 1) & 7;
+    const int nB = 16 * cg + (lane & 15), swB = b_swz(nB);
     auto b_index = [&](int s) -> int {
         return nB * S2_TK + 2 * ((2 * s + (lane >> 5)) ^ swB) + ((lane >> 4) & 1);
     };
@@ -990,9 +1001,9 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
         const int nb = (int)min((int64_t)S2_NB, M - b0);
         const int64_t blk = (b0 - k0) / S2_NB;
         mark(blk, 0);
-        int64_t boff[2];
+        int64_t boff[S::kBLoads];
 #pragma unroll
-        for (int v = 0; v < 2; ++v) boff[v] = ((int64_t)min(bn[v], nb - 1) * ldp + bk[v]) * 8;
+        for (int v = 0; v < S::kBLoads; ++v) boff[v] = ((int64_t)min(bn[v], nb - 1) * ldp + bk[v]) * 8;
         const char *Abase = reinterpret_cast<const char *>(L + r0);
         const char *Bbase = reinterpret_cast<const char *>(Lp + b0 * ldp);
 
@@ -1003,11 +1014,11 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
             if (kc + S2_TK <= b0) {
                 const char *a = Abase + kc * n_rows * 8;
 #pragma unroll
-                for (int v = 0; v < RT; ++v)
+                for (int v = 0; v < S::kALoads; ++v)
                     lds_dma4(a + aoff[v], (lds_void *)(st + 32 * (8 * v + w)));
                 const char *b = Bbase + kc * 8;
 #pragma unroll
-                for (int v = 0; v < 2; ++v)
+                for (int v = 0; v < S::kBLoads; ++v)
                     lds_dma16(b + boff[v], (lds_void *)(st + S::kA + 128 * (8 * v + w)));
             } else {
                 // ragged last chunk (only when k_start is not a multiple of 16):
@@ -1018,7 +1029,7 @@ __global__ __launch_bounds__(512) void k_step2(const Step2Batch B)
                 }
                 for (int e = tid; e < S::kB; e += 512) {
                     const int n = e / S2_TK, k = e % S2_TK;
-                    const int at = n * S2_TK + 2 * ((k >> 1) ^ ((n >> 1) & 7)) + (k & 1);
+                    const int at = n * S2_TK + 2 * ((k >> 1) ^ b_swz(n)) + (k & 1);
                     st[S::kA + at] =
                         (kc + k < b0) ? Lp[(b0 + min(n, nb - 1)) * ldp + kc + k] : 0.0;
                 }
