@@ -73,8 +73,17 @@ __global__ __launch_bounds__(256) void k_jV(const double *__restrict__ L, int64_
     const int64_t Pv = blockIdx.x;
     if (Pv >= *n_vectors) return;
     const double *row = L + Pv * n_rows;
-    double s = 0.0;
-    for (int64_t r = threadIdx.x; r < n_rows; r += 256) s = fma(row[r], w[r], s);
+    // four independent sums, so four loads per thread are in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t r = threadIdx.x;
+    for (; r + 768 < n_rows; r += 1024) {
+        s0 = fma(row[r], w[r], s0);
+        s1 = fma(row[r + 256], w[r + 256], s1);
+        s2 = fma(row[r + 512], w[r + 512], s2);
+        s3 = fma(row[r + 768], w[r + 768], s3);
+    }
+    for (; r < n_rows; r += 256) s0 = fma(row[r], w[r], s0);
+    double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
@@ -94,23 +103,25 @@ __global__ __launch_bounds__(256) void k_jJ(const double *__restrict__ L, int64_
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * 64 + lane;
     const int64_t M = *n_vectors;
-    double s0 = 0.0, s1 = 0.0;
+    // eight independent sums, so eight loads per lane are in flight
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (r < n_rows) {
         int64_t Pv = w;
-        for (; Pv + 4 < M; Pv += 8) {
-            s0 = fma(L[Pv * n_rows + r], V[Pv], s0);
-            s1 = fma(L[(Pv + 4) * n_rows + r], V[Pv + 4], s1);
+        for (; Pv + 28 < M; Pv += 32) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                s[j] = fma(L[(Pv + 4 * j) * n_rows + r], V[Pv + 4 * j], s[j]);
         }
-        for (; Pv < M; Pv += 4) s0 = fma(L[Pv * n_rows + r], V[Pv], s0);
+        for (; Pv < M; Pv += 4) s[0] = fma(L[Pv * n_rows + r], V[Pv], s[0]);
     }
-    s_part[w][lane] = s0 + s1;
+    s_part[w][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     if (w == 0 && r < n_rows) {
-        const double s = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
+        const double tot = (s_part[0][lane] + s_part[1][lane]) + (s_part[2][lane] + s_part[3][lane]);
         int mu, nu;
         unpack_pair(row_pair[r], mu, nu);
-        J[(int64_t)mu * N + nu] = s;
-        J[(int64_t)nu * N + mu] = s;
+        J[(int64_t)mu * N + nu] = tot;
+        J[(int64_t)nu * N + mu] = tot;
     }
 }
 
