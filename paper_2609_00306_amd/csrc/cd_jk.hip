@@ -496,21 +496,32 @@ __device__ __forceinline__ void syrk_tile_split(int N, int nsplit, int &t, int &
 //   Kp[s][mu][nu] = sum_{k in slab s} X[mu][k] X[nu][k]   (lower tile pairs)
 // A 256-thread workgroup owns a 64 x 64 tile pair; wave w the 32 x 32 quarter
 // (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 accumulators of the 16x16x4
-// FP64 instruction.  k-chunks of 16 values of the 128 rows (both sides: 16 KB)
-// go straight from memory into a three-buffer LDS ring two chunks ahead of the
-// products (global_load_lds, 16-byte pieces, 4 per lane per chunk; one
-// barrier per chunk); LDS rows are 128 bytes, unpadded, with the k-pair index
-// XORed with (row / 2) % 8.  Smaller tiles than the reduced-precision forms'
-// 128 x 128: N = 1200 pads to 1216 rows instead of 1280 and the diagonal tiles
-// compute less of the upper triangle (1.08x the lower-triangle flops instead
-// of 1.25x), and 48 KB of LDS leaves room for three workgroups per compute unit.
-constexpr int XR_TK = 16;
-constexpr int XR_STAGE = 128 * XR_TK;   // doubles per chunk (16 KB)
+// FP64 instruction.  k-chunks of 32 values of the 128 rows (both sides: 32 KB)
+// go straight from memory into two LDS buffers one chunk ahead of the products
+// (global_load_lds, 16-byte pieces, 8 per lane per chunk; one barrier per
+// chunk); LDS rows are 256 bytes, unpadded, with the k-pair index XORed with
+// row % 16.  64 KB of LDS: two workgroups per compute unit.  (Chunks of 16 in
+// a three-buffer ring, three workgroups per unit, made the 1200-function J/K
+// build 2 ms slower; chunks of 32 in three buffers, one workgroup per unit,
+// 6 ms slower.)  Smaller tiles than the reduced-precision forms' 128 x 128:
+// N = 1200 pads to 1216 rows instead of 1280 and the diagonal tiles compute
+// less of the upper triangle (1.08x the lower-triangle flops instead of
+// 1.25x).
+constexpr int XR_TK = 32;    // k per chunk
+constexpr int XR_NST = 2;    // chunk buffers (loads run XR_NST - 1 chunks ahead)
+constexpr int XR_STAGE = 128 * XR_TK;          // doubles per chunk
+constexpr int XR_LOADS = XR_STAGE / 2 / 256;   // 16-byte pieces per lane per chunk
+constexpr int XR_RPW = 64 / (XR_TK / 2);       // rows one wave's 64 pieces cover
+static_assert(XR_TK == 16 || XR_TK == 32, "chunk of 16 or 32 values");
+static_assert(XR_NST == 2 || XR_NST == 3, "two or three chunk buffers");
+// stored k-pair slot of k-pair g in row r: g ^ xr_swz(r), so the 16 rows read
+// at one k-pair by a quarter-wave fall on different banks
+__device__ __forceinline__ int xr_swz(int r) { return (XR_TK == 16) ? ((r >> 1) & 7) : (r & 15); }
 __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X, int64_t ldx,
                                                    int N, const int64_t *__restrict__ n_vectors,
                                                    int ncol, int nsplit, double *__restrict__ Kp)
 {
-    __shared__ __align__(16) double sX[3 * XR_STAGE];
+    __shared__ __align__(16) double sX[XR_NST * XR_STAGE];
     int t, s;
     syrk_tile_split(N, nsplit, t, s);
     int tm = 0;
@@ -523,35 +534,36 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
     const int64_t ke = (kb + per < nk) ? kb + per : nk;
     const int m0 = tm * 64, n0 = tn * 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..63 the
-    // A side m0.., 64..127 the B side n0..; rows past N read row N - 1), slot
-    // lane % 8, which holds k-pair (lane % 8) ^ ((r / 2) % 8) of that row
-    int64_t goff[4];
+    // piece v of this lane: LDS row r = XR_RPW (4 v + w) + lane / (XR_TK / 2)
+    // (rows 0..63 the A side m0.., 64..127 the B side n0..; rows past N read
+    // row N - 1), slot lane % (XR_TK / 2), which holds k-pair
+    // slot ^ xr_swz(r) of that row
+    int64_t goff[XR_LOADS];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = 8 * (4 * v + w) + (lane >> 3);
+    for (int v = 0; v < XR_LOADS; ++v) {
+        const int r = XR_RPW * (4 * v + w) + lane / (XR_TK / 2);
         const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
-        goff[v] = (int64_t)grow * ldx + 2 * ((lane & 7) ^ ((r >> 1) & 7));
+        goff[v] = (int64_t)grow * ldx + 2 * ((lane % (XR_TK / 2)) ^ xr_swz(r));
     }
     // a full chunk straight into LDS; a partial last chunk through registers
     // with the values past ke set to zero
     auto load_chunk = [&](double *st, int64_t k0) __attribute__((always_inline)) {
         if (k0 + XR_TK <= ke) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < XR_LOADS; ++v)
                 lds_dma16(X + k0 + goff[v], (lds_void *)(st + 128 * (4 * v + w)));
         } else {
             for (int e = tid; e < XR_STAGE; e += 256) {
                 const int r = e / XR_TK, k = e % XR_TK;
                 const int grow = min((r < 64) ? m0 + r : n0 + r - 64, N - 1);
-                st[r * XR_TK + 2 * ((k >> 1) ^ ((r >> 1) & 7)) + (k & 1)] =
+                st[r * XR_TK + 2 * ((k >> 1) ^ xr_swz(r)) + (k & 1)] =
                     (k0 + k < ke) ? X[(int64_t)grow * ldx + k0 + k] : 0.0;
             }
         }
     };
     // operands of this lane at k-step q: row r with r % 16 = lane % 16,
     // k = 4 q + lane / 16, i.e. k-pair 2 q + lane / 32, element (lane / 16) % 2
-    const int lr = lane & 15, sw = (lr >> 1) & 7, hi = lane >> 5, el = (lane >> 4) & 1;
+    const int lr = lane & 15, sw = xr_swz(lr), hi = lane >> 5, el = (lane >> 4) & 1;
     const int ar = 32 * (w >> 1) + lr, br = 64 + 32 * (w & 1) + lr;
     f64x4 acc[2][2];
 #pragma unroll
@@ -570,21 +582,23 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     };
-    // chunk c: its own loads landed (the next chunk's may stay in flight), a
-    // barrier (every wave's pieces of chunk c are in, and every wave is done
-    // with the buffer that chunk c + 2 refills), the loads of chunk c + 2, then
-    // the products of chunk c
+    // chunk c: its own loads landed (those of the next XR_NST - 2 chunks may
+    // stay in flight), a barrier (every wave's pieces of chunk c are in, and
+    // every wave is done with the buffer that chunk c + XR_NST - 1 refills), the
+    // loads of chunk c + XR_NST - 1, then the products of chunk c
     const int64_t nch = (ke > kb) ? (ke - kb + XR_TK - 1) / XR_TK : 0;
-    if (nch > 0) load_chunk(sX, kb);
-    if (nch > 1) load_chunk(sX + XR_STAGE, kb + XR_TK);
+#pragma unroll
+    for (int c = 0; c < XR_NST - 1; ++c)
+        if (c < nch) load_chunk(sX + c * XR_STAGE, kb + c * XR_TK);
     int buf = 0;
     for (int64_t c = 0; c < nch; ++c) {
-        if (c + 1 < nch) wait_vmcnt<4>();
+        if (XR_NST == 3 && c + 1 < nch) wait_vmcnt<XR_LOADS>();
         else wait_vmcnt<0>();
         lds_barrier();
-        if (c + 2 < nch) load_chunk(sX + ((buf == 0) ? 2 : buf - 1) * XR_STAGE, kb + (c + 2) * XR_TK);
+        if (c + XR_NST - 1 < nch)
+            load_chunk(sX + ((buf == 0) ? XR_NST - 1 : buf - 1) * XR_STAGE, kb + (c + XR_NST - 1) * XR_TK);
         mma_chunk(sX + buf * XR_STAGE);
-        buf = (buf == 2) ? 0 : buf + 1;
+        buf = (buf == XR_NST - 1) ? 0 : buf + 1;
     }
     double *out = Kp + (int64_t)s * N * N;
 #pragma unroll
