@@ -503,10 +503,9 @@ __device__ __forceinline__ void syrk_tile_split(int N, int nsplit, int &t, int &
 // row % 16.  64 KB of LDS: two workgroups per compute unit.  (Chunks of 16 in
 // a three-buffer ring, three workgroups per unit, made the 1200-function J/K
 // build 2 ms slower; chunks of 32 in three buffers, one workgroup per unit,
-// 6 ms slower.)  Smaller tiles than the reduced-precision forms' 128 x 128:
-// N = 1200 pads to 1216 rows instead of 1280 and the diagonal tiles compute
-// less of the upper triangle (1.08x the lower-triangle flops instead of
-// 1.25x).
+// 6 ms slower.)  It serves the sizes where 128 x 128 tiles (k_syrk_rows128)
+// would pad much more: N = 400 takes 448 rows in 64 x 64 tiles, 512 in 128 x
+// 128 ones, and the diagonal tiles compute less of the upper triangle.
 constexpr int XR_TK = 32;    // k per chunk
 constexpr int XR_NST = 2;    // chunk buffers (loads run XR_NST - 1 chunks ahead)
 constexpr int XR_STAGE = 128 * XR_TK;          // doubles per chunk
@@ -613,6 +612,110 @@ __global__ __launch_bounds__(256) void k_syrk_rows(const double *__restrict__ X,
             }
 }
 
+
+// The same partial K over lower 128 x 128 tile pairs: wave w owns the 64 x 64
+// quarter (rows 64 (w / 2), columns 64 (w % 2)) as 4 x 4 accumulators, so each
+// operand read from LDS feeds four products.  k-chunks of 16 values of the 256
+// rows (both sides: 32 KB) go straight into two LDS buffers one chunk ahead
+// (global_load_lds, 8 pieces per lane per chunk); LDS rows are 128 bytes with
+// the k-pair index XORed with (row / 2) % 8.  64 KB of LDS: two workgroups per
+// compute unit.  Workgroup g runs on XCD g % 8; its j = g / 8 -th item is tile
+// pair j % pairs of split 8 (j / pairs) + g % 8.
+constexpr int XQ_TK = 16;
+constexpr int XQ_STAGE = 256 * XQ_TK;          // doubles per chunk
+constexpr int XQ_LOADS = XQ_STAGE / 2 / 256;   // 16-byte pieces per lane per chunk (8)
+__global__ __launch_bounds__(256) void k_syrk_rows128(const double *__restrict__ X, int64_t ldx,
+                                                      int N, const int64_t *__restrict__ n_vectors,
+                                                      int ncol, int pairs, int nsplit,
+                                                      double *__restrict__ Kp)
+{
+    __shared__ __align__(16) double sX[2 * XQ_STAGE];
+    const int g = blockIdx.x, j = g >> 3, t = j % pairs, s = 8 * (j / pairs) + (g & 7);
+    int tm = 0;
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    const int64_t nk = *n_vectors * ncol;
+    int64_t per = (nk + nsplit - 1) / nsplit;
+    per = (per + XQ_TK - 1) / XQ_TK * XQ_TK;
+    const int64_t kb = s * per;
+    const int64_t ke = (kb + per < nk) ? kb + per : nk;
+    const int m0 = tm * 128, n0 = tn * 128;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // piece v of this lane: LDS row r = 8 (4 v + w) + lane / 8 (rows 0..127 the
+    // A side m0.., 128..255 the B side n0..; rows past N read row N - 1), slot
+    // lane % 8, which holds k-pair (lane % 8) ^ ((r / 2) % 8) of that row
+    int64_t goff[XQ_LOADS];
+#pragma unroll
+    for (int v = 0; v < XQ_LOADS; ++v) {
+        const int r = 8 * (4 * v + w) + (lane >> 3);
+        const int grow = min((r < 128) ? m0 + r : n0 + r - 128, N - 1);
+        goff[v] = (int64_t)grow * ldx + 2 * ((lane & 7) ^ ((r >> 1) & 7));
+    }
+    auto load_chunk = [&](double *st, int64_t k0) __attribute__((always_inline)) {
+        if (k0 + XQ_TK <= ke) {
+#pragma unroll
+            for (int v = 0; v < XQ_LOADS; ++v)
+                lds_dma16(X + k0 + goff[v], (lds_void *)(st + 128 * (4 * v + w)));
+        } else {
+            for (int e = tid; e < XQ_STAGE; e += 256) {
+                const int r = e / XQ_TK, k = e % XQ_TK;
+                const int grow = min((r < 128) ? m0 + r : n0 + r - 128, N - 1);
+                st[r * XQ_TK + 2 * ((k >> 1) ^ ((r >> 1) & 7)) + (k & 1)] =
+                    (k0 + k < ke) ? X[(int64_t)grow * ldx + k0 + k] : 0.0;
+            }
+        }
+    };
+    const int lr = lane & 15, sw = (lr >> 1) & 7, hi = lane >> 5, el = (lane >> 4) & 1;
+    const int ar = 64 * (w >> 1) + lr, br = 128 + 64 * (w & 1) + lr;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // a wave whose 64 rows or 64 columns all lie past N (the padding of the
+    // last tile) issues no products: the other workgroup on its compute unit
+    // gets the matrix unit
+    const bool idle = m0 + 64 * (w >> 1) >= N || n0 + 64 * (w & 1) >= N;
+    auto mma_chunk = [&](const double *S) __attribute__((always_inline)) {
+        if (idle) return;
+#pragma unroll
+        for (int q = 0; q < XQ_TK / 4; ++q) {
+            const int col = 2 * ((2 * q + hi) ^ sw) + el;
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = S[(ar + 16 * i) * XQ_TK + col];
+                b[i] = S[(br + 16 * i) * XQ_TK + col];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[jj], acc[i][jj], 0, 0, 0);
+        }
+    };
+    const int64_t nch = (ke > kb) ? (ke - kb + XQ_TK - 1) / XQ_TK : 0;
+    if (nch > 0) load_chunk(sX, kb);
+    int buf = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+        wait_vmcnt<0>();
+        lds_barrier();
+        if (c + 1 < nch) load_chunk(sX + (buf ^ 1) * XQ_STAGE, kb + (c + 1) * XQ_TK);
+        mma_chunk(sX + buf * XQ_STAGE);
+        buf ^= 1;
+    }
+    double *out = Kp + (int64_t)s * N * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 64 * (w >> 1) + 16 * i + mfma_row(lane, e);
+                const int n = n0 + 64 * (w & 1) + 16 * jj + lr;
+                if (m < N && n < N) out[(int64_t)m * N + n] = acc[i][jj][e];
+            }
+}
 
 // K[mu][nu] (+)= sum_s Kp[s][max][min]  -- exactly symmetric
 __global__ void k_kreduce(const double *__restrict__ Kp, int N, int nsplit, int accumulate,

@@ -884,6 +884,17 @@ namespace {
 
 // k-splits of the exchange product: a multiple of 8 (one XCD per split, see
 // syrk_tile_split) giving at least two workgroups per compute unit.
+// The FP64 exchange product runs on 128 x 128 tile pairs when their padded
+// work is within 1.17x that of 64 x 64 pairs, the speed per issued flop of the
+// larger tiles measured on the 1000-function workload (J/K 23.6 -> 20.4 ms,
+// both padding N to 1024); 400 functions stay on 64 x 64 tiles (1.13 ms
+// against 1.37 ms with 128 x 128).
+bool jk_tiles128(int N)
+{
+    const double t1 = (N + 63) / 64, t2 = (N + 127) / 128;
+    return t2 * (t2 + 1) / 2 * 16384.0 < 1.17 * (t1 * (t1 + 1) / 2 * 4096.0);
+}
+
 int jk_nsplit(int N, int n_cu)
 {
     const int T = (N + 63) / 64;
@@ -967,6 +978,7 @@ int jk_splits(int N, int n_cu, cd_precision prec)
         ns = (ns + 7) / 8 * 8;
         return std::max(8, std::min(ns, 64));
     }
+    if (jk_tiles128(N)) return 32;   // four k-ranges per XCD, two workgroups per compute unit
     return jk_nsplit(N, n_cu);
 }
 
@@ -1183,7 +1195,13 @@ cd_status cd_build_jk(const cd_jk_problem *probs, int32_t count, cd_precision pr
                                   sp);
             if (p.Lmo && (s = second_half(w.X))) return s;
             if ((s = j_chain())) return s;
-            k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
+            if (jk_tiles128((int)N)) {
+                const int T2 = (int)blocks_of(N, 128), pairs2 = T2 * (T2 + 1) / 2;
+                k_syrk_rows128<<<(unsigned)(pairs2 * nsplit), 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors,
+                                                                            O, pairs2, nsplit, w.Kp);
+            } else {
+                k_syrk_rows<<<sgrid, 256, 0, sp>>>(w.X, ldx, (int)N, p.n_vectors, O, nsplit, w.Kp);
+            }
         } else if (prec == CD_FP32) {
             // X in FP64 (matrix cores), written rounded to FP32 (k-blocked; and in
             // FP64 for C^T L C); the exchange product then runs on FP32 matrix cores
