@@ -978,7 +978,19 @@ int jk_splits(int N, int n_cu, cd_precision prec)
         ns = (ns + 7) / 8 * 8;
         return std::max(8, std::min(ns, 64));
     }
-    if (jk_tiles128(N)) return 32;   // four k-ranges per XCD, two workgroups per compute unit
+    if (jk_tiles128(N)) {
+        // 128 x 128 pairs, two workgroups per compute unit: the fewest k-ranges
+        // (32 to 64, whole per XCD) whose last round of workgroups is at least
+        // 80% full (the 1000-function J/K build: 32 k-ranges 20.6 ms, 40 (the
+        // choice) 19.8 ms, 48 19.8 ms; 1200 functions: 32 (the choice) and 64
+        // 36.7 ms, 48 37.6 ms)
+        const int T = (N + 127) / 128, pairs = T * (T + 1) / 2, slots = 2 * std::max(1, n_cu);
+        for (int ns = 32; ns < 64; ns += 8) {
+            const double r = (double)pairs * ns / slots;
+            if (r / std::ceil(r) >= 0.8) return ns;
+        }
+        return 64;
+    }
     return jk_nsplit(N, n_cu);
 }
 
