@@ -238,6 +238,27 @@ def test_jk_wide_occupied_sets(n_occ, prec):
     assert np.abs(jk.Lmo[:M].cpu().numpy() - exp).max() <= TOL_L
 
 
+def test_jk_large_tile_product():
+    """600 functions (150 centres), where the FP64 exchange product runs on
+    128 x 128 tile pairs: five tiles, the last holding 88 functions, so the
+    second 64-row half of that tile is partly padding (the 1200-function
+    workload, checked against stored oracle rows, has a fully padded half).
+    J and K in every precision against the oracle's FP64 build from the
+    oracle's vectors."""
+    m = make_molecule(150, 16.0 * 1.5 ** (1.0 / 3.0), (0.3, 1.5, 7.0, 30.0), 75, seed=17)
+    assert m.n_basis == 600
+    d, M = run_gpu(m, 1e-5, 1e-12)
+    rp, ref = check_against_oracle(m, 1e-5, 1e-12, d, M)
+    Jr, Kr = oracle.jk_cd(m.n_basis, rp, ref.L, m.C)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        J, K = cdlib.build_jk(d, m.C, prec)
+        J = J.cpu().numpy()
+        K = K.cpu().numpy()
+        assert np.abs(J - Jr).max() <= TOL_JK, prec
+        assert np.abs(K - Kr).max() <= (TOL_JK if prec == "fp64" else TOL_K[prec]), prec
+        assert np.array_equal(K, K.T), prec
+
+
 @pytest.mark.parametrize("name,eta", [("C1", 0.5), ("C1", 0.05), ("ragged", 0.1), ("C2", 0.1)])
 def test_span_factor_gives_a_valid_decomposition(name, eta):
     """Span factor eta < 1 (Sec. 3, Table 1): pivots are taken from the qualified
