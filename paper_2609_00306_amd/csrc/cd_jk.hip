@@ -651,18 +651,19 @@ __global__ __launch_bounds__(256) void k_syrk_rows128(const double *__restrict__
         const int grow = min((r < 128) ? m0 + r : n0 + r - 128, N - 1);
         goff[v] = (int64_t)grow * ldx + 2 * ((lane & 7) ^ ((r >> 1) & 7));
     }
+    // a full chunk straight into LDS
     auto load_chunk = [&](double *st, int64_t k0) __attribute__((always_inline)) {
-        if (k0 + XQ_TK <= ke) {
 #pragma unroll
-            for (int v = 0; v < XQ_LOADS; ++v)
-                lds_dma16(X + k0 + goff[v], (lds_void *)(st + 128 * (4 * v + w)));
-        } else {
-            for (int e = tid; e < XQ_STAGE; e += 256) {
-                const int r = e / XQ_TK, k = e % XQ_TK;
-                const int grow = min((r < 128) ? m0 + r : n0 + r - 128, N - 1);
-                st[r * XQ_TK + 2 * ((k >> 1) ^ ((r >> 1) & 7)) + (k & 1)] =
-                    (k0 + k < ke) ? X[(int64_t)grow * ldx + k0 + k] : 0.0;
-            }
+        for (int v = 0; v < XQ_LOADS; ++v)
+            lds_dma16(X + k0 + goff[v], (lds_void *)(st + 128 * (4 * v + w)));
+    };
+    // a partial last chunk through registers, the values past ke set to zero
+    auto load_tail = [&](double *st, int64_t k0) __attribute__((always_inline)) {
+        for (int e = tid; e < XQ_STAGE; e += 256) {
+            const int r = e / XQ_TK, k = e % XQ_TK;
+            const int grow = min((r < 128) ? m0 + r : n0 + r - 128, N - 1);
+            st[r * XQ_TK + 2 * ((k >> 1) ^ ((r >> 1) & 7)) + (k & 1)] =
+                (k0 + k < ke) ? X[(int64_t)grow * ldx + k0 + k] : 0.0;
         }
     };
     const int lr = lane & 15, sw = (lr >> 1) & 7, hi = lane >> 5, el = (lane >> 4) & 1;
@@ -694,15 +695,25 @@ __global__ __launch_bounds__(256) void k_syrk_rows128(const double *__restrict__
                     acc[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[jj], acc[i][jj], 0, 0, 0);
         }
     };
-    const int64_t nch = (ke > kb) ? (ke - kb + XQ_TK - 1) / XQ_TK : 0;
-    if (nch > 0) load_chunk(sX, kb);
+    // the full chunks in the loop (no other path inside it), then the partial
+    // last chunk, if any
+    const int64_t nfull = (ke > kb) ? (ke - kb) / XQ_TK : 0;
+    const bool tail = ke > kb + nfull * XQ_TK;
+    if (nfull > 0) load_chunk(sX, kb);
     int buf = 0;
-    for (int64_t c = 0; c < nch; ++c) {
+    for (int64_t c = 0; c < nfull; ++c) {
         wait_vmcnt<0>();
         lds_barrier();
-        if (c + 1 < nch) load_chunk(sX + (buf ^ 1) * XQ_STAGE, kb + (c + 1) * XQ_TK);
+        if (c + 1 < nfull) load_chunk(sX + (buf ^ 1) * XQ_STAGE, kb + (c + 1) * XQ_TK);
         mma_chunk(sX + buf * XQ_STAGE);
         buf ^= 1;
+    }
+    if (tail) {
+        wait_vmcnt<0>();
+        lds_barrier();   // every wave is done with the buffer the tail refills
+        load_tail(sX + buf * XQ_STAGE, kb + nfull * XQ_TK);
+        lds_barrier();
+        mma_chunk(sX + buf * XQ_STAGE);
     }
     double *out = Kp + (int64_t)s * N * N;
 #pragma unroll
